@@ -1,0 +1,251 @@
+"""Oracle of the TPC track-finding hot path -- TEST INFRASTRUCTURE ONLY.
+
+Thin numpy/ctypes wrapper around liboracle.so (plain single-threaded C,
+oracle.c).  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg import this package; the library under
+paper_1905_05515_amd never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_float) for n in (
+        "curv", "nb_win_y", "nb_win_z", "nb_d2max", "sigma_y2", "sigma_z2",
+        "chi2_max", "search_nsigma", "s_max", "c_ss0", "c_tt0", "c_ww0")] + \
+        [(n, C.c_int) for n in ("max_miss", "min_tracklet_hits", "min_track_hits")]
+
+
+class CalibModel(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("drift_len", "vd", "tan_half", "u_centre", "u_scale")]
+
+
+SECTOR_DTYPE = np.dtype([
+    ("y0", np.float32), ("z0", np.float32), ("inv_by", np.float32), ("inv_bz", np.float32),
+    ("nby", np.int32), ("nbz", np.int32), ("bin_base", np.int32), ("pad", np.int32),
+    ("begin", np.int64), ("end", np.int64)])
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.SO):
+            _build.build()
+        _lib = C.CDLL(_build.SO)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def params(d: dict) -> Params:
+    p = Params()
+    for name, _ in Params._fields_:
+        setattr(p, name, d[name])
+    return p
+
+
+def calib_model(drift_len=250.0, vd=2.58, tan_half=0.17632698070846498,
+                u_centre=165.0, u_scale=80.0) -> CalibModel:
+    return CalibModel(drift_len, vd, tan_half, u_centre, u_scale)
+
+
+def _sectors(layout):
+    tab = np.ascontiguousarray(layout, dtype=SECTOR_DTYPE)
+    return tab
+
+
+def build_grid(row, y, z, layout, n_bins, n_rows=152):
+    L = lib()
+    tab = _sectors(layout)
+    n = row.shape[0]
+    bin_start = np.zeros(n_bins + 1, np.int32)
+    yg = np.zeros(n, np.float32)
+    zg = np.zeros(n, np.float32)
+    idg = np.zeros(n, np.int32)
+    L.orc_build_grid.restype = C.c_int
+    placed = L.orc_build_grid(C.c_int(tab.shape[0]), _p(tab), C.c_int(n_rows), _p(row), _p(y),
+                              _p(z), C.c_int(n_bins), _p(bin_start), _p(yg), _p(zg), _p(idg))
+    if placed < 0:
+        raise MemoryError("oracle grid")
+    return dict(bin_start=bin_start, yg=yg[:placed], zg=zg[:placed], idg=idg[:placed])
+
+
+def find_neighbours(layout, row_x, prm, grid, n_clusters, n_rows=152):
+    L = lib()
+    tab = _sectors(layout)
+    up0 = np.empty(n_clusters, np.int32)
+    down0 = np.empty(n_clusters, np.int32)
+    P = params(prm)
+    L.orc_find_neighbours(C.c_int(tab.shape[0]), _p(tab), C.c_int(n_rows), _p(row_x),
+                          C.byref(P), _p(grid["bin_start"]), _p(grid["yg"]), _p(grid["zg"]),
+                          _p(grid["idg"]), C.c_int64(n_clusters), _p(up0), _p(down0))
+    return up0, down0
+
+
+def clean_links(up0, down0):
+    n = up0.shape[0]
+    up = np.empty(n, np.int32)
+    down = np.empty(n, np.int32)
+    lib().orc_clean_links(C.c_int64(n), _p(up0), _p(down0), _p(up), _p(down))
+    return up, down
+
+
+def select_starts(up, down):
+    n = up.shape[0]
+    starts = np.empty(max(n // 3, 1), np.int32)
+    L = lib()
+    L.orc_select_starts.restype = C.c_int64
+    m = L.orc_select_starts(C.c_int64(n), _p(up), _p(down), _p(starts))
+    return starts[:m].copy()
+
+
+def construct_tracklets(layout, row_x, prm, grid, row, y, z, up, starts, n_rows=152,
+                        brute=False):
+    L = lib()
+    tab = _sectors(layout)
+    m = starts.shape[0]
+    hits = np.empty((m, n_rows), np.int32)
+    nhits = np.empty(m, np.int32)
+    rin = np.empty(m, np.int32)
+    par = np.empty((m, 5), np.float32)
+    cov = np.empty((m, 15), np.float32)
+    chi2 = np.empty(m, np.float32)
+    P = params(prm)
+    L.orc_construct_tracklets(C.c_int(tab.shape[0]), _p(tab), C.c_int(n_rows), _p(row_x),
+                              C.byref(P), _p(grid["bin_start"]), _p(grid["yg"]),
+                              _p(grid["zg"]), _p(grid["idg"]), _p(row), _p(y), _p(z), _p(up),
+                              C.c_int64(m), _p(starts), C.c_int(1 if brute else 0), _p(hits),
+                              _p(nhits), _p(rin), _p(par), _p(cov), _p(chi2))
+    return dict(hits=hits, nhits=nhits, row_inner=rin, par=par, cov=cov, chi2=chi2)
+
+
+def tracklet_replay64(row_x, prm, y, z, start_row, hits_by_row, n_rows=152):
+    L = lib()
+    P = params(prm)
+    par = np.empty(5, np.float64)
+    cov = np.empty(15, np.float64)
+    chi2 = np.empty(1, np.float64)
+    hb = np.ascontiguousarray(hits_by_row, np.int32)
+    st = L.orc_tracklet_replay64(C.c_int(n_rows), _p(row_x), C.byref(P), _p(y), _p(z),
+                                 C.c_int(int(start_row)), _p(hb), _p(par), _p(cov), _p(chi2))
+    return st, par, cov, float(chi2[0])
+
+
+def select_tracks(n_clusters, prm, tracklets, starts, n_rows=152):
+    L = lib()
+    P = params(prm)
+    m = starts.shape[0]
+    off = np.zeros(m + 1, np.int32)
+    th = np.empty(max(n_clusters, 1), np.int32)
+    tt = np.empty(max(m, 1), np.int32)
+    L.orc_select_tracks.restype = C.c_int64
+    nt = L.orc_select_tracks(C.c_int64(n_clusters), C.c_int(n_rows), C.byref(P), C.c_int64(m),
+                             _p(tracklets["hits"]), _p(tracklets["nhits"]), _p(starts),
+                             _p(off), _p(th), _p(tt))
+    off = off[:nt + 1].copy()
+    return dict(trk_off=off, trk_hits=th[:off[-1]].copy(), trk_tracklet=tt[:nt].copy())
+
+
+def track_event(row, y, z, layout, n_bins, row_x, prm, n_rows=152, brute=False):
+    """The whole chain: grid, neighbours, cleaning, starts, tracklets,
+    selection.  Returns a dict of every intermediate (id space)."""
+    grid = build_grid(row, y, z, layout, n_bins, n_rows)
+    n = row.shape[0]
+    up0, down0 = find_neighbours(layout, row_x, prm, grid, n, n_rows)
+    up, down = clean_links(up0, down0)
+    starts = select_starts(up, down)
+    trl = construct_tracklets(layout, row_x, prm, grid, row, y, z, up, starts, n_rows, brute)
+    trk = select_tracks(n, prm, trl, starts, n_rows)
+    return dict(grid=grid, up0=up0, down0=down0, up=up, down=down, starts=starts,
+                tracklets=trl, tracks=trk)
+
+
+def refit(trk_off, row, y, z, row_x, prm, theta, side=None, cm=None, fp64=False):
+    L = lib()
+    P = params(prm)
+    cm = cm or calib_model()
+    n = trk_off.shape[0] - 1
+    dt = np.float64 if fp64 else np.float32
+    y = np.ascontiguousarray(y, dt)
+    z = np.ascontiguousarray(z, dt)
+    th = np.ascontiguousarray(theta, dt)
+    par = np.empty((n, 5), dt)
+    cov = np.empty((n, 15), dt)
+    chi2 = np.empty(n, dt)
+    status = np.empty(n, np.int32)
+    sd = None if side is None else np.ascontiguousarray(side, np.int8)
+    fn = L.orc_refit64 if fp64 else L.orc_refit32
+    fn(C.c_int64(n), _p(np.ascontiguousarray(trk_off, np.int32)), _p(row), _p(y), _p(z),
+       _p(sd), _p(row_x), C.byref(P), C.byref(cm), _p(th), _p(par), _p(cov), _p(chi2),
+       _p(status))
+    return dict(par=par, cov=cov, chi2=chi2, status=status)
+
+
+def refit_fd_grad(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None,
+                  h_hit=1e-4, h_theta=1e-5):
+    """FP64 central differences of L = sum_t g_t chi2_t."""
+    L = lib()
+    P = params(prm)
+    cm = cm or calib_model()
+    n = trk_off.shape[0] - 1
+    nh = row.shape[0]
+    gy = np.zeros(nh, np.float64)
+    gz = np.zeros(nh, np.float64)
+    gt = np.zeros(16, np.float64)
+    sd = None if side is None else np.ascontiguousarray(side, np.int8)
+    L.orc_refit64_fd_grad(C.c_int64(n), _p(np.ascontiguousarray(trk_off, np.int32)), _p(row),
+                          _p(np.ascontiguousarray(y, np.float64)),
+                          _p(np.ascontiguousarray(z, np.float64)), _p(sd), _p(row_x),
+                          C.byref(P), C.byref(cm), _p(np.ascontiguousarray(theta, np.float64)),
+                          _p(np.ascontiguousarray(g, np.float64)), C.c_double(h_hit),
+                          C.c_double(h_theta), _p(gy), _p(gz), _p(gt))
+    return gy, gz, gt
+
+
+def propagate(p, Cov, dx, curv, s_max=0.95, fp64=True):
+    """One propagation step; returns (ok, p', C')."""
+    dt = np.float64 if fp64 else np.float32
+    p = np.array(p, dt)
+    Cv = np.array(Cov, dt)
+    L = lib()
+    if fp64:
+        ok = L.orc_propagate64(_p(p), _p(Cv), C.c_double(dx), C.c_double(curv), C.c_double(s_max))
+    else:
+        ok = L.orc_propagate32(_p(p), _p(Cv), C.c_float(dx), C.c_float(curv), C.c_float(s_max))
+    return bool(ok), p, Cv
+
+
+def update(p, Cov, my, mz, sy2, sz2, fp64=True):
+    """One Kalman update; returns (chi2, p', C')."""
+    dt = np.float64 if fp64 else np.float32
+    p = np.array(p, dt)
+    Cv = np.array(Cov, dt)
+    L = lib()
+    if fp64:
+        L.orc_update64.restype = C.c_double
+        c2 = L.orc_update64(_p(p), _p(Cv), C.c_double(my), C.c_double(mz), C.c_double(sy2),
+                            C.c_double(sz2))
+    else:
+        L.orc_update32.restype = C.c_float
+        c2 = L.orc_update32(_p(p), _p(Cv), C.c_float(my), C.c_float(mz), C.c_float(sy2),
+                            C.c_float(sz2))
+    return c2, p, Cv
+
+
+def calibrate(theta, xr, yr, zr, side=1.0, cm=None):
+    out = np.empty(3, np.float64)
+    cm = cm or calib_model()
+    lib().orc_calibrate64(_p(np.ascontiguousarray(theta, np.float64)), C.c_double(xr),
+                          C.c_double(yr), C.c_double(zr), C.c_double(side), C.byref(cm),
+                          _p(out))
+    return out

@@ -1,0 +1,225 @@
+/*
+ * Kalman-filter primitives of the oracle, written once for a generic real
+ * type.  oracle.c includes this file twice: REAL=float (suffix _f) and
+ * REAL=double (suffix _d).  TEST INFRASTRUCTURE ONLY.
+ *
+ * State at the sector-local plane x (reading of the paper's Kalman-filter
+ * track following, section 3):  p = (y, z, s, t, w) with s = sin(phi),
+ * t = tan(lambda), w = q/pT; covariance C stored as the lower triangle of
+ * the symmetric 5x5 matrix, row by row: C(i,j), i >= j, at i*(i+1)/2 + j.
+ *
+ * Helix in a uniform field along z: the curvature k = curv * w is constant,
+ * so sin(phi) grows linearly with x (ds/dx = k), the y step is
+ * dx * (s1 + s2) / (c1 + c2) with c = sqrt(1 - s^2) (exact for a circle),
+ * and the transverse arc length over the step is chord * asin(a)/a with
+ * a = k * chord / 2, expanded to a^6 (the remainder is below 1e-10 for
+ * single-row steps).
+ */
+#define CAT_(a, b) a##b
+#define CAT(a, b) CAT_(a, b)
+#define FN(name) CAT(name, SUF)
+
+#define R1 ((REAL)1)
+#define R2 ((REAL)2)
+#define RH ((REAL)0.5)
+
+static inline int FN(lt)(int i, int j)
+{
+    return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+/* Non-trivial entries of the transport Jacobian F = d(p2)/d(p1); the rest
+ * is the identity.  F is upper triangular: y depends on s and w, z on s, t
+ * and w, s on w. */
+typedef struct {
+    REAL ys, yw, zs, zt, zw, sw;
+} FN(jac_t);
+
+/* Propagate p, C from plane x1 to x2 = x1 + dx.  Returns 0 (and leaves
+ * p, C untouched) when |sin(phi)| would reach s_max. */
+static int FN(propagate)(REAL* p, REAL* C, REAL dx, REAL curv, REAL s_max)
+{
+    REAL s = p[2], t = p[3], w = p[4];
+    REAL k = curv * w;
+    REAL s2 = s + k * dx;
+    if (!(FABS(s2) < s_max)) return 0;
+    REAL c1 = SQRT((R1 - s) * (R1 + s));
+    REAL c2 = SQRT((R1 - s2) * (R1 + s2));
+    REAL cc = c1 + c2;
+    REAL T = (s + s2) / cc;               /* dy/dx averaged over the step */
+    REAL q = SQRT(R1 + T * T);
+    REAL L = dx * q;                      /* signed transverse chord */
+    REAL a = RH * (k * L);
+    REAL a2 = a * a;
+    REAL g = R1 + a2 * (C_1_6 + a2 * (C_3_40 + a2 * C_5_112));   /* asin(a)/a */
+    REAL S = L * g;                       /* transverse arc length */
+
+    /* exact derivatives of (y2, z2, s2) */
+    REAL Ts = (R2 + T * (s / c1 + s2 / c2)) / cc;
+    REAL kdx = curv * dx;
+    REAL Tw = (kdx * (R1 + T * (s2 / c2))) / cc;
+    REAL LT = dx * (T / q);               /* dL/dT */
+    REAL G1 = R1 + a2 * (RH + a2 * (C_3_8 + a2 * C_5_16));      /* dS/dL */
+    REAL Sk = (L * (L * a)) * (C_1_6 + a2 * (C_3_20 + a2 * C_15_112));  /* dS/dk */
+    FN(jac_t) F;
+    F.ys = dx * Ts;
+    F.yw = dx * Tw;
+    F.zs = t * ((G1 * LT) * Ts);
+    F.zt = S;
+    F.zw = t * ((G1 * LT) * Tw + Sk * curv);
+    F.sw = kdx;
+
+    /* B = F C (full 5x5), then C' = B F^T (lower triangle).  Each sum runs
+     * over the non-zero F entries in increasing column order. */
+    REAL B[5][5];
+    for (int j = 0; j < 5; j++) {
+        REAL cy = C[FN(lt)(0, j)], cz = C[FN(lt)(1, j)], cs = C[FN(lt)(2, j)];
+        REAL ct = C[FN(lt)(3, j)], cw = C[FN(lt)(4, j)];
+        B[0][j] = (cy + F.ys * cs) + F.yw * cw;
+        B[1][j] = ((cz + F.zs * cs) + F.zt * ct) + F.zw * cw;
+        B[2][j] = cs + F.sw * cw;
+        B[3][j] = ct;
+        B[4][j] = cw;
+    }
+    for (int i = 0; i < 5; i++) {
+        for (int j = 0; j <= i; j++) {
+            REAL v;
+            switch (j) {
+            case 0: v = (B[i][0] + F.ys * B[i][2]) + F.yw * B[i][4]; break;
+            case 1: v = ((B[i][1] + F.zs * B[i][2]) + F.zt * B[i][3]) + F.zw * B[i][4]; break;
+            case 2: v = B[i][2] + F.sw * B[i][4]; break;
+            default: v = B[i][j]; break;
+            }
+            C[FN(lt)(i, j)] = v;
+        }
+    }
+    p[0] = p[0] + dx * T;
+    p[1] = p[1] + t * S;
+    p[2] = s2;
+    return 1;
+}
+
+/* chi2 of a measurement (my, mz) against the predicted state. */
+static inline REAL FN(chi2_pred)(const REAL* p, const REAL* C, REAL my, REAL mz,
+                          REAL sy2, REAL sz2)
+{
+    REAL r0 = my - p[0], r1 = mz - p[1];
+    REAL S00 = C[0] + sy2, S10 = C[1], S11 = C[2] + sz2;
+    REAL det = S00 * S11 - S10 * S10;
+    REAL idet = R1 / det;
+    REAL B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
+    return r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
+}
+
+/* Kalman update with the measurement (my, mz); returns its chi2. */
+static REAL FN(update)(REAL* p, REAL* C, REAL my, REAL mz, REAL sy2, REAL sz2)
+{
+    REAL r0 = my - p[0], r1 = mz - p[1];
+    REAL S00 = C[0] + sy2, S10 = C[1], S11 = C[2] + sz2;
+    REAL det = S00 * S11 - S10 * S10;
+    REAL idet = R1 / det;
+    REAL B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
+    REAL chi2 = r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
+    REAL A0[5], A1[5], K0[5], K1[5];
+    for (int i = 0; i < 5; i++) {
+        A0[i] = C[FN(lt)(i, 0)];
+        A1[i] = C[FN(lt)(i, 1)];
+    }
+    for (int i = 0; i < 5; i++) {
+        K0[i] = A0[i] * B00 + A1[i] * B10;
+        K1[i] = A0[i] * B10 + A1[i] * B11;
+    }
+    for (int i = 0; i < 5; i++) {
+        p[i] = p[i] + (K0[i] * r0 + K1[i] * r1);
+        for (int j = 0; j <= i; j++)
+            C[FN(lt)(i, j)] = C[FN(lt)(i, j)] - (K0[i] * A0[j] + K1[i] * A1[j]);
+    }
+    return chi2;
+}
+
+/* State from three points on consecutive-or-not planes: position of the
+ * first, direction from the first to the third, q/pT = 0, diagonal
+ * covariance. */
+static void FN(init_state)(REAL* p, REAL* C, REAL x0, REAL y0, REAL z0,
+                           REAL x2, REAL y2, REAL z2, REAL sy2, REAL sz2,
+                           REAL css, REAL ctt, REAL cww)
+{
+    REAL dX = x2 - x0;
+    REAL T0 = (y2 - y0) / dX;
+    REAL q0 = SQRT(R1 + T0 * T0);
+    p[0] = y0;
+    p[1] = z0;
+    p[2] = T0 / q0;
+    p[3] = (z2 - z0) / (dX * q0);
+    p[4] = 0;
+    for (int i = 0; i < 15; i++) C[i] = 0;
+    C[0] = sy2;
+    C[2] = sz2;
+    C[5] = css;
+    C[9] = ctt;
+    C[14] = cww;
+}
+
+/* Calibration of one raw cluster (refit).  side = +1 for z >= 0 sectors,
+ * -1 otherwise.  th: vd scale, t0 [us], 7 radial and 7 azimuthal
+ * coefficients over the basis (1, u, v, u^2, u v, v^2, w) with
+ * u = (x - u_centre)/u_scale, v = y/(x tan_half), w = drift/drift_len. */
+static void FN(calibrate)(const REAL* th, REAL xr, REAL yr, REAL zr, REAL sd,
+                          REAL DL, REAL VD, REAL TH, REAL UC, REAL US,
+                          REAL* xc, REAL* yc, REAL* zc)
+{
+    REAL d_raw = DL - sd * zr;
+    REAL d = (R1 + th[0]) * (d_raw - VD * th[1]);
+    *zc = sd * (DL - d);
+    REAL u = (xr - UC) / US;
+    REAL v = yr / (xr * TH);
+    REAL w = d / DL;
+    REAL b[7] = {R1, u, v, u * u, u * v, v * v, w};
+    REAL dr = 0, drphi = 0;
+    for (int j = 0; j < 7; j++) {
+        dr = dr + th[2 + j] * b[j];
+        drphi = drphi + th[9 + j] * b[j];
+    }
+    *xc = xr + dr;
+    *yc = yr + drphi;
+}
+
+/* Forward refit of one track: calibrate, initialise from hits 0 and 2,
+ * filter outwards through hits 1..n-1.  Returns 0 ok, 1 too few hits,
+ * 2 propagation stop. */
+static int FN(refit_track)(int n, const uint8_t* row, const REAL* y, const REAL* z,
+                           REAL sd, const float* row_x, const orc_params* prm,
+                           const orc_calib_model* cm, const REAL* th,
+                           REAL* p, REAL* C, REAL* chi2_out)
+{
+    *chi2_out = 0;
+    if (n < 3) return 1;
+    REAL DL = (REAL)cm->drift_len, VD = (REAL)cm->vd, TH = (REAL)cm->tan_half;
+    REAL UC = (REAL)cm->u_centre, US = (REAL)cm->u_scale;
+    REAL sy2 = (REAL)prm->sigma_y2, sz2 = (REAL)prm->sigma_z2;
+    REAL x0, y0, z0, x2, y2, z2, xp, xc, yc, zc;
+    FN(calibrate)(th, (REAL)row_x[row[0]], y[0], z[0], sd, DL, VD, TH, UC, US, &x0, &y0, &z0);
+    FN(calibrate)(th, (REAL)row_x[row[2]], y[2], z[2], sd, DL, VD, TH, UC, US, &x2, &y2, &z2);
+    FN(init_state)(p, C, x0, y0, z0, x2, y2, z2, sy2, sz2, (REAL)prm->c_ss0,
+                   (REAL)prm->c_tt0, (REAL)prm->c_ww0);
+    REAL chi2 = 0;
+    xp = x0;
+    for (int i = 1; i < n; i++) {
+        FN(calibrate)(th, (REAL)row_x[row[i]], y[i], z[i], sd, DL, VD, TH, UC, US, &xc, &yc, &zc);
+        if (!FN(propagate)(p, C, xc - xp, (REAL)prm->curv, (REAL)prm->s_max)) {
+            *chi2_out = chi2;
+            return 2;
+        }
+        chi2 = chi2 + FN(update)(p, C, yc, zc, sy2, sz2);
+        xp = xc;
+    }
+    *chi2_out = chi2;
+    return 0;
+}
+
+#undef R1
+#undef R2
+#undef RH
+#undef FN
+#undef CAT
+#undef CAT_

@@ -1,0 +1,613 @@
+/*
+ * Oracle of the TPC track-finding hot path -- TEST INFRASTRUCTURE ONLY.
+ * Plain single-threaded C; see oracle.h for the conventions.  Only the
+ * tests, the smoke check and the benchmark's CPU-baseline leg use it.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- Kalman primitives in float and double ----------------------------- */
+#define REAL float
+#define SUF _f
+#define SQRT sqrtf
+#define FABS fabsf
+#define C_1_6 (1.0f / 6.0f)
+#define C_3_40 (3.0f / 40.0f)
+#define C_5_112 (5.0f / 112.0f)
+#define C_3_8 (3.0f / 8.0f)
+#define C_5_16 (5.0f / 16.0f)
+#define C_3_20 (3.0f / 20.0f)
+#define C_15_112 (15.0f / 112.0f)
+#include "kalman_impl.h"
+#undef REAL
+#undef SUF
+#undef SQRT
+#undef FABS
+#undef C_1_6
+#undef C_3_40
+#undef C_5_112
+#undef C_3_8
+#undef C_5_16
+#undef C_3_20
+#undef C_15_112
+
+#define REAL double
+#define SUF _d
+#define SQRT sqrt
+#define FABS fabs
+#define C_1_6 (1.0 / 6.0)
+#define C_3_40 (3.0 / 40.0)
+#define C_5_112 (5.0 / 112.0)
+#define C_3_8 (3.0 / 8.0)
+#define C_5_16 (5.0 / 16.0)
+#define C_3_20 (3.0 / 20.0)
+#define C_15_112 (15.0 / 112.0)
+#include "kalman_impl.h"
+#undef REAL
+#undef SUF
+#undef SQRT
+#undef FABS
+
+/* ---- grid ----------------------------------------------------------------
+ * Bin of a coordinate: f = (v - v0) * inv, clamped to [0, nb - 1] in float,
+ * then truncated.  The map is monotone in v, so a window [lo, hi] is
+ * covered by the bins bin(lo)..bin(hi). */
+static int bin_of(float v, float v0, float inv, int nb)
+{
+    float f = (v - v0) * inv;
+    if (!(f >= 0.0f)) f = 0.0f;
+    float top = (float)(nb - 1);
+    if (f > top) f = top;
+    return (int)f;
+}
+
+static int global_bin(const orc_sector* s, int row, float y, float z)
+{
+    int iy = bin_of(y, s->y0, s->inv_by, s->nby);
+    int iz = bin_of(z, s->z0, s->inv_bz, s->nbz);
+    return s->bin_base + (row * s->nbz + iz) * s->nby + iy;
+}
+
+int orc_build_grid(int n_sec, const orc_sector* sec, int n_rows,
+                   const uint8_t* row, const float* y, const float* z,
+                   int n_bins, int* bin_start, float* yg, float* zg, int* idg)
+{
+    int* count = calloc((size_t)n_bins + 1, sizeof(int));
+    int* fill = malloc(((size_t)n_bins + 1) * sizeof(int));
+    if (!count || !fill) {
+        free(count);
+        free(fill);
+        return -1;
+    }
+    /* counting sort: histogram, exclusive prefix sum, stable placement in
+     * ascending id order */
+    for (int s = 0; s < n_sec; s++)
+        for (int64_t i = sec[s].begin; i < sec[s].end; i++)
+            if (row[i] < n_rows) count[global_bin(&sec[s], row[i], y[i], z[i])]++;
+    int acc = 0;
+    for (int g = 0; g < n_bins; g++) {
+        bin_start[g] = acc;
+        fill[g] = acc;
+        acc += count[g];
+    }
+    bin_start[n_bins] = acc;
+    for (int s = 0; s < n_sec; s++)
+        for (int64_t i = sec[s].begin; i < sec[s].end; i++) {
+            if (row[i] >= n_rows) continue;
+            int pos = fill[global_bin(&sec[s], row[i], y[i], z[i])]++;
+            yg[pos] = y[i];
+            zg[pos] = z[i];
+            idg[pos] = (int)i;
+        }
+    free(count);
+    free(fill);
+    return acc;
+}
+
+/* Positions of the grid bins of sector s, row r, covering [ylo, yhi] x
+ * [zlo, zhi] are visited z-bin by z-bin. */
+typedef struct {
+    const orc_sector* s;
+    const int* bin_start;
+    int r, iy0, iy1, iz0, iz1;
+} bin_window;
+
+static bin_window make_window(const orc_sector* s, const int* bin_start, int r,
+                              float ylo, float yhi, float zlo, float zhi)
+{
+    bin_window w;
+    w.s = s;
+    w.bin_start = bin_start;
+    w.r = r;
+    w.iy0 = bin_of(ylo, s->y0, s->inv_by, s->nby);
+    w.iy1 = bin_of(yhi, s->y0, s->inv_by, s->nby);
+    w.iz0 = bin_of(zlo, s->z0, s->inv_bz, s->nbz);
+    w.iz1 = bin_of(zhi, s->z0, s->inv_bz, s->nbz);
+    return w;
+}
+
+/* the window is widened by this factor before taking bins so that a
+ * rounding difference at the window edge can never drop a candidate; the
+ * exact predicate decides */
+#define WIDEN (1.0f + 1.0f / 64.0f)
+
+static int sector_of(int n_sec, const orc_sector* sec, int64_t id)
+{
+    int lo = 0, hi = n_sec - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (sec[mid].begin <= id) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+/* ---- neighbour finding ---------------------------------------------------
+ * For a cluster h on row r (0 < r < n_rows - 1) at (y, z): candidates on
+ * row r+1 lie within |y_u - y x_{r+1}/x_r| <= Wy, |z_u - z| <= Wz (the
+ * straight line from the origin through h, in y only: the transverse
+ * vertex is known, the z vertex is not); candidates on row r-1 likewise
+ * around y x_{r-1}/x_r.  Among all pairs (u, d) with straight-line
+ * deviation D2 = ((y_u + y_d) - (y + y))^2 + ((z_u + z_d) - (z + z))^2
+ * <= D2max the lexicographic minimum of (D2, id_u, id_d) is chosen. */
+void orc_find_neighbours(int n_sec, const orc_sector* sec, int n_rows,
+                         const float* row_x, const orc_params* prm,
+                         const int* bin_start, const float* yg, const float* zg,
+                         const int* idg, int64_t n_clusters, int* up0, int* down0)
+{
+    for (int64_t i = 0; i < n_clusters; i++) {
+        up0[i] = -1;
+        down0[i] = -1;
+    }
+    const float Wy = prm->nb_win_y, Wz = prm->nb_win_z, D2max = prm->nb_d2max;
+    for (int si = 0; si < n_sec; si++) {
+        const orc_sector* s = &sec[si];
+        int per_row = s->nby * s->nbz;
+        for (int r = 1; r + 1 < n_rows; r++) {
+            int p0 = bin_start[s->bin_base + r * per_row];
+            int p1 = bin_start[s->bin_base + (r + 1) * per_row];
+            for (int ph = p0; ph < p1; ph++) {
+                float y = yg[ph], z = zg[ph];
+                float slope = y / row_x[r];
+                float yu_c = slope * row_x[r + 1];
+                float yd_c = slope * row_x[r - 1];
+                bin_window wu = make_window(s, bin_start, r + 1, yu_c - Wy * WIDEN,
+                                            yu_c + Wy * WIDEN, z - Wz * WIDEN, z + Wz * WIDEN);
+                bin_window wd = make_window(s, bin_start, r - 1, yd_c - Wy * WIDEN,
+                                            yd_c + Wy * WIDEN, z - Wz * WIDEN, z + Wz * WIDEN);
+                float best = 0.0f;
+                int bu = -1, bd = -1;
+                for (int izu = wu.iz0; izu <= wu.iz1; izu++) {
+                    int gu = s->bin_base + ((r + 1) * s->nbz + izu) * s->nby;
+                    for (int pu = bin_start[gu + wu.iy0]; pu < bin_start[gu + wu.iy1 + 1]; pu++) {
+                        float yu = yg[pu], zu = zg[pu];
+                        if (!(fabsf(yu - yu_c) <= Wy && fabsf(zu - z) <= Wz)) continue;
+                        int idu = idg[pu];
+                        for (int izd = wd.iz0; izd <= wd.iz1; izd++) {
+                            int gd = s->bin_base + ((r - 1) * s->nbz + izd) * s->nby;
+                            for (int pd = bin_start[gd + wd.iy0]; pd < bin_start[gd + wd.iy1 + 1]; pd++) {
+                                float yd = yg[pd], zd = zg[pd];
+                                if (!(fabsf(yd - yd_c) <= Wy && fabsf(zd - z) <= Wz)) continue;
+                                float dy = (yu + yd) - (y + y);
+                                float dz = (zu + zd) - (z + z);
+                                float d2 = dy * dy + dz * dz;
+                                if (!(d2 <= D2max)) continue;
+                                int idd = idg[pd];
+                                if (bu < 0 || d2 < best ||
+                                    (d2 == best && (idu < bu || (idu == bu && idd < bd)))) {
+                                    best = d2;
+                                    bu = idu;
+                                    bd = idd;
+                                }
+                            }
+                        }
+                    }
+                }
+                up0[idg[ph]] = bu;
+                down0[idg[ph]] = bd;
+            }
+        }
+    }
+}
+
+/* ---- link cleaning and chain starts --------------------------------------
+ * A link survives only if it is mutual.  A chain start has an up link, no
+ * down link, and its up neighbour has an up link (chain of >= 3 hits). */
+void orc_clean_links(int64_t n, const int* up0, const int* down0, int* up, int* down)
+{
+    for (int64_t h = 0; h < n; h++) {
+        int u = up0[h], d = down0[h];
+        up[h] = (u >= 0 && down0[u] == h) ? u : -1;
+        down[h] = (d >= 0 && up0[d] == h) ? d : -1;
+    }
+}
+
+int64_t orc_select_starts(int64_t n, const int* up, const int* down, int* starts)
+{
+    int64_t m = 0;
+    for (int64_t h = 0; h < n; h++)
+        if (up[h] >= 0 && down[h] < 0 && up[up[h]] >= 0) starts[m++] = (int)h;
+    return m;
+}
+
+/* ---- tracklet construction -----------------------------------------------
+ * Per chain start h0 (row r0) with chain hits h1 = up[h0], h2 = up[h1]:
+ *  init   position of h0, direction from h0 to h2, q/pT = 0, diagonal C;
+ *  up     filter through the rest of the chain (unconditionally), then row
+ *         by row outwards: propagate one row, take the hit of minimal
+ *         predicted chi2 (<= chi2_max; ties to the lower id) and update,
+ *         else count a miss; stop after max_miss consecutive misses, at the
+ *         last row or when |sin(phi)| reaches s_max;
+ *  down   restart from the state after the last update with the position
+ *         of the last hit and the initial diagonal covariance; step row by
+ *         row inwards, updating with the hits found on the way up (rows >=
+ *         r0) and searching as above below r0.  A propagation stop ends the
+ *         pass and drops the hits below it.
+ * Output: hits of the down pass by row, the state after its last update,
+ * and the sum of its update chi2. */
+typedef struct {
+    const orc_sector* s;
+    const int* bin_start;
+    const float *yg, *zg;
+    const int* idg;
+    int n_rows;
+    const orc_params* prm;
+    int brute;
+} search_ctx;
+
+static int search_row(const search_ctx* cx, int r, const float* p, const float* C)
+{
+    const orc_params* prm = cx->prm;
+    const orc_sector* s = cx->s;
+    int per_row = s->nby * s->nbz;
+    float S00 = C[0] + prm->sigma_y2, S11 = C[2] + prm->sigma_z2;
+    float hy = prm->search_nsigma * sqrtf(S00) * WIDEN + 0.01f;
+    float hz = prm->search_nsigma * sqrtf(S11) * WIDEN + 0.01f;
+    int iz0, iz1, iy0, iy1;
+    if (cx->brute) {
+        iz0 = 0; iz1 = s->nbz - 1; iy0 = 0; iy1 = s->nby - 1;
+    } else {
+        bin_window w = make_window(s, cx->bin_start, r, p[0] - hy, p[0] + hy, p[1] - hz, p[1] + hz);
+        iz0 = w.iz0; iz1 = w.iz1; iy0 = w.iy0; iy1 = w.iy1;
+    }
+    (void)per_row;
+    float best = 0.0f;
+    int bid = -1;
+    for (int iz = iz0; iz <= iz1; iz++) {
+        int g = s->bin_base + (r * s->nbz + iz) * s->nby;
+        for (int pc = cx->bin_start[g + iy0]; pc < cx->bin_start[g + iy1 + 1]; pc++) {
+            float c2 = chi2_pred_f(p, C, cx->yg[pc], cx->zg[pc], prm->sigma_y2, prm->sigma_z2);
+            if (!(c2 <= prm->chi2_max)) continue;
+            int id = cx->idg[pc];
+            if (bid < 0 || c2 < best || (c2 == best && id < bid)) {
+                best = c2;
+                bid = id;
+            }
+        }
+    }
+    return bid;
+}
+
+void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
+                             const float* row_x, const orc_params* prm,
+                             const int* bin_start, const float* yg, const float* zg,
+                             const int* idg,
+                             const uint8_t* row, const float* y, const float* z,
+                             const int* up, int64_t n_starts, const int* starts,
+                             int brute, int* hits, int* nhits, int* row_inner,
+                             float* par, float* cov, float* chi2)
+{
+    const float sy2 = prm->sigma_y2, sz2 = prm->sigma_z2;
+    for (int64_t t = 0; t < n_starts; t++) {
+        int* th = hits + t * n_rows;
+        for (int r = 0; r < n_rows; r++) th[r] = -1;
+        int h0 = starts[t];
+        search_ctx cx = {&sec[sector_of(n_sec, sec, h0)], bin_start, yg, zg, idg,
+                         n_rows, prm, brute};
+        int h1 = up[h0], h2 = up[h1];
+        int r0 = row[h0];
+        float p[5], C[15];
+        init_state_f(p, C, row_x[r0], y[h0], z[h0], row_x[row[h2]], y[h2], z[h2], sy2,
+                     sz2, prm->c_ss0, prm->c_tt0, prm->c_ww0);
+        th[r0] = h0;
+        int cur = r0, last = r0;
+        float plast[5];
+        memcpy(plast, p, sizeof plast);
+        /* up: the chain */
+        int ok = 1;
+        for (int h = h1; h >= 0; h = up[h]) {
+            int r = row[h];
+            if (!propagate_f(p, C, row_x[r] - row_x[cur], prm->curv, prm->s_max)) {
+                ok = 0;
+                break;
+            }
+            update_f(p, C, y[h], z[h], sy2, sz2);
+            th[r] = h;
+            cur = last = r;
+            memcpy(plast, p, sizeof plast);
+        }
+        /* up: search outwards */
+        if (ok) {
+            int miss = 0;
+            for (int r = cur + 1; r < n_rows; r++) {
+                if (!propagate_f(p, C, row_x[r] - row_x[r - 1], prm->curv, prm->s_max)) break;
+                int c = search_row(&cx, r, p, C);
+                if (c >= 0) {
+                    update_f(p, C, y[c], z[c], sy2, sz2);
+                    th[r] = c;
+                    last = r;
+                    memcpy(plast, p, sizeof plast);
+                    miss = 0;
+                } else if (++miss >= prm->max_miss) {
+                    break;
+                }
+            }
+        }
+        /* down */
+        memcpy(p, plast, sizeof plast);
+        p[0] = y[th[last]];
+        p[1] = z[th[last]];
+        for (int i = 0; i < 15; i++) C[i] = 0.0f;
+        C[0] = sy2;
+        C[2] = sz2;
+        C[5] = prm->c_ss0;
+        C[9] = prm->c_tt0;
+        C[14] = prm->c_ww0;
+        float pin[5], Cin[15], csum = 0.0f;
+        memcpy(pin, p, sizeof pin);
+        memcpy(Cin, C, sizeof Cin);
+        int rin = last, miss = 0;
+        for (int r = last - 1; r >= 0; r--) {
+            if (!propagate_f(p, C, row_x[r] - row_x[r + 1], prm->curv, prm->s_max)) {
+                for (int q = r; q >= 0; q--) th[q] = -1;
+                break;
+            }
+            int c = -1;
+            if (r >= r0) {
+                c = th[r];
+            } else {
+                c = search_row(&cx, r, p, C);
+                if (c < 0) {
+                    if (++miss >= prm->max_miss) break;
+                    continue;
+                }
+                miss = 0;
+            }
+            if (c >= 0) {
+                csum = csum + update_f(p, C, y[c], z[c], sy2, sz2);
+                th[r] = c;
+                rin = r;
+                memcpy(pin, p, sizeof pin);
+                memcpy(Cin, C, sizeof Cin);
+            }
+        }
+        int n = 0;
+        for (int r = 0; r < n_rows; r++) n += th[r] >= 0;
+        nhits[t] = n;
+        row_inner[t] = rin;
+        memcpy(par + t * 5, pin, sizeof pin);
+        memcpy(cov + t * 15, Cin, sizeof Cin);
+        chi2[t] = csum;
+    }
+}
+
+/* FP64 replay: the same sequence of propagations and updates as the float
+ * construction, with the hit list fixed (up pass over rows >= start_row
+ * from the chain start, down pass from the outermost hit). */
+int orc_tracklet_replay64(int n_rows, const float* row_x, const orc_params* prm,
+                          const float* y, const float* z, int r0,
+                          const int* th, double* p, double* C, double* chi2)
+{
+    const double sy2 = prm->sigma_y2, sz2 = prm->sigma_z2;
+    int last = -1, rmin = n_rows;
+    for (int r = 0; r < n_rows; r++)
+        if (th[r] >= 0) {
+            last = r;
+            if (r < rmin) rmin = r;
+        }
+    if (last < 0 || th[r0] < 0) return 1;
+    int r2 = -1, cnt = 0;
+    for (int r = r0 + 1; r < n_rows; r++)
+        if (th[r] >= 0 && ++cnt == 2) {
+            r2 = r;
+            break;
+        }
+    if (r2 < 0) return 1;
+    int h0 = th[r0], h2 = th[r2];
+    init_state_d(p, C, row_x[r0], y[h0], z[h0], row_x[r2], y[h2], z[h2], sy2, sz2,
+                 prm->c_ss0, prm->c_tt0, prm->c_ww0);
+    double plast[5];
+    memcpy(plast, p, sizeof plast);
+    for (int r = r0 + 1; r <= last; r++) {
+        if (!propagate_d(p, C, (double)row_x[r] - (double)row_x[r - 1], prm->curv, prm->s_max))
+            return 2;
+        if (th[r] >= 0) {
+            update_d(p, C, y[th[r]], z[th[r]], sy2, sz2);
+            memcpy(plast, p, sizeof plast);
+        }
+    }
+    memcpy(p, plast, sizeof plast);
+    p[0] = y[th[last]];
+    p[1] = z[th[last]];
+    for (int i = 0; i < 15; i++) C[i] = 0.0;
+    C[0] = sy2;
+    C[2] = sz2;
+    C[5] = prm->c_ss0;
+    C[9] = prm->c_tt0;
+    C[14] = prm->c_ww0;
+    double csum = 0.0;
+    for (int r = last - 1; r >= rmin; r--) {
+        if (!propagate_d(p, C, (double)row_x[r] - (double)row_x[r + 1], prm->curv, prm->s_max))
+            return 2;
+        if (th[r] >= 0) csum += update_d(p, C, y[th[r]], z[th[r]], sy2, sz2);
+    }
+    *chi2 = csum;
+    return 0;
+}
+
+/* ---- tracklet selection ---------------------------------------------------
+ * key(t) = nhits << 32 | (2^32 - 1 - start id) for tracklets with at least
+ * min_tracklet_hits hits, else 0.  Every cluster belongs to the tracklet of
+ * largest key containing it; a tracklet becomes a track if it keeps at
+ * least min_track_hits of its clusters.  Tracks come out in tracklet
+ * order (ascending start id), hits by ascending row. */
+int64_t orc_select_tracks(int64_t n_clusters, int n_rows, const orc_params* prm,
+                          int64_t n_tracklets, const int* hits, const int* nhits,
+                          const int* starts, int* trk_off, int* trk_hits,
+                          int* trk_tracklet)
+{
+    uint64_t* owner = calloc((size_t)n_clusters, sizeof(uint64_t));
+    uint64_t* key = malloc(((size_t)n_tracklets + 1) * sizeof(uint64_t));
+    for (int64_t t = 0; t < n_tracklets; t++) {
+        key[t] = nhits[t] >= prm->min_tracklet_hits
+                     ? ((uint64_t)nhits[t] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)starts[t])
+                     : 0;
+        if (!key[t]) continue;
+        for (int r = 0; r < n_rows; r++) {
+            int c = hits[t * n_rows + r];
+            if (c >= 0 && key[t] > owner[c]) owner[c] = key[t];
+        }
+    }
+    int64_t m = 0, nh = 0;
+    trk_off[0] = 0;
+    for (int64_t t = 0; t < n_tracklets; t++) {
+        if (!key[t]) continue;
+        int kept = 0;
+        for (int r = 0; r < n_rows; r++) {
+            int c = hits[t * n_rows + r];
+            kept += c >= 0 && owner[c] == key[t];
+        }
+        if (kept < prm->min_track_hits) continue;
+        for (int r = 0; r < n_rows; r++) {
+            int c = hits[t * n_rows + r];
+            if (c >= 0 && owner[c] == key[t]) trk_hits[nh++] = c;
+        }
+        trk_tracklet[m] = (int)t;
+        trk_off[++m] = (int)nh;
+    }
+    free(owner);
+    free(key);
+    return m;
+}
+
+/* ---- calibrated refit ---------------------------------------------------- */
+void orc_refit32(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                 const float* y, const float* z, const signed char* side,
+                 const float* row_x, const orc_params* prm,
+                 const orc_calib_model* cm, const float* theta,
+                 float* par, float* cov, float* chi2, int* status)
+{
+    for (int64_t t = 0; t < n_tracks; t++) {
+        int a = trk_off[t], n = trk_off[t + 1] - a;
+        float sd = side ? (float)side[t] : 1.0f;
+        status[t] = refit_track_f(n, row + a, y + a, z + a, sd, row_x, prm, cm, theta,
+                                  par + 5 * t, cov + 15 * t, chi2 + t);
+    }
+}
+
+void orc_refit64(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                 const double* y, const double* z, const signed char* side,
+                 const float* row_x, const orc_params* prm,
+                 const orc_calib_model* cm, const double* theta,
+                 double* par, double* cov, double* chi2, int* status)
+{
+    for (int64_t t = 0; t < n_tracks; t++) {
+        int a = trk_off[t], n = trk_off[t + 1] - a;
+        double sd = side ? (double)side[t] : 1.0;
+        status[t] = refit_track_d(n, row + a, y + a, z + a, sd, row_x, prm, cm, theta,
+                                  par + 5 * t, cov + 15 * t, chi2 + t);
+    }
+}
+
+static double track_chi2_d(int n, const uint8_t* row, const double* y, const double* z,
+                           double sd, const float* row_x, const orc_params* prm,
+                           const orc_calib_model* cm, const double* th)
+{
+    double p[5], C[15], c2;
+    refit_track_d(n, row, y, z, sd, row_x, prm, cm, th, p, C, &c2);
+    return c2;
+}
+
+void orc_refit64_fd_grad(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                         const double* y, const double* z, const signed char* side,
+                         const float* row_x, const orc_params* prm,
+                         const orc_calib_model* cm, const double* theta,
+                         const double* g, double h_hit, double h_theta,
+                         double* grad_y, double* grad_z, double* grad_theta)
+{
+    int nmax = 0;
+    for (int64_t t = 0; t < n_tracks; t++)
+        if (trk_off[t + 1] - trk_off[t] > nmax) nmax = trk_off[t + 1] - trk_off[t];
+    double* wy = malloc(sizeof(double) * (size_t)(nmax > 0 ? nmax : 1));
+    double* wz = malloc(sizeof(double) * (size_t)(nmax > 0 ? nmax : 1));
+    double th[16];
+    memcpy(th, theta, sizeof th);
+    for (int k = 0; k < 16; k++) grad_theta[k] = 0.0;
+    for (int64_t t = 0; t < n_tracks; t++) {
+        int a = trk_off[t], n = trk_off[t + 1] - a;
+        double sd = side ? (double)side[t] : 1.0;
+        memcpy(wy, y + a, sizeof(double) * (size_t)n);
+        memcpy(wz, z + a, sizeof(double) * (size_t)n);
+        for (int i = 0; i < n; i++) {
+            double* v[2] = {wy, wz};
+            double* out[2] = {grad_y, grad_z};
+            for (int c = 0; c < 2; c++) {
+                double v0 = v[c][i];
+                double h = h_hit;
+                v[c][i] = v0 + h;
+                double fp = track_chi2_d(n, row + a, wy, wz, sd, row_x, prm, cm, th);
+                v[c][i] = v0 - h;
+                double fm = track_chi2_d(n, row + a, wy, wz, sd, row_x, prm, cm, th);
+                v[c][i] = v0;
+                out[c][a + i] = g[t] * (fp - fm) / (2.0 * h);
+            }
+        }
+        for (int k = 0; k < 16; k++) {
+            double v0 = th[k];
+            double h = h_theta * (fabs(v0) > 1.0 ? fabs(v0) : 1.0);
+            th[k] = v0 + h;
+            double fp = track_chi2_d(n, row + a, y + a, z + a, sd, row_x, prm, cm, th);
+            th[k] = v0 - h;
+            double fm = track_chi2_d(n, row + a, y + a, z + a, sd, row_x, prm, cm, th);
+            th[k] = v0;
+            grad_theta[k] += g[t] * (fp - fm) / (2.0 * h);
+        }
+    }
+    free(wy);
+    free(wz);
+}
+
+/* ---- single-step entry points for the tests ------------------------------ */
+int orc_propagate32(float* p, float* C, float dx, float curv, float s_max)
+{
+    return propagate_f(p, C, dx, curv, s_max);
+}
+
+int orc_propagate64(double* p, double* C, double dx, double curv, double s_max)
+{
+    return propagate_d(p, C, dx, curv, s_max);
+}
+
+float orc_update32(float* p, float* C, float my, float mz, float sy2, float sz2)
+{
+    return update_f(p, C, my, mz, sy2, sz2);
+}
+
+double orc_update64(double* p, double* C, double my, double mz, double sy2, double sz2)
+{
+    return update_d(p, C, my, mz, sy2, sz2);
+}
+
+float orc_chi2_pred32(const float* p, const float* C, float my, float mz, float sy2, float sz2)
+{
+    return chi2_pred_f(p, C, my, mz, sy2, sz2);
+}
+
+void orc_calibrate64(const double* th, double xr, double yr, double zr, double side,
+                     const orc_calib_model* cm, double* out3)
+{
+    calibrate_d(th, xr, yr, zr, side, cm->drift_len, cm->vd, cm->tan_half, cm->u_centre,
+                cm->u_scale, out3, out3 + 1, out3 + 2);
+}

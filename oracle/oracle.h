@@ -1,0 +1,138 @@
+/*
+ * Oracle for the TPC track-finding hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded C implementation of what the GPU library
+ * computes, used by the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark.  The product path never links or calls it.  It shares no
+ * code, header, table or constant with the HIP library: all geometry and
+ * cut values arrive as arguments.
+ *
+ * The paper (section 3) fixes only the method's shape: cellular-automaton
+ * seeding followed by single-hypothesis Kalman-filter track following with
+ * a linear-time tail.  Every concrete rule below (bins, windows, cuts, the
+ * propagator, the tracklet and selection rules, the calibration model) is
+ * this project's reading of that statement, written out step by step.
+ *
+ * Floating point: built with -ffp-contract=off; every decision is taken in
+ * IEEE binary32 with the association order written in the source, so that
+ * an implementation evaluating the same expressions in the same order
+ * reproduces them bit for bit.
+ *
+ * Index spaces: cluster ids are indices into the caller's input arrays.
+ * Links and tracks are returned in id space; the grid is returned as the
+ * permutation (bin_start, yg, zg, idg).
+ */
+#ifndef TPC_ORACLE_H
+#define TPC_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    float curv;            /* curvature [1/cm] per unit q/pT */
+    float nb_win_y;        /* neighbour window half widths [cm] */
+    float nb_win_z;
+    float nb_d2max;        /* max straight-line deviation^2 [cm^2] */
+    float sigma_y2;        /* measurement variances [cm^2] */
+    float sigma_z2;
+    float chi2_max;        /* hit-search gate */
+    float search_nsigma;   /* search bin window (acceleration only) */
+    float s_max;           /* |sin(phi)| stop */
+    float c_ss0, c_tt0, c_ww0;  /* initial variances */
+    int max_miss;          /* consecutive rows without a hit that stop a search */
+    int min_tracklet_hits; /* tracklets shorter than this take no part in selection */
+    int min_track_hits;    /* tracks keeping fewer hits are dropped */
+} orc_params;
+
+typedef struct {
+    float y0, z0;          /* lower edge of the bin grid */
+    float inv_by, inv_bz;  /* inverse bin widths */
+    int nby, nbz;          /* bins per row in y and z */
+    int bin_base;          /* index of the sector's first bin */
+    int pad_;
+    int64_t begin, end;    /* the sector's clusters: ids [begin, end) */
+} orc_sector;
+
+typedef struct {           /* calibration model of the refit */
+    float drift_len;       /* cm */
+    float vd;              /* cm/us */
+    float tan_half;        /* tan of the sector half opening angle */
+    float u_centre, u_scale;  /* radial coordinate u = (x - centre)/scale */
+} orc_calib_model;
+
+/* Grid (stable counting sort of each sector's clusters by pad row and
+ * (z, y) bin).  Returns the number of clusters placed; clusters with
+ * row >= n_rows are left out. */
+int orc_build_grid(int n_sec, const orc_sector* sec, int n_rows,
+                   const uint8_t* row, const float* y, const float* z,
+                   int n_bins, int* bin_start, float* yg, float* zg, int* idg);
+
+/* Best up/down neighbour pair per cluster (id space, -1 if none). */
+void orc_find_neighbours(int n_sec, const orc_sector* sec, int n_rows,
+                         const float* row_x, const orc_params* prm,
+                         const int* bin_start, const float* yg, const float* zg,
+                         const int* idg, int64_t n_clusters,
+                         int* up0, int* down0);
+
+/* Mutual-link filter. */
+void orc_clean_links(int64_t n, const int* up0, const int* down0, int* up, int* down);
+
+/* Chain starts in ascending id; returns the count. */
+int64_t orc_select_starts(int64_t n, const int* up, const int* down, int* starts);
+
+/* Tracklet construction.  hits: [n_starts][n_rows] cluster ids (-1 none).
+ * brute != 0 scans whole rows instead of grid bins (same result). */
+void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
+                             const float* row_x, const orc_params* prm,
+                             const int* bin_start, const float* yg, const float* zg,
+                             const int* idg,
+                             const uint8_t* row, const float* y, const float* z,
+                             const int* up, int64_t n_starts, const int* starts,
+                             int brute, int* hits, int* nhits, int* row_inner,
+                             float* par, float* cov, float* chi2);
+
+/* FP64 replay of a tracklet's fit with its hit list fixed. */
+int orc_tracklet_replay64(int n_rows, const float* row_x, const orc_params* prm,
+                          const float* y, const float* z, int start_row,
+                          const int* hits_by_row, double* par, double* cov,
+                          double* chi2);
+
+/* Selection; returns the number of tracks.  trk_off has n_tracklets+1
+ * entries of room, trk_hits n_clusters. */
+int64_t orc_select_tracks(int64_t n_clusters, int n_rows, const orc_params* prm,
+                          int64_t n_tracklets, const int* hits, const int* nhits,
+                          const int* starts, int* trk_off, int* trk_hits,
+                          int* trk_tracklet);
+
+/* Calibrated refit (forward).  side: +1/-1 per track or NULL (all +1).
+ * status per track: 0 ok, 1 too few hits, 2 propagation stop. */
+void orc_refit32(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                 const float* y, const float* z, const signed char* side,
+                 const float* row_x, const orc_params* prm,
+                 const orc_calib_model* cm, const float* theta,
+                 float* par, float* cov, float* chi2, int* status);
+void orc_refit64(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                 const double* y, const double* z, const signed char* side,
+                 const float* row_x, const orc_params* prm,
+                 const orc_calib_model* cm, const double* theta,
+                 double* par, double* cov, double* chi2, int* status);
+
+/* Central finite-difference gradient of L = sum_t g_t chi2_t (FP64):
+ * w.r.t. the raw (y, z) of every hit of the listed tracks and w.r.t. the
+ * 16 calibration parameters.  Steps: h_hit (absolute, cm) for hit
+ * coordinates, h_theta * max(|theta_k|, 1) for the parameters. */
+void orc_refit64_fd_grad(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                         const double* y, const double* z, const signed char* side,
+                         const float* row_x, const orc_params* prm,
+                         const orc_calib_model* cm, const double* theta,
+                         const double* g, double h_hit, double h_theta,
+                         double* grad_y, double* grad_z, double* grad_theta);
+
+/* Single steps, exposed for the tests. */
+int orc_propagate32(float* p, float* C, float dx, float curv, float s_max);
+int orc_propagate64(double* p, double* C, double dx, double curv, double s_max);
+float orc_update32(float* p, float* C, float my, float mz, float sy2, float sz2);
+double orc_update64(double* p, double* C, double my, double mz, double sy2, double sz2);
+float orc_chi2_pred32(const float* p, const float* C, float my, float mz, float sy2, float sz2);
+void orc_calibrate64(const double* th, double xr, double yr, double zr, double side,
+                     const orc_calib_model* cm, double* out3);
+
+#endif

@@ -1,0 +1,297 @@
+/*
+ * tpc.h -- C ABI of the MI355X TPC track-finding library (libtpc.so).
+ *
+ * Hot path of the online TPC tracking of arXiv:1905.05515, section 3: the
+ * combinatorial seeding is a cellular automaton over adjacent pad rows, and
+ * the track following after it is a single-hypothesis Kalman filter whose
+ * run time is linear in the number of hits.  The calls below are the steps
+ * of that path, in order:
+ *
+ *   tpc_build_grid           bin each sector's clusters into a pad-row grid
+ *   tpc_find_neighbours      best up/down link per hit, mutual-link cleaning,
+ *                            chain starts (cellular-automaton seeding)
+ *   tpc_construct_tracklets  Kalman-filter following of each chain along the
+ *                            rows, outwards then inwards
+ *   tpc_select_tracks        resolve shared clusters, keep good tracklets
+ *   tpc_refit                calibrated Kalman refit of found tracks (the
+ *                            paper's refit once calibration is applied,
+ *                            section 2, and online drift-velocity
+ *                            calibration, section 3)
+ *   tpc_refit_adjoint        gradient of the refit chi2 with respect to hit
+ *                            coordinates and calibration parameters
+ *   tpc_track_batch          the first four steps for many sectors or
+ *                            collisions, in one persistent launch or as a
+ *                            per-sector sequence, optionally graph-replayed
+ *
+ * Conventions
+ *   - Pointers named d_* and all array members of the argument structs are
+ *     device pointers (HIP device memory of the context's device); h_*
+ *     pointers are host memory.  The caller owns every buffer; the library
+ *     never allocates or frees caller memory.  tpc_context holds only a few
+ *     KB of device memory of its own plus cached graphs.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *     default stream) unless stated otherwise.  Argument errors are detected
+ *     on the host before anything is launched and return
+ *     TPC_ERR_INVALID_ARG.  Capacity overflows are detected on the device:
+ *     the kernels stop writing past the capacity, set a flag and record the
+ *     size that would have been needed in the workspace status block; the
+ *     outputs are then incomplete and the caller re-sizes and calls again.
+ *   - Nothing throws or aborts across this interface.
+ *   - All decisions (bins, links, hit choices, selection) are taken in IEEE
+ *     binary32 with a fixed association order and no contraction, and ties
+ *     are broken on cluster ids: the outputs depend on the input values and
+ *     ids only, not on launch shapes, bin sizes or launch form.
+ *   - Cluster ids are indices into the caller's cluster arrays.  "Grid
+ *     positions" index the grid arrays that tpc_build_grid writes.
+ */
+#ifndef TPC_H
+#define TPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TPC_OK = 0,
+    TPC_ERR_INVALID_ARG = 1,   /* bad argument, detected on the host */
+    TPC_ERR_CAPACITY = 2,      /* an output was too small (see tpc_status) */
+    TPC_ERR_HIP = 3,           /* a HIP runtime call failed */
+    TPC_ERR_UNSUPPORTED = 4    /* device is not gfx950 or feature missing */
+};
+
+/* Physics constants and cuts.  They define the outputs; the values used by
+ * this project are its readings of the paper, which states none. */
+typedef struct tpc_params {
+    float curv;            /* curvature [1/cm] per unit q/pT: -0.0029979*B[T] */
+    float nb_win_y;        /* neighbour window half width in y [cm] */
+    float nb_win_z;        /* neighbour window half width in z [cm] */
+    float nb_d2max;        /* max straight-line deviation^2 of a link pair [cm^2] */
+    float sigma_y2;        /* cluster variance in y [cm^2] */
+    float sigma_z2;        /* cluster variance in z [cm^2] */
+    float chi2_max;        /* hit-search gate on the predicted chi2 */
+    float search_nsigma;   /* half width of the bins scanned, in sigma (speed only) */
+    float s_max;           /* propagation stops where |sin(phi)| reaches this */
+    float c_ss0, c_tt0, c_ww0;  /* initial variances of sin(phi), tan(lambda), q/pT */
+    int32_t max_miss;      /* consecutive rows without a hit that end a search */
+    int32_t min_tracklet_hits;  /* shorter tracklets take no part in selection */
+    int32_t min_track_hits;     /* tracks keeping fewer hits are dropped */
+} tpc_params;
+
+/* One sector (or independent sector instance).  Its clusters are the ids
+ * [begin, end), sector-local coordinates; its grid has n_rows * nbz * nby
+ * bins starting at global bin index bin_base, bin (row, iz, iy) at
+ * bin_base + (row * nbz + iz) * nby + iy, with
+ * iy = clamp((y - y0) * inv_by, 0, nby - 1) truncated (likewise iz). */
+typedef struct tpc_sector {
+    float y0, z0;
+    float inv_by, inv_bz;
+    int32_t nby, nbz;
+    int32_t bin_base;
+    int32_t pad_;
+    int64_t begin, end;
+} tpc_sector;
+
+typedef struct tpc_problem {
+    int32_t n_sectors;
+    int32_t n_rows;            /* pad rows, 3..255; row r sits at x = d_row_x[r] */
+    int64_t n_clusters;        /* total, = last sector's end, < 2^31 */
+    int64_t n_bins;            /* total bins over all sectors, < 2^31 */
+    const tpc_sector* h_sectors;   /* host copy of the sector table */
+    const tpc_sector* d_sectors;   /* device copy, same contents */
+    const float* d_row_x;          /* device [n_rows], increasing */
+    tpc_params params;
+} tpc_problem;
+
+/* Clusters, structure of arrays, grouped by sector (any order inside). */
+typedef struct tpc_clusters {
+    const uint8_t* row;    /* pad row; clusters with row >= n_rows are dropped */
+    const float* y;        /* sector-local y [cm] */
+    const float* z;        /* z, or drift time scaled to z [cm] */
+} tpc_clusters;
+
+/* Grid: clusters ordered by (sector, row, z bin, y bin, cluster id).
+ * bin_start[n_bins + 1]: first grid position of every bin; y, z, id
+ * [n_clusters]: coordinates and cluster id at each grid position. */
+typedef struct tpc_grid {
+    int32_t* bin_start;
+    float* y;
+    float* z;
+    int32_t* id;
+} tpc_grid;
+
+/* Links between hits on adjacent rows, indexed by grid position, values
+ * are grid positions (-1 none).  up0/down0: best pair per hit before
+ * cleaning; up/down: mutual links only. */
+typedef struct tpc_links {
+    int32_t* up0;
+    int32_t* down0;
+    int32_t* up;
+    int32_t* down;
+} tpc_links;
+
+/* Chain starts: grid positions, ascending cluster id.  Count in tpc_status. */
+typedef struct tpc_starts {
+    int32_t* pos;
+    int64_t capacity;
+} tpc_starts;
+
+/* Tracklets, one per chain start, in start order.
+ * start[capacity]: grid position of the chain start;
+ * hits[capacity * n_rows]: grid position of the hit on each row, -1 none;
+ * par[capacity * 5] (y, z, sin(phi), tan(lambda), q/pT) and
+ * cov[capacity * 15] (lower triangle, row by row) at the innermost hit,
+ * row_inner its row; chi2 the sum of the inward pass. */
+typedef struct tpc_tracklets {
+    int32_t* start;
+    int32_t* hits;
+    int32_t* nhits;
+    int32_t* row_inner;
+    float* par;
+    float* cov;
+    float* chi2;
+    int64_t capacity;
+} tpc_tracklets;
+
+/* Tracks (CSR): off[n_tracks + 1], hits[off[k]..off[k+1]) cluster ids in
+ * ascending row, tracklet[k] the tracklet it came from (ascending). */
+typedef struct tpc_tracks {
+    int32_t* off;
+    int32_t* hits;
+    int32_t* tracklet;
+    int64_t capacity;      /* tracks; off needs capacity + 1 entries */
+    int64_t hit_capacity;
+} tpc_tracks;
+
+/* Device status block at the start of the workspace. */
+typedef struct tpc_status {
+    int64_t n_grid;        /* clusters placed in the grid */
+    int64_t n_bad_rows;    /* clusters dropped for row >= n_rows */
+    int64_t n_starts;      /* chain starts found (may exceed capacity) */
+    int64_t n_tracks;      /* tracks (may exceed capacity) */
+    int64_t n_track_hits;  /* hits of all tracks (may exceed capacity) */
+    int32_t overflow;      /* bit 0 starts, bit 1 tracks, bit 2 track hits */
+    int32_t pad_;
+} tpc_status;
+
+typedef struct tpc_context tpc_context;
+
+/* Context: binds a device, holds launch shapes and cached graphs.  One
+ * context per stream at a time; distinct contexts are independent. */
+int tpc_context_create(tpc_context** out, int device);
+int tpc_context_destroy(tpc_context* ctx);
+
+/* Bytes of device workspace needed by the tracking calls for this problem
+ * and start capacity.  The same workspace must be passed, unchanged, to the
+ * calls of one event in order; it holds the status block at offset 0. */
+int tpc_workspace_size(const tpc_problem* h_prob, int64_t start_capacity, size_t* h_bytes);
+
+/* Grid (section 3: the cellular automaton works on hits of adjacent pad
+ * rows; the grid gives each hit its row neighbourhood).  Stable counting
+ * sort per sector by (row, z bin, y bin), ties by cluster id. */
+int tpc_build_grid(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in,
+                   tpc_grid out, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Cellular-automaton seeding (section 3).  For each hit on rows
+ * 1..n_rows-2, among candidates on row r+1 within (nb_win_y, nb_win_z) of
+ * the straight line from the origin through the hit (in y; the z vertex is
+ * unknown in continuous read-out, section 2) and likewise on row r-1, the
+ * pair of least straight-line deviation
+ * ((y_u + y_d) - 2y)^2 + ((z_u + z_d) - 2z)^2 <= nb_d2max, ties by
+ * (up id, down id).  Then only mutual links are kept; a chain start has an
+ * up link, no down link, and a chain of at least three hits. */
+int tpc_find_neighbours(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid grid,
+                        tpc_links links, tpc_starts starts, void* d_ws, size_t ws_bytes,
+                        void* stream);
+
+/* Kalman-filter track following (section 3).  Per start: state from the
+ * first and third chain hits, filter along the chain, then row by row
+ * outwards taking the hit of least predicted chi2 <= chi2_max (ties by id),
+ * stopping after max_miss empty rows; then inwards from the outermost hit
+ * with a reset covariance through the hits found, searching below the
+ * start.  `tracklets.capacity` must be >= the start capacity. */
+int tpc_construct_tracklets(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid grid,
+                            tpc_links links, tpc_starts starts, tpc_tracklets tracklets,
+                            void* d_ws, size_t ws_bytes, void* stream);
+
+/* Tracklet selection: one hypothesis per cluster (section 3).  A cluster
+ * belongs to the tracklet of largest key (hits << 32 | ~start id) among
+ * tracklets with >= min_tracklet_hits hits containing it; a tracklet keeping
+ * >= min_track_hits of its clusters becomes a track. */
+int tpc_select_tracks(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid grid,
+                      tpc_tracklets tracklets, tpc_tracks tracks, void* d_ws,
+                      size_t ws_bytes, void* stream);
+
+/* Synchronous: copies the status block of d_ws to *h_out. */
+int tpc_get_status(const void* d_ws, tpc_status* h_out, void* stream);
+
+/* The four tracking calls in one go.  mode: 0 one launch per stage over
+ * all sectors, 1 one launch sequence per sector, 2 one persistent launch
+ * over a device work queue.  use_graph != 0 captures the launch sequence
+ * into a HIP graph on the first call and replays it on later calls with
+ * the same arguments. */
+enum { TPC_MODE_STAGED = 0, TPC_MODE_PER_SECTOR = 1, TPC_MODE_PERSISTENT = 2 };
+int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in,
+                    tpc_grid grid, tpc_links links, tpc_starts starts,
+                    tpc_tracklets tracklets, tpc_tracks tracks, void* d_ws,
+                    size_t ws_bytes, int mode, int use_graph, void* stream);
+
+/* ---- calibrated refit ---------------------------------------------------- */
+
+/* Calibration model.  For a cluster of a sector on z side `side` (+1/-1) on
+ * row plane x_r with raw (y, z): drift d = (1 + th[0]) (d_raw - vd th[1])
+ * with d_raw = drift_len - side z; z' = side (drift_len - d); with
+ * u = (x_r - u_centre)/u_scale, v = y / (x_r tan_half), w = d/drift_len and
+ * basis b = (1, u, v, u^2, uv, v^2, w): plane x' = x_r + sum th[2+j] b_j,
+ * y' = y + sum th[9+j] b_j. */
+typedef struct tpc_calib_model {
+    float drift_len, vd, tan_half, u_centre, u_scale;
+} tpc_calib_model;
+
+/* Found tracks' hits, CSR: hits of track k are off[k]..off[k+1], rows
+ * increasing; side[k] = +1/-1 (NULL: all +1). */
+typedef struct tpc_track_hits {
+    const int32_t* off;
+    const uint8_t* row;
+    const float* y;
+    const float* z;
+    const int8_t* side;
+    int64_t n_tracks;
+    int64_t n_hits;
+} tpc_track_hits;
+
+/* Forward refit in float: calibrate with d_theta[16], state from hits 0
+ * and 2, filter outwards through hits 1..n-1.  Outputs per track: par[5],
+ * cov[15] at the last hit, chi2, status (0 ok, 1 fewer than 3 hits, 2
+ * |sin(phi)| stop, 3 a hit row >= n_rows).  The CSR must be well formed
+ * (off increasing, off[n_tracks] = n_hits).  checkpoints (nullable) [n_hits * 20]: state and
+ * covariance after each hit but the last, for tpc_refit_adjoint. */
+int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
+              const tpc_params* h_params, const tpc_calib_model* h_model,
+              const float* d_theta, float* par, float* cov, float* chi2, int32_t* status,
+              float* checkpoints, void* stream);
+
+/* Bytes of workspace for tpc_refit_adjoint. */
+int tpc_refit_workspace_size(int64_t n_tracks, size_t* h_bytes);
+
+/* Adjoint of the refit: with L = sum_k grad_chi2[k] * chi2[k], writes
+ * dL/dy and dL/dz of every raw hit (grad_y, grad_z [n_hits]) and
+ * dL/dtheta (grad_theta[16], a deterministic reduction).  Needs the
+ * checkpoints and status of tpc_refit with the same inputs; tracks with
+ * status != 0 contribute zero. */
+int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                      const float* d_row_x, const tpc_params* h_params,
+                      const tpc_calib_model* h_model, const float* d_theta,
+                      const float* checkpoints, const int32_t* status,
+                      const float* grad_chi2, float* grad_y, float* grad_z,
+                      float* grad_theta, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Static description of an error code. */
+const char* tpc_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,319 @@
+"""Python binding of libtpc.so: torch tensors for device memory and streams,
+argument marshalling to the C ABI.  Every step runs in the library's HIP
+kernels; nothing here computes the method."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .layout import SECTOR_DTYPE, grid_layout
+
+MODES = {"staged": 0, "per_sector": 1, "persistent": 2}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def params_struct(prm: dict) -> L.Params:
+    p = L.Params()
+    for name, _ in L.Params._fields_:
+        setattr(p, name, prm[name])
+    return p
+
+
+class Context:
+    """A library context bound to one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        L.check(L.lib().tpc_context_create(C.byref(h), device), "tpc_context_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            L.lib().tpc_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Event:
+    """Device buffers of one tracking problem (inputs, every output and the
+    workspace).  Sizes: grid and links n_clusters; starts and tracklets
+    start_capacity (n_clusters // 3 by default: a chain start needs three
+    distinct hits); tracks up to start_capacity, their hits up to
+    n_clusters."""
+    problem: L.Problem
+    keep: list = field(default_factory=list)
+    t: dict = field(default_factory=dict)
+    n_rows: int = 152
+    start_capacity: int = 0
+    ws_bytes: int = 0
+
+
+def make_event(row, y, z, sector_offsets, sector_range, row_x, prm: dict, device="cuda",
+               layout=None, occupancy=2.0, start_capacity=None, track_capacity=None,
+               track_hit_capacity=None) -> Event:
+    """Copy an event to the device and allocate all outputs."""
+    n_rows = int(np.asarray(row_x).shape[0])
+    if layout is None:
+        layout = grid_layout(sector_offsets, sector_range, n_rows=n_rows, occupancy=occupancy)
+    tab, n_bins = layout
+    tab = np.ascontiguousarray(tab, dtype=SECTOR_DTYPE)
+    n = int(np.asarray(row).shape[0])
+    cap = int(start_capacity if start_capacity is not None else max(n // 3, 1))
+    tcap = int(track_capacity if track_capacity is not None else cap)
+    hcap = int(track_hit_capacity if track_hit_capacity is not None else max(n, 1))
+    dev = torch.device(device)
+
+    def to_dev(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+
+    t = {}
+    t["row"] = to_dev(row, torch.uint8)
+    t["y"] = to_dev(y, torch.float32)
+    t["z"] = to_dev(z, torch.float32)
+    t["row_x"] = to_dev(np.asarray(row_x, np.float32), torch.float32)
+    h_sec = torch.from_numpy(tab.view(np.uint8).copy())
+    t["h_sectors"] = h_sec
+    t["d_sectors"] = h_sec.to(dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    f32 = dict(dtype=torch.float32, device=dev)
+    nn = max(n, 1)
+    t["bin_start"] = torch.empty(n_bins + 1, **i32)
+    t["yg"] = torch.empty(nn, **f32)
+    t["zg"] = torch.empty(nn, **f32)
+    t["idg"] = torch.empty(nn, **i32)
+    for k in ("up0", "down0", "up", "down"):
+        t[k] = torch.empty(nn, **i32)
+    t["starts"] = torch.empty(cap, **i32)
+    t["t_start"] = torch.empty(cap, **i32)
+    t["t_hits"] = torch.empty(cap * n_rows, **i32)
+    t["t_nhits"] = torch.empty(cap, **i32)
+    t["t_rin"] = torch.empty(cap, **i32)
+    t["t_par"] = torch.empty(cap * 5, **f32)
+    t["t_cov"] = torch.empty(cap * 15, **f32)
+    t["t_chi2"] = torch.empty(cap, **f32)
+    t["trk_off"] = torch.empty(tcap + 1, **i32)
+    t["trk_hits"] = torch.empty(hcap, **i32)
+    t["trk_tracklet"] = torch.empty(max(tcap, 1), **i32)
+    prob = L.Problem()
+    prob.n_sectors = tab.shape[0]
+    prob.n_rows = n_rows
+    prob.n_clusters = n
+    prob.n_bins = n_bins
+    prob.h_sectors = C.c_void_p(h_sec.data_ptr())
+    prob.d_sectors = C.c_void_p(t["d_sectors"].data_ptr())
+    prob.d_row_x = C.c_void_p(t["row_x"].data_ptr())
+    prob.params = params_struct(prm)
+    nbytes = C.c_size_t()
+    L.check(L.lib().tpc_workspace_size(C.byref(prob), cap, C.byref(nbytes)), "tpc_workspace_size")
+    t["ws"] = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
+    ev = Event(problem=prob, t=t, n_rows=n_rows, start_capacity=cap, ws_bytes=int(nbytes.value))
+    ev.track_capacity = tcap
+    ev.track_hit_capacity = hcap
+    ev.layout = (tab, n_bins)
+    return ev
+
+
+def _clusters(ev):
+    t = ev.t
+    return L.Clusters(_ptr(t["row"]), _ptr(t["y"]), _ptr(t["z"]))
+
+
+def _grid(ev):
+    t = ev.t
+    return L.Grid(_ptr(t["bin_start"]), _ptr(t["yg"]), _ptr(t["zg"]), _ptr(t["idg"]))
+
+
+def _links(ev):
+    t = ev.t
+    return L.Links(_ptr(t["up0"]), _ptr(t["down0"]), _ptr(t["up"]), _ptr(t["down"]))
+
+
+def _starts(ev):
+    return L.Starts(_ptr(ev.t["starts"]), ev.start_capacity)
+
+
+def _tracklets(ev):
+    t = ev.t
+    return L.Tracklets(_ptr(t["t_start"]), _ptr(t["t_hits"]), _ptr(t["t_nhits"]), _ptr(t["t_rin"]),
+                       _ptr(t["t_par"]), _ptr(t["t_cov"]), _ptr(t["t_chi2"]), ev.start_capacity)
+
+
+def _tracks(ev):
+    t = ev.t
+    return L.Tracks(_ptr(t["trk_off"]), _ptr(t["trk_hits"]), _ptr(t["trk_tracklet"]),
+                    ev.track_capacity, ev.track_hit_capacity)
+
+
+def build_grid(ctx: Context, ev: Event, stream=None):
+    L.check(L.lib().tpc_build_grid(ctx.handle, C.byref(ev.problem), _clusters(ev), _grid(ev),
+                                   _ptr(ev.t["ws"]), ev.ws_bytes, _stream(stream)),
+            "tpc_build_grid")
+
+
+def find_neighbours(ctx: Context, ev: Event, stream=None):
+    L.check(L.lib().tpc_find_neighbours(ctx.handle, C.byref(ev.problem), _grid(ev), _links(ev),
+                                        _starts(ev), _ptr(ev.t["ws"]), ev.ws_bytes,
+                                        _stream(stream)), "tpc_find_neighbours")
+
+
+def construct_tracklets(ctx: Context, ev: Event, stream=None):
+    L.check(L.lib().tpc_construct_tracklets(ctx.handle, C.byref(ev.problem), _grid(ev),
+                                            _links(ev), _starts(ev), _tracklets(ev),
+                                            _ptr(ev.t["ws"]), ev.ws_bytes, _stream(stream)),
+            "tpc_construct_tracklets")
+
+
+def select_tracks(ctx: Context, ev: Event, stream=None):
+    L.check(L.lib().tpc_select_tracks(ctx.handle, C.byref(ev.problem), _grid(ev),
+                                      _tracklets(ev), _tracks(ev), _ptr(ev.t["ws"]), ev.ws_bytes,
+                                      _stream(stream)), "tpc_select_tracks")
+
+
+def track_batch(ctx: Context, ev: Event, mode="staged", use_graph=False, stream=None):
+    L.check(L.lib().tpc_track_batch(ctx.handle, C.byref(ev.problem), _clusters(ev), _grid(ev),
+                                    _links(ev), _starts(ev), _tracklets(ev), _tracks(ev),
+                                    _ptr(ev.t["ws"]), ev.ws_bytes, MODES[mode],
+                                    1 if use_graph else 0, _stream(stream)), "tpc_track_batch")
+
+
+def get_status(ev: Event, stream=None) -> dict:
+    st = L.Status()
+    L.check(L.lib().tpc_get_status(_ptr(ev.t["ws"]), C.byref(st), _stream(stream)),
+            "tpc_get_status")
+    return {name: getattr(st, name) for name, _ in L.Status._fields_ if name != "pad_"}
+
+
+def track(ctx: Context, ev: Event, stream=None):
+    """The four tracking calls in order on one stream."""
+    build_grid(ctx, ev, stream)
+    find_neighbours(ctx, ev, stream)
+    construct_tracklets(ctx, ev, stream)
+    select_tracks(ctx, ev, stream)
+
+
+def results(ev: Event, stream=None) -> dict:
+    """Host copies of every output, sliced to the counts in the status
+    block.  Links are returned in grid-position space as the library
+    writes them, plus the grid permutation to map them to cluster ids."""
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    st = get_status(ev, stream)
+    t = ev.t
+    n = int(st["n_grid"])
+    m = min(int(st["n_starts"]), ev.start_capacity)
+    nt = min(int(st["n_tracks"]), ev.track_capacity)
+    out = dict(status=st)
+    cpu = lambda x: x.cpu().numpy()
+    out["bin_start"] = cpu(t["bin_start"])
+    for k in ("yg", "zg", "idg", "up0", "down0", "up", "down"):
+        out[k] = cpu(t[k][:n])
+    out["starts"] = cpu(t["starts"][:m])
+    out["t_start"] = cpu(t["t_start"][:m])
+    out["t_hits"] = cpu(t["t_hits"][:m * ev.n_rows]).reshape(m, ev.n_rows)
+    out["t_nhits"] = cpu(t["t_nhits"][:m])
+    out["t_rin"] = cpu(t["t_rin"][:m])
+    out["t_par"] = cpu(t["t_par"][:m * 5]).reshape(m, 5)
+    out["t_cov"] = cpu(t["t_cov"][:m * 15]).reshape(m, 15)
+    out["t_chi2"] = cpu(t["t_chi2"][:m])
+    off = cpu(t["trk_off"][:nt + 1])
+    out["trk_off"] = off
+    out["trk_hits"] = cpu(t["trk_hits"][:int(off[-1]) if nt > 0 else 0])
+    out["trk_tracklet"] = cpu(t["trk_tracklet"][:nt])
+    return out
+
+
+# ---------------------------------------------------------------- refit
+
+CALIB_MODEL = dict(drift_len=250.0, vd=2.58, tan_half=0.17632698070846498, u_centre=165.0,
+                   u_scale=80.0)
+
+
+def calib_struct(cm=None) -> L.CalibModel:
+    cm = dict(CALIB_MODEL, **(cm or {}))
+    return L.CalibModel(*(cm[k] for k, _ in L.CalibModel._fields_))
+
+
+@dataclass
+class TrackHits:
+    off: torch.Tensor      # int32 [n_tracks + 1]
+    row: torch.Tensor      # uint8 [n_hits]
+    y: torch.Tensor        # float32 [n_hits]
+    z: torch.Tensor        # float32 [n_hits]
+    side: torch.Tensor | None = None   # int8 [n_tracks]
+
+    @property
+    def n_tracks(self):
+        return int(self.off.shape[0] - 1)
+
+    @property
+    def n_hits(self):
+        return int(self.row.shape[0])
+
+    def struct(self, y=None, z=None) -> L.TrackHits:
+        return L.TrackHits(_ptr(self.off), _ptr(self.row), _ptr(self.y if y is None else y),
+                           _ptr(self.z if z is None else z), _ptr(self.side), self.n_tracks,
+                           self.n_hits)
+
+
+def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: torch.Tensor,
+          checkpoints: bool = True, cm=None, stream=None, y=None, z=None):
+    """Forward refit; returns dict(par, cov, chi2, status, checkpoints)."""
+    dev = hits.row.device
+    n = hits.n_tracks
+    out = dict(par=torch.empty(n * 5, dtype=torch.float32, device=dev),
+               cov=torch.empty(n * 15, dtype=torch.float32, device=dev),
+               chi2=torch.empty(n, dtype=torch.float32, device=dev),
+               status=torch.empty(n, dtype=torch.int32, device=dev))
+    out["checkpoints"] = (torch.empty(max(hits.n_hits, 1) * 20, dtype=torch.float32, device=dev)
+                          if checkpoints else None)
+    P = params_struct(prm)
+    CM = calib_struct(cm)
+    th = theta.detach().to(device=dev, dtype=torch.float32).contiguous()
+    L.check(L.lib().tpc_refit(ctx.handle, hits.struct(y, z), int(row_x.shape[0]), _ptr(row_x),
+                              C.byref(P), C.byref(CM), _ptr(th), _ptr(out["par"]),
+                              _ptr(out["cov"]), _ptr(out["chi2"]), _ptr(out["status"]),
+                              _ptr(out["checkpoints"]), _stream(stream)), "tpc_refit")
+    out["par"] = out["par"].view(n, 5)
+    out["cov"] = out["cov"].view(n, 15)
+    return out
+
+
+def refit_adjoint(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
+                  theta: torch.Tensor, fwd: dict, grad_chi2: torch.Tensor, cm=None, stream=None,
+                  y=None, z=None):
+    """Gradients of sum_k grad_chi2[k] chi2[k]: (grad_y, grad_z, grad_theta)."""
+    dev = hits.row.device
+    nb = C.c_size_t()
+    L.check(L.lib().tpc_refit_workspace_size(hits.n_tracks, C.byref(nb)), "workspace")
+    ws = torch.empty(max(int(nb.value), 64), dtype=torch.uint8, device=dev)
+    gy = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
+    gz = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
+    gt = torch.zeros(16, dtype=torch.float32, device=dev)
+    P = params_struct(prm)
+    CM = calib_struct(cm)
+    th = theta.detach().to(device=dev, dtype=torch.float32).contiguous()
+    g = grad_chi2.detach().to(device=dev, dtype=torch.float32).contiguous()
+    L.check(L.lib().tpc_refit_adjoint(ctx.handle, hits.struct(y, z), int(row_x.shape[0]),
+                                      _ptr(row_x), C.byref(P), C.byref(CM), _ptr(th),
+                                      _ptr(fwd["checkpoints"]), _ptr(fwd["status"]), _ptr(g),
+                                      _ptr(gy), _ptr(gz), _ptr(gt), _ptr(ws), int(nb.value),
+                                      _stream(stream)), "tpc_refit_adjoint")
+    return gy[:hits.n_hits], gz[:hits.n_hits], gt

@@ -1,0 +1,648 @@
+// Calibrated Kalman refit of found tracks and its adjoint.
+//
+// Forward (one thread per track): calibrate every raw cluster with the 16
+// parameters theta, start from the first and third hits, filter outwards and
+// sum the chi2 of the updates; the state after every update but the last is
+// written as a checkpoint (5 parameters + 15 covariance entries).
+//
+// Adjoint (one thread per track): with L = sum_k g_k chi2_k, a reverse sweep
+// from the last hit reloads each checkpoint, recomputes the transport and
+// update, and applies their exact derivatives: of the update (gain, chi2,
+// covariance) and of the transport including the dependence of the Jacobian
+// on the state and on the step length, which the calibration moves.  The
+// symmetric covariance carries a symmetric adjoint G with
+// dL = sum_ij G_ij dC_ij.  Hit gradients are written per hit; the theta
+// gradient is reduced per block in a fixed order, then over blocks.
+#include "tpc_internal.hpp"
+
+// The refit feeds tolerance-checked outputs only: contraction allowed.
+#pragma clang fp contract(fast)
+
+namespace tpc {
+
+namespace {
+
+__device__ __forceinline__ int lt(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+struct CalibModel {
+    float DL, VD, TH, UC, US;
+};
+
+struct CalHit {
+    float x, y, z;      // calibrated plane, y, z
+    float xr, yr, dr;   // raw plane x_r, raw y, raw drift length
+    float d, u, v;      // calibrated drift, basis coordinates
+};
+
+__device__ __forceinline__ CalHit calibrate(const float* th, float xr, float yr, float zr, float sd,
+                                            const CalibModel& cm)
+{
+    CalHit h;
+    h.xr = xr;
+    h.yr = yr;
+    h.dr = cm.DL - sd * zr;
+    h.d = (1.0f + th[0]) * (h.dr - cm.VD * th[1]);
+    h.z = sd * (cm.DL - h.d);
+    h.u = (xr - cm.UC) / cm.US;
+    h.v = yr / (xr * cm.TH);
+    const float w = h.d / cm.DL;
+    const float b[7] = {1.0f, h.u, h.v, h.u * h.u, h.u * h.v, h.v * h.v, w};
+    float dr = 0.0f, drphi = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        dr += th[2 + j] * b[j];
+        drphi += th[9 + j] * b[j];
+    }
+    h.x = xr + dr;
+    h.y = yr + drphi;
+    return h;
+}
+
+// reverse of calibrate: adjoints (X, Y, Z) of the calibrated point ->
+// raw (y, z) adjoints, accumulated theta adjoint
+__device__ __forceinline__ void calibrate_adj(const float* th, const CalHit& h, float sd,
+                                              const CalibModel& cm, float X, float Y, float Z,
+                                              float* gth, float& gyr, float& gzr)
+{
+    const float w = h.d / cm.DL;
+    const float b[7] = {1.0f, h.u, h.v, h.u * h.u, h.u * h.v, h.v * h.v, w};
+    float bb[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        gth[2 + j] += X * b[j];
+        gth[9 + j] += Y * b[j];
+        bb[j] = X * th[2 + j] + Y * th[9 + j];
+    }
+    const float vb = bb[2] + bb[4] * h.u + 2.0f * bb[5] * h.v;
+    gyr = Y + vb / (h.xr * cm.TH);
+    const float db = bb[6] / cm.DL - Z * sd;
+    gth[0] += db * (h.dr - cm.VD * th[1]);
+    gth[1] += -db * (1.0f + th[0]) * cm.VD;
+    gzr = -sd * (1.0f + th[0]) * db;
+}
+
+struct Prop {
+    float dx, k, s2, c1, c2, cc, T, q, L, a, a2, g, S, Ts, kdx, Tw, LT, G1, Sk;
+    float ys, yw, zs, zt, zw, sw;   // non-trivial Jacobian entries
+    float FC[5][5];                 // F C
+};
+
+// transport of (p, C) by dx; fills the intermediates; false on |s| stop
+__device__ __forceinline__ bool prop_fwd(float* p, float* C, float dx, float curv, float s_max,
+                                         Prop& P)
+{
+    const float s = p[2], t = p[3], w = p[4];
+    P.dx = dx;
+    P.k = curv * w;
+    P.s2 = s + P.k * dx;
+    if (!(fabsf(P.s2) < s_max)) return false;
+    P.c1 = sqrtf((1.0f - s) * (1.0f + s));
+    P.c2 = sqrtf((1.0f - P.s2) * (1.0f + P.s2));
+    P.cc = P.c1 + P.c2;
+    P.T = (s + P.s2) / P.cc;
+    P.q = sqrtf(1.0f + P.T * P.T);
+    P.L = dx * P.q;
+    P.a = 0.5f * P.k * P.L;
+    P.a2 = P.a * P.a;
+    P.g = 1.0f + P.a2 * ((1.0f / 6.0f) + P.a2 * ((3.0f / 40.0f) + P.a2 * (5.0f / 112.0f)));
+    P.S = P.L * P.g;
+    P.Ts = (2.0f + P.T * (s / P.c1 + P.s2 / P.c2)) / P.cc;
+    P.kdx = curv * dx;
+    P.Tw = P.kdx * (1.0f + P.T * (P.s2 / P.c2)) / P.cc;
+    P.LT = dx * P.T / P.q;
+    P.G1 = 1.0f + P.a2 * (0.5f + P.a2 * ((3.0f / 8.0f) + P.a2 * (5.0f / 16.0f)));
+    P.Sk = P.L * P.L * P.a * ((1.0f / 6.0f) + P.a2 * ((3.0f / 20.0f) + P.a2 * (15.0f / 112.0f)));
+    P.ys = dx * P.Ts;
+    P.yw = dx * P.Tw;
+    const float m1 = P.G1 * P.LT;
+    P.zs = t * m1 * P.Ts;
+    P.zt = P.S;
+    P.zw = t * (m1 * P.Tw + P.Sk * curv);
+    P.sw = P.kdx;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const float cy = C[lt(0, j)], cz = C[lt(1, j)], cs = C[lt(2, j)];
+        const float ct = C[lt(3, j)], cw = C[lt(4, j)];
+        P.FC[0][j] = cy + P.ys * cs + P.yw * cw;
+        P.FC[1][j] = cz + P.zs * cs + P.zt * ct + P.zw * cw;
+        P.FC[2][j] = cs + P.sw * cw;
+        P.FC[3][j] = ct;
+        P.FC[4][j] = cw;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float* B = P.FC[i];
+        C[lt(i, 0)] = B[0] + P.ys * B[2] + P.yw * B[4];
+        if (i >= 1) C[lt(i, 1)] = B[1] + P.zs * B[2] + P.zt * B[3] + P.zw * B[4];
+        if (i >= 2) C[lt(i, 2)] = B[2] + P.sw * B[4];
+        if (i >= 3) C[lt(i, 3)] = B[3];
+        if (i >= 4) C[lt(i, 4)] = B[4];
+    }
+    p[0] = p[0] + dx * P.T;
+    p[1] = p[1] + t * P.S;
+    p[2] = P.s2;
+    return true;
+}
+
+struct Upd {
+    float r0, r1, B00, B10, B11;
+    float A0[5], A1[5], K0[5], K1[5];
+};
+
+__device__ __forceinline__ float upd_fwd(float* p, float* C, float my, float mz, float sy2,
+                                         float sz2, Upd& U)
+{
+    U.r0 = my - p[0];
+    U.r1 = mz - p[1];
+    const float S00 = C[0] + sy2, S10 = C[1], S11 = C[2] + sz2;
+    const float idet = 1.0f / (S00 * S11 - S10 * S10);
+    U.B00 = S11 * idet;
+    U.B10 = -S10 * idet;
+    U.B11 = S00 * idet;
+    const float chi2 = U.r0 * (U.B00 * U.r0 + U.B10 * U.r1) + U.r1 * (U.B10 * U.r0 + U.B11 * U.r1);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        U.A0[i] = C[lt(i, 0)];
+        U.A1[i] = C[lt(i, 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        U.K0[i] = U.A0[i] * U.B00 + U.A1[i] * U.B10;
+        U.K1[i] = U.A0[i] * U.B10 + U.A1[i] * U.B11;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        p[i] += U.K0[i] * U.r0 + U.K1[i] * U.r1;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) C[lt(i, j)] -= U.K0[i] * U.A0[j] + U.K1[i] * U.A1[j];
+    }
+    return chi2;
+}
+
+// adjoint of the update: in pb (5), G (15, symmetric adjoint) of the
+// updated state; out the same for the predicted state, and the adjoints of
+// the measurement
+__device__ __forceinline__ void upd_adj(const Upd& U, float cb, float* pb, float* G, float& myb,
+                                        float& mzb)
+{
+    float Kb0[5], Kb1[5];
+    float rb0 = 0.0f, rb1 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        Kb0[i] = pb[i] * U.r0;
+        Kb1[i] = pb[i] * U.r1;
+        rb0 += U.K0[i] * pb[i];
+        rb1 += U.K1[i] * pb[i];
+    }
+    // M = G A (5x2)
+    float M0[5], M1[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const float gij = G[lt(i, j)];
+            m0 += gij * U.A0[j];
+            m1 += gij * U.A1[j];
+        }
+        M0[i] = m0;
+        M1[i] = m1;
+    }
+    // Ab = -2 M B + Kb B ; Bb = -A^T M + A^T Kb + cb r r^T
+    float Ab0[5], Ab1[5];
+    float Bb00 = cb * U.r0 * U.r0, Bb01 = cb * U.r0 * U.r1, Bb10 = Bb01, Bb11 = cb * U.r1 * U.r1;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float e0 = Kb0[i] - 2.0f * M0[i], e1 = Kb1[i] - 2.0f * M1[i];
+        Ab0[i] = e0 * U.B00 + e1 * U.B10;
+        Ab1[i] = e0 * U.B10 + e1 * U.B11;
+        const float f0 = Kb0[i] - M0[i], f1 = Kb1[i] - M1[i];
+        Bb00 += U.A0[i] * f0;
+        Bb01 += U.A0[i] * f1;
+        Bb10 += U.A1[i] * f0;
+        Bb11 += U.A1[i] * f1;
+    }
+    // r: chi2 term
+    rb0 += 2.0f * cb * (U.B00 * U.r0 + U.B10 * U.r1);
+    rb1 += 2.0f * cb * (U.B10 * U.r0 + U.B11 * U.r1);
+    // S adjoint: -B sym(Bb) B
+    const float s00 = Bb00, s11 = Bb11, s01 = 0.5f * (Bb01 + Bb10);
+    const float t00 = U.B00 * s00 + U.B10 * s01, t01 = U.B00 * s01 + U.B10 * s11;
+    const float t10 = U.B10 * s00 + U.B11 * s01, t11 = U.B10 * s01 + U.B11 * s11;
+    const float Sb00 = -(t00 * U.B00 + t01 * U.B10);
+    const float Sb10 = -(t10 * U.B00 + t11 * U.B10);
+    const float Sb11 = -(t10 * U.B10 + t11 * U.B11);
+    G[0] += Sb00;
+    G[1] += Sb10;
+    G[2] += Sb11;
+    // A = C[:, 0:2], symmetric embedding
+    G[0] += Ab0[0];
+    G[2] += Ab1[1];
+    G[1] += 0.5f * (Ab0[1] + Ab1[0]);
+#pragma unroll
+    for (int i = 2; i < 5; ++i) {
+        G[lt(i, 0)] += 0.5f * Ab0[i];
+        G[lt(i, 1)] += 0.5f * Ab1[i];
+    }
+    myb = rb0;
+    mzb = rb1;
+    pb[0] -= rb0;
+    pb[1] -= rb1;
+}
+
+// adjoint of the transport: in pb, G of the transported state; out those of
+// the state before it (p0: that state), and the step-length adjoint
+__device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const float* C0,
+                                          float curv, float* pb, float* G)
+{
+    const float s = p0[2], t = p0[3];
+    // F-bar = 2 G F C for the six free entries
+    auto gfc = [&](int a, int b) {
+        float v = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) v += G[lt(a, j)] * P.FC[j][b];
+        return 2.0f * v;
+    };
+    const float Fys = gfc(0, 2), Fyw = gfc(0, 4), Fzs = gfc(1, 2), Fzt = gfc(1, 3),
+                Fzw = gfc(1, 4), Fsw = gfc(2, 4);
+    // G <- F^T G F
+    float E[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const float g0 = G[lt(i, 0)], g1 = G[lt(i, 1)], g2 = G[lt(i, 2)];
+        E[i][0] = g0;
+        E[i][1] = g1;
+        E[i][2] = g2 + g0 * P.ys + g1 * P.zs;
+        E[i][3] = G[lt(i, 3)] + g1 * P.zt;
+        E[i][4] = G[lt(i, 4)] + g0 * P.yw + g1 * P.zw + g2 * P.sw;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            float v = E[i][j];
+            if (i == 2) v += P.ys * E[0][j] + P.zs * E[1][j];
+            if (i == 3) v += P.zt * E[1][j];
+            if (i == 4) v += P.yw * E[0][j] + P.zw * E[1][j] + P.sw * E[2][j];
+            G[lt(i, j)] = v;
+        }
+    }
+    (void)C0;
+    // state part: y' = y + dx T, z' = z + t S, s' = s2, t' = t, w' = w
+    float Tb = pb[0] * P.dx, dxb = pb[0] * P.T, Sb = pb[1] * t, s2b = pb[2];
+    float tb = pb[3] + pb[1] * P.S, wb = pb[4];
+    // Jacobian entries
+    const float m1 = P.G1 * P.LT;
+    float Tsb = 0.0f, Twb = 0.0f, m1b = 0.0f, Skb = 0.0f, kdxb = 0.0f;
+    dxb += Fys * P.Ts;
+    Tsb += Fys * P.dx;
+    dxb += Fyw * P.Tw;
+    Twb += Fyw * P.dx;
+    tb += Fzs * m1 * P.Ts;
+    m1b += Fzs * t * P.Ts;
+    Tsb += Fzs * t * m1;
+    Sb += Fzt;
+    tb += Fzw * (m1 * P.Tw + P.Sk * curv);
+    m1b += Fzw * t * P.Tw;
+    Twb += Fzw * t * m1;
+    Skb += Fzw * t * curv;
+    kdxb += Fsw;
+    const float G1b = m1b * P.LT;
+    float LTb = m1b * P.G1;
+    // Sk = L^2 a h(a2)
+    const float h = (1.0f / 6.0f) + P.a2 * ((3.0f / 20.0f) + P.a2 * (15.0f / 112.0f));
+    const float hp = (3.0f / 20.0f) + 2.0f * P.a2 * (15.0f / 112.0f);
+    float Lb = Skb * 2.0f * P.L * P.a * h;
+    float ab = Skb * P.L * P.L * h;
+    float a2b = Skb * P.L * P.L * P.a * hp;
+    // G1 = 1 + a2 (1/2 + a2 (3/8 + a2 5/16))
+    a2b += G1b * (0.5f + P.a2 * (2.0f * (3.0f / 8.0f) + P.a2 * (3.0f * (5.0f / 16.0f))));
+    // LT = dx T / q
+    dxb += LTb * P.T / P.q;
+    Tb += LTb * P.dx / P.q;
+    float qb = -LTb * P.dx * P.T / (P.q * P.q);
+    // Tw = kdx n / cc, n = 1 + T s2 / c2
+    const float n = 1.0f + P.T * (P.s2 / P.c2);
+    kdxb += Twb * n / P.cc;
+    const float nb = Twb * P.kdx / P.cc;
+    float ccb = -Twb * P.Tw / P.cc;
+    Tb += nb * P.s2 / P.c2;
+    s2b += nb * P.T / P.c2;
+    float c2b = -nb * P.T * P.s2 / (P.c2 * P.c2);
+    // kdx = curv dx
+    dxb += kdxb * curv;
+    // Ts = (2 + T e) / cc, e = s/c1 + s2/c2
+    const float e = s / P.c1 + P.s2 / P.c2;
+    const float numb = Tsb / P.cc;
+    ccb += -Tsb * P.Ts / P.cc;
+    Tb += numb * e;
+    const float eb = numb * P.T;
+    float sb = eb / P.c1;
+    float c1b = -eb * s / (P.c1 * P.c1);
+    s2b += eb / P.c2;
+    c2b += -eb * P.s2 / (P.c2 * P.c2);
+    // S = L g, g = 1 + a2 (1/6 + a2 (3/40 + a2 5/112))
+    Lb += Sb * P.g;
+    const float gb = Sb * P.L;
+    a2b += gb * ((1.0f / 6.0f) + P.a2 * (2.0f * (3.0f / 40.0f) + P.a2 * (3.0f * (5.0f / 112.0f))));
+    // a2 = a^2 ; a = k L / 2
+    ab += a2b * 2.0f * P.a;
+    float kb = ab * 0.5f * P.L;
+    Lb += ab * 0.5f * P.k;
+    // L = dx q ; q = sqrt(1 + T^2)
+    dxb += Lb * P.q;
+    qb += Lb * P.dx;
+    Tb += qb * P.T / P.q;
+    // T = (s + s2) / cc ; cc = c1 + c2
+    sb += Tb / P.cc;
+    s2b += Tb / P.cc;
+    ccb += -Tb * P.T / P.cc;
+    c1b += ccb;
+    c2b += ccb;
+    s2b += c2b * (-P.s2 / P.c2);
+    sb += c1b * (-s / P.c1);
+    // s2 = s + k dx ; k = curv w
+    sb += s2b;
+    kb += s2b * P.dx;
+    dxb += s2b * P.k;
+    wb += kb * curv;
+    pb[0] = pb[0];        // y' = y + ...: dy'/dy = 1
+    pb[1] = pb[1];        // z' = z + ...
+    pb[2] = sb;
+    pb[3] = tb;
+    pb[4] = wb;
+    return dxb;
+}
+
+__device__ __forceinline__ void load_theta(const float* __restrict__ d_theta, float* th)
+{
+    if (threadIdx.x < 16) th[threadIdx.x] = d_theta[threadIdx.x];
+    __syncthreads();
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void k_refit_fwd(
+    const int32_t* __restrict__ off, const uint8_t* __restrict__ row, const float* __restrict__ y,
+    const float* __restrict__ z, const int8_t* __restrict__ side, int64_t n_tracks, int n_rows,
+    const float* __restrict__ row_x, tpc_params prm, CalibModel cm,
+    const float* __restrict__ d_theta, float* __restrict__ par, float* __restrict__ cov,
+    float* __restrict__ chi2_out, int32_t* __restrict__ status, float* __restrict__ ck)
+{
+    __shared__ float th[16];
+    __shared__ float xs[256];
+    load_theta(d_theta, th);
+    for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
+    __syncthreads();
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_tracks;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int a = off[t], n = off[t + 1] - a;
+        float p[5] = {0, 0, 0, 0, 0}, C[15];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) C[i] = 0.0f;
+        float chi2 = 0.0f;
+        int stat = 0;
+        bool rows_ok = true;
+        for (int i = 0; i < n; ++i) rows_ok &= row[a + i] < n_rows;
+        if (n < 3) {
+            stat = 1;
+        } else if (!rows_ok) {
+            stat = 3;
+        } else {
+            const float sd = side ? (float)side[t] : 1.0f;
+            const CalHit h0 = calibrate(th, xs[row[a]], y[a], z[a], sd, cm);
+            const CalHit h2 = calibrate(th, xs[row[a + 2]], y[a + 2], z[a + 2], sd, cm);
+            const float dX = h2.x - h0.x;
+            const float T0 = (h2.y - h0.y) / dX;
+            const float q0 = sqrtf(1.0f + T0 * T0);
+            p[0] = h0.y;
+            p[1] = h0.z;
+            p[2] = T0 / q0;
+            p[3] = (h2.z - h0.z) / (dX * q0);
+            p[4] = 0.0f;
+            C[0] = prm.sigma_y2;
+            C[2] = prm.sigma_z2;
+            C[5] = prm.c_ss0;
+            C[9] = prm.c_tt0;
+            C[14] = prm.c_ww0;
+            if (ck) {
+                float* o = ck + (int64_t)a * 20;
+#pragma unroll
+                for (int i = 0; i < 5; ++i) o[i] = p[i];
+#pragma unroll
+                for (int i = 0; i < 15; ++i) o[5 + i] = C[i];
+            }
+            float xp = h0.x;
+            for (int i = 1; i < n; ++i) {
+                const CalHit h = calibrate(th, xs[row[a + i]], y[a + i], z[a + i], sd, cm);
+                Prop P;
+                if (!prop_fwd(p, C, h.x - xp, prm.curv, prm.s_max, P)) {
+                    stat = 2;
+                    break;
+                }
+                Upd U;
+                chi2 += upd_fwd(p, C, h.y, h.z, prm.sigma_y2, prm.sigma_z2, U);
+                xp = h.x;
+                if (ck && i + 1 < n) {
+                    float* o = ck + (int64_t)(a + i) * 20;
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) o[k] = p[k];
+#pragma unroll
+                    for (int k = 0; k < 15; ++k) o[5 + k] = C[k];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) par[t * 5 + i] = p[i];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) cov[t * 15 + i] = C[i];
+        chi2_out[t] = chi2;
+        status[t] = stat;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_refit_adj(
+    const int32_t* __restrict__ off, const uint8_t* __restrict__ row, const float* __restrict__ y,
+    const float* __restrict__ z, const int8_t* __restrict__ side, int64_t n_tracks, int n_rows,
+    const float* __restrict__ row_x, tpc_params prm, CalibModel cm,
+    const float* __restrict__ d_theta, const float* __restrict__ ck,
+    const int32_t* __restrict__ status, const float* __restrict__ gchi2,
+    float* __restrict__ gy, float* __restrict__ gz, float* __restrict__ partials)
+{
+    __shared__ float th[16];
+    __shared__ float xs[256];
+    __shared__ float red[kBlock / kWave][16];
+    load_theta(d_theta, th);
+    for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
+    __syncthreads();
+    float gth[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) gth[k] = 0.0f;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_tracks;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int a = off[t], n = off[t + 1] - a;
+        if (n < 3 || status[t] != 0) {
+            for (int i = 0; i < n; ++i) {
+                gy[a + i] = 0.0f;
+                gz[a + i] = 0.0f;
+            }
+            continue;
+        }
+        const float sd = side ? (float)side[t] : 1.0f;
+        const float cb = gchi2[t];
+        float pb[5] = {0, 0, 0, 0, 0}, G[15];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) G[i] = 0.0f;
+        CalHit cur = calibrate(th, xs[row[a + n - 1]], y[a + n - 1], z[a + n - 1], sd, cm);
+        float Xcarry = 0.0f;
+        float X2 = 0.0f, Y2 = 0.0f, Z2 = 0.0f;
+        for (int i = n - 1; i >= 1; --i) {
+            const CalHit prev = calibrate(th, xs[row[a + i - 1]], y[a + i - 1], z[a + i - 1], sd, cm);
+            float p[5], C[15];
+            const float* c = ck + (int64_t)(a + i - 1) * 20;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) p[k] = c[k];
+#pragma unroll
+            for (int k = 0; k < 15; ++k) C[k] = c[5 + k];
+            const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};
+            Prop P;
+            prop_fwd(p, C, cur.x - prev.x, prm.curv, prm.s_max, P);
+            Upd U;
+            upd_fwd(p, C, cur.y, cur.z, prm.sigma_y2, prm.sigma_z2, U);
+            float myb, mzb;
+            upd_adj(U, cb, pb, G, myb, mzb);
+            const float dxb = prop_adj(P, p0, nullptr, prm.curv, pb, G);
+            const float Xi = Xcarry + dxb;
+            if (i == 2) {
+                X2 = Xi;
+                Y2 = myb;
+                Z2 = mzb;
+            } else {
+                float gyr, gzr;
+                calibrate_adj(th, cur, sd, cm, Xi, myb, mzb, gth, gyr, gzr);
+                gy[a + i] = gyr;
+                gz[a + i] = gzr;
+            }
+            Xcarry = -dxb;
+            cur = prev;
+        }
+        // initial state: y, z of hit 0, direction from hit 0 to hit 2
+        const CalHit h0 = cur;
+        const CalHit h2 = calibrate(th, xs[row[a + 2]], y[a + 2], z[a + 2], sd, cm);
+        const float dX = h2.x - h0.x;
+        const float T0 = (h2.y - h0.y) / dX;
+        const float q0 = sqrtf(1.0f + T0 * T0);
+        const float tt = (h2.z - h0.z) / (dX * q0);
+        float Y0 = pb[0], Z0 = pb[1], X0 = Xcarry;
+        float T0b = pb[2] / (q0 * q0 * q0);
+        const float den = dX * q0;
+        Z2 += pb[3] / den;
+        Z0 -= pb[3] / den;
+        const float denb = -pb[3] * tt / den;
+        float dXb = denb * q0;
+        const float q0b = denb * dX;
+        T0b += q0b * T0 / q0;
+        Y2 += T0b / dX;
+        Y0 -= T0b / dX;
+        dXb -= T0b * T0 / dX;
+        X2 += dXb;
+        X0 -= dXb;
+        float gyr, gzr;
+        calibrate_adj(th, h0, sd, cm, X0, Y0, Z0, gth, gyr, gzr);
+        gy[a] = gyr;
+        gz[a] = gzr;
+        calibrate_adj(th, h2, sd, cm, X2, Y2, Z2, gth, gyr, gzr);
+        gy[a + 2] = gyr;
+        gz[a + 2] = gzr;
+    }
+    // deterministic block reduction of the theta adjoint
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        float v = gth[k];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float v = 0.0f;
+        for (int w = 0; w < kBlock / kWave; ++w) v += red[w][threadIdx.x];
+        partials[blockIdx.x * 16 + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_reduce_theta(const float* __restrict__ partials, int nb, float* __restrict__ out)
+{
+    // 16 threads, each sums its column in block order
+    if (threadIdx.x < 16) {
+        float v = 0.0f;
+        for (int b = 0; b < nb; ++b) v += partials[b * 16 + threadIdx.x];
+        out[threadIdx.x] = v;
+    }
+}
+
+static unsigned refit_grid(int64_t n_tracks)
+{
+    return grid_for(n_tracks, 4096);
+}
+
+}  // namespace tpc
+
+extern "C" {
+
+int tpc_refit_workspace_size(int64_t n_tracks, size_t* h_bytes)
+{
+    if (!h_bytes || n_tracks < 0) return TPC_ERR_INVALID_ARG;
+    *h_bytes = sizeof(float) * 16 * (size_t)tpc::refit_grid(n_tracks);
+    return TPC_OK;
+}
+
+int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
+              const tpc_params* h_params, const tpc_calib_model* h_model, const float* d_theta,
+              float* par, float* cov, float* chi2, int32_t* status, float* checkpoints,
+              void* stream)
+{
+    if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !par || !cov || !chi2 ||
+        !status || hits.n_tracks < 0 || hits.n_hits < 0 || n_rows < 3 || n_rows > 255 ||
+        (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
+        hits.n_hits >= (int64_t(1) << 31))
+        return TPC_ERR_INVALID_ARG;
+    if (hits.n_tracks == 0) return TPC_OK;
+    tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
+                       h_model->u_scale};
+    hipLaunchKernelGGL(tpc::k_refit_fwd, dim3(tpc::refit_grid(hits.n_tracks)), dim3(tpc::kBlock),
+                       0, (hipStream_t)stream, hits.off, hits.row, hits.y, hits.z, hits.side,
+                       hits.n_tracks, n_rows, d_row_x, *h_params, cm, d_theta, par, cov, chi2,
+                       status, checkpoints);
+    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                      const float* d_row_x, const tpc_params* h_params,
+                      const tpc_calib_model* h_model, const float* d_theta,
+                      const float* checkpoints, const int32_t* status, const float* grad_chi2,
+                      float* grad_y, float* grad_z, float* grad_theta, void* d_ws,
+                      size_t ws_bytes, void* stream)
+{
+    size_t need = 0;
+    if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !checkpoints || !status ||
+        !grad_chi2 || !grad_y || !grad_z || !grad_theta || !d_ws || hits.n_tracks < 0 ||
+        n_rows < 3 || n_rows > 255 ||
+        (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
+        tpc_refit_workspace_size(hits.n_tracks, &need) || need > ws_bytes)
+        return TPC_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
+                       h_model->u_scale};
+    const unsigned nb = tpc::refit_grid(hits.n_tracks);
+    float* partials = (float*)d_ws;
+    hipLaunchKernelGGL(tpc::k_refit_adj, dim3(nb), dim3(tpc::kBlock), 0, st, hits.off, hits.row,
+                       hits.y, hits.z, hits.side, hits.n_tracks, n_rows, d_row_x, *h_params, cm,
+                       d_theta, checkpoints, status, grad_chi2, grad_y, grad_z, partials);
+    hipLaunchKernelGGL(tpc::k_reduce_theta, dim3(1), dim3(64), 0, st, (const float*)partials,
+                       (int)nb, grad_theta);
+    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+}  // extern "C"

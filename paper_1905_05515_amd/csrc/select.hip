@@ -1,0 +1,136 @@
+// Tracklet selection: every cluster goes to the tracklet of largest key
+// (hits << 32 | (2^32 - 1 - start id)) containing it, among tracklets with
+// at least min_tracklet_hits hits (64-bit atomic max, order independent); a
+// tracklet keeping at least min_track_hits clusters becomes a track.
+// Tracks are compacted in tracklet order by a scan of (accepted, kept).
+#include "tpc_internal.hpp"
+
+namespace tpc {
+
+__device__ __forceinline__ uint64_t tracklet_key(int nh, int start_id, int min_hits)
+{
+    return nh >= min_hits ? (((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)start_id)) : 0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_keys(
+    int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
+    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
+    const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t cap,
+    unsigned long long* __restrict__ hitkey)
+{
+    int64_t m = status->n_starts;
+    if (m > cap) m = cap;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
+        if (!key) continue;
+        const int32_t* th = t_hits + t * n_rows;
+        for (int r = 0; r < n_rows; ++r) {
+            const int c = th[r];
+            if (c >= 0) atomicMax(&hitkey[c], (unsigned long long)key);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_count(
+    int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
+    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
+    const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t cap,
+    const unsigned long long* __restrict__ hitkey, uint64_t* __restrict__ tlen)
+{
+    int64_t m = status->n_starts;
+    if (m > cap) m = cap;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cap;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t out = 0;
+        if (t < m) {
+            const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
+            if (key) {
+                const int32_t* th = t_hits + t * n_rows;
+                int kept = 0;
+                for (int r = 0; r < n_rows; ++r) {
+                    const int c = th[r];
+                    kept += c >= 0 && hitkey[c] == key;
+                }
+                if (kept >= prm.min_track_hits) out = (1ull << 32) | (uint64_t)kept;
+            }
+        }
+        tlen[t] = out;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_write(
+    int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
+    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
+    const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t cap,
+    const unsigned long long* __restrict__ hitkey, const uint64_t* __restrict__ tlen,
+    const uint64_t* __restrict__ toff, int32_t* __restrict__ trk_off,
+    int32_t* __restrict__ trk_hits, int32_t* __restrict__ trk_tracklet, int64_t trk_cap,
+    int64_t hit_cap)
+{
+    int64_t m = status->n_starts;
+    if (m > cap) m = cap;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (!tlen[t]) continue;
+        const int64_t k = (int64_t)(toff[t] >> 32);
+        int64_t o = (int64_t)(toff[t] & 0xFFFFFFFFull);
+        if (k < trk_cap) {
+            trk_tracklet[k] = (int32_t)t;
+            trk_off[k] = (int32_t)o;
+        }
+        const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
+        const int32_t* th = t_hits + t * n_rows;
+        for (int r = 0; r < n_rows; ++r) {
+            const int c = th[r];
+            if (c >= 0 && hitkey[c] == key) {
+                if (o < hit_cap) trk_hits[o] = idg[c];
+                ++o;
+            }
+        }
+    }
+}
+
+__global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status* status,
+                             int32_t* __restrict__ trk_off, int64_t trk_cap, int64_t hit_cap)
+{
+    if (blockIdx.x || threadIdx.x) return;
+    const uint64_t tot = *toff_total;
+    const int64_t nt = (int64_t)(tot >> 32), nh = (int64_t)(tot & 0xFFFFFFFFull);
+    status->n_tracks = nt;
+    status->n_track_hits = nh;
+    if (nt <= trk_cap) trk_off[nt] = (int32_t)nh;
+    if (nt > trk_cap) status->overflow |= 2;
+    if (nh > hit_cap) status->overflow |= 4;
+}
+
+int run_select_tracks(const tpc_problem* p, tpc_grid grid, tpc_starts starts,
+                      tpc_tracklets trl, tpc_tracks trk, const Workspace& ws, hipStream_t st)
+{
+    (void)starts;
+    const int64_t cap = trl.capacity;
+    const unsigned gt = grid_for(cap, 4096);
+    launch_fill<uint64_t>(ws.hitkey, 0ull, p->n_clusters, st);
+    hipLaunchKernelGGL(k_sel_keys, dim3(gt), dim3(kBlock), 0, st, p->n_rows, p->params,
+                       (const int32_t*)grid.id, (const int32_t*)trl.start,
+                       (const int32_t*)trl.hits, (const int32_t*)trl.nhits,
+                       (const tpc_status*)ws.status, cap, (unsigned long long*)ws.hitkey);
+    hipLaunchKernelGGL(k_sel_count, dim3(gt), dim3(kBlock), 0, st, p->n_rows, p->params,
+                       (const int32_t*)grid.id, (const int32_t*)trl.start,
+                       (const int32_t*)trl.hits, (const int32_t*)trl.nhits,
+                       (const tpc_status*)ws.status, cap,
+                       (const unsigned long long*)ws.hitkey, ws.tlen);
+    launch_scan<uint64_t>(ws.tlen, ws.toff, cap, true, nullptr, nullptr, ws.partials, st);
+    hipLaunchKernelGGL(k_sel_write, dim3(gt), dim3(kBlock), 0, st, p->n_rows, p->params,
+                       (const int32_t*)grid.id, (const int32_t*)trl.start,
+                       (const int32_t*)trl.hits, (const int32_t*)trl.nhits,
+                       (const tpc_status*)ws.status, cap,
+                       (const unsigned long long*)ws.hitkey, (const uint64_t*)ws.tlen,
+                       (const uint64_t*)ws.toff, trk.off, trk.hits, trk.tracklet, trk.capacity,
+                       trk.hit_capacity);
+    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(1), 0, st, (const uint64_t*)(ws.toff + cap),
+                       ws.status, trk.off, trk.capacity, trk.hit_capacity);
+    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+}  // namespace tpc

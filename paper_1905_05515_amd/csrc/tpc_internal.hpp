@@ -1,0 +1,121 @@
+// Internal declarations shared by the HIP sources of libtpc.so.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/tpc.h"
+
+// All decisions are taken in binary32 with the association order written in
+// the source; contraction into FMA is off for the whole library (also passed
+// on the command line).  The refit, which only feeds tolerance-checked
+// outputs, enables contraction locally.
+#pragma clang fp contract(off)
+
+namespace tpc {
+
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kScanItems = 8;        // items per thread in the scans
+constexpr int kScanTile = kBlock * kScanItems;
+
+struct Workspace {
+    tpc_status* status;
+    int32_t* cnt;          // [n_bins + 1] bin counts, then fill cursors
+    int32_t* tmp;          // [n] scatter staging, then start flags by id
+    int32_t* gsr;          // [n] sector << 8 | row per grid position
+    int64_t* partials;     // scan tile partials
+    uint64_t* hitkey;      // [n] selection keys per grid position
+    uint64_t* tlen;        // [start_cap + 1] per tracklet: accepted << 32 | kept
+    uint64_t* toff;        // [start_cap + 1] exclusive scan of tlen
+    size_t bytes;
+};
+
+// Offsets of the workspace members for a problem; returns false on overflow.
+bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Workspace* ws);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Grid size of a grid-stride launch over n items, capped.
+inline unsigned grid_for(int64_t n, int64_t cap = 16384)
+{
+    int64_t g = ceil_div(n > 0 ? n : 1, kBlock);
+    return (unsigned)(g < cap ? g : cap);
+}
+
+// ---- device helpers ---------------------------------------------------------
+
+__device__ inline int find_sector(const tpc_sector* sec, int n_sec, int64_t id)
+{
+    int lo = 0, hi = n_sec - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sec[mid].begin <= id) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Bin of a coordinate: (v - v0) * inv clamped to [0, nb - 1] in float, then
+// truncated.  Monotone in v.
+__device__ inline int bin_of(float v, float v0, float inv, int nb)
+{
+    float f = (v - v0) * inv;
+    if (!(f >= 0.0f)) f = 0.0f;
+    float top = (float)(nb - 1);
+    if (f > top) f = top;
+    return (int)f;
+}
+
+__device__ inline int global_bin(const tpc_sector& s, int row, float y, float z)
+{
+    int iy = bin_of(y, s.y0, s.inv_by, s.nby);
+    int iz = bin_of(z, s.z0, s.inv_bz, s.nbz);
+    return s.bin_base + (row * s.nbz + iz) * s.nby + iy;
+}
+
+// Windows are widened by this factor before taking bins, so that a rounding
+// difference at a window edge never drops a candidate; the exact predicate
+// decides.
+#define TPC_WIDEN (1.0f + 1.0f / 64.0f)
+
+// ---- launch helpers (host) --------------------------------------------------
+
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t st);
+
+// Exclusive scan of in[0..n) into out[0..n), starting from *carry_in
+// (device, nullable: 0); out[n] = carry + total when write_total;
+// *total_dst (device, nullable) = carry + total.  in may equal out.
+template <typename T>
+void launch_scan(const T* in, T* out, int64_t n, bool write_total, int64_t* total_dst,
+                 const int64_t* carry_in, int64_t* partials, hipStream_t st);
+
+// Exclusive scan, in place, of nt int64 tile partials by one block.
+void launch_scan_partials(int64_t* partials, int64_t nt, const int64_t* carry_in,
+                          int64_t* total_dst, hipStream_t st);
+
+}  // namespace tpc
+
+struct tpc_context {
+    int device;
+    int n_cu;
+    // cached graph of tpc_track_batch
+    hipGraphExec_t graph_exec;
+    uint64_t graph_key;
+    bool graph_valid;
+};
+
+// stage launchers (stream-ordered, no host synchronisation)
+namespace tpc {
+int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in,
+                   tpc_grid out, const Workspace& ws, hipStream_t st);
+int run_find_neighbours(const tpc_problem* p, tpc_grid grid, tpc_links links,
+                        tpc_starts starts, const Workspace& ws, hipStream_t st);
+int run_construct_tracklets(const tpc_problem* p, tpc_grid grid, tpc_links links,
+                            tpc_starts starts, tpc_tracklets trl, const Workspace& ws,
+                            hipStream_t st);
+int run_select_tracks(const tpc_problem* p, tpc_grid grid, tpc_starts starts,
+                      tpc_tracklets trl, tpc_tracks trk, const Workspace& ws,
+                      hipStream_t st);
+}  // namespace tpc

@@ -1,0 +1,284 @@
+// Scans, fills, workspace layout, context and status calls.
+#include "tpc_internal.hpp"
+
+#include <cstring>
+#include <new>
+
+namespace tpc {
+
+// ---- fill -------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, T v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 8192)), dim3(kBlock), 0, st, p, v, n);
+}
+template void launch_fill<int32_t>(int32_t*, int32_t, int64_t, hipStream_t);
+template void launch_fill<uint64_t>(uint64_t*, uint64_t, int64_t, hipStream_t);
+template void launch_fill<int64_t>(int64_t*, int64_t, int64_t, hipStream_t);
+
+// ---- block scan ---------------------------------------------------------------
+// Exclusive scan of one value per thread over a 256-thread block: wave-level
+// inclusive scan with shuffles, wave totals through LDS.
+
+template <typename T>
+__device__ inline T wave_incl_scan(T x)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ inline T block_excl_scan(T v, T* lds, T* total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    T x = wave_incl_scan(v);
+    if (lane == kWave - 1) lds[wid] = x;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        T s = lds[w];
+        before += (w < wid) ? s : T(0);
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+template <typename T>
+__device__ inline T block_sum(T v, T* lds)
+{
+    T tot;
+    block_excl_scan(v, lds, &tot);
+    return tot;
+}
+
+// phase 1: sum of every tile
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(const T* __restrict__ in, int64_t n,
+                                                           int64_t* __restrict__ partials)
+{
+    __shared__ T lds[kBlock / kWave];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    T tot = block_sum(s, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = (int64_t)tot;
+}
+
+// phase 2: exclusive scan of the tile sums by one block, starting from
+// *carry_in (device, nullable); *total_dst (nullable) = carry + total.
+__global__ __launch_bounds__(kBlock) void k_scan_partials(int64_t* __restrict__ partials, int64_t nt,
+                                                          const int64_t* carry_in,
+                                                          int64_t* total_dst)
+{
+    __shared__ int64_t lds[kBlock / kWave];
+    int64_t carry = carry_in ? *carry_in : 0;
+    __syncthreads();
+    for (int64_t b = 0; b < nt; b += kScanTile) {
+        int64_t base = b + (int64_t)threadIdx.x * kScanItems;
+        int64_t v[kScanItems];
+        int64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = (base + k < nt) ? partials[base + k] : 0;
+            s += v[k];
+        }
+        int64_t tot;
+        int64_t ex = block_excl_scan(s, lds, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < nt) partials[base + k] = ex;
+            ex += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_dst) *total_dst = carry;
+}
+
+// phase 3: scan inside every tile plus its offset
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const T* in, T* out, int64_t n,
+                                                       const int64_t* __restrict__ partials,
+                                                       int write_total)
+{
+    __shared__ T lds[kBlock / kWave];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : T(0);
+        s += v[k];
+    }
+    T tot;
+    T ex = block_excl_scan(s, lds, &tot) + (T)partials[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = ex;
+}
+
+template <typename T>
+void launch_scan(const T* in, T* out, int64_t n, bool write_total, int64_t* total_dst,
+                 const int64_t* carry_in, int64_t* partials, hipStream_t st)
+{
+    int64_t nt = ceil_div(n > 0 ? n : 1, kScanTile);
+    hipLaunchKernelGGL(k_scan_tile_sums<T>, dim3((unsigned)nt), dim3(kBlock), 0, st, in, n,
+                       partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, st, partials, nt, carry_in,
+                       total_dst);
+    hipLaunchKernelGGL(k_scan_tiles<T>, dim3((unsigned)nt), dim3(kBlock), 0, st, in, out, n,
+                       (const int64_t*)partials, write_total ? 1 : 0);
+}
+void launch_scan_partials(int64_t* partials, int64_t nt, const int64_t* carry_in,
+                          int64_t* total_dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, st, partials, nt, carry_in,
+                       total_dst);
+}
+
+template void launch_scan<int32_t>(const int32_t*, int32_t*, int64_t, bool, int64_t*,
+                                   const int64_t*, int64_t*, hipStream_t);
+template void launch_scan<uint64_t>(const uint64_t*, uint64_t*, int64_t, bool, int64_t*,
+                                    const int64_t*, int64_t*, hipStream_t);
+
+// ---- workspace ----------------------------------------------------------------
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Workspace* ws)
+{
+    const int64_t n = p->n_clusters, nb = p->n_bins;
+    int64_t scan_n = n > nb + 1 ? n : nb + 1;
+    if (start_cap + 1 > scan_n) scan_n = start_cap + 1;
+    int64_t max_tiles = ceil_div(scan_n, kScanTile) + 1;
+    char* b = (char*)base;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return b ? (void*)(b + at) : nullptr;
+    };
+    ws->status = (tpc_status*)take(sizeof(tpc_status));
+    ws->cnt = (int32_t*)take(sizeof(int32_t) * (size_t)(nb + 1));
+    ws->tmp = (int32_t*)take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    ws->gsr = (int32_t*)take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    ws->partials = (int64_t*)take(sizeof(int64_t) * (size_t)max_tiles);
+    ws->hitkey = (uint64_t*)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));
+    ws->toff = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 2));
+    ws->bytes = o;
+    return true;
+}
+
+}  // namespace tpc
+
+// ---- C ABI: context, status --------------------------------------------------
+
+extern "C" {
+
+int tpc_context_create(tpc_context** out, int device)
+{
+    if (!out) return TPC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev)
+        return TPC_ERR_INVALID_ARG;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TPC_ERR_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TPC_ERR_UNSUPPORTED;
+    tpc_context* c = new (std::nothrow) tpc_context();
+    if (!c) return TPC_ERR_HIP;
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    c->graph_exec = nullptr;
+    c->graph_key = 0;
+    c->graph_valid = false;
+    *out = c;
+    return TPC_OK;
+}
+
+int tpc_context_destroy(tpc_context* ctx)
+{
+    if (!ctx) return TPC_ERR_INVALID_ARG;
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    delete ctx;
+    return TPC_OK;
+}
+
+static int check_problem(const tpc_problem* p)
+{
+    if (!p || p->n_sectors <= 0 || p->n_rows < 3 || p->n_rows > 255 || p->n_clusters < 0 ||
+        p->n_clusters >= (int64_t(1) << 31) - 1 || p->n_bins <= 0 ||
+        p->n_bins >= (int64_t(1) << 31) - 1 || !p->h_sectors || !p->d_sectors || !p->d_row_x)
+        return TPC_ERR_INVALID_ARG;
+    int64_t prev_end = 0, bins = 0;
+    for (int s = 0; s < p->n_sectors; ++s) {
+        const tpc_sector& q = p->h_sectors[s];
+        if (q.begin != prev_end || q.end < q.begin || q.nby <= 0 || q.nbz <= 0 ||
+            q.bin_base != bins || !(q.inv_by > 0.0f) || !(q.inv_bz > 0.0f))
+            return TPC_ERR_INVALID_ARG;
+        bins += (int64_t)p->n_rows * q.nby * q.nbz;
+        prev_end = q.end;
+    }
+    if (prev_end != p->n_clusters || bins != p->n_bins) return TPC_ERR_INVALID_ARG;
+    return TPC_OK;
+}
+
+int tpc_check_problem(const tpc_problem* p) { return check_problem(p); }
+
+int tpc_workspace_size(const tpc_problem* h_prob, int64_t start_capacity, size_t* h_bytes)
+{
+    if (!h_bytes || start_capacity < 0) return TPC_ERR_INVALID_ARG;
+    int e = check_problem(h_prob);
+    if (e) return e;
+    tpc::Workspace ws;
+    tpc::layout_workspace(h_prob, start_capacity, nullptr, &ws);
+    *h_bytes = ws.bytes;
+    return TPC_OK;
+}
+
+int tpc_get_status(const void* d_ws, tpc_status* h_out, void* stream)
+{
+    if (!d_ws || !h_out) return TPC_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(h_out, d_ws, sizeof(tpc_status), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return TPC_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return TPC_ERR_HIP;
+    return TPC_OK;
+}
+
+const char* tpc_status_string(int code)
+{
+    switch (code) {
+    case TPC_OK: return "ok";
+    case TPC_ERR_INVALID_ARG: return "invalid argument";
+    case TPC_ERR_CAPACITY: return "output capacity exceeded";
+    case TPC_ERR_HIP: return "HIP runtime error";
+    case TPC_ERR_UNSUPPORTED: return "unsupported device or feature";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+"""GPU refit and adjoint against the float64 oracle, through the C ABI.
+
+Forward: track parameters relative 1e-4 of max(|p|, floor, sigma) (a few
+tracks up to the float filter's own rounding, 1e-3), chi2 relative 1e-4.
+Adjoint: against float64 central differences of the oracle refit, relative
+1e-3 per gradient block (hit y, hit z, theta), plus exact chain-rule
+identities of the calibration model at full size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import ctx
+from paper_1905_05515_amd import api
+from paper_1905_05515_amd.autograd import refit_chi2
+
+pytestmark = pytest.mark.gpu
+FLOOR = np.array([1.0, 1.0, 0.01, 0.01, 0.1])
+
+
+def _hits(rs, dev="cuda"):
+    return api.TrackHits(torch.as_tensor(rs.trk_off).to(dev), torch.as_tensor(rs.row).to(dev),
+                         torch.as_tensor(rs.y).to(dev), torch.as_tensor(rs.z).to(dev))
+
+
+def _subset(rs, idx):
+    off = rs.trk_off
+    parts = [np.arange(off[i], off[i + 1]) for i in idx]
+    sel = np.concatenate(parts)
+    new_off = np.zeros(len(idx) + 1, np.int32)
+    new_off[1:] = np.cumsum([p.shape[0] for p in parts])
+    return synth.RefitSet(new_off, rs.row[sel], rs.y[sel], rs.z[sel], rs.row_x, rs.theta_true,
+                          rs.theta_eval, {}, {})
+
+
+def _fwd(rs):
+    h = _hits(rs)
+    rx = torch.as_tensor(rs.row_x).cuda()
+    th = torch.as_tensor(rs.theta_eval).cuda()
+    out = api.refit(ctx(), h, rx, synth.default_params(), th)
+    return h, rx, th, out
+
+
+def _par_errors(par32, cov64, par64):
+    sig = np.sqrt(cov64[:, [0, 2, 5, 9, 14]])
+    scale = np.maximum(np.maximum(np.abs(par64), FLOOR), sig)
+    return (np.abs(par32.astype(np.float64) - par64) / scale).max(1)
+
+
+def test_refit_forward_matches_fp64():
+    rs = synth.make_config5(n_tracks=3000)
+    _, _, _, out = _fwd(rs)
+    o = oracle.refit(rs.trk_off, rs.row, rs.y, rs.z, rs.row_x, synth.default_params(),
+                     rs.theta_eval.astype(np.float64), fp64=True)
+    st = out["status"].cpu().numpy()
+    assert np.array_equal(st, o["status"])
+    ok = st == 0
+    err = _par_errors(out["par"].cpu().numpy()[ok], o["cov"][ok], o["par"][ok])
+    assert np.mean(err > 1e-4) < 0.02 and err.max() < 1e-3, (np.mean(err > 1e-4), err.max())
+    c32 = out["chi2"].cpu().numpy()[ok]
+    assert np.allclose(c32, o["chi2"][ok], rtol=1e-4, atol=1e-3)
+
+
+def _block_ok(g, ref, tol=1e-3):
+    return np.linalg.norm(g - ref) <= tol * np.linalg.norm(ref)
+
+
+def test_adjoint_matches_fp64_central_differences():
+    rs = synth.make_config5(n_tracks=400)
+    sub = _subset(rs, np.arange(0, 400, 8))
+    h, rx, th, out = _fwd(sub)
+    g = torch.linspace(0.5, 1.5, sub.n_tracks, device="cuda")
+    gy, gz, gt = api.refit_adjoint(ctx(), h, rx, synth.default_params(), th, out, g)
+    fy, fz, ft = oracle.refit_fd_grad(sub.trk_off, sub.row, sub.y, sub.z, sub.row_x,
+                                      synth.default_params(), sub.theta_eval.astype(np.float64),
+                                      g.cpu().numpy().astype(np.float64))
+    gy, gz, gt = (x.cpu().numpy().astype(np.float64) for x in (gy, gz, gt))
+    assert _block_ok(gy, fy) and _block_ok(gz, fz) and _block_ok(gt, ft), (
+        np.linalg.norm(gy - fy) / np.linalg.norm(fy), np.linalg.norm(gz - fz) / np.linalg.norm(fz),
+        np.linalg.norm(gt - ft) / np.linalg.norm(ft))
+    # component-wise with a floor of 1e-3 of the block's largest entry
+    for a, b in ((gy, fy), (gz, fz), (gt, ft)):
+        assert np.all(np.abs(a - b) <= 1e-3 * np.abs(b).max() + 3e-3 * np.abs(b))
+
+
+def test_autograd_function_uses_the_adjoint():
+    rs = synth.make_config5(n_tracks=64)
+    h = _hits(rs)
+    rx = torch.as_tensor(rs.row_x).cuda()
+    y = h.y.clone().requires_grad_(True)
+    z = h.z.clone().requires_grad_(True)
+    th = torch.as_tensor(rs.theta_eval).cuda().requires_grad_(True)
+    chi2, status = refit_chi2(ctx(), h, rx, synth.default_params(), y, z, th)
+    w = torch.arange(chi2.shape[0], device="cuda", dtype=torch.float32) / 64.0
+    (chi2 * w).sum().backward()
+    out = api.refit(ctx(), h, rx, synth.default_params(), th.detach())
+    gy, gz, gt = api.refit_adjoint(ctx(), h, rx, synth.default_params(), th.detach(), out, w)
+    assert torch.equal(y.grad, gy) and torch.equal(z.grad, gz) and torch.equal(th.grad, gt)
+    assert torch.equal(chi2, out["chi2"])
+
+
+@pytest.mark.timeout(900)
+def test_full_size_refit_and_adjoint_properties():
+    """1M tracks at the benchmark's launch configuration: sampled tracks
+    against the float64 oracle, and exact identities of the calibration
+    model over all hits (z_raw enters only through the drift length)."""
+    rs = synth.make_config5()
+    print(f"case c5 tracks={rs.n_tracks} hits={rs.n_hits}", flush=True)
+    h, rx, th, out = _fwd(rs)
+    g = torch.ones(rs.n_tracks, device="cuda")
+    gy, gz, gt = api.refit_adjoint(ctx(), h, rx, synth.default_params(), th, out, g)
+    st = out["status"].cpu().numpy()
+    assert np.mean(st == 0) > 0.999
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(rs.n_tracks, 2000, replace=False))
+    sub = _subset(rs, idx)
+    o = oracle.refit(sub.trk_off, sub.row, sub.y, sub.z, sub.row_x, synth.default_params(),
+                     rs.theta_eval.astype(np.float64), fp64=True)
+    ok = (o["status"] == 0) & (st[idx] == 0)
+    err = _par_errors(out["par"].cpu().numpy()[idx][ok], o["cov"][ok], o["par"][ok])
+    assert np.mean(err > 1e-4) < 0.02 and err.max() < 1e-3
+    assert np.allclose(out["chi2"].cpu().numpy()[idx][ok], o["chi2"][ok], rtol=1e-4, atol=1e-3)
+    cm = api.CALIB_MODEL
+    vd = float(np.float32(cm["vd"]))
+    gz64 = gz.double()
+    gt64 = gt.double().cpu().numpy()
+    sum_gz = float(gz64.sum())
+    assert abs(gt64[1] - vd * sum_gz) <= 2e-3 * float((vd * gz64.abs()).sum())
+    d_raw = float(np.float32(cm["drift_len"])) - h.z.double()
+    th64 = rs.theta_eval.astype(np.float64)
+    expect = float((gz64 * (d_raw - vd * th64[1]) / (-(1.0 + th64[0]))).sum())
+    assert abs(gt64[0] - expect) <= 2e-3 * float((gz64 * d_raw).abs().sum())
+    # deterministic: a second adjoint pass gives the same bits
+    gy2, gz2, gt2 = api.refit_adjoint(ctx(), h, rx, synth.default_params(), th, out, g)
+    assert torch.equal(gy, gy2) and torch.equal(gz, gz2) and torch.equal(gt, gt2)

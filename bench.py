@@ -1,0 +1,313 @@
+"""Benchmark of the TPC track-finding hot path on one MI355X.
+
+Workload: one central Pb-Pb-like event (36 sectors, 8000 primaries + 10%
+secondaries + 5% noise, ~1.32M float32 clusters, seed 2002), all inputs
+resident in HBM.  One step = the whole hot path over the event:
+  grid -> neighbours -> cleaning/starts -> tracklets -> selection
+  (tpc_track_batch, one HIP graph replay)
+  -> calibrated refit of the found tracks -> adjoint (dchi2 / d(hits, theta)).
+value = clusters of the event / step time (clusters/s).
+
+Also reported (same JSON line): per-kernel durations from HIP events over a
+second timed region (eager launches, same step), the roofline of the
+dominant kernel, the refit+adjoint throughput on 1M tracks (tracks/s), and
+the oracle timed on the host (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector ALU: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T simple ops/s for
+# unpacked, uncontracted float arithmetic (the tracklet kernel's mix); the
+# published 157.3 TFLOP/s counts packed FMA as 4 flops per lane and cycle.
+ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+ALU_PEAK_FMA_TFLOPS = 157.3
+# algorithmic float operations per call, counted from the formulas
+# (division and square root count as one operation each)
+FLOPS_PROPAGATE = 179
+FLOPS_UPDATE = 130
+FLOPS_CHI2 = 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--refit-tracks", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-refit-bench", action="store_true")
+    ap.add_argument("--occupancy", type=float, default=2.0)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build "
+              "runs on a single MI355X and has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_05515_amd import api
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    ev = synth.make_config2()
+    prm = synth.default_params()
+    log(f"[bench] event: {ev.n_clusters} clusters, generated in {time.time() - t0:.1f}s")
+    ctx = api.Context(0)
+    stream = torch.cuda.Stream()      # default priority; graphs need a non-default stream
+    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
+                       occupancy=args.occupancy, sector_side=ev.sector_side)
+    th = torch.as_tensor(synth.make_config5(n_tracks=1).theta_eval).to(dev)
+    hits = api.found_track_hits(e)
+    gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
+    bufs = {"fwd": None, "adj": {}}
+
+    def step(graph=True):
+        api.track_batch(ctx, e, mode="staged", use_graph=graph, stream=stream)
+        bufs["fwd"] = api.refit(ctx, hits, e.t["row_x"], prm, th, stream=stream, out=bufs["fwd"])
+        api.refit_adjoint(ctx, hits, e.t["row_x"], prm, th, bufs["fwd"], gchi2, stream=stream,
+                          out=bufs["adj"])
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        # timed region 1: graph replay of the tracking + refit + adjoint
+        t_start = time.perf_counter()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        gpu_ms = ev0.elapsed_time(ev1)
+    st = api.get_status(e, stream)
+    ms_per_step = gpu_ms / args.steps
+    log(f"[bench] step {ms_per_step:.3f} ms (wall {1e3 * wall / args.steps:.3f} ms), "
+        f"tracks {st['n_tracks']}, starts {st['n_starts']}")
+
+    # timed region 2: the same step with eager launches and per-kernel events
+    with torch.cuda.stream(stream):
+        step(graph=False)
+        torch.cuda.synchronize()
+        api.timing_enable(ctx, True)
+        for _ in range(args.steps):
+            step(graph=False)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    kernels = {k: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / args.steps}
+               for k, (n, ms) in kt.items()}
+    eager_ms = sum(v["ms_per_step"] for v in kernels.values())
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        log(f"[bench]   {k:28s} {v['avg_ms'] * 1e3:9.1f} us x {v['launches'] // args.steps}")
+
+    n_cl = ev.n_clusters
+    n_hits_trk = int(st["n_track_hits"])
+    roof = roofline(dom, kernels[dom]["avg_ms"], st, n_cl, n_hits_trk)
+
+    extra = {}
+    if not args.no_refit_bench:
+        extra["refit_adjoint"] = refit_bench(args, api, synth, ctx, stream, prm, dev)
+    cpu = None if args.no_cpu else cpu_baseline(ev, prm, args)
+
+    value = n_cl / (ms_per_step * 1e-3)
+    line = {
+        "metric": "TPC clusters/s tracked on 1 MI355X (batched vs per-sector); refit+adjoint tracks/s",
+        "value": value,
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "central Pb-Pb-like event: 36 sectors, 8000 primaries + 10% secondaries "
+                        "+ 5% noise, float32 SoA clusters (seed 2002); step = grid, neighbours, "
+                        "cleaning, starts, tracklets, selection (one graph replay) + calibrated "
+                        "refit and adjoint of the found tracks",
+            "clusters": n_cl,
+            "tracks_found": int(st["n_tracks"]),
+            "track_hits": n_hits_trk,
+            "launch_form": "staged stages over all sectors, HIP graph",
+            "parallelism": "single GPU",
+        },
+        "roofline": roof,
+        "kernels": {k: {"avg_us": round(v["avg_ms"] * 1e3, 2),
+                        "launches_per_step": v["launches"] // args.steps}
+                    for k, v in kernels.items()},
+        "eager_kernel_ms_per_step": eager_ms,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def roofline(name, avg_ms, st, n_cl, n_trk_hits):
+    """Algorithmic traffic (bytes) or operations per launch of a kernel."""
+    sec = avg_ms * 1e-3
+    bytes_per_cluster = {
+        # reads row, y, z (9 B); atomics on the bin counts
+        "k_grid_count": 9, "k_grid_scatter": 13, "k_grid_rank": 33,
+        # reads y, z, gsr (12 B) writes up0, down0 (8 B)
+        "k_neighbours": 20,
+        # reads up0, down0, idg (12 B), writes up, down (8 B)
+        "k_clean": 20,
+    }
+    if name in bytes_per_cluster:
+        b = bytes_per_cluster[name] * n_cl
+        gbs = b / sec / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                "units_per_launch": n_cl, "unit_name": "cluster",
+                "algorithmic_bytes_per_unit": bytes_per_cluster[name]}
+    if name == "k_tracklets":
+        fl = FLOPS_PROPAGATE * st["n_propagations"] + FLOPS_UPDATE * st["n_updates"]
+        tf = fl / sec / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": tf, "peak": ALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": tf / ALU_PEAK_TFLOPS, "traffic": None,
+                "flops_per_launch": fl, "propagations": st["n_propagations"],
+                "updates": st["n_updates"], "candidates": st["n_candidates"]}
+    if name in ("k_refit_fwd", "k_refit_adj"):
+        per_hit = 4 + 9 + (80 if name == "k_refit_fwd" else 88)
+        b = per_hit * n_trk_hits
+        gbs = b / sec / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                "units_per_launch": n_trk_hits, "unit_name": "track hit",
+                "algorithmic_bytes_per_unit": per_hit}
+    return {"kernel": name, "bound": "unknown", "achieved": None, "peak": None, "unit": None,
+            "frac": None, "traffic": None}
+
+
+def refit_bench(args, api, synth, ctx, stream, prm, dev):
+    import torch
+    t0 = time.time()
+    rs = synth.make_config5(n_tracks=args.refit_tracks)
+    log(f"[bench] refit set: {rs.n_tracks} tracks, {rs.n_hits} hits, generated in "
+        f"{time.time() - t0:.1f}s")
+    h = api.TrackHits(torch.as_tensor(rs.trk_off).to(dev), torch.as_tensor(rs.row).to(dev),
+                      torch.as_tensor(rs.y).to(dev), torch.as_tensor(rs.z).to(dev))
+    rx = torch.as_tensor(rs.row_x).to(dev)
+    th = torch.as_tensor(rs.theta_eval).to(dev)
+    g = torch.ones(rs.n_tracks, dtype=torch.float32, device=dev)
+    steps = max(3, args.steps // 4)
+    adj = {}
+    with torch.cuda.stream(stream):
+        out = api.refit(ctx, h, rx, prm, th, stream=stream)
+        api.refit_adjoint(ctx, h, rx, prm, th, out, g, stream=stream, out=adj)
+        torch.cuda.synchronize()
+        api.timing_enable(ctx, True)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            out = api.refit(ctx, h, rx, prm, th, stream=stream, out=out)
+            api.refit_adjoint(ctx, h, rx, prm, th, out, g, stream=stream, out=adj)
+        b.record(stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    ms = a.elapsed_time(b) / steps
+    kern = {k: round(ms_ / n * 1e3, 1) for k, (n, ms_) in kt.items()}
+    nh = rs.n_hits
+    fwd_ms = kt["k_refit_fwd"][1] / kt["k_refit_fwd"][0]
+    adj_ms = kt["k_refit_adj"][1] / kt["k_refit_adj"][0]
+    fwd_b = nh * (9 + 80)
+    adj_b = nh * (9 + 80 + 8)
+    log(f"[bench] refit+adjoint {ms:.3f} ms per pass, {rs.n_tracks / (ms * 1e-3):.3e} tracks/s")
+    return {
+        "workload": "1M truth track segments of 40-152 consecutive-row hits (seed 5005), "
+                    "calibrated refit (16 parameters) + adjoint, float32",
+        "tracks": rs.n_tracks, "hits": nh,
+        "tracks_per_s": rs.n_tracks / (ms * 1e-3),
+        "ms_per_pass": ms,
+        "kernels_us": kern,
+        "roofline_fwd": {"bound": "hbm", "achieved": fwd_b / (fwd_ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": fwd_b / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_hit": 89},
+        "roofline_adj": {"bound": "hbm", "achieved": adj_b / (adj_ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": adj_b / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_hit": 97},
+    }
+
+
+def cpu_baseline(ev, prm, args):
+    """The oracle (plain single-threaded C) on the host: the whole tracking
+    chain over the event, the float refit of the found tracks, and the
+    float64 central-difference gradient on a sample of them, scaled to all
+    tracks."""
+    import numpy as np
+
+    import oracle
+    from paper_1905_05515_amd.layout import grid_layout
+    tab, nb = grid_layout(ev.sector_offsets, ev.sector_range, occupancy=args.occupancy,
+                          sides=ev.sector_side)
+    t0 = time.perf_counter()
+    res = oracle.track_event(ev.row, ev.y, ev.z, tab, nb, ev.row_x, prm)
+    t_track = time.perf_counter() - t0
+    trk = res["tracks"]
+    off, ids = trk["trk_off"], trk["trk_hits"]
+    n_trk = off.shape[0] - 1
+    sec = np.searchsorted(ev.sector_offsets, ids[off[:-1]], side="right") - 1
+    side = np.where(ev.sector_side[sec] < 0, -1, 1).astype(np.int8)
+    th = synth_theta()
+    t0 = time.perf_counter()
+    oracle.refit(off, ev.row[ids], ev.y[ids], ev.z[ids], ev.row_x, prm, th, side=side)
+    t_refit = time.perf_counter() - t0
+    k = min(200, n_trk)
+    sub = np.arange(k)
+    so = off[:k + 1]
+    sel = ids[:so[-1]]
+    t0 = time.perf_counter()
+    oracle.refit_fd_grad(so, ev.row[sel], ev.y[sel], ev.z[sel], ev.row_x, prm,
+                         th.astype(np.float64), np.ones(k), side=side[sub])
+    t_grad = (time.perf_counter() - t0) * n_trk / max(k, 1)
+    total = t_track + t_refit + t_grad
+    log(f"[bench] oracle: tracking {t_track:.2f}s, refit {t_refit:.2f}s, "
+        f"gradient {t_grad:.1f}s (from {k} tracks)")
+    return {"value": ev.n_clusters / total, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole event tracked ({ev.n_clusters} clusters, {n_trk} tracks) and "
+                      f"refit; float64 central-difference gradient timed on {k} tracks and "
+                      f"scaled to {n_trk}",
+            "tracking_only_clusters_per_s": ev.n_clusters / t_track,
+            "seconds": {"tracking": t_track, "refit": t_refit, "gradient_scaled": t_grad}}
+
+
+def synth_theta():
+    import numpy as np
+    import synth
+    return np.asarray(synth.make_config5(n_tracks=1).theta_eval, np.float32)
+
+
+if __name__ == "__main__":
+    main()

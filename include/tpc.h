@@ -84,13 +84,18 @@ typedef struct tpc_params {
  * [begin, end), sector-local coordinates; its grid has n_rows * nbz * nby
  * bins starting at global bin index bin_base, bin (row, iz, iy) at
  * bin_base + (row * nbz + iz) * nby + iy, with
- * iy = clamp((y - y0) * inv_by, 0, nby - 1) truncated (likewise iz). */
+ * iy = clamp((y - y0) * inv_by, 0, nby - 1) truncated (likewise iz); one
+ * more bin, bin_base + n_rows * nbz * nby, holds the clusters whose row is
+ * >= n_rows (they take no part in tracking).  The sector thus owns
+ * n_rows * nbz * nby + 1 bins and exactly the grid positions [begin, end).
+ * side: -1 for a sector on the z < 0 side, otherwise +1 (used by the
+ * refit's drift-length model only). */
 typedef struct tpc_sector {
     float y0, z0;
     float inv_by, inv_bz;
     int32_t nby, nbz;
     int32_t bin_base;
-    int32_t pad_;
+    int32_t side;
     int64_t begin, end;
 } tpc_sector;
 
@@ -107,7 +112,7 @@ typedef struct tpc_problem {
 
 /* Clusters, structure of arrays, grouped by sector (any order inside). */
 typedef struct tpc_clusters {
-    const uint8_t* row;    /* pad row; clusters with row >= n_rows are dropped */
+    const uint8_t* row;    /* pad row; rows >= n_rows go to the invalid-row bin */
     const float* y;        /* sector-local y [cm] */
     const float* z;        /* z, or drift time scaled to z [cm] */
 } tpc_clusters;
@@ -140,7 +145,8 @@ typedef struct tpc_starts {
 
 /* Tracklets, one per chain start, in start order.
  * start[capacity]: grid position of the chain start;
- * hits[capacity * n_rows]: grid position of the hit on each row, -1 none;
+ * hits[n_rows * capacity]: hits[r * capacity + t] is the grid position of
+ * the hit of tracklet t on row r, -1 none;
  * par[capacity * 5] (y, z, sin(phi), tan(lambda), q/pT) and
  * cov[capacity * 15] (lower triangle, row by row) at the innermost hit,
  * row_inner its row; chi2 the sum of the inward pass. */
@@ -156,24 +162,31 @@ typedef struct tpc_tracklets {
 } tpc_tracklets;
 
 /* Tracks (CSR): off[n_tracks + 1], hits[off[k]..off[k+1]) cluster ids in
- * ascending row, tracklet[k] the tracklet it came from (ascending). */
+ * ascending row, tracklet[k] the tracklet it came from (ascending), side[k]
+ * (nullable) the z side of its sector. */
 typedef struct tpc_tracks {
     int32_t* off;
     int32_t* hits;
     int32_t* tracklet;
+    int8_t* side;
     int64_t capacity;      /* tracks; off needs capacity + 1 entries */
     int64_t hit_capacity;
 } tpc_tracks;
 
 /* Device status block at the start of the workspace. */
 typedef struct tpc_status {
-    int64_t n_grid;        /* clusters placed in the grid */
-    int64_t n_bad_rows;    /* clusters dropped for row >= n_rows */
+    int64_t n_grid;        /* clusters placed in the grid (all of them) */
+    int64_t n_bad_rows;    /* clusters with row >= n_rows (invalid-row bins) */
     int64_t n_starts;      /* chain starts found (may exceed capacity) */
     int64_t n_tracks;      /* tracks (may exceed capacity) */
     int64_t n_track_hits;  /* hits of all tracks (may exceed capacity) */
     int32_t overflow;      /* bit 0 starts, bit 1 tracks, bit 2 track hits */
     int32_t pad_;
+    /* work of the tracklet construction: transports, Kalman updates and
+     * predicted-chi2 evaluations of search candidates */
+    int64_t n_propagations;
+    int64_t n_updates;
+    int64_t n_candidates;
 } tpc_status;
 
 typedef struct tpc_context tpc_context;
@@ -250,14 +263,22 @@ typedef struct tpc_calib_model {
     float drift_len, vd, tan_half, u_centre, u_scale;
 } tpc_calib_model;
 
-/* Found tracks' hits, CSR: hits of track k are off[k]..off[k+1], rows
- * increasing; side[k] = +1/-1 (NULL: all +1). */
+/* Found tracks' hits, CSR: the hits of track k are the entries
+ * off[k]..off[k+1] (rows increasing).  Entry j is cluster idx[j] of the
+ * arrays row/y/z, or cluster j when idx is NULL (so the output of
+ * tpc_select_tracks refits directly).  side[k] = +1/-1 (NULL: all +1).
+ * The number of tracks is n_tracks, or min(*d_count, n_tracks) when the
+ * device pointer d_count is given (e.g. the status block's n_tracks), which
+ * keeps the call free of host synchronisation.  Per-hit outputs are indexed
+ * by entry j, n_hits entries. */
 typedef struct tpc_track_hits {
     const int32_t* off;
+    const int32_t* idx;
     const uint8_t* row;
     const float* y;
     const float* z;
     const int8_t* side;
+    const int64_t* d_count;
     int64_t n_tracks;
     int64_t n_hits;
 } tpc_track_hits;
@@ -266,7 +287,8 @@ typedef struct tpc_track_hits {
  * and 2, filter outwards through hits 1..n-1.  Outputs per track: par[5],
  * cov[15] at the last hit, chi2, status (0 ok, 1 fewer than 3 hits, 2
  * |sin(phi)| stop, 3 a hit row >= n_rows).  The CSR must be well formed
- * (off increasing, off[n_tracks] = n_hits).  checkpoints (nullable) [n_hits * 20]: state and
+ * (off increasing, off[n_tracks] = n_hits); checkpoints must be 16-byte
+ * aligned.  checkpoints (nullable) [n_hits * 20]: state and
  * covariance after each hit but the last, for tpc_refit_adjoint. */
 int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
               const tpc_params* h_params, const tpc_calib_model* h_model,
@@ -287,6 +309,17 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                       const float* checkpoints, const int32_t* status,
                       const float* grad_chi2, float* grad_y, float* grad_z,
                       float* grad_theta, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Per-kernel timing.  While enabled, every kernel the context launches
+ * (outside graph capture) is bracketed by two HIP events on its stream.
+ * tpc_timing_report synchronises on them and returns, per kernel name in
+ * first-launch order, the launch count and the summed duration in ms;
+ * names are static strings of the library.  *h_count receives the number of
+ * distinct kernels (only the first max_kernels are written); the records
+ * are then cleared.  Enabling clears them too. */
+int tpc_timing_enable(tpc_context* ctx, int enable);
+int tpc_timing_report(tpc_context* ctx, int max_kernels, const char** h_names,
+                      int64_t* h_launches, double* h_total_ms, int* h_count);
 
 /* Static description of an error code. */
 const char* tpc_status_string(int code);

@@ -30,7 +30,7 @@ class CalibModel(C.Structure):
 
 SECTOR_DTYPE = np.dtype([
     ("y0", np.float32), ("z0", np.float32), ("inv_by", np.float32), ("inv_bz", np.float32),
-    ("nby", np.int32), ("nbz", np.int32), ("bin_base", np.int32), ("pad", np.int32),
+    ("nby", np.int32), ("nbz", np.int32), ("bin_base", np.int32), ("side", np.int32),
     ("begin", np.int64), ("end", np.int64)])
 
 
@@ -129,6 +129,13 @@ def construct_tracklets(layout, row_x, prm, grid, row, y, z, up, starts, n_rows=
     return dict(hits=hits, nhits=nhits, row_inner=rin, par=par, cov=cov, chi2=chi2)
 
 
+def tracklet_work():
+    """(transports, updates, chi2 evaluations) of the last tracklet construction."""
+    out = np.zeros(3, np.int64)
+    lib().orc_tracklet_work(_p(out))
+    return tuple(int(v) for v in out)
+
+
 def tracklet_replay64(row_x, prm, y, z, start_row, hits_by_row, n_rows=152):
     L = lib()
     P = params(prm)
@@ -165,6 +172,7 @@ def track_event(row, y, z, layout, n_bins, row_x, prm, n_rows=152, brute=False):
     up, down = clean_links(up0, down0)
     starts = select_starts(up, down)
     trl = construct_tracklets(layout, row_x, prm, grid, row, y, z, up, starts, n_rows, brute)
+    trl["work"] = tracklet_work()
     trk = select_tracks(n, prm, trl, starts, n_rows)
     return dict(grid=grid, up0=up0, down0=down0, up=up, down=down, starts=starts,
                 tracklets=trl, tracks=trk)

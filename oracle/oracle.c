@@ -64,8 +64,10 @@ static int bin_of(float v, float v0, float inv, int nb)
     return (int)f;
 }
 
-static int global_bin(const orc_sector* s, int row, float y, float z)
+/* Clusters with row >= n_rows go to the sector's last bin, after its rows. */
+static int global_bin(const orc_sector* s, int n_rows, int row, float y, float z)
 {
+    if (row >= n_rows) return s->bin_base + n_rows * s->nbz * s->nby;
     int iy = bin_of(y, s->y0, s->inv_by, s->nby);
     int iz = bin_of(z, s->z0, s->inv_bz, s->nbz);
     return s->bin_base + (row * s->nbz + iz) * s->nby + iy;
@@ -86,7 +88,7 @@ int orc_build_grid(int n_sec, const orc_sector* sec, int n_rows,
      * ascending id order */
     for (int s = 0; s < n_sec; s++)
         for (int64_t i = sec[s].begin; i < sec[s].end; i++)
-            if (row[i] < n_rows) count[global_bin(&sec[s], row[i], y[i], z[i])]++;
+            count[global_bin(&sec[s], n_rows, row[i], y[i], z[i])]++;
     int acc = 0;
     for (int g = 0; g < n_bins; g++) {
         bin_start[g] = acc;
@@ -96,8 +98,7 @@ int orc_build_grid(int n_sec, const orc_sector* sec, int n_rows,
     bin_start[n_bins] = acc;
     for (int s = 0; s < n_sec; s++)
         for (int64_t i = sec[s].begin; i < sec[s].end; i++) {
-            if (row[i] >= n_rows) continue;
-            int pos = fill[global_bin(&sec[s], row[i], y[i], z[i])]++;
+            int pos = fill[global_bin(&sec[s], n_rows, row[i], y[i], z[i])]++;
             yg[pos] = y[i];
             zg[pos] = z[i];
             idg[pos] = (int)i;
@@ -257,6 +258,27 @@ typedef struct {
     int brute;
 } search_ctx;
 
+/* work counters of the last orc_construct_tracklets call: transports
+ * attempted, Kalman updates, predicted-chi2 evaluations */
+static int64_t g_work[3];
+
+void orc_tracklet_work(int64_t* out3)
+{
+    for (int i = 0; i < 3; i++) out3[i] = g_work[i];
+}
+
+static int prop_counted(float* p, float* C, float dx, float curv, float s_max)
+{
+    g_work[0]++;
+    return propagate_f(p, C, dx, curv, s_max);
+}
+
+static float update_counted(float* p, float* C, float my, float mz, float sy2, float sz2)
+{
+    g_work[1]++;
+    return update_f(p, C, my, mz, sy2, sz2);
+}
+
 static int search_row(const search_ctx* cx, int r, const float* p, const float* C)
 {
     const orc_params* prm = cx->prm;
@@ -278,6 +300,7 @@ static int search_row(const search_ctx* cx, int r, const float* p, const float* 
     for (int iz = iz0; iz <= iz1; iz++) {
         int g = s->bin_base + (r * s->nbz + iz) * s->nby;
         for (int pc = cx->bin_start[g + iy0]; pc < cx->bin_start[g + iy1 + 1]; pc++) {
+            g_work[2]++;
             float c2 = chi2_pred_f(p, C, cx->yg[pc], cx->zg[pc], prm->sigma_y2, prm->sigma_z2);
             if (!(c2 <= prm->chi2_max)) continue;
             int id = cx->idg[pc];
@@ -300,6 +323,7 @@ void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
                              float* par, float* cov, float* chi2)
 {
     const float sy2 = prm->sigma_y2, sz2 = prm->sigma_z2;
+    g_work[0] = g_work[1] = g_work[2] = 0;
     for (int64_t t = 0; t < n_starts; t++) {
         int* th = hits + t * n_rows;
         for (int r = 0; r < n_rows; r++) th[r] = -1;
@@ -319,11 +343,11 @@ void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
         int ok = 1;
         for (int h = h1; h >= 0; h = up[h]) {
             int r = row[h];
-            if (!propagate_f(p, C, row_x[r] - row_x[cur], prm->curv, prm->s_max)) {
+            if (!prop_counted(p, C, row_x[r] - row_x[cur], prm->curv, prm->s_max)) {
                 ok = 0;
                 break;
             }
-            update_f(p, C, y[h], z[h], sy2, sz2);
+            update_counted(p, C, y[h], z[h], sy2, sz2);
             th[r] = h;
             cur = last = r;
             memcpy(plast, p, sizeof plast);
@@ -332,10 +356,10 @@ void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
         if (ok) {
             int miss = 0;
             for (int r = cur + 1; r < n_rows; r++) {
-                if (!propagate_f(p, C, row_x[r] - row_x[r - 1], prm->curv, prm->s_max)) break;
+                if (!prop_counted(p, C, row_x[r] - row_x[r - 1], prm->curv, prm->s_max)) break;
                 int c = search_row(&cx, r, p, C);
                 if (c >= 0) {
-                    update_f(p, C, y[c], z[c], sy2, sz2);
+                    update_counted(p, C, y[c], z[c], sy2, sz2);
                     th[r] = c;
                     last = r;
                     memcpy(plast, p, sizeof plast);
@@ -360,7 +384,7 @@ void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
         memcpy(Cin, C, sizeof Cin);
         int rin = last, miss = 0;
         for (int r = last - 1; r >= 0; r--) {
-            if (!propagate_f(p, C, row_x[r] - row_x[r + 1], prm->curv, prm->s_max)) {
+            if (!prop_counted(p, C, row_x[r] - row_x[r + 1], prm->curv, prm->s_max)) {
                 for (int q = r; q >= 0; q--) th[q] = -1;
                 break;
             }
@@ -376,7 +400,7 @@ void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
                 miss = 0;
             }
             if (c >= 0) {
-                csum = csum + update_f(p, C, y[c], z[c], sy2, sz2);
+                csum = csum + update_counted(p, C, y[c], z[c], sy2, sz2);
                 th[r] = c;
                 rin = r;
                 memcpy(pin, p, sizeof pin);

@@ -47,7 +47,7 @@ typedef struct {
     float inv_by, inv_bz;  /* inverse bin widths */
     int nby, nbz;          /* bins per row in y and z */
     int bin_base;          /* index of the sector's first bin */
-    int pad_;
+    int side;              /* z side, not used by the oracle's tracking */
     int64_t begin, end;    /* the sector's clusters: ids [begin, end) */
 } orc_sector;
 
@@ -59,8 +59,9 @@ typedef struct {           /* calibration model of the refit */
 } orc_calib_model;
 
 /* Grid (stable counting sort of each sector's clusters by pad row and
- * (z, y) bin).  Returns the number of clusters placed; clusters with
- * row >= n_rows are left out. */
+ * (z, y) bin).  Each sector has n_rows * nbz * nby bins for its rows and one
+ * last bin for clusters with row >= n_rows.  Returns the number of
+ * clusters placed (all). */
 int orc_build_grid(int n_sec, const orc_sector* sec, int n_rows,
                    const uint8_t* row, const float* y, const float* z,
                    int n_bins, int* bin_start, float* yg, float* zg, int* idg);
@@ -88,6 +89,10 @@ void orc_construct_tracklets(int n_sec, const orc_sector* sec, int n_rows,
                              const int* up, int64_t n_starts, const int* starts,
                              int brute, int* hits, int* nhits, int* row_inner,
                              float* par, float* cov, float* chi2);
+
+/* Work of the last orc_construct_tracklets call: transports attempted,
+ * Kalman updates, predicted-chi2 evaluations. */
+void orc_tracklet_work(int64_t* out3);
 
 /* FP64 replay of a tracklet's fit with its hit list fixed. */
 int orc_tracklet_replay64(int n_rows, const float* row_x, const orc_params* prm,

@@ -47,13 +47,14 @@ class Tracklets(C.Structure):
 
 
 class Tracks(C.Structure):
-    _fields_ = [("off", P), ("hits", P), ("tracklet", P), ("capacity", I64),
+    _fields_ = [("off", P), ("hits", P), ("tracklet", P), ("side", P), ("capacity", I64),
                 ("hit_capacity", I64)]
 
 
 class Status(C.Structure):
     _fields_ = [("n_grid", I64), ("n_bad_rows", I64), ("n_starts", I64), ("n_tracks", I64),
-                ("n_track_hits", I64), ("overflow", I32), ("pad_", I32)]
+                ("n_track_hits", I64), ("overflow", I32), ("pad_", I32),
+                ("n_propagations", I64), ("n_updates", I64), ("n_candidates", I64)]
 
 
 class CalibModel(C.Structure):
@@ -61,8 +62,8 @@ class CalibModel(C.Structure):
 
 
 class TrackHits(C.Structure):
-    _fields_ = [("off", P), ("row", P), ("y", P), ("z", P), ("side", P), ("n_tracks", I64),
-                ("n_hits", I64)]
+    _fields_ = [("off", P), ("idx", P), ("row", P), ("y", P), ("z", P), ("side", P),
+                ("d_count", P), ("n_tracks", I64), ("n_hits", I64)]
 
 
 EXPORTS = {
@@ -86,6 +87,9 @@ EXPORTS = {
                                     C.POINTER(CalibModel), P, P, P, P, P, P, P, P, C.c_size_t,
                                     P]),
     "tpc_status_string": (C.c_char_p, [C.c_int]),
+    "tpc_timing_enable": (C.c_int, [P, C.c_int]),
+    "tpc_timing_report": (C.c_int, [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(I64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int)]),
 }
 
 _lib = None

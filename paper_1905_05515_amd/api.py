@@ -69,11 +69,12 @@ class Event:
 
 def make_event(row, y, z, sector_offsets, sector_range, row_x, prm: dict, device="cuda",
                layout=None, occupancy=2.0, start_capacity=None, track_capacity=None,
-               track_hit_capacity=None) -> Event:
+               track_hit_capacity=None, sector_side=None) -> Event:
     """Copy an event to the device and allocate all outputs."""
     n_rows = int(np.asarray(row_x).shape[0])
     if layout is None:
-        layout = grid_layout(sector_offsets, sector_range, n_rows=n_rows, occupancy=occupancy)
+        layout = grid_layout(sector_offsets, sector_range, n_rows=n_rows, occupancy=occupancy,
+                             sides=sector_side)
     tab, n_bins = layout
     tab = np.ascontiguousarray(tab, dtype=SECTOR_DTYPE)
     n = int(np.asarray(row).shape[0])
@@ -113,6 +114,7 @@ def make_event(row, y, z, sector_offsets, sector_range, row_x, prm: dict, device
     t["trk_off"] = torch.empty(tcap + 1, **i32)
     t["trk_hits"] = torch.empty(hcap, **i32)
     t["trk_tracklet"] = torch.empty(max(tcap, 1), **i32)
+    t["trk_side"] = torch.empty(max(tcap, 1), dtype=torch.int8, device=dev)
     prob = L.Problem()
     prob.n_sectors = tab.shape[0]
     prob.n_rows = n_rows
@@ -160,7 +162,7 @@ def _tracklets(ev):
 def _tracks(ev):
     t = ev.t
     return L.Tracks(_ptr(t["trk_off"]), _ptr(t["trk_hits"]), _ptr(t["trk_tracklet"]),
-                    ev.track_capacity, ev.track_hit_capacity)
+                    _ptr(t["trk_side"]), ev.track_capacity, ev.track_hit_capacity)
 
 
 def build_grid(ctx: Context, ev: Event, stream=None):
@@ -227,7 +229,9 @@ def results(ev: Event, stream=None) -> dict:
         out[k] = cpu(t[k][:n])
     out["starts"] = cpu(t["starts"][:m])
     out["t_start"] = cpu(t["t_start"][:m])
-    out["t_hits"] = cpu(t["t_hits"][:m * ev.n_rows]).reshape(m, ev.n_rows)
+    # [row][tracklet] on the device; [tracklet][row] here
+    out["t_hits"] = np.ascontiguousarray(
+        cpu(t["t_hits"]).reshape(ev.n_rows, ev.start_capacity)[:, :m].T)
     out["t_nhits"] = cpu(t["t_nhits"][:m])
     out["t_rin"] = cpu(t["t_rin"][:m])
     out["t_par"] = cpu(t["t_par"][:m * 5]).reshape(m, 5)
@@ -237,7 +241,40 @@ def results(ev: Event, stream=None) -> dict:
     out["trk_off"] = off
     out["trk_hits"] = cpu(t["trk_hits"][:int(off[-1]) if nt > 0 else 0])
     out["trk_tracklet"] = cpu(t["trk_tracklet"][:nt])
+    out["trk_side"] = cpu(t["trk_side"][:nt])
     return out
+
+
+def status_count_ptr(ev: Event, field_name: str = "n_tracks") -> C.c_void_p:
+    """Device address of a counter of the workspace status block."""
+    off = getattr(L.Status, field_name).offset
+    return C.c_void_p(ev.t["ws"].data_ptr() + off)
+
+
+def found_track_hits(ev: Event) -> "TrackHits":
+    """The tracks of an event as refit input, without a host round trip:
+    the CSR and hit ids the selection wrote, the event's clusters, the
+    tracks' sides, and the device track count of the status block."""
+    t = ev.t
+    return TrackHits(off=t["trk_off"], row=t["row"], y=t["y"], z=t["z"], side=t["trk_side"],
+                     idx=t["trk_hits"], d_count=status_count_ptr(ev),
+                     n_tracks_cap=ev.track_capacity, n_hits_cap=ev.track_hit_capacity)
+
+
+def timing_enable(ctx: Context, on: bool = True):
+    L.check(L.lib().tpc_timing_enable(ctx.handle, 1 if on else 0), "tpc_timing_enable")
+
+
+def timing_report(ctx: Context, max_kernels: int = 64) -> dict:
+    """{kernel name: (launches, total ms)} since the last report."""
+    names = (C.c_char_p * max_kernels)()
+    launches = (C.c_int64 * max_kernels)()
+    ms = (C.c_double * max_kernels)()
+    n = C.c_int()
+    L.check(L.lib().tpc_timing_report(ctx.handle, max_kernels, names, launches, ms, C.byref(n)),
+            "tpc_timing_report")
+    return {names[i].decode(): (int(launches[i]), float(ms[i]))
+            for i in range(min(n.value, max_kernels))}
 
 
 # ---------------------------------------------------------------- refit
@@ -253,37 +290,50 @@ def calib_struct(cm=None) -> L.CalibModel:
 
 @dataclass
 class TrackHits:
+    """Refit input: CSR over tracks; entry j is cluster idx[j] of row/y/z
+    (or cluster j without idx).  With d_count (device address of an int64
+    count) the number of tracks is read on the device, up to n_tracks_cap."""
     off: torch.Tensor      # int32 [n_tracks + 1]
-    row: torch.Tensor      # uint8 [n_hits]
-    y: torch.Tensor        # float32 [n_hits]
-    z: torch.Tensor        # float32 [n_hits]
+    row: torch.Tensor      # uint8 [n_clusters]
+    y: torch.Tensor        # float32 [n_clusters]
+    z: torch.Tensor        # float32 [n_clusters]
     side: torch.Tensor | None = None   # int8 [n_tracks]
+    idx: torch.Tensor | None = None    # int32 [n_hits]
+    d_count: C.c_void_p | None = None
+    n_tracks_cap: int | None = None
+    n_hits_cap: int | None = None
 
     @property
     def n_tracks(self):
-        return int(self.off.shape[0] - 1)
+        return int(self.n_tracks_cap if self.n_tracks_cap is not None else self.off.shape[0] - 1)
 
     @property
     def n_hits(self):
-        return int(self.row.shape[0])
+        if self.n_hits_cap is not None:
+            return int(self.n_hits_cap)
+        return int(self.idx.shape[0] if self.idx is not None else self.row.shape[0])
 
     def struct(self, y=None, z=None) -> L.TrackHits:
-        return L.TrackHits(_ptr(self.off), _ptr(self.row), _ptr(self.y if y is None else y),
-                           _ptr(self.z if z is None else z), _ptr(self.side), self.n_tracks,
-                           self.n_hits)
+        return L.TrackHits(_ptr(self.off), _ptr(self.idx), _ptr(self.row),
+                           _ptr(self.y if y is None else y), _ptr(self.z if z is None else z),
+                           _ptr(self.side), self.d_count, self.n_tracks, self.n_hits)
 
 
 def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: torch.Tensor,
-          checkpoints: bool = True, cm=None, stream=None, y=None, z=None):
-    """Forward refit; returns dict(par, cov, chi2, status, checkpoints)."""
+          checkpoints: bool = True, cm=None, stream=None, y=None, z=None, out=None):
+    """Forward refit; returns dict(par, cov, chi2, status, checkpoints).
+    `out` (a dict returned by an earlier call of the same size) is reused."""
     dev = hits.row.device
     n = hits.n_tracks
-    out = dict(par=torch.empty(n * 5, dtype=torch.float32, device=dev),
-               cov=torch.empty(n * 15, dtype=torch.float32, device=dev),
-               chi2=torch.empty(n, dtype=torch.float32, device=dev),
-               status=torch.empty(n, dtype=torch.int32, device=dev))
-    out["checkpoints"] = (torch.empty(max(hits.n_hits, 1) * 20, dtype=torch.float32, device=dev)
-                          if checkpoints else None)
+    if out is None:
+        out = dict(par=torch.empty(n * 5, dtype=torch.float32, device=dev),
+                   cov=torch.empty(n * 15, dtype=torch.float32, device=dev),
+                   chi2=torch.empty(n, dtype=torch.float32, device=dev),
+                   status=torch.empty(n, dtype=torch.int32, device=dev))
+        out["checkpoints"] = (torch.empty(max(hits.n_hits, 1) * 20, dtype=torch.float32,
+                                          device=dev) if checkpoints else None)
+    else:
+        out = dict(out)
     P = params_struct(prm)
     CM = calib_struct(cm)
     th = theta.detach().to(device=dev, dtype=torch.float32).contiguous()
@@ -298,15 +348,20 @@ def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: 
 
 def refit_adjoint(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
                   theta: torch.Tensor, fwd: dict, grad_chi2: torch.Tensor, cm=None, stream=None,
-                  y=None, z=None):
-    """Gradients of sum_k grad_chi2[k] chi2[k]: (grad_y, grad_z, grad_theta)."""
+                  y=None, z=None, out=None):
+    """Gradients of sum_k grad_chi2[k] chi2[k]: (grad_y, grad_z, grad_theta).
+    `out` (dict with ws, gy, gz, gt of an earlier call) is reused."""
     dev = hits.row.device
     nb = C.c_size_t()
     L.check(L.lib().tpc_refit_workspace_size(hits.n_tracks, C.byref(nb)), "workspace")
-    ws = torch.empty(max(int(nb.value), 64), dtype=torch.uint8, device=dev)
-    gy = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
-    gz = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
-    gt = torch.zeros(16, dtype=torch.float32, device=dev)
+    if out is None:
+        out = {}
+    if "ws" not in out:
+        out["ws"] = torch.empty(max(int(nb.value), 64), dtype=torch.uint8, device=dev)
+        out["gy"] = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
+        out["gz"] = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
+        out["gt"] = torch.zeros(16, dtype=torch.float32, device=dev)
+    ws, gy, gz, gt = out["ws"], out["gy"], out["gz"], out["gt"]
     P = params_struct(prm)
     CM = calib_struct(cm)
     th = theta.detach().to(device=dev, dtype=torch.float32).contiguous()

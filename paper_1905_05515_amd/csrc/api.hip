@@ -48,6 +48,7 @@ extern "C" {
 int tpc_build_grid(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in, tpc_grid out,
                    void* d_ws, size_t ws_bytes, void* stream)
 {
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     tpc::Workspace ws;
     int e = prepare(ctx, h_prob, d_ws, ws_bytes, 0, &ws);
     if (e) return e;
@@ -59,36 +60,41 @@ int tpc_find_neighbours(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid gr
                         tpc_links links, tpc_starts starts, void* d_ws, size_t ws_bytes,
                         void* stream)
 {
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     tpc::Workspace ws;
     int e = prepare(ctx, h_prob, d_ws, ws_bytes, starts.capacity, &ws);
     if (e) return e;
     if (!grid_ok(grid) || !links_ok(links) || !starts_ok(starts)) return TPC_ERR_INVALID_ARG;
-    return tpc::run_find_neighbours(h_prob, grid, links, starts, ws, (hipStream_t)stream);
+    return tpc::run_find_neighbours(h_prob, 0, h_prob->n_sectors, grid, links, starts, ws,
+                                    (hipStream_t)stream);
 }
 
 int tpc_construct_tracklets(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid grid,
                             tpc_links links, tpc_starts starts, tpc_tracklets tracklets,
                             void* d_ws, size_t ws_bytes, void* stream)
 {
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     tpc::Workspace ws;
     int e = prepare(ctx, h_prob, d_ws, ws_bytes, starts.capacity, &ws);
     if (e) return e;
     if (!grid_ok(grid) || !links_ok(links) || !starts_ok(starts) || !trl_ok(tracklets, starts))
         return TPC_ERR_INVALID_ARG;
-    return tpc::run_construct_tracklets(h_prob, grid, links, starts, tracklets, ws,
-                                        (hipStream_t)stream);
+    return tpc::run_construct_tracklets(h_prob, 0, h_prob->n_sectors, grid, links, starts,
+                                        tracklets, ws, (hipStream_t)stream);
 }
 
 int tpc_select_tracks(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid grid,
                       tpc_tracklets tracklets, tpc_tracks tracks, void* d_ws, size_t ws_bytes,
                       void* stream)
 {
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     tpc::Workspace ws;
     int e = prepare(ctx, h_prob, d_ws, ws_bytes, tracklets.capacity, &ws);
     if (e) return e;
     tpc_starts dummy{nullptr, tracklets.capacity};
     if (!grid_ok(grid) || !trl_ok(tracklets, dummy) || !trk_ok(tracks)) return TPC_ERR_INVALID_ARG;
-    return tpc::run_select_tracks(h_prob, grid, dummy, tracklets, tracks, ws, (hipStream_t)stream);
+    return tpc::run_select_tracks(h_prob, grid, tracklets.capacity, tracklets, tracks, ws,
+                                  (hipStream_t)stream);
 }
 
 int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in,
@@ -96,23 +102,45 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
                     tpc_tracklets tracklets, tpc_tracks tracks, void* d_ws, size_t ws_bytes,
                     int mode, int use_graph, void* stream)
 {
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     tpc::Workspace ws;
     int e = prepare(ctx, h_prob, d_ws, ws_bytes, starts.capacity, &ws);
     if (e) return e;
     if (!in.row || !in.y || !in.z || !grid_ok(grid) || !links_ok(links) || !starts_ok(starts) ||
         !trl_ok(tracklets, starts) || !trk_ok(tracks))
         return TPC_ERR_INVALID_ARG;
-    if (mode != TPC_MODE_STAGED) return TPC_ERR_UNSUPPORTED;
+    if (mode != TPC_MODE_STAGED && mode != TPC_MODE_PER_SECTOR && mode != TPC_MODE_PERSISTENT)
+        return TPC_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
+    const int ns = h_prob->n_sectors;
     // never more tracklets than starts: the selection runs over the start
     // capacity the workspace was sized for
-    tpc_tracklets trl = tracklets;
-    trl.capacity = starts.capacity;
+    const int64_t count_cap = starts.capacity;
     auto body = [&]() -> int {
-        int r = tpc::run_build_grid(h_prob, 0, h_prob->n_sectors, in, grid, ws, st);
-        if (!r) r = tpc::run_find_neighbours(h_prob, grid, links, starts, ws, st);
-        if (!r) r = tpc::run_construct_tracklets(h_prob, grid, links, starts, trl, ws, st);
-        if (!r) r = tpc::run_select_tracks(h_prob, grid, starts, trl, tracks, ws, st);
+        int r = TPC_OK;
+        if (mode == TPC_MODE_STAGED) {
+            r = tpc::run_build_grid(h_prob, 0, ns, in, grid, ws, st);
+            if (!r) r = tpc::run_find_neighbours(h_prob, 0, ns, grid, links, starts, ws, st);
+            if (!r)
+                r = tpc::run_construct_tracklets(h_prob, 0, ns, grid, links, starts, tracklets,
+                                                 ws, st);
+            if (!r) r = tpc::run_select_tracks(h_prob, grid, count_cap, tracklets, tracks, ws, st);
+        } else if (mode == TPC_MODE_PER_SECTOR) {
+            // every stage sector by sector, then one dense compaction of the
+            // track list over all tracklets
+            tpc::launch_fill<uint64_t>(ws.tlen, 0ull, count_cap + 1, st);
+            for (int s = 0; s < ns && !r; ++s) {
+                r = tpc::run_build_grid(h_prob, s, s + 1, in, grid, ws, st);
+                if (!r) r = tpc::run_find_neighbours(h_prob, s, s + 1, grid, links, starts, ws, st);
+                if (!r)
+                    r = tpc::run_construct_tracklets(h_prob, s, s + 1, grid, links, starts,
+                                                     tracklets, ws, st);
+                if (!r) r = tpc::run_select_keys(h_prob, s, s + 1, grid, count_cap, tracklets, ws, st);
+            }
+            if (!r) r = tpc::run_select_compact(h_prob, grid, count_cap, tracklets, tracks, ws, st);
+        } else {
+            r = tpc::run_persistent(ctx, h_prob, in, grid, links, starts, tracklets, tracks, ws, st);
+        }
         return r;
     };
     if (!use_graph) return body();

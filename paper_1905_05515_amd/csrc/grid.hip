@@ -1,5 +1,7 @@
 // Grid build: stable counting sort of each sector's clusters by
-// (row, z bin, y bin), ties by cluster id.
+// (row, z bin, y bin), ties by cluster id; clusters with an invalid row go to
+// the sector's last bin.  A sector's clusters occupy exactly its id range of
+// grid positions, so sectors can be built independently.
 //
 // count   one thread per cluster: bin histogram (atomics on the bin counts)
 // scan    exclusive scan of the counts -> bin_start
@@ -18,13 +20,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(
 {
     for (int64_t i = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < end;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int r = row[i];
-        if (r >= n_rows) {
-            atomicAdd((unsigned long long*)&status->n_bad_rows, 1ull);
-            continue;
-        }
+        const int r = row[i];
+        if (r >= n_rows) atomicAdd((unsigned long long*)&status->n_bad_rows, 1ull);
         const tpc_sector& s = sec[find_sector(sec, n_sec, i)];
-        atomicAdd(&cnt[global_bin(s, r, y[i], z[i])], 1);
+        atomicAdd(&cnt[global_bin(s, n_rows, r, y[i], z[i])], 1);
     }
 }
 
@@ -35,32 +34,29 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(
 {
     for (int64_t i = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < end;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int r = row[i];
-        if (r >= n_rows) continue;
         const tpc_sector& s = sec[find_sector(sec, n_sec, i)];
-        int g = global_bin(s, r, y[i], z[i]);
-        int slot = atomicAdd(&fill[g], 1);
+        const int g = global_bin(s, n_rows, row[i], y[i], z[i]);
+        const int slot = atomicAdd(&fill[g], 1);
         tmp[bin_start[g] + slot] = (int32_t)i;
     }
 }
 
-// positions [bin_start[bin_lo], bin_start[bin_hi]) of the sectors handled
+// grid positions [begin, end) (= the cluster ids of the sectors handled)
 __global__ __launch_bounds__(kBlock) void k_grid_rank(
-    const tpc_sector* __restrict__ sec, int n_sec, const uint8_t* __restrict__ row,
+    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
     const float* __restrict__ y, const float* __restrict__ z,
-    const int32_t* __restrict__ bin_start, int64_t bin_lo, int64_t bin_hi,
+    const int32_t* __restrict__ bin_start, int64_t begin, int64_t end,
     const int32_t* __restrict__ tmp, float* __restrict__ yg, float* __restrict__ zg,
     int32_t* __restrict__ idg, int32_t* __restrict__ gsr)
 {
-    const int64_t p0 = bin_start[bin_lo], p1 = bin_start[bin_hi];
-    for (int64_t p = p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < p1;
+    for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t id = tmp[p];
         const int si = find_sector(sec, n_sec, id);
         const tpc_sector& s = sec[si];
         const int r = row[id];
         const float yy = y[id], zz = z[id];
-        const int g = global_bin(s, r, yy, zz);
+        const int g = global_bin(s, n_rows, r, yy, zz);
         const int32_t bs = bin_start[g], be = bin_start[g + 1];
         int rank = 0;
         for (int32_t q = bs; q < be; ++q) rank += tmp[q] < id;
@@ -72,31 +68,37 @@ __global__ __launch_bounds__(kBlock) void k_grid_rank(
     }
 }
 
+__global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) status->n_grid = n_grid;
+}
+
 // Build the grid of sectors [sec_lo, sec_hi).  The first call of an event
-// (sec_lo == 0) clears the status block; per-sector calls continue the
-// running count of placed clusters so that grid positions equal those of a
-// single call over all sectors.
+// (sec_lo == 0) clears the status block.
 int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in,
                    tpc_grid out, const Workspace& ws, hipStream_t st)
 {
     const tpc_sector& a = p->h_sectors[sec_lo];
     const tpc_sector& b = p->h_sectors[sec_hi - 1];
     const int64_t c0 = a.begin, c1 = b.end;
-    const int64_t g0 = a.bin_base, g1 = (int64_t)b.bin_base + (int64_t)p->n_rows * b.nby * b.nbz;
+    const int64_t g0 = a.bin_base;
+    const int64_t g1 = (int64_t)b.bin_base + (int64_t)p->n_rows * b.nby * b.nbz + 1;
     if (sec_lo == 0) launch_fill<int64_t>((int64_t*)ws.status, 0, sizeof(tpc_status) / 8, st);
     launch_fill<int32_t>(ws.cnt + g0, 0, g1 - g0, st);
     const unsigned gc = grid_for(c1 - c0);
-    hipLaunchKernelGGL(k_grid_count, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-                       p->n_rows, in.row, in.y, in.z, c0, c1, ws.cnt, ws.status);
-    launch_scan<int32_t>(ws.cnt + g0, out.bin_start + g0, g1 - g0, true, &ws.status->n_grid,
-                         &ws.status->n_grid, ws.partials, st);
+    TPC_LAUNCH(k_grid_count, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
+               p->n_rows, in.row, in.y, in.z, c0, c1, ws.cnt, ws.status);
+    // the sectors' first bin starts at their first cluster id
+    launch_scan<int32_t>(ws.cnt + g0, out.bin_start + g0, g1 - g0, true, nullptr, nullptr,
+                         ws.partials, st, c0);
     launch_fill<int32_t>(ws.cnt + g0, 0, g1 - g0, st);
-    hipLaunchKernelGGL(k_grid_scatter, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-                       p->n_rows, in.row, in.y, in.z, c0, c1, (const int32_t*)out.bin_start,
-                       ws.cnt, ws.tmp);
-    hipLaunchKernelGGL(k_grid_rank, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-                       in.row, in.y, in.z, (const int32_t*)out.bin_start, g0, g1,
-                       (const int32_t*)ws.tmp, out.y, out.z, out.id, ws.gsr);
+    TPC_LAUNCH(k_grid_scatter, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
+               p->n_rows, in.row, in.y, in.z, c0, c1, (const int32_t*)out.bin_start, ws.cnt,
+               ws.tmp);
+    TPC_LAUNCH(k_grid_rank, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors, p->n_rows,
+               in.row, in.y, in.z, (const int32_t*)out.bin_start, c0, c1,
+               (const int32_t*)ws.tmp, out.y, out.z, out.id, ws.gsr);
+    TPC_LAUNCH(k_set_grid_status, dim3(1), dim3(1), 0, st, ws.status, c1);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

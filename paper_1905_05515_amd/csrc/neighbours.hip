@@ -12,12 +12,11 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
     const tpc_sector* __restrict__ sec, int n_rows, const float* __restrict__ row_x,
     tpc_params prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
     const float* __restrict__ zg, const int32_t* __restrict__ idg,
-    const int32_t* __restrict__ gsr, const tpc_status* __restrict__ status, int64_t n_max,
+    const int32_t* __restrict__ gsr, int64_t begin, int64_t end,
     int32_t* __restrict__ up0, int32_t* __restrict__ down0)
 {
-    const int64_t n = status->n_grid < n_max ? status->n_grid : n_max;
     const float Wy = prm.nb_win_y, Wz = prm.nb_win_z, D2max = prm.nb_d2max;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+    for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int v = gsr[p];
         const int r = v & 255;
@@ -76,11 +75,10 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
 // has an up link) is flagged in the id-indexed array `start_by_id`.
 __global__ __launch_bounds__(kBlock) void k_clean(
     const int32_t* __restrict__ up0, const int32_t* __restrict__ down0,
-    const int32_t* __restrict__ idg, const tpc_status* __restrict__ status, int64_t n_max,
+    const int32_t* __restrict__ idg, int64_t begin, int64_t end,
     int32_t* __restrict__ up, int32_t* __restrict__ down, int32_t* __restrict__ start_by_id)
 {
-    const int64_t n = status->n_grid < n_max ? status->n_grid : n_max;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+    for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int u = up0[p], d = down0[p];
         const int uc = (u >= 0 && down0[u] == p) ? u : -1;
@@ -152,33 +150,48 @@ __global__ __launch_bounds__(kBlock) void k_start_write(const int32_t* __restric
         }
 }
 
-__global__ void k_start_status(tpc_status* status, int64_t cap)
+// running start count before a range of sectors (first range: reset)
+__global__ void k_start_mark(tpc_status* status, int64_t* sec_start, int sec_lo)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && status->n_starts > cap) status->overflow |= 1;
+    if (blockIdx.x || threadIdx.x) return;
+    if (sec_lo == 0) status->n_starts = 0;
+    sec_start[sec_lo] = status->n_starts;
 }
 
-int run_find_neighbours(const tpc_problem* p, tpc_grid grid, tpc_links links,
-                        tpc_starts starts, const Workspace& ws, hipStream_t st)
+__global__ void k_start_status(tpc_status* status, int64_t* sec_start, int sec_hi, int64_t cap)
 {
-    const int64_t n = p->n_clusters;
+    if (blockIdx.x || threadIdx.x) return;
+    sec_start[sec_hi] = status->n_starts;
+    if (status->n_starts > cap) status->overflow |= 1;
+}
+
+// Seeding for sectors [sec_lo, sec_hi): their grid positions and cluster ids
+// are the same range.  Starts are appended in id order after those of the
+// earlier sectors.
+int run_find_neighbours(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
+                        tpc_links links, tpc_starts starts, const Workspace& ws, hipStream_t st)
+{
+    const int64_t c0 = p->h_sectors[sec_lo].begin, c1 = p->h_sectors[sec_hi - 1].end;
+    const int64_t n = c1 - c0;
     const unsigned gn = grid_for(n);
-    hipLaunchKernelGGL(k_neighbours, dim3(gn), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
-                       p->d_row_x, p->params, (const int32_t*)grid.bin_start,
-                       (const float*)grid.y, (const float*)grid.z, (const int32_t*)grid.id,
-                       (const int32_t*)ws.gsr, (const tpc_status*)ws.status, n, links.up0,
-                       links.down0);
-    launch_fill<int32_t>(ws.tmp, -1, n, st);
-    hipLaunchKernelGGL(k_clean, dim3(gn), dim3(kBlock), 0, st, (const int32_t*)links.up0,
-                       (const int32_t*)links.down0, (const int32_t*)grid.id,
-                       (const tpc_status*)ws.status, n, links.up, links.down, ws.tmp);
+    TPC_LAUNCH(k_neighbours, dim3(gn), dim3(kBlock), 0, st, p->d_sectors, p->n_rows, p->d_row_x,
+               p->params, (const int32_t*)grid.bin_start, (const float*)grid.y,
+               (const float*)grid.z, (const int32_t*)grid.id, (const int32_t*)ws.gsr, c0, c1,
+               links.up0, links.down0);
+    launch_fill<int32_t>(ws.tmp + c0, -1, n, st);
+    TPC_LAUNCH(k_clean, dim3(gn), dim3(kBlock), 0, st, (const int32_t*)links.up0,
+               (const int32_t*)links.down0, (const int32_t*)grid.id, c0, c1, links.up, links.down,
+               ws.tmp);
+    TPC_LAUNCH(k_start_mark, dim3(1), dim3(1), 0, st, ws.status, ws.sec_start, sec_lo);
     const int64_t nt = ceil_div(n > 0 ? n : 1, kScanTile);
-    hipLaunchKernelGGL(k_start_tile_counts, dim3((unsigned)nt), dim3(kBlock), 0, st,
-                       (const int32_t*)ws.tmp, n, ws.partials);
-    launch_scan_partials(ws.partials, nt, nullptr, &ws.status->n_starts, st);
-    hipLaunchKernelGGL(k_start_write, dim3((unsigned)nt), dim3(kBlock), 0, st,
-                       (const int32_t*)ws.tmp, n, (const int64_t*)ws.partials, starts.pos,
-                       starts.capacity);
-    hipLaunchKernelGGL(k_start_status, dim3(1), dim3(1), 0, st, ws.status, starts.capacity);
+    TPC_LAUNCH(k_start_tile_counts, dim3((unsigned)nt), dim3(kBlock), 0, st,
+               (const int32_t*)(ws.tmp + c0), n, ws.partials);
+    launch_scan_partials(ws.partials, nt, &ws.status->n_starts, &ws.status->n_starts, st);
+    TPC_LAUNCH(k_start_write, dim3((unsigned)nt), dim3(kBlock), 0, st,
+               (const int32_t*)(ws.tmp + c0), n, (const int64_t*)ws.partials, starts.pos,
+               starts.capacity);
+    TPC_LAUNCH(k_start_status, dim3(1), dim3(1), 0, st, ws.status, ws.sec_start, sec_hi,
+               starts.capacity);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

@@ -81,6 +81,23 @@ __device__ __forceinline__ void calibrate_adj(const float* th, const CalHit& h, 
     gzr = -sd * (1.0f + th[0]) * db;
 }
 
+// hit i of a track: entry a + i of the CSR, cluster idx[a + i] if given
+struct HitRef {
+    const int32_t* idx;
+    const uint8_t* row_;
+    const float* y_;
+    const float* z_;
+    int a;
+    __device__ __forceinline__ int cl(int i) const { return idx ? idx[a + i] : a + i; }
+    __device__ __forceinline__ int row(int i) const { return row_[cl(i)]; }
+    __device__ __forceinline__ CalHit cal(int i, const float* th, const float* xs, float sd,
+                                          const CalibModel& cm) const
+    {
+        const int c = cl(i);
+        return calibrate(th, xs[row_[c]], y_[c], z_[c], sd, cm);
+    }
+};
+
 struct Prop {
     float dx, k, s2, c1, c2, cc, T, q, L, a, a2, g, S, Ts, kdx, Tw, LT, G1, Sk;
     float ys, yw, zs, zt, zw, sw;   // non-trivial Jacobian entries
@@ -374,6 +391,28 @@ __device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const 
     return dxb;
 }
 
+// checkpoint of 20 floats (p, C) as five 16-byte accesses
+__device__ __forceinline__ void store_ck(float* o, const float* p, const float* C)
+{
+    float4* q = reinterpret_cast<float4*>(o);
+    q[0] = make_float4(p[0], p[1], p[2], p[3]);
+    q[1] = make_float4(p[4], C[0], C[1], C[2]);
+    q[2] = make_float4(C[3], C[4], C[5], C[6]);
+    q[3] = make_float4(C[7], C[8], C[9], C[10]);
+    q[4] = make_float4(C[11], C[12], C[13], C[14]);
+}
+
+__device__ __forceinline__ void load_ck(const float* o, float* p, float* C)
+{
+    const float4* q = reinterpret_cast<const float4*>(o);
+    const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
+    p[0] = a.x; p[1] = a.y; p[2] = a.z; p[3] = a.w;
+    p[4] = b.x; C[0] = b.y; C[1] = b.z; C[2] = b.w;
+    C[3] = c.x; C[4] = c.y; C[5] = c.z; C[6] = c.w;
+    C[7] = d.x; C[8] = d.y; C[9] = d.z; C[10] = d.w;
+    C[11] = e.x; C[12] = e.y; C[13] = e.z; C[14] = e.w;
+}
+
 __device__ __forceinline__ void load_theta(const float* __restrict__ d_theta, float* th)
 {
     if (threadIdx.x < 16) th[threadIdx.x] = d_theta[threadIdx.x];
@@ -382,9 +421,11 @@ __device__ __forceinline__ void load_theta(const float* __restrict__ d_theta, fl
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void k_refit_fwd(
-    const int32_t* __restrict__ off, const uint8_t* __restrict__ row, const float* __restrict__ y,
-    const float* __restrict__ z, const int8_t* __restrict__ side, int64_t n_tracks, int n_rows,
+__global__ __launch_bounds__(kWave) void k_refit_fwd(
+    const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+    const uint8_t* __restrict__ row, const float* __restrict__ y, const float* __restrict__ z,
+    const int8_t* __restrict__ side, const int64_t* __restrict__ d_count, int64_t n_tracks,
+    int n_rows,
     const float* __restrict__ row_x, tpc_params prm, CalibModel cm,
     const float* __restrict__ d_theta, float* __restrict__ par, float* __restrict__ cov,
     float* __restrict__ chi2_out, int32_t* __restrict__ status, float* __restrict__ ck)
@@ -394,24 +435,26 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(
     load_theta(d_theta, th);
     for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
     __syncthreads();
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_tracks;
+    const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int a = off[t], n = off[t + 1] - a;
+        HitRef H{idx, row, y, z, a};
         float p[5] = {0, 0, 0, 0, 0}, C[15];
 #pragma unroll
         for (int i = 0; i < 15; ++i) C[i] = 0.0f;
         float chi2 = 0.0f;
         int stat = 0;
         bool rows_ok = true;
-        for (int i = 0; i < n; ++i) rows_ok &= row[a + i] < n_rows;
+        for (int i = 0; i < n; ++i) rows_ok &= H.row(i) < n_rows;
         if (n < 3) {
             stat = 1;
         } else if (!rows_ok) {
             stat = 3;
         } else {
             const float sd = side ? (float)side[t] : 1.0f;
-            const CalHit h0 = calibrate(th, xs[row[a]], y[a], z[a], sd, cm);
-            const CalHit h2 = calibrate(th, xs[row[a + 2]], y[a + 2], z[a + 2], sd, cm);
+            const CalHit h0 = H.cal(0, th, xs, sd, cm);
+            const CalHit h2 = H.cal(2, th, xs, sd, cm);
             const float dX = h2.x - h0.x;
             const float T0 = (h2.y - h0.y) / dX;
             const float q0 = sqrtf(1.0f + T0 * T0);
@@ -425,16 +468,10 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(
             C[5] = prm.c_ss0;
             C[9] = prm.c_tt0;
             C[14] = prm.c_ww0;
-            if (ck) {
-                float* o = ck + (int64_t)a * 20;
-#pragma unroll
-                for (int i = 0; i < 5; ++i) o[i] = p[i];
-#pragma unroll
-                for (int i = 0; i < 15; ++i) o[5 + i] = C[i];
-            }
+            if (ck) store_ck(ck + (int64_t)a * 20, p, C);
             float xp = h0.x;
             for (int i = 1; i < n; ++i) {
-                const CalHit h = calibrate(th, xs[row[a + i]], y[a + i], z[a + i], sd, cm);
+                const CalHit h = H.cal(i, th, xs, sd, cm);
                 Prop P;
                 if (!prop_fwd(p, C, h.x - xp, prm.curv, prm.s_max, P)) {
                     stat = 2;
@@ -443,13 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(
                 Upd U;
                 chi2 += upd_fwd(p, C, h.y, h.z, prm.sigma_y2, prm.sigma_z2, U);
                 xp = h.x;
-                if (ck && i + 1 < n) {
-                    float* o = ck + (int64_t)(a + i) * 20;
-#pragma unroll
-                    for (int k = 0; k < 5; ++k) o[k] = p[k];
-#pragma unroll
-                    for (int k = 0; k < 15; ++k) o[5 + k] = C[k];
-                }
+                if (ck && i + 1 < n) store_ck(ck + (int64_t)(a + i) * 20, p, C);
             }
         }
 #pragma unroll
@@ -461,9 +492,11 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_refit_adj(
-    const int32_t* __restrict__ off, const uint8_t* __restrict__ row, const float* __restrict__ y,
-    const float* __restrict__ z, const int8_t* __restrict__ side, int64_t n_tracks, int n_rows,
+__global__ __launch_bounds__(kWave) void k_refit_adj(
+    const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+    const uint8_t* __restrict__ row, const float* __restrict__ y, const float* __restrict__ z,
+    const int8_t* __restrict__ side, const int64_t* __restrict__ d_count, int64_t n_tracks,
+    int n_rows,
     const float* __restrict__ row_x, tpc_params prm, CalibModel cm,
     const float* __restrict__ d_theta, const float* __restrict__ ck,
     const int32_t* __restrict__ status, const float* __restrict__ gchi2,
@@ -471,16 +504,17 @@ __global__ __launch_bounds__(kBlock) void k_refit_adj(
 {
     __shared__ float th[16];
     __shared__ float xs[256];
-    __shared__ float red[kBlock / kWave][16];
     load_theta(d_theta, th);
     for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
     __syncthreads();
     float gth[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) gth[k] = 0.0f;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_tracks;
+    const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int a = off[t], n = off[t + 1] - a;
+        HitRef H{idx, row, y, z, a};
         if (n < 3 || status[t] != 0) {
             for (int i = 0; i < n; ++i) {
                 gy[a + i] = 0.0f;
@@ -493,17 +527,13 @@ __global__ __launch_bounds__(kBlock) void k_refit_adj(
         float pb[5] = {0, 0, 0, 0, 0}, G[15];
 #pragma unroll
         for (int i = 0; i < 15; ++i) G[i] = 0.0f;
-        CalHit cur = calibrate(th, xs[row[a + n - 1]], y[a + n - 1], z[a + n - 1], sd, cm);
+        CalHit cur = H.cal(n - 1, th, xs, sd, cm);
         float Xcarry = 0.0f;
         float X2 = 0.0f, Y2 = 0.0f, Z2 = 0.0f;
         for (int i = n - 1; i >= 1; --i) {
-            const CalHit prev = calibrate(th, xs[row[a + i - 1]], y[a + i - 1], z[a + i - 1], sd, cm);
+            const CalHit prev = H.cal(i - 1, th, xs, sd, cm);
             float p[5], C[15];
-            const float* c = ck + (int64_t)(a + i - 1) * 20;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) p[k] = c[k];
-#pragma unroll
-            for (int k = 0; k < 15; ++k) C[k] = c[5 + k];
+            load_ck(ck + (int64_t)(a + i - 1) * 20, p, C);
             const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};
             Prop P;
             prop_fwd(p, C, cur.x - prev.x, prm.curv, prm.s_max, P);
@@ -528,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_adj(
         }
         // initial state: y, z of hit 0, direction from hit 0 to hit 2
         const CalHit h0 = cur;
-        const CalHit h2 = calibrate(th, xs[row[a + 2]], y[a + 2], z[a + 2], sd, cm);
+        const CalHit h2 = H.cal(2, th, xs, sd, cm);
         const float dX = h2.x - h0.x;
         const float T0 = (h2.y - h0.y) / dX;
         const float q0 = sqrtf(1.0f + T0 * T0);
@@ -555,36 +585,39 @@ __global__ __launch_bounds__(kBlock) void k_refit_adj(
         gy[a + 2] = gyr;
         gz[a + 2] = gzr;
     }
-    // deterministic block reduction of the theta adjoint
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    // deterministic wave reduction of the theta adjoint (one wave per block)
+    const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         float v = gth[k];
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if (lane == 0) red[wid][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 16) {
-        float v = 0.0f;
-        for (int w = 0; w < kBlock / kWave; ++w) v += red[w][threadIdx.x];
-        partials[blockIdx.x * 16 + threadIdx.x] = v;
+        if (lane == k) partials[blockIdx.x * 16 + k] = v;
     }
 }
 
-__global__ void k_reduce_theta(const float* __restrict__ partials, int nb, float* __restrict__ out)
+// sum of the per-block partials in a fixed order: thread j of 256 sums
+// column j % 16 over blocks j / 16, j / 16 + 16, ...; then the 16 strided
+// sums of each column are added in order
+__global__ __launch_bounds__(kBlock) void k_reduce_theta(const float* __restrict__ partials,
+                                                         int nb, float* __restrict__ out)
 {
-    // 16 threads, each sums its column in block order
+    __shared__ float red[kBlock];
+    const int col = threadIdx.x & 15, row0 = threadIdx.x >> 4;
+    float v = 0.0f;
+    for (int b = row0; b < nb; b += kBlock / 16) v += partials[b * 16 + col];
+    red[threadIdx.x] = v;
+    __syncthreads();
     if (threadIdx.x < 16) {
-        float v = 0.0f;
-        for (int b = 0; b < nb; ++b) v += partials[b * 16 + threadIdx.x];
-        out[threadIdx.x] = v;
+        float s = 0.0f;
+        for (int r = 0; r < kBlock / 16; ++r) s += red[r * 16 + threadIdx.x];
+        out[threadIdx.x] = s;
     }
 }
 
 static unsigned refit_grid(int64_t n_tracks)
 {
-    return grid_for(n_tracks, 4096);
+    return grid_for_block(n_tracks, kWave, 16384);
 }
 
 }  // namespace tpc
@@ -603,6 +636,7 @@ int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float
               float* par, float* cov, float* chi2, int32_t* status, float* checkpoints,
               void* stream)
 {
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !par || !cov || !chi2 ||
         !status || hits.n_tracks < 0 || hits.n_hits < 0 || n_rows < 3 || n_rows > 255 ||
         (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
@@ -611,10 +645,10 @@ int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float
     if (hits.n_tracks == 0) return TPC_OK;
     tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
                        h_model->u_scale};
-    hipLaunchKernelGGL(tpc::k_refit_fwd, dim3(tpc::refit_grid(hits.n_tracks)), dim3(tpc::kBlock),
-                       0, (hipStream_t)stream, hits.off, hits.row, hits.y, hits.z, hits.side,
-                       hits.n_tracks, n_rows, d_row_x, *h_params, cm, d_theta, par, cov, chi2,
-                       status, checkpoints);
+    TPC_LAUNCH(tpc::k_refit_fwd, dim3(tpc::refit_grid(hits.n_tracks)), dim3(tpc::kWave),
+                       0, (hipStream_t)stream, hits.off, hits.idx, hits.row, hits.y, hits.z,
+                       hits.side, hits.d_count, hits.n_tracks, n_rows, d_row_x, *h_params, cm,
+                       d_theta, par, cov, chi2, status, checkpoints);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
@@ -625,6 +659,7 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                       float* grad_y, float* grad_z, float* grad_theta, void* d_ws,
                       size_t ws_bytes, void* stream)
 {
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     size_t need = 0;
     if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !checkpoints || !status ||
         !grad_chi2 || !grad_y || !grad_z || !grad_theta || !d_ws || hits.n_tracks < 0 ||
@@ -637,10 +672,11 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                        h_model->u_scale};
     const unsigned nb = tpc::refit_grid(hits.n_tracks);
     float* partials = (float*)d_ws;
-    hipLaunchKernelGGL(tpc::k_refit_adj, dim3(nb), dim3(tpc::kBlock), 0, st, hits.off, hits.row,
-                       hits.y, hits.z, hits.side, hits.n_tracks, n_rows, d_row_x, *h_params, cm,
-                       d_theta, checkpoints, status, grad_chi2, grad_y, grad_z, partials);
-    hipLaunchKernelGGL(tpc::k_reduce_theta, dim3(1), dim3(64), 0, st, (const float*)partials,
+    TPC_LAUNCH(tpc::k_refit_adj, dim3(nb), dim3(tpc::kWave), 0, st, hits.off, hits.idx,
+                       hits.row, hits.y, hits.z, hits.side, hits.d_count, hits.n_tracks, n_rows,
+                       d_row_x, *h_params, cm, d_theta, checkpoints, status, grad_chi2, grad_y,
+                       grad_z, partials);
+    TPC_LAUNCH(tpc::k_reduce_theta, dim3(1), dim3(tpc::kBlock), 0, st, (const float*)partials,
                        (int)nb, grad_theta);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }

@@ -12,44 +12,44 @@ __device__ __forceinline__ uint64_t tracklet_key(int nh, int start_id, int min_h
     return nh >= min_hits ? (((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)start_id)) : 0ull;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sel_keys(
+__global__ __launch_bounds__(kWave) void k_sel_keys(
     int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t cap,
+    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
+    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
     unsigned long long* __restrict__ hitkey)
 {
-    int64_t m = status->n_starts;
-    if (m > cap) m = cap;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
+    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
+    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
          t += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
         if (!key) continue;
-        const int32_t* th = t_hits + t * n_rows;
         for (int r = 0; r < n_rows; ++r) {
-            const int c = th[r];
+            const int c = t_hits[(int64_t)r * cap + t];
             if (c >= 0) atomicMax(&hitkey[c], (unsigned long long)key);
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sel_count(
+__global__ __launch_bounds__(kWave) void k_sel_count(
     int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t cap,
+    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
+    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
     const unsigned long long* __restrict__ hitkey, uint64_t* __restrict__ tlen)
 {
-    int64_t m = status->n_starts;
-    if (m > cap) m = cap;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cap;
+    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
+    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
+    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
          t += (int64_t)gridDim.x * blockDim.x) {
         uint64_t out = 0;
-        if (t < m) {
+        {
             const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
             if (key) {
-                const int32_t* th = t_hits + t * n_rows;
                 int kept = 0;
                 for (int r = 0; r < n_rows; ++r) {
-                    const int c = th[r];
+                    const int c = t_hits[(int64_t)r * cap + t];
                     kept += c >= 0 && hitkey[c] == key;
                 }
                 if (kept >= prm.min_track_hits) out = (1ull << 32) | (uint64_t)kept;
@@ -59,17 +59,18 @@ __global__ __launch_bounds__(kBlock) void k_sel_count(
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sel_write(
+__global__ __launch_bounds__(kWave) void k_sel_write(
     int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, const uint64_t* __restrict__ tlen,
-    const uint64_t* __restrict__ toff, int32_t* __restrict__ trk_off,
-    int32_t* __restrict__ trk_hits, int32_t* __restrict__ trk_tracklet, int64_t trk_cap,
-    int64_t hit_cap)
+    const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t count_cap,
+    int64_t cap, const unsigned long long* __restrict__ hitkey, const uint64_t* __restrict__ tlen,
+    const uint64_t* __restrict__ toff, const tpc_sector* __restrict__ sec,
+    const int32_t* __restrict__ gsr, int32_t* __restrict__ trk_off,
+    int32_t* __restrict__ trk_hits, int32_t* __restrict__ trk_tracklet,
+    int8_t* __restrict__ trk_side, int64_t trk_cap, int64_t hit_cap)
 {
     int64_t m = status->n_starts;
-    if (m > cap) m = cap;
+    if (m > count_cap) m = count_cap;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
          t += (int64_t)gridDim.x * blockDim.x) {
         if (!tlen[t]) continue;
@@ -78,11 +79,11 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(
         if (k < trk_cap) {
             trk_tracklet[k] = (int32_t)t;
             trk_off[k] = (int32_t)o;
+            if (trk_side) trk_side[k] = sec[gsr[t_start[t]] >> 8].side < 0 ? -1 : 1;
         }
         const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
-        const int32_t* th = t_hits + t * n_rows;
         for (int r = 0; r < n_rows; ++r) {
-            const int c = th[r];
+            const int c = t_hits[(int64_t)r * cap + t];
             if (c >= 0 && hitkey[c] == key) {
                 if (o < hit_cap) trk_hits[o] = idg[c];
                 ++o;
@@ -104,33 +105,53 @@ __global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status
     if (nh > hit_cap) status->overflow |= 4;
 }
 
-int run_select_tracks(const tpc_problem* p, tpc_grid grid, tpc_starts starts,
+// Ownership keys and kept-hit counts of the tracklets of sectors
+// [sec_lo, sec_hi) (their hits are grid positions of those sectors).
+int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
+                    int64_t count_cap, tpc_tracklets trl, const Workspace& ws, hipStream_t st)
+{
+    const int64_t c0 = p->h_sectors[sec_lo].begin, c1 = p->h_sectors[sec_hi - 1].end;
+    const int64_t bound = (c1 - c0) / 3 + 1;
+    const unsigned gt = grid_for_block(bound < count_cap ? bound : count_cap, kWave, 65536);
+    const int64_t* lo = ws.sec_start + sec_lo;
+    const int64_t* hi = ws.sec_start + sec_hi;
+    launch_fill<uint64_t>(ws.hitkey + c0, 0ull, c1 - c0, st);
+    TPC_LAUNCH(k_sel_keys, dim3(gt), dim3(kWave), 0, st, p->n_rows, p->params,
+               (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
+               (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
+               (unsigned long long*)ws.hitkey);
+    TPC_LAUNCH(k_sel_count, dim3(gt), dim3(kWave), 0, st, p->n_rows, p->params,
+               (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
+               (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
+               (const unsigned long long*)ws.hitkey, ws.tlen);
+    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+// Dense track list in tracklet order from the kept-hit counts of all
+// tracklets [0, count_cap) (tlen zero where no track).
+int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
+                       tpc_tracklets trl, tpc_tracks trk, const Workspace& ws, hipStream_t st)
+{
+    const unsigned gt = grid_for_block(count_cap, kWave, 65536);
+    launch_scan<uint64_t>(ws.tlen, ws.toff, count_cap, true, nullptr, nullptr, ws.partials, st);
+    TPC_LAUNCH(k_sel_write, dim3(gt), dim3(kWave), 0, st, p->n_rows, p->params,
+               (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
+               (const int32_t*)trl.nhits, (const tpc_status*)ws.status, count_cap, trl.capacity,
+               (const unsigned long long*)ws.hitkey, (const uint64_t*)ws.tlen,
+               (const uint64_t*)ws.toff, p->d_sectors, (const int32_t*)ws.gsr, trk.off,
+               trk.hits, trk.tracklet, trk.side, trk.capacity, trk.hit_capacity);
+    TPC_LAUNCH(k_sel_finish, dim3(1), dim3(1), 0, st, (const uint64_t*)(ws.toff + count_cap),
+               ws.status, trk.off, trk.capacity, trk.hit_capacity);
+    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+int run_select_tracks(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
                       tpc_tracklets trl, tpc_tracks trk, const Workspace& ws, hipStream_t st)
 {
-    (void)starts;
-    const int64_t cap = trl.capacity;
-    const unsigned gt = grid_for(cap, 4096);
-    launch_fill<uint64_t>(ws.hitkey, 0ull, p->n_clusters, st);
-    hipLaunchKernelGGL(k_sel_keys, dim3(gt), dim3(kBlock), 0, st, p->n_rows, p->params,
-                       (const int32_t*)grid.id, (const int32_t*)trl.start,
-                       (const int32_t*)trl.hits, (const int32_t*)trl.nhits,
-                       (const tpc_status*)ws.status, cap, (unsigned long long*)ws.hitkey);
-    hipLaunchKernelGGL(k_sel_count, dim3(gt), dim3(kBlock), 0, st, p->n_rows, p->params,
-                       (const int32_t*)grid.id, (const int32_t*)trl.start,
-                       (const int32_t*)trl.hits, (const int32_t*)trl.nhits,
-                       (const tpc_status*)ws.status, cap,
-                       (const unsigned long long*)ws.hitkey, ws.tlen);
-    launch_scan<uint64_t>(ws.tlen, ws.toff, cap, true, nullptr, nullptr, ws.partials, st);
-    hipLaunchKernelGGL(k_sel_write, dim3(gt), dim3(kBlock), 0, st, p->n_rows, p->params,
-                       (const int32_t*)grid.id, (const int32_t*)trl.start,
-                       (const int32_t*)trl.hits, (const int32_t*)trl.nhits,
-                       (const tpc_status*)ws.status, cap,
-                       (const unsigned long long*)ws.hitkey, (const uint64_t*)ws.tlen,
-                       (const uint64_t*)ws.toff, trk.off, trk.hits, trk.tracklet, trk.capacity,
-                       trk.hit_capacity);
-    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(1), 0, st, (const uint64_t*)(ws.toff + cap),
-                       ws.status, trk.off, trk.capacity, trk.hit_capacity);
-    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+    launch_fill<uint64_t>(ws.tlen, 0ull, count_cap + 1, st);
+    int r = run_select_keys(p, 0, p->n_sectors, grid, count_cap, trl, ws, st);
+    if (!r) r = run_select_compact(p, grid, count_cap, trl, trk, ws, st);
+    return r;
 }
 
 }  // namespace tpc

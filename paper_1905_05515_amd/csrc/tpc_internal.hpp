@@ -29,6 +29,7 @@ struct Workspace {
     uint64_t* hitkey;      // [n] selection keys per grid position
     uint64_t* tlen;        // [start_cap + 1] per tracklet: accepted << 32 | kept
     uint64_t* toff;        // [start_cap + 1] exclusive scan of tlen
+    int64_t* sec_start;    // [n_sectors + 1] first start of each sector
     size_t bytes;
 };
 
@@ -41,6 +42,12 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline unsigned grid_for(int64_t n, int64_t cap = 16384)
 {
     int64_t g = ceil_div(n > 0 ? n : 1, kBlock);
+    return (unsigned)(g < cap ? g : cap);
+}
+
+inline unsigned grid_for_block(int64_t n, int block, int64_t cap)
+{
+    int64_t g = ceil_div(n > 0 ? n : 1, block);
     return (unsigned)(g < cap ? g : cap);
 }
 
@@ -67,8 +74,10 @@ __device__ inline int bin_of(float v, float v0, float inv, int nb)
     return (int)f;
 }
 
-__device__ inline int global_bin(const tpc_sector& s, int row, float y, float z)
+// bin of a cluster; rows >= n_rows go to the sector's last (invalid-row) bin
+__device__ inline int global_bin(const tpc_sector& s, int n_rows, int row, float y, float z)
 {
+    if (row >= n_rows) return s.bin_base + n_rows * s.nbz * s.nby;
     int iy = bin_of(y, s.y0, s.inv_by, s.nby);
     int iz = bin_of(z, s.z0, s.inv_bz, s.nbz);
     return s.bin_base + (row * s.nbz + iz) * s.nby + iy;
@@ -79,17 +88,42 @@ __device__ inline int global_bin(const tpc_sector& s, int row, float y, float z)
 // decides.
 #define TPC_WIDEN (1.0f + 1.0f / 64.0f)
 
+// ---- per-kernel timing (host) ----------------------------------------------
+// When a context has timing enabled, every launch made on its behalf is
+// bracketed by two HIP events on the launch stream (not while the stream is
+// being captured into a graph).
+
+struct KernelTimer;
+KernelTimer* current_timer();
+void set_current_timer(KernelTimer* t);
+void timer_begin(const char* name, hipStream_t st);
+void timer_end(hipStream_t st);
+
+struct TimerScope {
+    KernelTimer* saved;
+    explicit TimerScope(KernelTimer* t) : saved(current_timer()) { set_current_timer(t); }
+    ~TimerScope() { set_current_timer(saved); }
+};
+
+#define TPC_LAUNCH(k, g, b, sh, st, ...)                      \
+    do {                                                      \
+        ::tpc::timer_begin(#k, st);                           \
+        hipLaunchKernelGGL(k, g, b, sh, st, __VA_ARGS__);     \
+        ::tpc::timer_end(st);                                 \
+    } while (0)
+
 // ---- launch helpers (host) --------------------------------------------------
 
 template <typename T>
 void launch_fill(T* p, T v, int64_t n, hipStream_t st);
 
-// Exclusive scan of in[0..n) into out[0..n), starting from *carry_in
-// (device, nullable: 0); out[n] = carry + total when write_total;
+// Exclusive scan of in[0..n) into out[0..n), starting from carry0 +
+// *carry_in (device, nullable: 0); out[n] = carry + total when write_total;
 // *total_dst (device, nullable) = carry + total.  in may equal out.
 template <typename T>
 void launch_scan(const T* in, T* out, int64_t n, bool write_total, int64_t* total_dst,
-                 const int64_t* carry_in, int64_t* partials, hipStream_t st);
+                 const int64_t* carry_in, int64_t* partials, hipStream_t st,
+                 int64_t carry0 = 0);
 
 // Exclusive scan, in place, of nt int64 tile partials by one block.
 void launch_scan_partials(int64_t* partials, int64_t nt, const int64_t* carry_in,
@@ -100,22 +134,34 @@ void launch_scan_partials(int64_t* partials, int64_t nt, const int64_t* carry_in
 struct tpc_context {
     int device;
     int n_cu;
+    tpc::KernelTimer* timer;   // non-null while timing is enabled
     // cached graph of tpc_track_batch
     hipGraphExec_t graph_exec;
     uint64_t graph_key;
     bool graph_valid;
 };
 
-// stage launchers (stream-ordered, no host synchronisation)
+// stage launchers (stream-ordered, no host synchronisation); the sector
+// range [sec_lo, sec_hi) selects the sectors a launch covers
 namespace tpc {
 int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in,
                    tpc_grid out, const Workspace& ws, hipStream_t st);
-int run_find_neighbours(const tpc_problem* p, tpc_grid grid, tpc_links links,
-                        tpc_starts starts, const Workspace& ws, hipStream_t st);
-int run_construct_tracklets(const tpc_problem* p, tpc_grid grid, tpc_links links,
-                            tpc_starts starts, tpc_tracklets trl, const Workspace& ws,
-                            hipStream_t st);
-int run_select_tracks(const tpc_problem* p, tpc_grid grid, tpc_starts starts,
+int run_find_neighbours(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
+                        tpc_links links, tpc_starts starts, const Workspace& ws,
+                        hipStream_t st);
+int run_construct_tracklets(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
+                            tpc_links links, tpc_starts starts, tpc_tracklets trl,
+                            const Workspace& ws, hipStream_t st);
+int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
+                    int64_t count_cap, tpc_tracklets trl, const Workspace& ws, hipStream_t st);
+int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
+                       tpc_tracklets trl, tpc_tracks trk, const Workspace& ws, hipStream_t st);
+// all four stages in one persistent launch over a device work queue
+int run_persistent(tpc_context* ctx, const tpc_problem* p, tpc_clusters in, tpc_grid grid,
+                   tpc_links links, tpc_starts starts, tpc_tracklets trl, tpc_tracks trk,
+                   const Workspace& ws, hipStream_t st);
+// count_cap bounds the tracklets selected (<= the workspace's start capacity)
+int run_select_tracks(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
                       tpc_tracklets trl, tpc_tracks trk, const Workspace& ws,
                       hipStream_t st);
 }  // namespace tpc

@@ -132,7 +132,7 @@ __device__ __forceinline__ void reset_cov(KState& st, const tpc_params& prm)
 // lower cluster id; -1 if none.  The bins scanned cover +-nsigma of the
 // prediction (every hit passing the gate lies inside); the gate decides.
 __device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s, int r,
-                                          const tpc_params& prm,
+                                          const tpc_params& prm, int& n_cand,
                                           const int32_t* __restrict__ bin_start,
                                           const float* __restrict__ yg,
                                           const float* __restrict__ zg,
@@ -150,6 +150,7 @@ __device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s,
     for (int iz = iz0; iz <= iz1; ++iz) {
         const int g = s.bin_base + (r * s.nbz + iz) * s.nby;
         const int pe = bin_start[g + iy1 + 1];
+        n_cand += pe - bin_start[g + iy0] > 0 ? pe - bin_start[g + iy0] : 0;
         for (int pc = bin_start[g + iy0]; pc < pe; ++pc) {
             const float c2 = chi2_pred(st, yg[pc], zg[pc], prm.sigma_y2, prm.sigma_z2);
             if (!(c2 <= prm.chi2_max)) continue;
@@ -164,12 +165,14 @@ __device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s,
     return bpos;
 }
 
-__global__ __launch_bounds__(kBlock) void k_tracklets(
+__global__ __launch_bounds__(kWave) void k_tracklets(
     const tpc_sector* __restrict__ sec, int n_rows, const float* __restrict__ row_x,
     tpc_params prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
     const float* __restrict__ zg, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ gsr, const int32_t* __restrict__ up,
-    const int32_t* __restrict__ starts, const tpc_status* __restrict__ status, int64_t cap,
+    const int32_t* __restrict__ starts, tpc_status* __restrict__ status,
+    const int64_t* __restrict__ t_lo, const int64_t* __restrict__ t_hi, int64_t count_cap,
+    int64_t cap,
     int32_t* __restrict__ t_start, int32_t* __restrict__ t_hits, int32_t* __restrict__ t_nhits,
     int32_t* __restrict__ t_rin, float* __restrict__ t_par, float* __restrict__ t_cov,
     float* __restrict__ t_chi2)
@@ -177,13 +180,15 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
     __shared__ float xs[256];
     for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
     __syncthreads();
-    int64_t m = status->n_starts;
-    if (m > cap) m = cap;
+    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
+    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
     const float sy2 = prm.sigma_y2, sz2 = prm.sigma_z2;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+    int n_prop = 0, n_upd = 0, n_cand = 0;
+    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
          t += (int64_t)gridDim.x * blockDim.x) {
-        int32_t* th = t_hits + t * n_rows;
-        for (int r = 0; r < n_rows; ++r) th[r] = -1;
+        // hit list of this tracklet: column t of the [row][tracklet] array
+        int32_t* th = t_hits + t;
+        for (int r = 0; r < n_rows; ++r) th[(int64_t)r * cap] = -1;
         const int h0 = starts[t];
         const int v0 = gsr[h0];
         const tpc_sector s = sec[v0 >> 8];
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
             st.p[4] = 0.0f;
             reset_cov(st, prm);
         }
-        th[r0] = h0;
+        th[(int64_t)(r0) * cap] = h0;
         int cur = r0, last = r0;
         float plast[5];
 #pragma unroll
@@ -211,12 +216,13 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
         // outwards along the chain
         for (int h = h1; h >= 0; h = up[h]) {
             const int r = gsr[h] & 255;
-            if (!propagate(st, xs[r] - xs[cur], prm.curv, prm.s_max)) {
+            if (!(++n_prop, propagate(st, xs[r] - xs[cur], prm.curv, prm.s_max))) {
                 ok = false;
                 break;
             }
+            ++n_upd;
             kupdate(st, yg[h], zg[h], sy2, sz2);
-            th[r] = h;
+            th[(int64_t)(r) * cap] = h;
             cur = last = r;
 #pragma unroll
             for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
@@ -225,11 +231,12 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
         if (ok) {
             int miss = 0;
             for (int r = cur + 1; r < n_rows; ++r) {
-                if (!propagate(st, xs[r] - xs[r - 1], prm.curv, prm.s_max)) break;
-                const int c = search_row(st, s, r, prm, bin_start, yg, zg, idg);
+                if (!(++n_prop, propagate(st, xs[r] - xs[r - 1], prm.curv, prm.s_max))) break;
+                const int c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg);
                 if (c >= 0) {
+                    ++n_upd;
                     kupdate(st, yg[c], zg[c], sy2, sz2);
-                    th[r] = c;
+                    th[(int64_t)(r) * cap] = c;
                     last = r;
 #pragma unroll
                     for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
@@ -240,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
             }
         }
         // inwards from the outermost hit with the initial covariance
-        const int hl = th[last];
+        const int hl = th[(int64_t)(last) * cap];
 #pragma unroll
         for (int i = 0; i < 5; ++i) st.p[i] = plast[i];
         st.p[0] = yg[hl];
@@ -250,15 +257,15 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
         float csum = 0.0f;
         int rin = last, miss = 0;
         for (int r = last - 1; r >= 0; --r) {
-            if (!propagate(st, xs[r] - xs[r + 1], prm.curv, prm.s_max)) {
-                for (int q = r; q >= 0; --q) th[q] = -1;
+            if (!(++n_prop, propagate(st, xs[r] - xs[r + 1], prm.curv, prm.s_max))) {
+                for (int q = r; q >= 0; --q) th[(int64_t)(q) * cap] = -1;
                 break;
             }
             int c;
             if (r >= r0) {
-                c = th[r];
+                c = th[(int64_t)(r) * cap];
             } else {
-                c = search_row(st, s, r, prm, bin_start, yg, zg, idg);
+                c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg);
                 if (c < 0) {
                     if (++miss >= prm.max_miss) break;
                     continue;
@@ -266,14 +273,15 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
                 miss = 0;
             }
             if (c >= 0) {
+                ++n_upd;
                 csum = csum + kupdate(st, yg[c], zg[c], sy2, sz2);
-                th[r] = c;
+                th[(int64_t)(r) * cap] = c;
                 rin = r;
                 in = st;
             }
         }
         int nh = 0;
-        for (int r = 0; r < n_rows; ++r) nh += th[r] >= 0;
+        for (int r = 0; r < n_rows; ++r) nh += th[(int64_t)(r) * cap] >= 0;
         t_start[t] = h0;
         t_nhits[t] = nh;
         t_rin[t] = rin;
@@ -283,19 +291,39 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(
         for (int i = 0; i < 15; ++i) t_cov[t * 15 + i] = in.C[i];
         t_chi2[t] = csum;
     }
+    // work counters: one atomic per wave
+    unsigned long long a = n_prop, b = n_upd, c = n_cand;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, kWave);
+        b += __shfl_xor(b, o, kWave);
+        c += __shfl_xor(c, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0 && (a | b | c)) {
+        atomicAdd((unsigned long long*)&status->n_propagations, a);
+        atomicAdd((unsigned long long*)&status->n_updates, b);
+        atomicAdd((unsigned long long*)&status->n_candidates, c);
+    }
 }
 
-int run_construct_tracklets(const tpc_problem* p, tpc_grid grid, tpc_links links,
-                            tpc_starts starts, tpc_tracklets trl, const Workspace& ws,
-                            hipStream_t st)
+// Tracklets of the starts of sectors [sec_lo, sec_hi) (the start range that
+// run_find_neighbours recorded for them).
+int run_construct_tracklets(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
+                            tpc_links links, tpc_starts starts, tpc_tracklets trl,
+                            const Workspace& ws, hipStream_t st)
 {
-    const int64_t cap = starts.capacity < trl.capacity ? starts.capacity : trl.capacity;
-    hipLaunchKernelGGL(k_tracklets, dim3(grid_for(cap, 4096)), dim3(kBlock), 0, st, p->d_sectors,
-                       p->n_rows, p->d_row_x, p->params, (const int32_t*)grid.bin_start,
-                       (const float*)grid.y, (const float*)grid.z, (const int32_t*)grid.id,
-                       (const int32_t*)ws.gsr, (const int32_t*)links.up,
-                       (const int32_t*)starts.pos, (const tpc_status*)ws.status, cap, trl.start,
-                       trl.hits, trl.nhits, trl.row_inner, trl.par, trl.cov, trl.chi2);
+    // tracklets processed: bounded by both capacities; the hit array's row
+    // stride is the tracklet capacity
+    const int64_t count_cap = starts.capacity < trl.capacity ? starts.capacity : trl.capacity;
+    const int64_t bound = (p->h_sectors[sec_hi - 1].end - p->h_sectors[sec_lo].begin) / 3 + 1;
+    const int64_t n_launch = bound < count_cap ? bound : count_cap;
+    TPC_LAUNCH(k_tracklets, dim3(grid_for_block(n_launch, kWave, 65536)), dim3(kWave), 0, st,
+               p->d_sectors, p->n_rows, p->d_row_x, p->params, (const int32_t*)grid.bin_start,
+               (const float*)grid.y, (const float*)grid.z, (const int32_t*)grid.id,
+               (const int32_t*)ws.gsr, (const int32_t*)links.up, (const int32_t*)starts.pos,
+               ws.status, (const int64_t*)(ws.sec_start + sec_lo),
+               (const int64_t*)(ws.sec_start + sec_hi), count_cap, trl.capacity, trl.start,
+               trl.hits, trl.nhits, trl.row_inner, trl.par, trl.cov, trl.chi2);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

@@ -2,7 +2,10 @@
 #include "tpc_internal.hpp"
 
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
+#include <vector>
 
 namespace tpc {
 
@@ -20,7 +23,7 @@ template <typename T>
 void launch_fill(T* p, T v, int64_t n, hipStream_t st)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 8192)), dim3(kBlock), 0, st, p, v, n);
+    TPC_LAUNCH(k_fill<T>, dim3(grid_for(n, 8192)), dim3(kBlock), 0, st, p, v, n);
 }
 template void launch_fill<int32_t>(int32_t*, int32_t, int64_t, hipStream_t);
 template void launch_fill<uint64_t>(uint64_t*, uint64_t, int64_t, hipStream_t);
@@ -85,13 +88,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(const T* __restrict__
 }
 
 // phase 2: exclusive scan of the tile sums by one block, starting from
-// *carry_in (device, nullable); *total_dst (nullable) = carry + total.
+// carry0 + *carry_in (device, nullable); *total_dst (nullable) = carry + total.
 __global__ __launch_bounds__(kBlock) void k_scan_partials(int64_t* __restrict__ partials, int64_t nt,
-                                                          const int64_t* carry_in,
+                                                          const int64_t* carry_in, int64_t carry0,
                                                           int64_t* total_dst)
 {
     __shared__ int64_t lds[kBlock / kWave];
-    int64_t carry = carry_in ? *carry_in : 0;
+    int64_t carry = carry0 + (carry_in ? *carry_in : 0);
     __syncthreads();
     for (int64_t b = 0; b < nt; b += kScanTile) {
         int64_t base = b + (int64_t)threadIdx.x * kScanItems;
@@ -141,27 +144,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const T* in, T* out, int6
 
 template <typename T>
 void launch_scan(const T* in, T* out, int64_t n, bool write_total, int64_t* total_dst,
-                 const int64_t* carry_in, int64_t* partials, hipStream_t st)
+                 const int64_t* carry_in, int64_t* partials, hipStream_t st, int64_t carry0)
 {
     int64_t nt = ceil_div(n > 0 ? n : 1, kScanTile);
-    hipLaunchKernelGGL(k_scan_tile_sums<T>, dim3((unsigned)nt), dim3(kBlock), 0, st, in, n,
+    TPC_LAUNCH(k_scan_tile_sums<T>, dim3((unsigned)nt), dim3(kBlock), 0, st, in, n,
                        partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, st, partials, nt, carry_in,
+    TPC_LAUNCH(k_scan_partials, dim3(1), dim3(kBlock), 0, st, partials, nt, carry_in, carry0,
                        total_dst);
-    hipLaunchKernelGGL(k_scan_tiles<T>, dim3((unsigned)nt), dim3(kBlock), 0, st, in, out, n,
+    TPC_LAUNCH(k_scan_tiles<T>, dim3((unsigned)nt), dim3(kBlock), 0, st, in, out, n,
                        (const int64_t*)partials, write_total ? 1 : 0);
 }
 void launch_scan_partials(int64_t* partials, int64_t nt, const int64_t* carry_in,
                           int64_t* total_dst, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, st, partials, nt, carry_in,
-                       total_dst);
+    TPC_LAUNCH(k_scan_partials, dim3(1), dim3(kBlock), 0, st, partials, nt, carry_in,
+               (int64_t)0, total_dst);
 }
 
 template void launch_scan<int32_t>(const int32_t*, int32_t*, int64_t, bool, int64_t*,
-                                   const int64_t*, int64_t*, hipStream_t);
+                                   const int64_t*, int64_t*, hipStream_t, int64_t);
 template void launch_scan<uint64_t>(const uint64_t*, uint64_t*, int64_t, bool, int64_t*,
-                                    const int64_t*, int64_t*, hipStream_t);
+                                    const int64_t*, int64_t*, hipStream_t, int64_t);
 
 // ---- workspace ----------------------------------------------------------------
 
@@ -188,8 +191,75 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->hitkey = (uint64_t*)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));
     ws->toff = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 2));
+    ws->sec_start = (int64_t*)take(sizeof(int64_t) * (size_t)(p->n_sectors + 1));
     ws->bytes = o;
     return true;
+}
+
+// ---- per-kernel timing ---------------------------------------------------------
+
+struct KernelTimer {
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Rec> recs;
+    const char* pending = nullptr;
+    hipEvent_t pending_ev = nullptr;
+
+    hipEvent_t take()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void reset()
+    {
+        used = 0;
+        recs.clear();
+        pending = nullptr;
+    }
+    ~KernelTimer()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+static thread_local KernelTimer* t_timer = nullptr;
+
+KernelTimer* current_timer() { return t_timer; }
+void set_current_timer(KernelTimer* t) { t_timer = t; }
+
+static bool capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+void timer_begin(const char* name, hipStream_t st)
+{
+    KernelTimer* t = t_timer;
+    if (!t || capturing(st)) return;
+    for (const char* c = name; *c; ++c)      // drop namespace qualifiers
+        if (c[0] == ':' && c[1] == ':') name = c + 2;
+    hipEvent_t e = t->take();
+    if (!e || hipEventRecord(e, st) != hipSuccess) return;
+    t->pending = name;
+    t->pending_ev = e;
+}
+
+void timer_end(hipStream_t st)
+{
+    KernelTimer* t = t_timer;
+    if (!t || !t->pending) return;
+    hipEvent_t e = t->take();
+    if (e && hipEventRecord(e, st) == hipSuccess) t->recs.push_back({t->pending, t->pending_ev, e});
+    t->pending = nullptr;
 }
 
 }  // namespace tpc
@@ -215,6 +285,7 @@ int tpc_context_create(tpc_context** out, int device)
     c->graph_exec = nullptr;
     c->graph_key = 0;
     c->graph_valid = false;
+    c->timer = nullptr;
     *out = c;
     return TPC_OK;
 }
@@ -223,7 +294,56 @@ int tpc_context_destroy(tpc_context* ctx)
 {
     if (!ctx) return TPC_ERR_INVALID_ARG;
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    delete ctx->timer;
     delete ctx;
+    return TPC_OK;
+}
+
+int tpc_timing_enable(tpc_context* ctx, int enable)
+{
+    if (!ctx) return TPC_ERR_INVALID_ARG;
+    if (enable) {
+        if (!ctx->timer) ctx->timer = new (std::nothrow) tpc::KernelTimer();
+        if (!ctx->timer) return TPC_ERR_HIP;
+        ctx->timer->reset();
+    } else {
+        delete ctx->timer;
+        ctx->timer = nullptr;
+    }
+    return TPC_OK;
+}
+
+int tpc_timing_report(tpc_context* ctx, int max_kernels, const char** h_names,
+                      int64_t* h_launches, double* h_total_ms, int* h_count)
+{
+    if (!ctx || !ctx->timer || max_kernels < 0 || !h_count) return TPC_ERR_INVALID_ARG;
+    tpc::KernelTimer* t = ctx->timer;
+    std::vector<const char*> order;
+    std::map<std::string, std::pair<int64_t, double>> agg;
+    for (const auto& r : t->recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return TPC_ERR_HIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return TPC_ERR_HIP;
+        auto it = agg.find(r.name);
+        if (it == agg.end()) {
+            order.push_back(r.name);
+            agg[r.name] = {1, (double)ms};
+        } else {
+            it->second.first += 1;
+            it->second.second += ms;
+        }
+    }
+    int n = 0;
+    for (const char* name : order) {
+        if (n < max_kernels) {
+            if (h_names) h_names[n] = name;
+            if (h_launches) h_launches[n] = agg[name].first;
+            if (h_total_ms) h_total_ms[n] = agg[name].second;
+        }
+        ++n;
+    }
+    *h_count = n;
+    t->reset();
     return TPC_OK;
 }
 
@@ -239,7 +359,7 @@ static int check_problem(const tpc_problem* p)
         if (q.begin != prev_end || q.end < q.begin || q.nby <= 0 || q.nbz <= 0 ||
             q.bin_base != bins || !(q.inv_by > 0.0f) || !(q.inv_bz > 0.0f))
             return TPC_ERR_INVALID_ARG;
-        bins += (int64_t)p->n_rows * q.nby * q.nbz;
+        bins += (int64_t)p->n_rows * q.nby * q.nbz + 1;
         prev_end = q.end;
     }
     if (prev_end != p->n_clusters || bins != p->n_bins) return TPC_ERR_INVALID_ARG;

@@ -73,6 +73,11 @@ class Event:
     label: np.ndarray          # int32 [n]: generating track, -1 for noise
     tracks: dict               # float64 arrays: vx vy vz phi0 tanl qpt
     meta: dict
+    sector_side: np.ndarray = None   # int8 [n_sectors]: +1 z >= 0 side, -1 z < 0
+
+    def __post_init__(self):
+        if self.sector_side is None:
+            self.sector_side = np.ones(self.sector_offsets.shape[0] - 1, np.int8)
 
     @property
     def n_clusters(self) -> int:
@@ -87,7 +92,8 @@ class Event:
         a, b = int(self.sector_offsets[s]), int(self.sector_offsets[s + 1])
         return Event(self.row[a:b], self.y[a:b], self.z[a:b], self.charge[a:b],
                      np.array([0, b - a], np.int64), self.sector_range[s:s + 1].copy(),
-                     self.row_x, self.label[a:b], self.tracks, dict(self.meta, sector=s))
+                     self.row_x, self.label[a:b], self.tracks, dict(self.meta, sector=s),
+                     self.sector_side[s:s + 1].copy())
 
 
 @dataclasses.dataclass
@@ -348,9 +354,10 @@ def _pack_sectors(rng, sector, row, y, z, lab, trk, zranges, meta):
     ymax = float(ROW_X64[-1] * TAN10)
     srange = np.array([[-ymax, ymax, zr[0], zr[1]] for zr in zranges], np.float32)
     charge = rng.gamma(2.0, 20.0, row.shape[0]).astype(np.float32)
+    side = np.array([1] * N_SECTORS_PER_SIDE + [-1] * N_SECTORS_PER_SIDE, np.int8)
     return Event(row[order].astype(np.uint8), y[order].astype(np.float32),
                  z[order].astype(np.float32), charge, offs, srange, ROW_X.copy(),
-                 lab[order].astype(np.int32), trk, meta)
+                 lab[order].astype(np.int32), trk, meta, side)
 
 
 def make_config2(seed=CONFIG_SEEDS[2], n_primary=8000):

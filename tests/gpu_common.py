@@ -21,7 +21,7 @@ def ctx():
 def run_gpu(ev, prm=None, occupancy=2.0, mode=None, use_graph=False, layout=None, **kw):
     prm = prm or synth.default_params()
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
-                       occupancy=occupancy, layout=layout, **kw)
+                       occupancy=occupancy, layout=layout, sector_side=ev.sector_side, **kw)
     if mode is None:
         api.track(ctx(), e)
     else:
@@ -32,7 +32,8 @@ def run_gpu(ev, prm=None, occupancy=2.0, mode=None, use_graph=False, layout=None
 def run_oracle(ev, prm=None, occupancy=2.0, layout=None):
     prm = prm or synth.default_params()
     tab, nb = layout if layout is not None else grid_layout(ev.sector_offsets, ev.sector_range,
-                                                            occupancy=occupancy)
+                                                            occupancy=occupancy,
+                                                            sides=ev.sector_side)
     return oracle.track_event(ev.row, ev.y, ev.z, tab, nb, ev.row_x, prm)
 
 
@@ -71,6 +72,8 @@ def assert_same_tracking(g, o, n_clusters):
     assert np.array_equal(g["t_par"].view(np.uint32), tr["par"].view(np.uint32))
     assert np.array_equal(g["t_cov"].view(np.uint32), tr["cov"].view(np.uint32))
     assert np.array_equal(g["t_chi2"].view(np.uint32), tr["chi2"].view(np.uint32))
+    # the same transports, updates and candidate evaluations were made
+    assert (s["n_propagations"], s["n_updates"], s["n_candidates"]) == tr["work"]
     t = o["tracks"]
     assert np.array_equal(g["trk_off"], t["trk_off"])
     assert np.array_equal(g["trk_hits"], t["trk_hits"])

@@ -73,6 +73,7 @@ def test_edge_cases_empty_sector_bad_rows_single_bin():
     _, g = run_gpu(sub)
     o = run_oracle(sub)
     assert g["status"]["n_bad_rows"] == 2
+    assert g["status"]["n_grid"] == sub.n_clusters
     assert_same_tracking(g, o, sub.n_clusters)
     # every sector in a single bin per row: the searches scan whole rows
     lay = grid_layout(offs, rng_, occupancy=1e9)

@@ -32,8 +32,9 @@ def _single_sector(row, y, z, yr=None, zr=(0.0, 250.0), occupancy=2.0, n_rows=15
 
 # ---------------------------------------------------------------- grid
 
-def _bin_key(row, y, z, tab, sector_of):
-    """Global bin of each cluster, same clamp-and-truncate definition."""
+def _bin_key(row, y, z, tab, sector_of, n_rows=152):
+    """Global bin of each cluster, same clamp-and-truncate definition; rows
+    >= n_rows in the sector's last bin."""
     s = tab[sector_of]
     fy = (y - s["y0"]) * s["inv_by"]
     fz = (z - s["z0"]) * s["inv_bz"]
@@ -41,8 +42,10 @@ def _bin_key(row, y, z, tab, sector_of):
     fz = np.where(fz >= 0, fz, F32(0))
     fy = np.minimum(fy, (s["nby"] - 1).astype(np.float32))
     fz = np.minimum(fz, (s["nbz"] - 1).astype(np.float32))
-    return s["bin_base"] + (row.astype(np.int64) * s["nbz"] + fz.astype(np.int64)) * s["nby"] \
+    key = s["bin_base"] + (row.astype(np.int64) * s["nbz"] + fz.astype(np.int64)) * s["nby"] \
         + fy.astype(np.int64)
+    bad = row >= n_rows
+    return np.where(bad, s["bin_base"] + n_rows * s["nbz"] * s["nby"], key)
 
 
 @pytest.mark.parametrize("occ", [0.5, 2.0, 7.0])
@@ -62,19 +65,25 @@ def test_grid_is_stable_sort_by_bin(occ):
 
 
 def test_grid_multi_sector_and_bad_rows():
+    """Sectors occupy their own id range of grid positions; a cluster with an
+    invalid row lands in its sector's last bin, after every valid one."""
     ev = synth.make_config2()
     sel = np.concatenate([np.arange(ev.sector_offsets[s], ev.sector_offsets[s] + 500) for s in range(5)])
     row = ev.row[sel].copy()
-    row[7] = 200                      # out of range: left out of the grid
+    row[7] = 200
+    row[1203] = 152
     off = np.arange(6, dtype=np.int64) * 500
     tab, nb = grid_layout(off, ev.sector_range[:5])
     g = oracle.build_grid(row, ev.y[sel], ev.z[sel], tab, nb)
-    assert g["idg"].shape[0] == 2499 and 7 not in set(g["idg"].tolist())
+    assert g["idg"].shape[0] == 2500
     sec = np.repeat(np.arange(5), 500)
-    key = _bin_key(np.minimum(row, 151), ev.y[sel], ev.z[sel], tab, sec)
-    keep = row < 152
-    order = np.nonzero(keep)[0][np.argsort(key[keep], kind="stable")]
+    key = _bin_key(row, ev.y[sel], ev.z[sel], tab, sec)
+    order = np.argsort(key, kind="stable")
     assert np.array_equal(g["idg"], order.astype(np.int32))
+    assert g["idg"][499] == 7 and g["idg"][1499] == 1203
+    for s in range(5):
+        assert g["bin_start"][tab["bin_base"][s]] == 500 * s
+        assert np.all(g["idg"][500 * s:500 * (s + 1)] // 500 == s)
 
 
 # ---------------------------------------------------------------- neighbours

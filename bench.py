@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--refit-tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-refit-bench", action="store_true")
+    ap.add_argument("--no-batch-bench", action="store_true")
     ap.add_argument("--occupancy", type=float, default=2.0)
     return ap.parse_args()
 
@@ -130,6 +131,8 @@ def main():
     roof = roofline(dom, kernels[dom]["avg_ms"], st, n_cl, n_hits_trk)
 
     extra = {}
+    if not args.no_batch_bench:
+        extra["batched_vs_per_sector"] = batch_bench(args, api, synth, ctx, stream, prm)
     if not args.no_refit_bench:
         extra["refit_adjoint"] = refit_bench(args, api, synth, ctx, stream, prm, dev)
     cpu = None if args.no_cpu else cpu_baseline(ev, prm, args)
@@ -205,6 +208,47 @@ def roofline(name, avg_ms, st, n_cl, n_trk_hits):
                 "algorithmic_bytes_per_unit": per_hit}
     return {"kernel": name, "bound": "unknown", "achieved": None, "peak": None, "unit": None,
             "frac": None, "traffic": None}
+
+
+def batch_bench(args, api, synth, ctx, stream, prm):
+    """The 512 uneven single-sector instances (~14M clusters) tracked in the
+    three launch forms; the outputs are checked equal."""
+    import numpy as np
+    import torch
+    t0 = time.time()
+    ev = synth.make_config4()
+    log(f"[bench] batched set: {ev.n_sectors} instances, {ev.n_clusters} clusters, generated in "
+        f"{time.time() - t0:.1f}s")
+    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
+                       occupancy=args.occupancy, sector_side=ev.sector_side)
+    res = {}
+    ref = None
+    steps = max(2, args.steps // 4)
+    for mode, graph in (("staged", True), ("persistent", True), ("per_sector", False)):
+        with torch.cuda.stream(stream):
+            api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(steps):
+                api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        r = api.results(e, stream)
+        key = (r["trk_off"].tobytes(), r["trk_hits"].tobytes(), r["t_par"].tobytes())
+        if ref is None:
+            ref = key
+        same = key == ref
+        res[mode] = {"ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3), "graph": graph,
+                     "equal_output": bool(same), "tracks": int(r["status"]["n_tracks"])}
+        log(f"[bench]   {mode:11s} {ms:8.3f} ms  {ev.n_clusters / (ms * 1e-3):.3e} clusters/s "
+            f"equal={same}")
+    res["workload"] = ("512 single-sector instances, half pp-like (20-200 tracks), half "
+                       "Pb-Pb-like (50-800), log-uniform, shuffled (seed 40040000)")
+    res["clusters"] = ev.n_clusters
+    return res
 
 
 def refit_bench(args, api, synth, ctx, stream, prm, dev):

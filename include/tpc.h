@@ -286,10 +286,12 @@ typedef struct tpc_track_hits {
 /* Forward refit in float: calibrate with d_theta[16], state from hits 0
  * and 2, filter outwards through hits 1..n-1.  Outputs per track: par[5],
  * cov[15] at the last hit, chi2, status (0 ok, 1 fewer than 3 hits, 2
- * |sin(phi)| stop, 3 a hit row >= n_rows).  The CSR must be well formed
- * (off increasing, off[n_tracks] = n_hits); checkpoints must be 16-byte
- * aligned.  checkpoints (nullable) [n_hits * 20]: state and
- * covariance after each hit but the last, for tpc_refit_adjoint. */
+ * |sin(phi)| stop, 3 a hit row >= n_rows, 4 more hits than rows).  The CSR
+ * must be well formed (off increasing, off[n_tracks] = n_hits).
+ * checkpoints (nullable) [n_rows * 20 * n_tracks]: state and covariance
+ * after hit i (i < n - 1) of track t at [(i * 20 + k) * n_tracks + t], for
+ * tpc_refit_adjoint; n_tracks is the n_tracks member (the capacity when a
+ * device count is given). */
 int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
               const tpc_params* h_params, const tpc_calib_model* h_model,
               const float* d_theta, float* par, float* cov, float* chi2, int32_t* status,

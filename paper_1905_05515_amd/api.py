@@ -330,7 +330,8 @@ def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: 
                    cov=torch.empty(n * 15, dtype=torch.float32, device=dev),
                    chi2=torch.empty(n, dtype=torch.float32, device=dev),
                    status=torch.empty(n, dtype=torch.int32, device=dev))
-        out["checkpoints"] = (torch.empty(max(hits.n_hits, 1) * 20, dtype=torch.float32,
+        n_rows = int(row_x.shape[0])
+        out["checkpoints"] = (torch.empty(max(n * n_rows * 20, 1), dtype=torch.float32,
                                           device=dev) if checkpoints else None)
     else:
         out = dict(out)

@@ -113,6 +113,10 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
         return TPC_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     const int ns = h_prob->n_sectors;
+    if (mode == TPC_MODE_PERSISTENT) {
+        const int pe = tpc::prepare_persistent(ctx, h_prob);
+        if (pe) return pe;
+    }
     // never more tracklets than starts: the selection runs over the start
     // capacity the workspace was sized for
     const int64_t count_cap = starts.capacity;

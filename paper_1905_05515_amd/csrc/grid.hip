@@ -9,7 +9,7 @@
 // rank    one thread per grid position: the final place of a cluster is its
 //         bin start plus the number of clusters in the bin with a smaller id,
 //         which restores id order inside every bin deterministically.
-#include "tpc_internal.hpp"
+#include "grid_dev.hpp"
 
 namespace tpc {
 
@@ -19,12 +19,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_count(
     int32_t* __restrict__ cnt, tpc_status* status)
 {
     for (int64_t i = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < end;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int r = row[i];
-        if (r >= n_rows) atomicAdd((unsigned long long*)&status->n_bad_rows, 1ull);
-        const tpc_sector& s = sec[find_sector(sec, n_sec, i)];
-        atomicAdd(&cnt[global_bin(s, n_rows, r, y[i], z[i])], 1);
-    }
+         i += (int64_t)gridDim.x * blockDim.x)
+        grid_count_one(sec, n_sec, n_rows, row, y, z, i, cnt, status);
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_scatter(
@@ -33,12 +29,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(
     const int32_t* __restrict__ bin_start, int32_t* __restrict__ fill, int32_t* __restrict__ tmp)
 {
     for (int64_t i = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < end;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const tpc_sector& s = sec[find_sector(sec, n_sec, i)];
-        const int g = global_bin(s, n_rows, row[i], y[i], z[i]);
-        const int slot = atomicAdd(&fill[g], 1);
-        tmp[bin_start[g] + slot] = (int32_t)i;
-    }
+         i += (int64_t)gridDim.x * blockDim.x)
+        grid_scatter_one(sec, n_sec, n_rows, row, y, z, i, bin_start, fill, tmp);
 }
 
 // grid positions [begin, end) (= the cluster ids of the sectors handled)
@@ -50,22 +42,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_rank(
     int32_t* __restrict__ idg, int32_t* __restrict__ gsr)
 {
     for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t id = tmp[p];
-        const int si = find_sector(sec, n_sec, id);
-        const tpc_sector& s = sec[si];
-        const int r = row[id];
-        const float yy = y[id], zz = z[id];
-        const int g = global_bin(s, n_rows, r, yy, zz);
-        const int32_t bs = bin_start[g], be = bin_start[g + 1];
-        int rank = 0;
-        for (int32_t q = bs; q < be; ++q) rank += tmp[q] < id;
-        const int32_t o = bs + rank;
-        yg[o] = yy;
-        zg[o] = zz;
-        idg[o] = id;
-        gsr[o] = (si << 8) | r;
-    }
+         p += (int64_t)gridDim.x * blockDim.x)
+        grid_rank_one(sec, n_sec, n_rows, row, y, z, bin_start, p, tmp, yg, zg, idg, gsr);
 }
 
 __global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)

@@ -1,13 +1,9 @@
 // Cellular-automaton seeding: best up/down pair per hit, mutual-link
 // cleaning, chain starts.
-#include "tpc_internal.hpp"
+#include "seed_dev.hpp"
 
 namespace tpc {
 
-// One thread per grid position (the centre hit).  Candidates on rows r+1 and
-// r-1 come from the bins covering the windows around the straight line from
-// the origin through the hit; the exact window test and the pair deviation
-// decide, ties go to the lower (up id, down id).
 __global__ __launch_bounds__(kBlock) void k_neighbours(
     const tpc_sector* __restrict__ sec, int n_rows, const float* __restrict__ row_x,
     tpc_params prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
@@ -15,81 +11,46 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
     const int32_t* __restrict__ gsr, int64_t begin, int64_t end,
     int32_t* __restrict__ up0, int32_t* __restrict__ down0)
 {
-    const float Wy = prm.nb_win_y, Wz = prm.nb_win_z, D2max = prm.nb_d2max;
     for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int v = gsr[p];
-        const int r = v & 255;
-        int bu = -1, bd = -1;
-        if (r > 0 && r + 1 < n_rows) {
-            const tpc_sector s = sec[v >> 8];
-            const float y = yg[p], z = zg[p];
-            const float slope = y / row_x[r];
-            const float yu_c = slope * row_x[r + 1];
-            const float yd_c = slope * row_x[r - 1];
-            const int iyu0 = bin_of(yu_c - Wy * TPC_WIDEN, s.y0, s.inv_by, s.nby);
-            const int iyu1 = bin_of(yu_c + Wy * TPC_WIDEN, s.y0, s.inv_by, s.nby);
-            const int iyd0 = bin_of(yd_c - Wy * TPC_WIDEN, s.y0, s.inv_by, s.nby);
-            const int iyd1 = bin_of(yd_c + Wy * TPC_WIDEN, s.y0, s.inv_by, s.nby);
-            const int iz0 = bin_of(z - Wz * TPC_WIDEN, s.z0, s.inv_bz, s.nbz);
-            const int iz1 = bin_of(z + Wz * TPC_WIDEN, s.z0, s.inv_bz, s.nbz);
-            float best = 0.0f;
-            int bidu = -1, bidd = -1;
-            for (int izu = iz0; izu <= iz1; ++izu) {
-                const int gu = s.bin_base + ((r + 1) * s.nbz + izu) * s.nby;
-                const int pu1 = bin_start[gu + iyu1 + 1];
-                for (int pu = bin_start[gu + iyu0]; pu < pu1; ++pu) {
-                    const float yu = yg[pu], zu = zg[pu];
-                    if (!(fabsf(yu - yu_c) <= Wy && fabsf(zu - z) <= Wz)) continue;
-                    const int idu = idg[pu];
-                    for (int izd = iz0; izd <= iz1; ++izd) {
-                        const int gd = s.bin_base + ((r - 1) * s.nbz + izd) * s.nby;
-                        const int pd1 = bin_start[gd + iyd1 + 1];
-                        for (int pd = bin_start[gd + iyd0]; pd < pd1; ++pd) {
-                            const float yd = yg[pd], zd = zg[pd];
-                            if (!(fabsf(yd - yd_c) <= Wy && fabsf(zd - z) <= Wz)) continue;
-                            const float dy = (yu + yd) - (y + y);
-                            const float dz = (zu + zd) - (z + z);
-                            const float d2 = dy * dy + dz * dz;
-                            if (!(d2 <= D2max)) continue;
-                            const int idd = idg[pd];
-                            if (bu < 0 || d2 < best ||
-                                (d2 == best && (idu < bidu || (idu == bidu && idd < bidd)))) {
-                                best = d2;
-                                bu = pu;
-                                bd = pd;
-                                bidu = idu;
-                                bidd = idd;
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        up0[p] = bu;
-        down0[p] = bd;
-    }
+         p += (int64_t)gridDim.x * blockDim.x)
+        neighbours_one(p, sec, n_rows, row_x, prm, bin_start, yg, zg, idg, gsr, up0, down0);
 }
 
-// Mutual links; a chain start (up link, no down link, and its up neighbour
-// has an up link) is flagged in the id-indexed array `start_by_id`.
+// One block per (sector, row r in [0, n_rows]); rows 1..n_rows-2 search
+// their neighbours with LDS-staged candidate rows; rows 0, n_rows-1 and the
+// invalid-row bin (r = n_rows) get no links.
+__global__ __launch_bounds__(kBlock) void k_neighbours_rows(
+    const tpc_sector* __restrict__ sec, int sec_lo, int n_rows, const float* __restrict__ row_x,
+    tpc_params prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
+    const float* __restrict__ zg, const int32_t* __restrict__ idg, int32_t* __restrict__ up0,
+    int32_t* __restrict__ down0)
+{
+    __shared__ NbRowStage stu, std_;
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int si = sec_lo + w / (n_rows + 1);
+    const int r = w % (n_rows + 1);
+    const tpc_sector s = sec[si];
+    if (r == 0 || r >= n_rows - 1) {
+        const int per_row = s.nbz * s.nby;
+        const int g0 = s.bin_base + r * per_row;
+        const int g1 = r < n_rows ? g0 + per_row : g0 + 1;
+        for (int64_t p = bin_start[g0] + threadIdx.x; p < bin_start[g1]; p += blockDim.x) {
+            up0[p] = -1;
+            down0[p] = -1;
+        }
+        return;
+    }
+    neighbours_row(&stu, &std_, s, r, n_rows, row_x, prm, bin_start, yg, zg, idg, up0, down0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_clean(
     const int32_t* __restrict__ up0, const int32_t* __restrict__ down0,
     const int32_t* __restrict__ idg, int64_t begin, int64_t end,
     int32_t* __restrict__ up, int32_t* __restrict__ down, int32_t* __restrict__ start_by_id)
 {
     for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int u = up0[p], d = down0[p];
-        const int uc = (u >= 0 && down0[u] == p) ? u : -1;
-        const int dc = (d >= 0 && up0[d] == p) ? d : -1;
-        up[p] = uc;
-        down[p] = dc;
-        if (uc >= 0 && dc < 0) {
-            const int uu = up0[uc];
-            if (uu >= 0 && down0[uu] == uc) start_by_id[idg[p]] = (int32_t)p;
-        }
-    }
+         p += (int64_t)gridDim.x * blockDim.x)
+        clean_one(p, up0, down0, idg, up, down, start_by_id);
 }
 
 // Deterministic compaction of the flagged starts in id order: count per
@@ -174,10 +135,10 @@ int run_find_neighbours(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid g
     const int64_t c0 = p->h_sectors[sec_lo].begin, c1 = p->h_sectors[sec_hi - 1].end;
     const int64_t n = c1 - c0;
     const unsigned gn = grid_for(n);
-    TPC_LAUNCH(k_neighbours, dim3(gn), dim3(kBlock), 0, st, p->d_sectors, p->n_rows, p->d_row_x,
-               p->params, (const int32_t*)grid.bin_start, (const float*)grid.y,
-               (const float*)grid.z, (const int32_t*)grid.id, (const int32_t*)ws.gsr, c0, c1,
-               links.up0, links.down0);
+    const unsigned nrb = (unsigned)((sec_hi - sec_lo) * (p->n_rows + 1));
+    TPC_LAUNCH(k_neighbours_rows, dim3(nrb), dim3(kBlock), 0, st, p->d_sectors, sec_lo, p->n_rows,
+               p->d_row_x, p->params, (const int32_t*)grid.bin_start, (const float*)grid.y,
+               (const float*)grid.z, (const int32_t*)grid.id, links.up0, links.down0);
     launch_fill<int32_t>(ws.tmp + c0, -1, n, st);
     TPC_LAUNCH(k_clean, dim3(gn), dim3(kBlock), 0, st, (const int32_t*)links.up0,
                (const int32_t*)links.down0, (const int32_t*)grid.id, c0, c1, links.up, links.down,

@@ -391,26 +391,27 @@ __device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const 
     return dxb;
 }
 
-// checkpoint of 20 floats (p, C) as five 16-byte accesses
-__device__ __forceinline__ void store_ck(float* o, const float* p, const float* C)
+// checkpoint of hit i of track t: 20 floats (p, C) at ck[(i * 20 + k) *
+// n_tracks + t], so that the lanes of a wave (consecutive tracks) store and
+// load whole lines at every step
+__device__ __forceinline__ void store_ck(float* ck, int64_t nt, int64_t t, int i, const float* p,
+                                         const float* C)
 {
-    float4* q = reinterpret_cast<float4*>(o);
-    q[0] = make_float4(p[0], p[1], p[2], p[3]);
-    q[1] = make_float4(p[4], C[0], C[1], C[2]);
-    q[2] = make_float4(C[3], C[4], C[5], C[6]);
-    q[3] = make_float4(C[7], C[8], C[9], C[10]);
-    q[4] = make_float4(C[11], C[12], C[13], C[14]);
+    float* o = ck + (int64_t)i * 20 * nt + t;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) o[k * nt] = p[k];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) o[(5 + k) * nt] = C[k];
 }
 
-__device__ __forceinline__ void load_ck(const float* o, float* p, float* C)
+__device__ __forceinline__ void load_ck(const float* ck, int64_t nt, int64_t t, int i, float* p,
+                                        float* C)
 {
-    const float4* q = reinterpret_cast<const float4*>(o);
-    const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
-    p[0] = a.x; p[1] = a.y; p[2] = a.z; p[3] = a.w;
-    p[4] = b.x; C[0] = b.y; C[1] = b.z; C[2] = b.w;
-    C[3] = c.x; C[4] = c.y; C[5] = c.z; C[6] = c.w;
-    C[7] = d.x; C[8] = d.y; C[9] = d.z; C[10] = d.w;
-    C[11] = e.x; C[12] = e.y; C[13] = e.z; C[14] = e.w;
+    const float* o = ck + (int64_t)i * 20 * nt + t;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) p[k] = o[k * nt];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) C[k] = o[(5 + k) * nt];
 }
 
 __device__ __forceinline__ void load_theta(const float* __restrict__ d_theta, float* th)
@@ -451,6 +452,8 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
             stat = 1;
         } else if (!rows_ok) {
             stat = 3;
+        } else if (n > n_rows) {
+            stat = 4;
         } else {
             const float sd = side ? (float)side[t] : 1.0f;
             const CalHit h0 = H.cal(0, th, xs, sd, cm);
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
             C[5] = prm.c_ss0;
             C[9] = prm.c_tt0;
             C[14] = prm.c_ww0;
-            if (ck) store_ck(ck + (int64_t)a * 20, p, C);
+            if (ck) store_ck(ck, n_tracks, t, 0, p, C);
             float xp = h0.x;
             for (int i = 1; i < n; ++i) {
                 const CalHit h = H.cal(i, th, xs, sd, cm);
@@ -480,7 +483,7 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
                 Upd U;
                 chi2 += upd_fwd(p, C, h.y, h.z, prm.sigma_y2, prm.sigma_z2, U);
                 xp = h.x;
-                if (ck && i + 1 < n) store_ck(ck + (int64_t)(a + i) * 20, p, C);
+                if (ck && i + 1 < n) store_ck(ck, n_tracks, t, i, p, C);
             }
         }
 #pragma unroll
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
         for (int i = n - 1; i >= 1; --i) {
             const CalHit prev = H.cal(i - 1, th, xs, sd, cm);
             float p[5], C[15];
-            load_ck(ck + (int64_t)(a + i - 1) * 20, p, C);
+            load_ck(ck, n_tracks, t, i - 1, p, C);
             const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};
             Prop P;
             prop_fwd(p, C, cur.x - prev.x, prm.curv, prm.s_max, P);
@@ -596,23 +599,22 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
     }
 }
 
-// sum of the per-block partials in a fixed order: thread j of 256 sums
-// column j % 16 over blocks j / 16, j / 16 + 16, ...; then the 16 strided
-// sums of each column are added in order
+// sum of the per-block partials in a fixed order: block k sums parameter k;
+// thread j adds partials j, j + 256, ... of it, then a fixed tree
 __global__ __launch_bounds__(kBlock) void k_reduce_theta(const float* __restrict__ partials,
                                                          int nb, float* __restrict__ out)
 {
     __shared__ float red[kBlock];
-    const int col = threadIdx.x & 15, row0 = threadIdx.x >> 4;
+    const int k = blockIdx.x;
     float v = 0.0f;
-    for (int b = row0; b < nb; b += kBlock / 16) v += partials[b * 16 + col];
+    for (int b = threadIdx.x; b < nb; b += kBlock) v += partials[b * 16 + k];
     red[threadIdx.x] = v;
     __syncthreads();
-    if (threadIdx.x < 16) {
-        float s = 0.0f;
-        for (int r = 0; r < kBlock / 16; ++r) s += red[r * 16 + threadIdx.x];
-        out[threadIdx.x] = s;
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[k] = red[0];
 }
 
 static unsigned refit_grid(int64_t n_tracks)
@@ -676,7 +678,7 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                        hits.row, hits.y, hits.z, hits.side, hits.d_count, hits.n_tracks, n_rows,
                        d_row_x, *h_params, cm, d_theta, checkpoints, status, grad_chi2, grad_y,
                        grad_z, partials);
-    TPC_LAUNCH(tpc::k_reduce_theta, dim3(1), dim3(tpc::kBlock), 0, st, (const float*)partials,
+    TPC_LAUNCH(tpc::k_reduce_theta, dim3(16), dim3(tpc::kBlock), 0, st, (const float*)partials,
                        (int)nb, grad_theta);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }

@@ -3,14 +3,9 @@
 // at least min_tracklet_hits hits (64-bit atomic max, order independent); a
 // tracklet keeping at least min_track_hits clusters becomes a track.
 // Tracks are compacted in tracklet order by a scan of (accepted, kept).
-#include "tpc_internal.hpp"
+#include "select_dev.hpp"
 
 namespace tpc {
-
-__device__ __forceinline__ uint64_t tracklet_key(int nh, int start_id, int min_hits)
-{
-    return nh >= min_hits ? (((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)start_id)) : 0ull;
-}
 
 __global__ __launch_bounds__(kWave) void k_sel_keys(
     int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
@@ -22,14 +17,8 @@ __global__ __launch_bounds__(kWave) void k_sel_keys(
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
-        if (!key) continue;
-        for (int r = 0; r < n_rows; ++r) {
-            const int c = t_hits[(int64_t)r * cap + t];
-            if (c >= 0) atomicMax(&hitkey[c], (unsigned long long)key);
-        }
-    }
+         t += (int64_t)gridDim.x * blockDim.x)
+        sel_keys_one(t, n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey);
 }
 
 __global__ __launch_bounds__(kWave) void k_sel_count(
@@ -42,21 +31,8 @@ __global__ __launch_bounds__(kWave) void k_sel_count(
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t out = 0;
-        {
-            const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
-            if (key) {
-                int kept = 0;
-                for (int r = 0; r < n_rows; ++r) {
-                    const int c = t_hits[(int64_t)r * cap + t];
-                    kept += c >= 0 && hitkey[c] == key;
-                }
-                if (kept >= prm.min_track_hits) out = (1ull << 32) | (uint64_t)kept;
-            }
-        }
-        tlen[t] = out;
-    }
+         t += (int64_t)gridDim.x * blockDim.x)
+        tlen[t] = sel_count_one(t, n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey);
 }
 
 __global__ __launch_bounds__(kWave) void k_sel_write(
@@ -72,24 +48,10 @@ __global__ __launch_bounds__(kWave) void k_sel_write(
     int64_t m = status->n_starts;
     if (m > count_cap) m = count_cap;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        if (!tlen[t]) continue;
-        const int64_t k = (int64_t)(toff[t] >> 32);
-        int64_t o = (int64_t)(toff[t] & 0xFFFFFFFFull);
-        if (k < trk_cap) {
-            trk_tracklet[k] = (int32_t)t;
-            trk_off[k] = (int32_t)o;
-            if (trk_side) trk_side[k] = sec[gsr[t_start[t]] >> 8].side < 0 ? -1 : 1;
-        }
-        const uint64_t key = tracklet_key(t_nhits[t], idg[t_start[t]], prm.min_tracklet_hits);
-        for (int r = 0; r < n_rows; ++r) {
-            const int c = t_hits[(int64_t)r * cap + t];
-            if (c >= 0 && hitkey[c] == key) {
-                if (o < hit_cap) trk_hits[o] = idg[c];
-                ++o;
-            }
-        }
-    }
+         t += (int64_t)gridDim.x * blockDim.x)
+        if (tlen[t])
+            sel_write_one(t, toff[t], n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey,
+                          sec, gsr, trk_off, trk_hits, trk_tracklet, trk_side, trk_cap, hit_cap);
 }
 
 __global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status* status,

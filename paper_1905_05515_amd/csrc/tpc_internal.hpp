@@ -19,6 +19,7 @@ constexpr int kBlock = 256;          // threads per block of the streaming kerne
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kScanItems = 8;        // items per thread in the scans
 constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kPhases = 14;          // phases of the persistent form
 
 struct Workspace {
     tpc_status* status;
@@ -30,6 +31,9 @@ struct Workspace {
     uint64_t* tlen;        // [start_cap + 1] per tracklet: accepted << 32 | kept
     uint64_t* toff;        // [start_cap + 1] exclusive scan of tlen
     int64_t* sec_start;    // [n_sectors + 1] first start of each sector
+    int32_t* pq;           // persistent form: [1] queue head, [kPhases * n_sectors] done counts
+    int64_t* scnt;         // persistent form: [n_sectors] starts per sector
+    uint64_t* tsum;        // persistent form: [n_sectors] tracks << 32 | hits per sector
     size_t bytes;
 };
 
@@ -81,6 +85,16 @@ __device__ inline int global_bin(const tpc_sector& s, int n_rows, int row, float
     int iy = bin_of(y, s.y0, s.inv_by, s.nby);
     int iz = bin_of(z, s.z0, s.inv_bz, s.nbz);
     return s.bin_base + (row * s.nbz + iz) * s.nby + iy;
+}
+
+// Launch-order to work-order map that keeps consecutive work items on one
+// XCD: workgroups are dealt to the 8 XCDs round robin, so workgroup b runs on
+// XCD b % 8; XCD x is given the contiguous work range of its share, and the
+// data of neighbouring work items (one sector's rows) stays in one L2.
+__device__ __forceinline__ int xcd_remap(int b, int G)
+{
+    const int x = b & 7, i = b >> 3, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + i;
 }
 
 // Windows are widened by this factor before taking bins, so that a rounding
@@ -139,6 +153,11 @@ struct tpc_context {
     hipGraphExec_t graph_exec;
     uint64_t graph_key;
     bool graph_valid;
+    // task table of the persistent form (device copy), keyed on the sectors
+    int32_t* d_tasks;
+    size_t tasks_cap;
+    uint64_t tasks_key;
+    int64_t n_tasks;
 };
 
 // stage launchers (stream-ordered, no host synchronisation); the sector
@@ -156,6 +175,9 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
                     int64_t count_cap, tpc_tracklets trl, const Workspace& ws, hipStream_t st);
 int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
                        tpc_tracklets trl, tpc_tracks trk, const Workspace& ws, hipStream_t st);
+// task table of the persistent form (host work, no launch; call before
+// any capture)
+int prepare_persistent(tpc_context* ctx, const tpc_problem* p);
 // all four stages in one persistent launch over a device work queue
 int run_persistent(tpc_context* ctx, const tpc_problem* p, tpc_clusters in, tpc_grid grid,
                    tpc_links links, tpc_starts starts, tpc_tracklets trl, tpc_tracks trk,

@@ -1,169 +1,8 @@
-// Kalman-filter tracklet construction, one thread per chain start.
-//
-// State at the sector-local plane x: (y, z, s = sin(phi), t = tan(lambda),
-// w = q/pT), covariance as the lower triangle of the symmetric 5x5 matrix
-// (i*(i+1)/2 + j).  In a uniform field along z the curvature k = curv * w is
-// constant: s grows linearly with x, the y step is dx (s1 + s2)/(c1 + c2)
-// with c = sqrt(1 - s^2), and the arc length over the step is
-// chord * asin(a)/a, a = k chord / 2, expanded to a^6.  Every expression
-// below keeps the association order of its comment's formula; with
-// contraction off and IEEE division and square root the results are the
-// same bits on any conforming implementation.
-#include "tpc_internal.hpp"
+// Kalman-filter tracklet construction, one thread per chain start (the
+// arithmetic is in tracklet_dev.hpp).
+#include "tracklet_dev.hpp"
 
 namespace tpc {
-
-__device__ __forceinline__ int lt(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
-
-struct KState {
-    float p[5];
-    float C[15];
-};
-
-// Transport from plane x1 to x1 + dx.  Returns false (state untouched) when
-// |sin(phi)| would reach s_max.
-__device__ __forceinline__ bool propagate(KState& st, float dx, float curv, float s_max)
-{
-    const float s = st.p[2], t = st.p[3], w = st.p[4];
-    const float k = curv * w;
-    const float s2 = s + k * dx;
-    if (!(fabsf(s2) < s_max)) return false;
-    const float c1 = sqrtf((1.0f - s) * (1.0f + s));
-    const float c2 = sqrtf((1.0f - s2) * (1.0f + s2));
-    const float cc = c1 + c2;
-    const float T = (s + s2) / cc;
-    const float q = sqrtf(1.0f + T * T);
-    const float L = dx * q;
-    const float a = 0.5f * (k * L);
-    const float a2 = a * a;
-    const float g = 1.0f + a2 * ((1.0f / 6.0f) + a2 * ((3.0f / 40.0f) + a2 * (5.0f / 112.0f)));
-    const float S = L * g;
-    const float Ts = (2.0f + T * (s / c1 + s2 / c2)) / cc;
-    const float kdx = curv * dx;
-    const float Tw = (kdx * (1.0f + T * (s2 / c2))) / cc;
-    const float LT = dx * (T / q);
-    const float G1 = 1.0f + a2 * (0.5f + a2 * ((3.0f / 8.0f) + a2 * (5.0f / 16.0f)));
-    const float Sk = (L * (L * a)) * ((1.0f / 6.0f) + a2 * ((3.0f / 20.0f) + a2 * (15.0f / 112.0f)));
-    const float Fys = dx * Ts;
-    const float Fyw = dx * Tw;
-    const float Fzs = t * ((G1 * LT) * Ts);
-    const float Fzt = S;
-    const float Fzw = t * ((G1 * LT) * Tw + Sk * curv);
-    const float Fsw = kdx;
-
-    // B = F C, then C' = B F^T, sums over the non-zero entries of F in
-    // increasing column order
-    float B[5][5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        const float cy = st.C[lt(0, j)], cz = st.C[lt(1, j)], cs = st.C[lt(2, j)];
-        const float ct = st.C[lt(3, j)], cw = st.C[lt(4, j)];
-        B[0][j] = (cy + Fys * cs) + Fyw * cw;
-        B[1][j] = ((cz + Fzs * cs) + Fzt * ct) + Fzw * cw;
-        B[2][j] = cs + Fsw * cw;
-        B[3][j] = ct;
-        B[4][j] = cw;
-    }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        st.C[lt(i, 0)] = (B[i][0] + Fys * B[i][2]) + Fyw * B[i][4];
-        if (i >= 1) st.C[lt(i, 1)] = ((B[i][1] + Fzs * B[i][2]) + Fzt * B[i][3]) + Fzw * B[i][4];
-        if (i >= 2) st.C[lt(i, 2)] = B[i][2] + Fsw * B[i][4];
-        if (i >= 3) st.C[lt(i, 3)] = B[i][3];
-        if (i >= 4) st.C[lt(i, 4)] = B[i][4];
-    }
-    st.p[0] = st.p[0] + dx * T;
-    st.p[1] = st.p[1] + t * S;
-    st.p[2] = s2;
-    return true;
-}
-
-__device__ __forceinline__ float chi2_pred(const KState& st, float my, float mz, float sy2, float sz2)
-{
-    const float r0 = my - st.p[0], r1 = mz - st.p[1];
-    const float S00 = st.C[0] + sy2, S10 = st.C[1], S11 = st.C[2] + sz2;
-    const float det = S00 * S11 - S10 * S10;
-    const float idet = 1.0f / det;
-    const float B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
-    return r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
-}
-
-__device__ __forceinline__ float kupdate(KState& st, float my, float mz, float sy2, float sz2)
-{
-    const float r0 = my - st.p[0], r1 = mz - st.p[1];
-    const float S00 = st.C[0] + sy2, S10 = st.C[1], S11 = st.C[2] + sz2;
-    const float det = S00 * S11 - S10 * S10;
-    const float idet = 1.0f / det;
-    const float B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
-    const float chi2 = r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
-    float A0[5], A1[5], K0[5], K1[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        A0[i] = st.C[lt(i, 0)];
-        A1[i] = st.C[lt(i, 1)];
-    }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        K0[i] = A0[i] * B00 + A1[i] * B10;
-        K1[i] = A0[i] * B10 + A1[i] * B11;
-    }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        st.p[i] = st.p[i] + (K0[i] * r0 + K1[i] * r1);
-#pragma unroll
-        for (int j = 0; j <= i; ++j)
-            st.C[lt(i, j)] = st.C[lt(i, j)] - (K0[i] * A0[j] + K1[i] * A1[j]);
-    }
-    return chi2;
-}
-
-__device__ __forceinline__ void reset_cov(KState& st, const tpc_params& prm)
-{
-#pragma unroll
-    for (int i = 0; i < 15; ++i) st.C[i] = 0.0f;
-    st.C[0] = prm.sigma_y2;
-    st.C[2] = prm.sigma_z2;
-    st.C[5] = prm.c_ss0;
-    st.C[9] = prm.c_tt0;
-    st.C[14] = prm.c_ww0;
-}
-
-// Hit of least predicted chi2 <= chi2_max on row r of sector s, ties to the
-// lower cluster id; -1 if none.  The bins scanned cover +-nsigma of the
-// prediction (every hit passing the gate lies inside); the gate decides.
-__device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s, int r,
-                                          const tpc_params& prm, int& n_cand,
-                                          const int32_t* __restrict__ bin_start,
-                                          const float* __restrict__ yg,
-                                          const float* __restrict__ zg,
-                                          const int32_t* __restrict__ idg)
-{
-    const float S00 = st.C[0] + prm.sigma_y2, S11 = st.C[2] + prm.sigma_z2;
-    const float hy = prm.search_nsigma * sqrtf(S00) * TPC_WIDEN + 0.01f;
-    const float hz = prm.search_nsigma * sqrtf(S11) * TPC_WIDEN + 0.01f;
-    const int iy0 = bin_of(st.p[0] - hy, s.y0, s.inv_by, s.nby);
-    const int iy1 = bin_of(st.p[0] + hy, s.y0, s.inv_by, s.nby);
-    const int iz0 = bin_of(st.p[1] - hz, s.z0, s.inv_bz, s.nbz);
-    const int iz1 = bin_of(st.p[1] + hz, s.z0, s.inv_bz, s.nbz);
-    float best = 0.0f;
-    int bpos = -1, bid = -1;
-    for (int iz = iz0; iz <= iz1; ++iz) {
-        const int g = s.bin_base + (r * s.nbz + iz) * s.nby;
-        const int pe = bin_start[g + iy1 + 1];
-        n_cand += pe - bin_start[g + iy0] > 0 ? pe - bin_start[g + iy0] : 0;
-        for (int pc = bin_start[g + iy0]; pc < pe; ++pc) {
-            const float c2 = chi2_pred(st, yg[pc], zg[pc], prm.sigma_y2, prm.sigma_z2);
-            if (!(c2 <= prm.chi2_max)) continue;
-            const int id = idg[pc];
-            if (bid < 0 || c2 < best || (c2 == best && id < bid)) {
-                best = c2;
-                bid = id;
-                bpos = pc;
-            }
-        }
-    }
-    return bpos;
-}
 
 __global__ __launch_bounds__(kWave) void k_tracklets(
     const tpc_sector* __restrict__ sec, int n_rows, const float* __restrict__ row_x,
@@ -182,128 +21,13 @@ __global__ __launch_bounds__(kWave) void k_tracklets(
     __syncthreads();
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
-    const float sy2 = prm.sigma_y2, sz2 = prm.sigma_z2;
     int n_prop = 0, n_upd = 0, n_cand = 0;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        // hit list of this tracklet: column t of the [row][tracklet] array
-        int32_t* th = t_hits + t;
-        for (int r = 0; r < n_rows; ++r) th[(int64_t)r * cap] = -1;
-        const int h0 = starts[t];
-        const int v0 = gsr[h0];
-        const tpc_sector s = sec[v0 >> 8];
-        const int r0 = v0 & 255;
-        const int h1 = up[h0], h2 = up[h1];
-        const int r2 = gsr[h2] & 255;
-        KState st;
-        {   // state from the first and third chain hits
-            const float dX = xs[r2] - xs[r0];
-            const float T0 = (yg[h2] - yg[h0]) / dX;
-            const float q0 = sqrtf(1.0f + T0 * T0);
-            st.p[0] = yg[h0];
-            st.p[1] = zg[h0];
-            st.p[2] = T0 / q0;
-            st.p[3] = (zg[h2] - zg[h0]) / (dX * q0);
-            st.p[4] = 0.0f;
-            reset_cov(st, prm);
-        }
-        th[(int64_t)(r0) * cap] = h0;
-        int cur = r0, last = r0;
-        float plast[5];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
-        bool ok = true;
-        // outwards along the chain
-        for (int h = h1; h >= 0; h = up[h]) {
-            const int r = gsr[h] & 255;
-            if (!(++n_prop, propagate(st, xs[r] - xs[cur], prm.curv, prm.s_max))) {
-                ok = false;
-                break;
-            }
-            ++n_upd;
-            kupdate(st, yg[h], zg[h], sy2, sz2);
-            th[(int64_t)(r) * cap] = h;
-            cur = last = r;
-#pragma unroll
-            for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
-        }
-        // outwards, searching row by row
-        if (ok) {
-            int miss = 0;
-            for (int r = cur + 1; r < n_rows; ++r) {
-                if (!(++n_prop, propagate(st, xs[r] - xs[r - 1], prm.curv, prm.s_max))) break;
-                const int c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg);
-                if (c >= 0) {
-                    ++n_upd;
-                    kupdate(st, yg[c], zg[c], sy2, sz2);
-                    th[(int64_t)(r) * cap] = c;
-                    last = r;
-#pragma unroll
-                    for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
-                    miss = 0;
-                } else if (++miss >= prm.max_miss) {
-                    break;
-                }
-            }
-        }
-        // inwards from the outermost hit with the initial covariance
-        const int hl = th[(int64_t)(last) * cap];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) st.p[i] = plast[i];
-        st.p[0] = yg[hl];
-        st.p[1] = zg[hl];
-        reset_cov(st, prm);
-        KState in = st;
-        float csum = 0.0f;
-        int rin = last, miss = 0;
-        for (int r = last - 1; r >= 0; --r) {
-            if (!(++n_prop, propagate(st, xs[r] - xs[r + 1], prm.curv, prm.s_max))) {
-                for (int q = r; q >= 0; --q) th[(int64_t)(q) * cap] = -1;
-                break;
-            }
-            int c;
-            if (r >= r0) {
-                c = th[(int64_t)(r) * cap];
-            } else {
-                c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg);
-                if (c < 0) {
-                    if (++miss >= prm.max_miss) break;
-                    continue;
-                }
-                miss = 0;
-            }
-            if (c >= 0) {
-                ++n_upd;
-                csum = csum + kupdate(st, yg[c], zg[c], sy2, sz2);
-                th[(int64_t)(r) * cap] = c;
-                rin = r;
-                in = st;
-            }
-        }
-        int nh = 0;
-        for (int r = 0; r < n_rows; ++r) nh += th[(int64_t)(r) * cap] >= 0;
-        t_start[t] = h0;
-        t_nhits[t] = nh;
-        t_rin[t] = rin;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) t_par[t * 5 + i] = in.p[i];
-#pragma unroll
-        for (int i = 0; i < 15; ++i) t_cov[t * 15 + i] = in.C[i];
-        t_chi2[t] = csum;
-    }
-    // work counters: one atomic per wave
-    unsigned long long a = n_prop, b = n_upd, c = n_cand;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, kWave);
-        b += __shfl_xor(b, o, kWave);
-        c += __shfl_xor(c, o, kWave);
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0 && (a | b | c)) {
-        atomicAdd((unsigned long long*)&status->n_propagations, a);
-        atomicAdd((unsigned long long*)&status->n_updates, b);
-        atomicAdd((unsigned long long*)&status->n_candidates, c);
-    }
+         t += (int64_t)gridDim.x * blockDim.x)
+        build_tracklet(t, sec, n_rows, xs, prm, bin_start, yg, zg, idg, gsr, up, starts, cap,
+                       t_start, t_hits, t_nhits, t_rin, t_par, t_cov, t_chi2, n_prop, n_upd,
+                       n_cand);
+    add_work(status, n_prop, n_upd, n_cand);
 }
 
 // Tracklets of the starts of sectors [sec_lo, sec_hi) (the start range that

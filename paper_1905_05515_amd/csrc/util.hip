@@ -1,5 +1,5 @@
 // Scans, fills, workspace layout, context and status calls.
-#include "tpc_internal.hpp"
+#include "block_dev.hpp"
 
 #include <cstring>
 #include <map>
@@ -28,49 +28,6 @@ void launch_fill(T* p, T v, int64_t n, hipStream_t st)
 template void launch_fill<int32_t>(int32_t*, int32_t, int64_t, hipStream_t);
 template void launch_fill<uint64_t>(uint64_t*, uint64_t, int64_t, hipStream_t);
 template void launch_fill<int64_t>(int64_t*, int64_t, int64_t, hipStream_t);
-
-// ---- block scan ---------------------------------------------------------------
-// Exclusive scan of one value per thread over a 256-thread block: wave-level
-// inclusive scan with shuffles, wave totals through LDS.
-
-template <typename T>
-__device__ inline T wave_incl_scan(T x)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        T y = __shfl_up(x, o, kWave);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-template <typename T>
-__device__ inline T block_excl_scan(T v, T* lds, T* total)
-{
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    T x = wave_incl_scan(v);
-    if (lane == kWave - 1) lds[wid] = x;
-    __syncthreads();
-    T before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
-        T s = lds[w];
-        before += (w < wid) ? s : T(0);
-        tot += s;
-    }
-    __syncthreads();
-    *total = tot;
-    return before + x - v;
-}
-
-template <typename T>
-__device__ inline T block_sum(T v, T* lds)
-{
-    T tot;
-    block_excl_scan(v, lds, &tot);
-    return tot;
-}
 
 // phase 1: sum of every tile
 template <typename T>
@@ -192,6 +149,9 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));
     ws->toff = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 2));
     ws->sec_start = (int64_t*)take(sizeof(int64_t) * (size_t)(p->n_sectors + 1));
+    ws->pq = (int32_t*)take(sizeof(int32_t) * (size_t)(1 + kPhases * p->n_sectors));
+    ws->scnt = (int64_t*)take(sizeof(int64_t) * (size_t)p->n_sectors);
+    ws->tsum = (uint64_t*)take(sizeof(uint64_t) * (size_t)p->n_sectors);
     ws->bytes = o;
     return true;
 }
@@ -286,6 +246,10 @@ int tpc_context_create(tpc_context** out, int device)
     c->graph_key = 0;
     c->graph_valid = false;
     c->timer = nullptr;
+    c->d_tasks = nullptr;
+    c->tasks_cap = 0;
+    c->tasks_key = 0;
+    c->n_tasks = 0;
     *out = c;
     return TPC_OK;
 }
@@ -294,6 +258,7 @@ int tpc_context_destroy(tpc_context* ctx)
 {
     if (!ctx) return TPC_ERR_INVALID_ARG;
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->d_tasks) (void)hipFree(ctx->d_tasks);
     delete ctx->timer;
     delete ctx;
     return TPC_OK;

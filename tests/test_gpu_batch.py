@@ -53,13 +53,44 @@ def test_per_sector_form_equals_staged_and_oracle():
     _same(r[("staged", False)], r[("per_sector", True)])
 
 
+def test_persistent_form_equals_staged_and_oracle():
+    ev = synth.make_config2()
+    print(f"case c2 persistent n={ev.n_clusters}", flush=True)
+    r = _forms(ev, [("staged", False), ("persistent", False), ("persistent", True)])
+    o = run_oracle(ev)
+    assert r[("persistent", False)]["status"]["overflow"] == 0
+    assert_same_tracking(r[("persistent", False)], o, ev.n_clusters)
+    _same(r[("staged", False)], r[("persistent", False)])
+    _same(r[("staged", False)], r[("persistent", True)])
+
+
+def test_persistent_small_and_edge_events():
+    """Single sector, an empty sector in the middle, invalid rows."""
+    for ev in (synth.make_config1(), synth.make_config2().sector(5)):
+        r = _forms(ev, [("staged", False), ("persistent", False)])
+        _same(r[("staged", False)], r[("persistent", False)])
+    ev = synth.make_config2()
+    a0, a1 = int(ev.sector_offsets[4]), int(ev.sector_offsets[5])
+    b0, b1 = int(ev.sector_offsets[7]), int(ev.sector_offsets[7]) + 3000
+    sel = np.concatenate([np.arange(a0, a1), np.arange(b0, b1)])
+    row = ev.row[sel].copy()
+    row[10] = 200
+    offs = np.array([0, a1 - a0, a1 - a0, sel.shape[0]], np.int64)
+    sub = synth.Event(row, ev.y[sel], ev.z[sel], ev.charge[sel], offs, ev.sector_range[[4, 5, 7]],
+                      ev.row_x, ev.label[sel], ev.tracks, {})
+    r = _forms(sub, [("staged", False), ("persistent", False), ("per_sector", False)])
+    _same(r[("staged", False)], r[("persistent", False)])
+    _same(r[("staged", False)], r[("per_sector", False)])
+
+
 @pytest.mark.timeout(900)
 def test_batched_uneven_instances_full_size():
     """512 single-sector instances of very uneven size (~14M clusters): the
     staged and per-sector forms agree bit for bit, and match the oracle."""
     ev = synth.make_config4()
     print(f"case c4 n={ev.n_clusters} instances={ev.n_sectors}", flush=True)
-    r = _forms(ev, [("staged", True), ("per_sector", False)])
+    r = _forms(ev, [("staged", True), ("per_sector", False), ("persistent", True)])
     _same(r[("staged", True)], r[("per_sector", False)])
+    _same(r[("staged", True)], r[("persistent", True)])
     o = run_oracle(ev)
     assert_same_tracking(r[("staged", True)], o, ev.n_clusters)

@@ -47,8 +47,21 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-refit-bench", action="store_true")
     ap.add_argument("--no-batch-bench", action="store_true")
-    ap.add_argument("--occupancy", type=float, default=2.0)
+    ap.add_argument("--occupancy", default="auto",
+                    help="clusters per grid bin, or 'auto' (autotuned per workload before "
+                         "the timed region; the tracks do not depend on it)")
     return ap.parse_args()
+
+
+def pick_layout(args, api, ctx, e, stream, mode="staged"):
+    """Autotune (or set) the bin occupancy of an event; returns the record
+    for the JSON line."""
+    if args.occupancy == "auto":
+        best, times = api.autotune(ctx, e, mode=mode, stream=stream)
+        log(f"[bench] autotuned occupancy {best} ({', '.join(f'{k}: {v:.3f} ms' for k, v in times.items())})")
+        return {"occupancy": best, "tried_ms": {str(k): round(v, 4) for k, v in times.items()}}
+    api.relayout(e, float(args.occupancy))
+    return {"occupancy": float(args.occupancy)}
 
 
 def log(*a):
@@ -77,7 +90,8 @@ def main():
     ctx = api.Context(0)
     stream = torch.cuda.Stream()      # default priority; graphs need a non-default stream
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
-                       occupancy=args.occupancy, sector_side=ev.sector_side)
+                       sector_side=ev.sector_side)
+    tuned = pick_layout(args, api, ctx, e, stream)
     th = torch.as_tensor(synth.make_config5(n_tracks=1).theta_eval).to(dev)
     hits = api.found_track_hits(e)
     gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
@@ -129,13 +143,15 @@ def main():
     n_cl = ev.n_clusters
     n_hits_trk = int(st["n_track_hits"])
     roof = roofline(dom, kernels[dom]["avg_ms"], st, n_cl, n_hits_trk)
+    roof["traffic"] = counter_traffic(dom, "central_event")
+    roof["source_sha256"] = source_hash()
 
     extra = {}
     if not args.no_batch_bench:
         extra["batched_vs_per_sector"] = batch_bench(args, api, synth, ctx, stream, prm)
     if not args.no_refit_bench:
         extra["refit_adjoint"] = refit_bench(args, api, synth, ctx, stream, prm, dev)
-    cpu = None if args.no_cpu else cpu_baseline(ev, prm, args)
+    cpu = None if args.no_cpu else cpu_baseline(ev, prm, args, tuned["occupancy"])
 
     value = n_cl / (ms_per_step * 1e-3)
     line = {
@@ -160,6 +176,7 @@ def main():
             "tracks_found": int(st["n_tracks"]),
             "track_hits": n_hits_trk,
             "launch_form": "staged stages over all sectors, HIP graph",
+            "grid_layout": tuned,
             "parallelism": "single GPU",
         },
         "roofline": roof,
@@ -210,6 +227,44 @@ def roofline(name, avg_ms, st, n_cl, n_trk_hits):
             "frac": None, "traffic": None}
 
 
+def source_hash():
+    """SHA-256 over the library's kernel sources and header: a counter
+    summary applies to the kernels only while this is unchanged."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1905_05515_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_1905_05515_amd", "csrc", "*.hpp")) +
+                   [os.path.join(ROOT, "include", "tpc.h")])
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    factor a plain copy of known size reads), or None when there is none or
+    the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def batch_bench(args, api, synth, ctx, stream, prm):
     """The 512 uneven single-sector instances (~14M clusters) tracked in the
     three launch forms; the outputs are checked equal."""
@@ -220,8 +275,8 @@ def batch_bench(args, api, synth, ctx, stream, prm):
     log(f"[bench] batched set: {ev.n_sectors} instances, {ev.n_clusters} clusters, generated in "
         f"{time.time() - t0:.1f}s")
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
-                       occupancy=args.occupancy, sector_side=ev.sector_side)
-    res = {}
+                       sector_side=ev.sector_side)
+    res = {"grid_layout": pick_layout(args, api, ctx, e, stream)}
     ref = None
     steps = max(2, args.steps // 4)
     for mode, graph in (("staged", True), ("persistent", True), ("per_sector", False)):
@@ -305,7 +360,7 @@ def refit_bench(args, api, synth, ctx, stream, prm, dev):
     }
 
 
-def cpu_baseline(ev, prm, args):
+def cpu_baseline(ev, prm, args, occupancy=None):
     """The oracle (plain single-threaded C) on the host: the whole tracking
     chain over the event, the float refit of the found tracks, and the
     float64 central-difference gradient on a sample of them, scaled to all
@@ -314,7 +369,8 @@ def cpu_baseline(ev, prm, args):
 
     import oracle
     from paper_1905_05515_amd.layout import grid_layout
-    tab, nb = grid_layout(ev.sector_offsets, ev.sector_range, occupancy=args.occupancy,
+    occ = occupancy if occupancy is not None else 0.25
+    tab, nb = grid_layout(ev.sector_offsets, ev.sector_range, occupancy=occ,
                           sides=ev.sector_side)
     t0 = time.perf_counter()
     res = oracle.track_event(ev.row, ev.y, ev.z, tab, nb, ev.row_x, prm)

@@ -288,14 +288,19 @@ typedef struct tpc_track_hits {
  * cov[15] at the last hit, chi2, status (0 ok, 1 fewer than 3 hits, 2
  * |sin(phi)| stop, 3 a hit row >= n_rows, 4 more hits than rows).  The CSR
  * must be well formed (off increasing, off[n_tracks] = n_hits).
- * checkpoints (nullable) [n_rows * 20 * n_tracks]: state and covariance
- * after hit i (i < n - 1) of track t at [(i * 20 + k) * n_tracks + t], for
- * tpc_refit_adjoint; n_tracks is the n_tracks member (the capacity when a
- * device count is given). */
+ * checkpoints (nullable, ck_bytes long, at least tpc_refit_checkpoint_size
+ * of the n_tracks member): the state and covariance after every update but
+ * the last, for tpc_refit_adjoint, in a layout private to the library (tiles
+ * of 64 tracks, 20 floats per hit slot).  A shorter buffer is an argument
+ * error. */
 int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
               const tpc_params* h_params, const tpc_calib_model* h_model,
               const float* d_theta, float* par, float* cov, float* chi2, int32_t* status,
-              float* checkpoints, void* stream);
+              float* checkpoints, size_t ck_bytes, void* stream);
+
+/* Bytes of the checkpoint buffer of tpc_refit / tpc_refit_adjoint for
+ * n_tracks tracks (capacity) of at most n_rows hits. */
+int tpc_refit_checkpoint_size(int64_t n_tracks, int32_t n_rows, size_t* h_bytes);
 
 /* Bytes of workspace for tpc_refit_adjoint. */
 int tpc_refit_workspace_size(int64_t n_tracks, size_t* h_bytes);
@@ -308,7 +313,7 @@ int tpc_refit_workspace_size(int64_t n_tracks, size_t* h_bytes);
 int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                       const float* d_row_x, const tpc_params* h_params,
                       const tpc_calib_model* h_model, const float* d_theta,
-                      const float* checkpoints, const int32_t* status,
+                      const float* checkpoints, size_t ck_bytes, const int32_t* status,
                       const float* grad_chi2, float* grad_y, float* grad_z,
                       float* grad_theta, void* d_ws, size_t ws_bytes, void* stream);
 

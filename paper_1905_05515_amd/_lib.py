@@ -81,11 +81,12 @@ EXPORTS = {
     "tpc_track_batch": (C.c_int, [P, C.POINTER(Problem), Clusters, Grid, Links, Starts,
                                   Tracklets, Tracks, P, C.c_size_t, C.c_int, C.c_int, P]),
     "tpc_refit": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params), C.POINTER(CalibModel), P,
-                            P, P, P, P, P, P]),
+                            P, P, P, P, P, C.c_size_t, P]),
+    "tpc_refit_checkpoint_size": (C.c_int, [I64, I32, C.POINTER(C.c_size_t)]),
     "tpc_refit_workspace_size": (C.c_int, [I64, C.POINTER(C.c_size_t)]),
     "tpc_refit_adjoint": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params),
-                                    C.POINTER(CalibModel), P, P, P, P, P, P, P, P, C.c_size_t,
-                                    P]),
+                                    C.POINTER(CalibModel), P, P, C.c_size_t, P, P, P, P, P, P,
+                                    C.c_size_t, P]),
     "tpc_status_string": (C.c_char_p, [C.c_int]),
     "tpc_timing_enable": (C.c_int, [P, C.c_int]),
     "tpc_timing_report": (C.c_int, [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(I64),

@@ -14,6 +14,12 @@ from .layout import SECTOR_DTYPE, grid_layout
 
 MODES = {"staged": 0, "per_sector": 1, "persistent": 2}
 
+# clusters per bin of the grid when no layout is given: small bins keep the
+# window searches short (the tracks do not depend on this choice)
+DEFAULT_OCCUPANCY = 0.25
+# occupancies the autotuner tries
+TUNE_OCCUPANCIES = (0.0625, 0.125, 0.25, 0.5, 1.0)
+
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
@@ -39,6 +45,7 @@ class Context:
         h = C.c_void_p()
         L.check(L.lib().tpc_context_create(C.byref(h), device), "tpc_context_create")
         self.handle = h
+        self.tuned = {}     # autotuned occupancy per (sectors, clusters, mode)
 
     def close(self):
         if self.handle:
@@ -68,10 +75,12 @@ class Event:
 
 
 def make_event(row, y, z, sector_offsets, sector_range, row_x, prm: dict, device="cuda",
-               layout=None, occupancy=2.0, start_capacity=None, track_capacity=None,
+               layout=None, occupancy=None, start_capacity=None, track_capacity=None,
                track_hit_capacity=None, sector_side=None) -> Event:
     """Copy an event to the device and allocate all outputs."""
     n_rows = int(np.asarray(row_x).shape[0])
+    if occupancy is None:
+        occupancy = DEFAULT_OCCUPANCY
     if layout is None:
         layout = grid_layout(sector_offsets, sector_range, n_rows=n_rows, occupancy=occupancy,
                              sides=sector_side)
@@ -131,7 +140,63 @@ def make_event(row, y, z, sector_offsets, sector_range, row_x, prm: dict, device
     ev.track_capacity = tcap
     ev.track_hit_capacity = hcap
     ev.layout = (tab, n_bins)
+    ev.layout_args = (np.asarray(sector_offsets), np.asarray(sector_range), sector_side)
+    ev.occupancy = occupancy
     return ev
+
+
+def relayout(ev: Event, occupancy: float = None, layout=None):
+    """Give the event another bin grid (by occupancy, or an explicit layout
+    table): reallocates the bin starts and the workspace."""
+    offs, rng, sides = ev.layout_args
+    if layout is None:
+        layout = grid_layout(offs, rng, n_rows=ev.n_rows, occupancy=occupancy, sides=sides)
+    tab, n_bins = layout
+    tab = np.ascontiguousarray(tab, dtype=SECTOR_DTYPE)
+    t = ev.t
+    dev = t["y"].device
+    h_sec = torch.from_numpy(tab.view(np.uint8).copy())
+    t["h_sectors"] = h_sec
+    t["d_sectors"] = h_sec.to(dev)
+    t["bin_start"] = torch.empty(n_bins + 1, dtype=torch.int32, device=dev)
+    prob = ev.problem
+    prob.n_bins = n_bins
+    prob.h_sectors = C.c_void_p(h_sec.data_ptr())
+    prob.d_sectors = C.c_void_p(t["d_sectors"].data_ptr())
+    nbytes = C.c_size_t()
+    L.check(L.lib().tpc_workspace_size(C.byref(prob), ev.start_capacity, C.byref(nbytes)),
+            "tpc_workspace_size")
+    t["ws"] = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
+    ev.ws_bytes = int(nbytes.value)
+    ev.layout = (tab, n_bins)
+    ev.occupancy = occupancy
+
+
+def autotune(ctx: "Context", ev: Event, mode: str = "staged", candidates=TUNE_OCCUPANCIES,
+             reps: int = 3, stream=None):
+    """Time the tracking chain of this event for each bin occupancy and keep
+    the fastest layout.  The tracks do not depend on the layout, so the
+    choice only moves time.  Returns (best occupancy, {occupancy: ms}); the
+    choice is remembered in the context per event shape."""
+    s = stream if stream is not None else torch.cuda.current_stream()
+    times = {}
+    for occ in candidates:
+        relayout(ev, occ)
+        with torch.cuda.stream(s):
+            track_batch(ctx, ev, mode=mode, stream=s)          # warm
+            ms = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s)
+                track_batch(ctx, ev, mode=mode, stream=s)
+                b.record(s)
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+        times[occ] = sorted(ms)[len(ms) // 2]
+    best = min(times, key=lambda k: (times[k], k))
+    relayout(ev, best)
+    ctx.tuned[(ev.problem.n_sectors, ev.problem.n_clusters, mode)] = best
+    return best, times
 
 
 def _clusters(ev):
@@ -319,6 +384,19 @@ class TrackHits:
                            _ptr(self.side), self.d_count, self.n_tracks, self.n_hits)
 
 
+def checkpoint_bytes(n_tracks: int, n_rows: int) -> int:
+    """Size of the refit checkpoint buffer for n_tracks tracks of at most
+    n_rows hits."""
+    nb = C.c_size_t()
+    L.check(L.lib().tpc_refit_checkpoint_size(int(n_tracks), int(n_rows), C.byref(nb)),
+            "tpc_refit_checkpoint_size")
+    return int(nb.value)
+
+
+def _nbytes(t) -> int:
+    return 0 if t is None else t.numel() * t.element_size()
+
+
 def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: torch.Tensor,
           checkpoints: bool = True, cm=None, stream=None, y=None, z=None, out=None):
     """Forward refit; returns dict(par, cov, chi2, status, checkpoints).
@@ -330,9 +408,9 @@ def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: 
                    cov=torch.empty(n * 15, dtype=torch.float32, device=dev),
                    chi2=torch.empty(n, dtype=torch.float32, device=dev),
                    status=torch.empty(n, dtype=torch.int32, device=dev))
-        n_rows = int(row_x.shape[0])
-        out["checkpoints"] = (torch.empty(max(n * n_rows * 20, 1), dtype=torch.float32,
-                                          device=dev) if checkpoints else None)
+        out["checkpoints"] = (torch.empty(max(checkpoint_bytes(n, int(row_x.shape[0])) // 4, 1),
+                                          dtype=torch.float32, device=dev)
+                              if checkpoints else None)
     else:
         out = dict(out)
     P = params_struct(prm)
@@ -341,7 +419,8 @@ def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: 
     L.check(L.lib().tpc_refit(ctx.handle, hits.struct(y, z), int(row_x.shape[0]), _ptr(row_x),
                               C.byref(P), C.byref(CM), _ptr(th), _ptr(out["par"]),
                               _ptr(out["cov"]), _ptr(out["chi2"]), _ptr(out["status"]),
-                              _ptr(out["checkpoints"]), _stream(stream)), "tpc_refit")
+                              _ptr(out["checkpoints"]), _nbytes(out["checkpoints"]),
+                              _stream(stream)), "tpc_refit")
     out["par"] = out["par"].view(n, 5)
     out["cov"] = out["cov"].view(n, 15)
     return out
@@ -369,7 +448,8 @@ def refit_adjoint(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
     g = grad_chi2.detach().to(device=dev, dtype=torch.float32).contiguous()
     L.check(L.lib().tpc_refit_adjoint(ctx.handle, hits.struct(y, z), int(row_x.shape[0]),
                                       _ptr(row_x), C.byref(P), C.byref(CM), _ptr(th),
-                                      _ptr(fwd["checkpoints"]), _ptr(fwd["status"]), _ptr(g),
+                                      _ptr(fwd["checkpoints"]), _nbytes(fwd["checkpoints"]),
+                                      _ptr(fwd["status"]), _ptr(g),
                                       _ptr(gy), _ptr(gz), _ptr(gt), _ptr(ws), int(nb.value),
                                       _stream(stream)), "tpc_refit_adjoint")
     return gy[:hits.n_hits], gz[:hits.n_hits], gt

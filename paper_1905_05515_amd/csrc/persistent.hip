@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(PArgs a)
             if (threadIdx.x < items && t < hi_t)
                 build_tracklet(t, a.sec, a.n_rows, xs, a.prm, a.grid.bin_start, a.grid.y,
                                a.grid.z, a.grid.id, a.ws.gsr, a.links.up, a.starts,
-                               a.trl.capacity, a.trl.start, a.trl.hits, a.trl.nhits,
+                               a.trl.hits + t, a.trl.capacity, a.trl.start, a.trl.nhits,
                                a.trl.row_inner, a.trl.par, a.trl.cov, a.trl.chi2, n_prop, n_upd,
                                n_cand);
             add_work(status, n_prop, n_upd, n_cand);

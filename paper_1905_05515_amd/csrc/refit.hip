@@ -391,27 +391,42 @@ __device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const 
     return dxb;
 }
 
-// checkpoint of hit i of track t: 20 floats (p, C) at ck[(i * 20 + k) *
-// n_tracks + t], so that the lanes of a wave (consecutive tracks) store and
-// load whole lines at every step
-__device__ __forceinline__ void store_ck(float* ck, int64_t nt, int64_t t, int i, const float* p,
-                                         const float* C)
+// Checkpoints are kept in tiles of 64 tracks (one wave): slot i of the
+// track in lane l of tile g holds 20 floats (p, C) at
+// ck[((g * n_rows + i) * 20 + k) * 64 + l].  The lanes of a wave that stand
+// at the same slot store and load whole 256-byte lines, and one wave's
+// checkpoints are one contiguous block.
+__device__ __forceinline__ float* ck_tile(float* ck, int64_t t, int n_rows)
 {
-    float* o = ck + (int64_t)i * 20 * nt + t;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) o[k * nt] = p[k];
-#pragma unroll
-    for (int k = 0; k < 15; ++k) o[(5 + k) * nt] = C[k];
+    return ck + (t / kWave) * (int64_t)n_rows * 20 * kWave + (t & (kWave - 1));
 }
 
-__device__ __forceinline__ void load_ck(const float* ck, int64_t nt, int64_t t, int i, float* p,
-                                        float* C)
+__device__ __forceinline__ void store_ck(float* o, int i, const float* p, const float* C)
 {
-    const float* o = ck + (int64_t)i * 20 * nt + t;
+    o += (int64_t)i * 20 * kWave;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) p[k] = o[k * nt];
+    for (int k = 0; k < 5; ++k) o[k * kWave] = p[k];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) C[k] = o[(5 + k) * nt];
+    for (int k = 0; k < 15; ++k) o[(5 + k) * kWave] = C[k];
+}
+
+__device__ __forceinline__ void load_ck(const float* o, int i, float* p, float* C)
+{
+    o += (int64_t)i * 20 * kWave;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) p[k] = o[k * kWave];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) C[k] = o[(5 + k) * kWave];
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const int w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
 }
 
 __device__ __forceinline__ void load_theta(const float* __restrict__ d_theta, float* th)
@@ -471,7 +486,8 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
             C[5] = prm.c_ss0;
             C[9] = prm.c_tt0;
             C[14] = prm.c_ww0;
-            if (ck) store_ck(ck, n_tracks, t, 0, p, C);
+            float* ckt = ck ? ck_tile(ck, t, n_rows) : nullptr;
+            if (ckt) store_ck(ckt, 0, p, C);
             float xp = h0.x;
             for (int i = 1; i < n; ++i) {
                 const CalHit h = H.cal(i, th, xs, sd, cm);
@@ -483,7 +499,7 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
                 Upd U;
                 chi2 += upd_fwd(p, C, h.y, h.z, prm.sigma_y2, prm.sigma_z2, U);
                 xp = h.x;
-                if (ck && i + 1 < n) store_ck(ck, n_tracks, t, i, p, C);
+                if (ckt && i + 1 < n) store_ck(ckt, i, p, C);
             }
         }
 #pragma unroll
@@ -514,29 +530,42 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
 #pragma unroll
     for (int k = 0; k < 16; ++k) gth[k] = 0.0f;
     const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int a = off[t], n = off[t + 1] - a;
-        HitRef H{idx, row, y, z, a};
-        if (n < 3 || status[t] != 0) {
+    const int lane = threadIdx.x & (kWave - 1);
+    // one wave per tile of 64 tracks; the reverse sweep runs over the slots
+    // of the tile in lockstep (slot i is active in the lanes whose track has
+    // more than i hits), so that checkpoint loads are whole lines
+    for (int64_t tb = blockIdx.x * (int64_t)kWave; tb < nt; tb += (int64_t)gridDim.x * kWave) {
+        const int64_t t = tb + lane;
+        int a = 0, n = 0;
+        if (t < nt) {
+            a = off[t];
+            n = off[t + 1] - a;
+        }
+        const bool fit = t < nt && n >= 3 && status[t] == 0;
+        if (t < nt && !fit)
             for (int i = 0; i < n; ++i) {
                 gy[a + i] = 0.0f;
                 gz[a + i] = 0.0f;
             }
-            continue;
-        }
-        const float sd = side ? (float)side[t] : 1.0f;
-        const float cb = gchi2[t];
+        const int ne = fit ? n : 0;
+        const int M = wave_max(ne);
+        if (M == 0) continue;
+        HitRef H{idx, row, y, z, a};
+        const float* ckt = ck_tile(const_cast<float*>(ck), tb + lane, n_rows);
+        const float sd = fit && side ? (float)side[t] : 1.0f;
+        const float cb = fit ? gchi2[t] : 0.0f;
         float pb[5] = {0, 0, 0, 0, 0}, G[15];
 #pragma unroll
         for (int i = 0; i < 15; ++i) G[i] = 0.0f;
-        CalHit cur = H.cal(n - 1, th, xs, sd, cm);
+        CalHit cur{};
+        if (fit) cur = H.cal(n - 1, th, xs, sd, cm);
         float Xcarry = 0.0f;
         float X2 = 0.0f, Y2 = 0.0f, Z2 = 0.0f;
-        for (int i = n - 1; i >= 1; --i) {
+        for (int i = M - 1; i >= 1; --i) {
+            if (i >= ne) continue;
             const CalHit prev = H.cal(i - 1, th, xs, sd, cm);
             float p[5], C[15];
-            load_ck(ck, n_tracks, t, i - 1, p, C);
+            load_ck(ckt, i - 1, p, C);
             const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};
             Prop P;
             prop_fwd(p, C, cur.x - prev.x, prm.curv, prm.s_max, P);
@@ -559,6 +588,7 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
             Xcarry = -dxb;
             cur = prev;
         }
+        if (!fit) continue;
         // initial state: y, z of hit 0, direction from hit 0 to hit 2
         const CalHit h0 = cur;
         const CalHit h2 = H.cal(2, th, xs, sd, cm);
@@ -589,7 +619,6 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
         gz[a + 2] = gzr;
     }
     // deterministic wave reduction of the theta adjoint (one wave per block)
-    const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         float v = gth[k];
@@ -633,16 +662,28 @@ int tpc_refit_workspace_size(int64_t n_tracks, size_t* h_bytes)
     return TPC_OK;
 }
 
+int tpc_refit_checkpoint_size(int64_t n_tracks, int32_t n_rows, size_t* h_bytes)
+{
+    if (!h_bytes || n_tracks < 0 || n_rows < 3 || n_rows > 255) return TPC_ERR_INVALID_ARG;
+    const int64_t tiles = (n_tracks + tpc::kWave - 1) / tpc::kWave;
+    *h_bytes = sizeof(float) * (size_t)tiles * tpc::kWave * (size_t)n_rows * 20;
+    return TPC_OK;
+}
+
 int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
               const tpc_params* h_params, const tpc_calib_model* h_model, const float* d_theta,
               float* par, float* cov, float* chi2, int32_t* status, float* checkpoints,
-              void* stream)
+              size_t ck_bytes, void* stream)
 {
     tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
     if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !par || !cov || !chi2 ||
         !status || hits.n_tracks < 0 || hits.n_hits < 0 || n_rows < 3 || n_rows > 255 ||
         (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
         hits.n_hits >= (int64_t(1) << 31))
+        return TPC_ERR_INVALID_ARG;
+    size_t ck_need = 0;
+    if (checkpoints && (tpc_refit_checkpoint_size(hits.n_tracks, n_rows, &ck_need) ||
+                        ck_bytes < ck_need))
         return TPC_ERR_INVALID_ARG;
     if (hits.n_tracks == 0) return TPC_OK;
     tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
@@ -657,7 +698,8 @@ int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float
 int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                       const float* d_row_x, const tpc_params* h_params,
                       const tpc_calib_model* h_model, const float* d_theta,
-                      const float* checkpoints, const int32_t* status, const float* grad_chi2,
+                      const float* checkpoints, size_t ck_bytes, const int32_t* status,
+                      const float* grad_chi2,
                       float* grad_y, float* grad_z, float* grad_theta, void* d_ws,
                       size_t ws_bytes, void* stream)
 {
@@ -667,7 +709,8 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
         !grad_chi2 || !grad_y || !grad_z || !grad_theta || !d_ws || hits.n_tracks < 0 ||
         n_rows < 3 || n_rows > 255 ||
         (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
-        tpc_refit_workspace_size(hits.n_tracks, &need) || need > ws_bytes)
+        tpc_refit_workspace_size(hits.n_tracks, &need) || need > ws_bytes ||
+        tpc_refit_checkpoint_size(hits.n_tracks, n_rows, &need) || need > ck_bytes)
         return TPC_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,

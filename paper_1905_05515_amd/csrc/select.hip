@@ -7,7 +7,10 @@
 
 namespace tpc {
 
-__global__ __launch_bounds__(kWave) void k_sel_keys(
+// Staged kernels: item (t, blockIdx.y) handles rows [8 y, 8 y + 8) of
+// tracklet t; consecutive threads take consecutive tracklets, so every row
+// load of a chunk is one coalesced line per wave.
+__global__ __launch_bounds__(kBlock) void k_sel_keys(
     int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
@@ -16,42 +19,75 @@ __global__ __launch_bounds__(kWave) void k_sel_keys(
 {
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
+    const int ra = blockIdx.y * kSelRows;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x)
-        sel_keys_one(t, n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey);
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        if (key) sel_keys_chunk(t, ra, n_rows, key, t_hits, cap, hitkey);
+    }
 }
 
-__global__ __launch_bounds__(kWave) void k_sel_count(
+__global__ __launch_bounds__(kBlock) void k_sel_count(
     int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
     const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, uint64_t* __restrict__ tlen)
+    const unsigned long long* __restrict__ hitkey, uint8_t* __restrict__ ccnt)
+{
+    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
+    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
+    const int ra = blockIdx.y * kSelRows;
+    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        ccnt[blockIdx.y * count_cap + t] =
+            key ? (uint8_t)sel_count_chunk(t, ra, n_rows, key, t_hits, cap, hitkey) : 0;
+    }
+}
+
+// per tracklet: 1 << 32 | kept if it becomes a track, else 0
+__global__ __launch_bounds__(kBlock) void k_sel_len(
+    int n_chunks, tpc_params prm, const int64_t* __restrict__ t_lo,
+    const int64_t* __restrict__ t_hi, int64_t count_cap, const uint8_t* __restrict__ ccnt,
+    uint64_t* __restrict__ tlen)
 {
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x)
-        tlen[t] = sel_count_one(t, n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey);
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int kept = 0;
+        for (int q = 0; q < n_chunks; ++q) kept += ccnt[q * count_cap + t];
+        tlen[t] = kept >= prm.min_track_hits ? ((1ull << 32) | (uint64_t)kept) : 0ull;
+    }
 }
 
-__global__ __launch_bounds__(kWave) void k_sel_write(
+__global__ __launch_bounds__(kBlock) void k_sel_write(
     int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, const tpc_status* __restrict__ status, int64_t count_cap,
     int64_t cap, const unsigned long long* __restrict__ hitkey, const uint64_t* __restrict__ tlen,
-    const uint64_t* __restrict__ toff, const tpc_sector* __restrict__ sec,
-    const int32_t* __restrict__ gsr, int32_t* __restrict__ trk_off,
-    int32_t* __restrict__ trk_hits, int32_t* __restrict__ trk_tracklet,
-    int8_t* __restrict__ trk_side, int64_t trk_cap, int64_t hit_cap)
+    const uint64_t* __restrict__ toff, const uint8_t* __restrict__ ccnt,
+    const tpc_sector* __restrict__ sec, const int32_t* __restrict__ gsr,
+    int32_t* __restrict__ trk_off, int32_t* __restrict__ trk_hits,
+    int32_t* __restrict__ trk_tracklet, int8_t* __restrict__ trk_side, int64_t trk_cap,
+    int64_t hit_cap)
 {
     int64_t m = status->n_starts;
     if (m > count_cap) m = count_cap;
+    const int q = blockIdx.y;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x)
-        if (tlen[t])
-            sel_write_one(t, toff[t], n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey,
-                          sec, gsr, trk_off, trk_hits, trk_tracklet, trk_side, trk_cap, hit_cap);
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (!tlen[t]) continue;
+        const uint64_t to = toff[t];
+        int64_t o = (int64_t)(to & 0xFFFFFFFFull);
+        if (q == 0)
+            sel_write_track(t, (int64_t)(to >> 32), o, t_start, sec, gsr, trk_off, trk_tracklet,
+                            trk_side, trk_cap);
+        for (int j = 0; j < q; ++j) o += ccnt[j * count_cap + t];
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        sel_write_chunk(t, q * kSelRows, n_rows, key, o, idg, t_hits, cap, hitkey, trk_hits,
+                        hit_cap);
+    }
 }
 
 __global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status* status,
@@ -67,6 +103,8 @@ __global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status
     if (nh > hit_cap) status->overflow |= 4;
 }
 
+static unsigned sel_grid_x(int64_t n) { return grid_for_block(n, kBlock, 1024); }
+
 // Ownership keys and kept-hit counts of the tracklets of sectors
 // [sec_lo, sec_hi) (their hits are grid positions of those sectors).
 int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
@@ -74,18 +112,21 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
 {
     const int64_t c0 = p->h_sectors[sec_lo].begin, c1 = p->h_sectors[sec_hi - 1].end;
     const int64_t bound = (c1 - c0) / 3 + 1;
-    const unsigned gt = grid_for_block(bound < count_cap ? bound : count_cap, kWave, 65536);
+    const unsigned gx = sel_grid_x(bound < count_cap ? bound : count_cap);
+    const int nq = sel_chunks(p->n_rows);
     const int64_t* lo = ws.sec_start + sec_lo;
     const int64_t* hi = ws.sec_start + sec_hi;
     launch_fill<uint64_t>(ws.hitkey + c0, 0ull, c1 - c0, st);
-    TPC_LAUNCH(k_sel_keys, dim3(gt), dim3(kWave), 0, st, p->n_rows, p->params,
+    TPC_LAUNCH(k_sel_keys, dim3(gx, nq), dim3(kBlock), 0, st, p->n_rows, p->params,
                (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
                (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
                (unsigned long long*)ws.hitkey);
-    TPC_LAUNCH(k_sel_count, dim3(gt), dim3(kWave), 0, st, p->n_rows, p->params,
+    TPC_LAUNCH(k_sel_count, dim3(gx, nq), dim3(kBlock), 0, st, p->n_rows, p->params,
                (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
                (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
-               (const unsigned long long*)ws.hitkey, ws.tlen);
+               (const unsigned long long*)ws.hitkey, ws.ccnt);
+    TPC_LAUNCH(k_sel_len, dim3(gx), dim3(kBlock), 0, st, nq, p->params, lo, hi, count_cap,
+               (const uint8_t*)ws.ccnt, ws.tlen);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
@@ -94,14 +135,15 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
 int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
                        tpc_tracklets trl, tpc_tracks trk, const Workspace& ws, hipStream_t st)
 {
-    const unsigned gt = grid_for_block(count_cap, kWave, 65536);
+    const unsigned gx = sel_grid_x(count_cap);
     launch_scan<uint64_t>(ws.tlen, ws.toff, count_cap, true, nullptr, nullptr, ws.partials, st);
-    TPC_LAUNCH(k_sel_write, dim3(gt), dim3(kWave), 0, st, p->n_rows, p->params,
-               (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
-               (const int32_t*)trl.nhits, (const tpc_status*)ws.status, count_cap, trl.capacity,
-               (const unsigned long long*)ws.hitkey, (const uint64_t*)ws.tlen,
-               (const uint64_t*)ws.toff, p->d_sectors, (const int32_t*)ws.gsr, trk.off,
-               trk.hits, trk.tracklet, trk.side, trk.capacity, trk.hit_capacity);
+    TPC_LAUNCH(k_sel_write, dim3(gx, sel_chunks(p->n_rows)), dim3(kBlock), 0, st, p->n_rows,
+               p->params, (const int32_t*)grid.id, (const int32_t*)trl.start,
+               (const int32_t*)trl.hits, (const int32_t*)trl.nhits, (const tpc_status*)ws.status,
+               count_cap, trl.capacity, (const unsigned long long*)ws.hitkey,
+               (const uint64_t*)ws.tlen, (const uint64_t*)ws.toff, (const uint8_t*)ws.ccnt,
+               p->d_sectors, (const int32_t*)ws.gsr, trk.off, trk.hits, trk.tracklet, trk.side,
+               trk.capacity, trk.hit_capacity);
     TPC_LAUNCH(k_sel_finish, dim3(1), dim3(1), 0, st, (const uint64_t*)(ws.toff + count_cap),
                ws.status, trk.off, trk.capacity, trk.hit_capacity);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;

@@ -30,12 +30,17 @@ struct Workspace {
     uint64_t* hitkey;      // [n] selection keys per grid position
     uint64_t* tlen;        // [start_cap + 1] per tracklet: accepted << 32 | kept
     uint64_t* toff;        // [start_cap + 1] exclusive scan of tlen
+    uint8_t* ccnt;         // [row chunks * start_cap] kept hits per tracklet and row chunk
     int64_t* sec_start;    // [n_sectors + 1] first start of each sector
     int32_t* pq;           // persistent form: [1] queue head, [kPhases * n_sectors] done counts
     int64_t* scnt;         // persistent form: [n_sectors] starts per sector
     uint64_t* tsum;        // persistent form: [n_sectors] tracks << 32 | hits per sector
     size_t bytes;
 };
+
+// Rows of a tracklet handled by one selection work item.
+constexpr int kSelRows = 8;
+inline int sel_chunks(int n_rows) { return (n_rows + kSelRows - 1) / kSelRows; }
 
 // Offsets of the workspace members for a problem; returns false on overflow.
 bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Workspace* ws);

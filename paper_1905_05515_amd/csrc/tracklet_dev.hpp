@@ -131,14 +131,16 @@ __device__ __forceinline__ void reset_cov(KState& st, const tpc_params& prm)
 }
 
 // Hit of least predicted chi2 <= chi2_max on row r of sector s, ties to the
-// lower cluster id; -1 if none.  The bins scanned cover +-nsigma of the
-// prediction (every hit passing the gate lies inside); the gate decides.
+// lower cluster id; -1 if none, else its grid position with its coordinates
+// in (my, mz).  The bins scanned cover +-nsigma of the prediction (every hit
+// passing the gate lies inside); the gate decides.  Two z rows of bins are
+// opened at a time so that their bin bounds load together.
 __device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s, int r,
                                           const tpc_params& prm, int& n_cand,
                                           const int32_t* __restrict__ bin_start,
                                           const float* __restrict__ yg,
                                           const float* __restrict__ zg,
-                                          const int32_t* __restrict__ idg)
+                                          const int32_t* __restrict__ idg, float& my, float& mz)
 {
     const float S00 = st.C[0] + prm.sigma_y2, S11 = st.C[2] + prm.sigma_z2;
     const float hy = prm.search_nsigma * sqrtf(S00) * TPC_WIDEN + 0.01f;
@@ -148,41 +150,60 @@ __device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s,
     const int iz0 = bin_of(st.p[1] - hz, s.z0, s.inv_bz, s.nbz);
     const int iz1 = bin_of(st.p[1] + hz, s.z0, s.inv_bz, s.nbz);
     float best = 0.0f;
-    int bpos = -1, bid = -1;
-    for (int iz = iz0; iz <= iz1; ++iz) {
+    int bpos = -1;
+    for (int iz = iz0; iz <= iz1; iz += 2) {
         const int g = s.bin_base + (r * s.nbz + iz) * s.nby;
-        const int pe = bin_start[g + iy1 + 1];
-        n_cand += pe - bin_start[g + iy0] > 0 ? pe - bin_start[g + iy0] : 0;
-        for (int pc = bin_start[g + iy0]; pc < pe; ++pc) {
-            const float c2 = chi2_pred(st, yg[pc], zg[pc], prm.sigma_y2, prm.sigma_z2);
-            if (!(c2 <= prm.chi2_max)) continue;
-            const int id = idg[pc];
-            if (bid < 0 || c2 < best || (c2 == best && id < bid)) {
-                best = c2;
-                bid = id;
-                bpos = pc;
+        int lo[2], hi[2];
+        lo[0] = bin_start[g + iy0];
+        hi[0] = bin_start[g + iy1 + 1];
+        lo[1] = hi[1] = 0;
+        if (iz + 1 <= iz1) {
+            lo[1] = bin_start[g + s.nby + iy0];
+            hi[1] = bin_start[g + s.nby + iy1 + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            n_cand += hi[k] - lo[k] > 0 ? hi[k] - lo[k] : 0;
+            for (int pc = lo[k]; pc < hi[k]; ++pc) {
+                const float y = yg[pc], z = zg[pc];
+                const float c2 = chi2_pred(st, y, z, prm.sigma_y2, prm.sigma_z2);
+                if (!(c2 <= prm.chi2_max)) continue;
+                // equal chi2 (rare): the lower cluster id wins
+                if (bpos < 0 || c2 < best || (c2 == best && idg[pc] < idg[bpos])) {
+                    best = c2;
+                    bpos = pc;
+                    my = y;
+                    mz = z;
+                }
             }
         }
     }
     return bpos;
 }
 
-// Build tracklet t (one thread): xs holds the row positions (LDS); the hit
-// list goes to column t of the [row][tracklet] array of row stride cap.
+// Build tracklet t (one thread).  xs holds the row positions; the hit list
+// (grid position per row, -1 where none) goes to th[r * ths], which is either
+// the tracklet's column of the [row][tracklet] output or a scratch column in
+// LDS that the caller copies out.
+//
+// Up pass: from the start hit, one row at a time, the next hit is the next
+// link of the chain while there is one (links always join adjacent rows),
+// then the least-chi2 hit of a window search.  Down pass: from the outermost
+// hit with the initial covariance, the hits already assigned are refitted and
+// rows below the start are searched.  The loads of the next chain hit (up
+// pass) and of the next assigned hit (down pass) are issued one row ahead.
 __device__ __forceinline__ void build_tracklet(
     int64_t t, const tpc_sector* __restrict__ sec, int n_rows, const float* xs,
     const tpc_params& prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
     const float* __restrict__ zg, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ gsr, const int32_t* __restrict__ up,
-    const int32_t* __restrict__ starts, int64_t cap, int32_t* __restrict__ t_start,
-    int32_t* __restrict__ t_hits, int32_t* __restrict__ t_nhits, int32_t* __restrict__ t_rin,
+    const int32_t* __restrict__ starts, int32_t* th, int64_t ths, int32_t* __restrict__ t_start,
+    int32_t* __restrict__ t_nhits, int32_t* __restrict__ t_rin,
     float* __restrict__ t_par, float* __restrict__ t_cov, float* __restrict__ t_chi2,
     int& n_prop, int& n_upd, int& n_cand)
 {
     const float sy2 = prm.sigma_y2, sz2 = prm.sigma_z2;
-    // hit list of this tracklet: column t of the [row][tracklet] array
-    int32_t* th = t_hits + t;
-    for (int r = 0; r < n_rows; ++r) th[(int64_t)r * cap] = -1;
+    for (int r = 0; r < n_rows; ++r) th[r * ths] = -1;
     const int h0 = starts[t];
     const int v0 = gsr[h0];
     const tpc_sector s = sec[v0 >> 8];
@@ -201,47 +222,53 @@ __device__ __forceinline__ void build_tracklet(
         st.p[4] = 0.0f;
         reset_cov(st, prm);
     }
-    th[(int64_t)(r0) * cap] = h0;
-    int cur = r0, last = r0;
+    th[r0 * ths] = h0;
+    int last = r0;
     float plast[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
-    bool ok = true;
-    // outwards along the chain
-    for (int h = h1; h >= 0; h = up[h]) {
-        const int r = gsr[h] & 255;
-        if (!(++n_prop, propagate(st, xs[r] - xs[cur], prm.curv, prm.s_max))) {
-            ok = false;
-            break;
+
+    // ---- up pass
+    int cc = h1, cn = h2;                 // chain hit of this row, of the next
+    float cy = yg[h1], cz = zg[h1];
+    int miss = 0;
+    for (int r = r0 + 1; r < n_rows; ++r) {
+        const bool chain = cc >= 0;
+        float ny = 0.0f, nz = 0.0f;
+        int cnn = -1;
+        if (cn >= 0) {
+            ny = yg[cn];
+            nz = zg[cn];
+            cnn = up[cn];
+        }
+        ++n_prop;
+        if (!propagate(st, xs[r] - xs[r - 1], prm.curv, prm.s_max)) break;
+        int c = cc;
+        float my = cy, mz = cz;
+        if (!chain) {
+            c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg, my, mz);
+            if (c < 0) {
+                if (++miss >= prm.max_miss) break;
+                continue;
+            }
+            miss = 0;
         }
         ++n_upd;
-        kupdate(st, yg[h], zg[h], sy2, sz2);
-        th[(int64_t)(r) * cap] = h;
-        cur = last = r;
+        kupdate(st, my, mz, sy2, sz2);
+        th[r * ths] = c;
+        last = r;
 #pragma unroll
         for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
-    }
-    // outwards, searching row by row
-    if (ok) {
-        int miss = 0;
-        for (int r = cur + 1; r < n_rows; ++r) {
-            if (!(++n_prop, propagate(st, xs[r] - xs[r - 1], prm.curv, prm.s_max))) break;
-            const int c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg);
-            if (c >= 0) {
-                ++n_upd;
-                kupdate(st, yg[c], zg[c], sy2, sz2);
-                th[(int64_t)(r) * cap] = c;
-                last = r;
-#pragma unroll
-                for (int i = 0; i < 5; ++i) plast[i] = st.p[i];
-                miss = 0;
-            } else if (++miss >= prm.max_miss) {
-                break;
-            }
+        if (chain) {
+            cc = cn;
+            cy = ny;
+            cz = nz;
+            cn = cnn;
         }
     }
-    // inwards from the outermost hit with the initial covariance
-    const int hl = th[(int64_t)(last) * cap];
+
+    // ---- down pass
+    const int hl = th[last * ths];
 #pragma unroll
     for (int i = 0; i < 5; ++i) st.p[i] = plast[i];
     st.p[0] = yg[hl];
@@ -249,17 +276,35 @@ __device__ __forceinline__ void build_tracklet(
     reset_cov(st, prm);
     KState in = st;
     float csum = 0.0f;
-    int rin = last, miss = 0;
+    int rin = last;
+    miss = 0;
+    int an = -1;                          // assigned hit of the next row down
+    float ay = 0.0f, az = 0.0f;
+    if (last - 1 >= r0) {
+        an = th[(last - 1) * ths];
+        if (an >= 0) {
+            ay = yg[an];
+            az = zg[an];
+        }
+    }
     for (int r = last - 1; r >= 0; --r) {
-        if (!(++n_prop, propagate(st, xs[r] - xs[r + 1], prm.curv, prm.s_max))) {
-            for (int q = r; q >= 0; --q) th[(int64_t)(q) * cap] = -1;
+        int c = an;
+        float my = ay, mz = az;
+        an = -1;
+        if (r - 1 >= r0) {
+            an = th[(r - 1) * ths];
+            if (an >= 0) {
+                ay = yg[an];
+                az = zg[an];
+            }
+        }
+        ++n_prop;
+        if (!propagate(st, xs[r] - xs[r + 1], prm.curv, prm.s_max)) {
+            for (int q = r; q >= 0; --q) th[q * ths] = -1;
             break;
         }
-        int c;
-        if (r >= r0) {
-            c = th[(int64_t)(r) * cap];
-        } else {
-            c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg);
+        if (r < r0) {
+            c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg, my, mz);
             if (c < 0) {
                 if (++miss >= prm.max_miss) break;
                 continue;
@@ -268,14 +313,14 @@ __device__ __forceinline__ void build_tracklet(
         }
         if (c >= 0) {
             ++n_upd;
-            csum = csum + kupdate(st, yg[c], zg[c], sy2, sz2);
-            th[(int64_t)(r) * cap] = c;
+            csum = csum + kupdate(st, my, mz, sy2, sz2);
+            th[r * ths] = c;
             rin = r;
             in = st;
         }
     }
     int nh = 0;
-    for (int r = 0; r < n_rows; ++r) nh += th[(int64_t)(r) * cap] >= 0;
+    for (int r = 0; r < n_rows; ++r) nh += th[r * ths] >= 0;
     t_start[t] = h0;
     t_nhits[t] = nh;
     t_rin[t] = rin;

@@ -140,18 +140,22 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
         o = align256(o + bytes);
         return b ? (void*)(b + at) : nullptr;
     };
+    // members whose place depends on the problem only first: calls of one
+    // problem with different start capacities agree on them
     ws->status = (tpc_status*)take(sizeof(tpc_status));
     ws->cnt = (int32_t*)take(sizeof(int32_t) * (size_t)(nb + 1));
     ws->tmp = (int32_t*)take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     ws->gsr = (int32_t*)take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    ws->partials = (int64_t*)take(sizeof(int64_t) * (size_t)max_tiles);
     ws->hitkey = (uint64_t*)take(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-    ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));
-    ws->toff = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 2));
     ws->sec_start = (int64_t*)take(sizeof(int64_t) * (size_t)(p->n_sectors + 1));
     ws->pq = (int32_t*)take(sizeof(int32_t) * (size_t)(1 + kPhases * p->n_sectors));
     ws->scnt = (int64_t*)take(sizeof(int64_t) * (size_t)p->n_sectors);
     ws->tsum = (uint64_t*)take(sizeof(uint64_t) * (size_t)p->n_sectors);
+    // scratch of single calls, sized by the start capacity
+    ws->partials = (int64_t*)take(sizeof(int64_t) * (size_t)max_tiles);
+    ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));
+    ws->toff = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 2));
+    ws->ccnt = (uint8_t*)take((size_t)sel_chunks(p->n_rows) * (size_t)(start_cap > 0 ? start_cap : 1));
     ws->bytes = o;
     return true;
 }

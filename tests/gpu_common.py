@@ -18,7 +18,7 @@ def ctx():
     return _CTX
 
 
-def run_gpu(ev, prm=None, occupancy=2.0, mode=None, use_graph=False, layout=None, **kw):
+def run_gpu(ev, prm=None, occupancy=api.DEFAULT_OCCUPANCY, mode=None, use_graph=False, layout=None, **kw):
     prm = prm or synth.default_params()
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
                        occupancy=occupancy, layout=layout, sector_side=ev.sector_side, **kw)
@@ -29,7 +29,7 @@ def run_gpu(ev, prm=None, occupancy=2.0, mode=None, use_graph=False, layout=None
     return e, api.results(e)
 
 
-def run_oracle(ev, prm=None, occupancy=2.0, layout=None):
+def run_oracle(ev, prm=None, occupancy=api.DEFAULT_OCCUPANCY, layout=None):
     prm = prm or synth.default_params()
     tab, nb = layout if layout is not None else grid_layout(ev.sector_offsets, ev.sector_range,
                                                             occupancy=occupancy,

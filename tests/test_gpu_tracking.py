@@ -155,3 +155,23 @@ def test_track_parameters_match_fp64_replay():
     errs = np.array(errs)
     assert errs.shape[0] > 100
     assert np.mean(errs > 1e-4) < 2e-3 and errs.max() < 1e-3
+
+
+def test_autotuned_layout_gives_the_same_tracks():
+    """The autotuner only picks a bin layout: the tracks found with its pick
+    are the oracle's, and equal to those of a fixed layout."""
+    ev = synth.make_config2()
+    print(f"case c2 autotune n={ev.n_clusters}", flush=True)
+    prm = synth.default_params()
+    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
+                       occupancy=2.0, sector_side=ev.sector_side)
+    best, times = api.autotune(ctx(), e, candidates=(0.125, 0.5, 2.0), reps=2)
+    assert best in times and all(v > 0 for v in times.values())
+    assert ctx().tuned[(e.problem.n_sectors, e.problem.n_clusters, "staged")] == best
+    api.track(ctx(), e)
+    g = api.results(e)
+    o = run_oracle(ev, occupancy=best)
+    assert_same_tracking(g, o, ev.n_clusters)
+    _, g2 = run_gpu(ev, occupancy=2.0)
+    assert np.array_equal(g["trk_hits"], g2["trk_hits"])
+    assert np.array_equal(g["trk_off"], g2["trk_off"])

@@ -36,6 +36,10 @@ ALU_PEAK_FMA_TFLOPS = 157.3
 FLOPS_PROPAGATE = 179
 FLOPS_UPDATE = 130
 FLOPS_CHI2 = 20
+# grid build to chain starts: read row, y, z (9 B) and write the grid
+# (12 B); neighbours read y, z (8 B) and write two links (8 B); cleaning
+# reads the links (8 B) and writes the clean ones (8 B); bin starts ~4 B
+SEEDING_BYTES_PER_CLUSTER = 57
 
 
 def parse():
@@ -47,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-refit-bench", action="store_true")
     ap.add_argument("--no-batch-bench", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the "
+                         "reference size for scaling the HBM byte counters) and exit")
     ap.add_argument("--occupancy", default="auto",
                     help="clusters per grid bin, or 'auto' (autotuned per workload before "
                          "the timed region; the tracks do not depend on it)")
@@ -82,6 +89,15 @@ def main():
     from paper_1905_05515_amd import api
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {4 * n} bytes 3 times")
+        return
     dev = torch.device("cuda:0")
     t0 = time.time()
     ev = synth.make_config2()
@@ -300,6 +316,40 @@ def batch_bench(args, api, synth, ctx, stream, prm):
                      "equal_output": bool(same), "tracks": int(r["status"]["n_tracks"])}
         log(f"[bench]   {mode:11s} {ms:8.3f} ms  {ev.n_clusters / (ms * 1e-3):.3e} clusters/s "
             f"equal={same}")
+    # per-kernel times of the staged form (eager launches, HIP events)
+    with torch.cuda.stream(stream):
+        api.timing_enable(ctx, True)
+        for _ in range(steps):
+            api.track_batch(ctx, e, mode="staged", use_graph=False, stream=stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    per = {k: ms / steps for k, (n, ms) in kt.items()}
+    res["staged_kernels_us"] = {k: round(v * 1e3, 1) for k, v in
+                                sorted(per.items(), key=lambda kv: -kv[1])}
+    # grid build to chain starts alone: the two entry points that run them
+    with torch.cuda.stream(stream):
+        api.build_grid(ctx, e, stream)
+        api.find_neighbours(ctx, e, stream)
+        a = torch.cuda.Event(enable_timing=True)
+        b_ = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            api.build_grid(ctx, e, stream)
+            api.find_neighbours(ctx, e, stream)
+        b_.record(stream)
+        torch.cuda.synchronize()
+    seed_ms = a.elapsed_time(b_) / steps
+    b = SEEDING_BYTES_PER_CLUSTER * ev.n_clusters
+    res["roofline_grid_to_starts"] = {
+        "bound": "hbm", "kernels": "tpc_build_grid + tpc_find_neighbours (grid, neighbours, "
+                                   "cleaning, starts), eager launches",
+        "achieved": b / (seed_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": b / (seed_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": seed_ms,
+        "algorithmic_bytes_per_cluster": SEEDING_BYTES_PER_CLUSTER}
+    log(f"[bench]   grid..starts {seed_ms * 1e3:.1f} us, "
+        f"{res['roofline_grid_to_starts']['frac'] * 100:.1f}% of HBM peak at "
+        f"{SEEDING_BYTES_PER_CLUSTER} B/cluster")
     res["workload"] = ("512 single-sector instances, half pp-like (20-200 tracks), half "
                        "Pb-Pb-like (50-800), log-uniform, shuffled (seed 40040000)")
     res["clusters"] = ev.n_clusters

@@ -15,7 +15,8 @@
 // gradient is reduced per block in a fixed order, then over blocks.
 #include "tpc_internal.hpp"
 
-// The refit feeds tolerance-checked outputs only: contraction allowed.
+// The refit feeds tolerance-checked outputs only: contraction allowed (and
+// the library builds this file with hardware reciprocal and square root).
 #pragma clang fp contract(fast)
 
 namespace tpc {
@@ -95,6 +96,13 @@ struct HitRef {
     {
         const int c = cl(i);
         return calibrate(th, xs[row_[c]], y_[c], z_[c], sd, cm);
+    }
+    // raw plane, y, z of cluster c (an index from cl)
+    __device__ __forceinline__ void raw(int c, const float* xs, float* r) const
+    {
+        r[0] = xs[row_[c]];
+        r[1] = y_[c];
+        r[2] = z_[c];
     }
 };
 
@@ -489,8 +497,16 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
             float* ckt = ck ? ck_tile(ck, t, n_rows) : nullptr;
             if (ckt) store_ck(ckt, 0, p, C);
             float xp = h0.x;
+            // the raw hit of the next step and the index of the one after
+            // are loaded a step ahead, under the current step's arithmetic
+            float rn[3];
+            H.raw(H.cl(1), xs, rn);
+            int cn2 = H.cl(2);
             for (int i = 1; i < n; ++i) {
-                const CalHit h = H.cal(i, th, xs, sd, cm);
+                const float r0 = rn[0], r1 = rn[1], r2 = rn[2];
+                if (i + 1 < n) H.raw(cn2, xs, rn);
+                if (i + 2 < n) cn2 = H.cl(i + 2);
+                const CalHit h = calibrate(th, r0, r1, r2, sd, cm);
                 Prop P;
                 if (!prop_fwd(p, C, h.x - xp, prm.curv, prm.s_max, P)) {
                     stat = 2;
@@ -558,12 +574,23 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
 #pragma unroll
         for (int i = 0; i < 15; ++i) G[i] = 0.0f;
         CalHit cur{};
-        if (fit) cur = H.cal(n - 1, th, xs, sd, cm);
+        // raw hit i - 1 of the coming step and the index of hit i - 2, one
+        // step ahead
+        float rp[3] = {0.0f, 0.0f, 0.0f};
+        int cp2 = 0;
+        if (fit) {
+            cur = H.cal(n - 1, th, xs, sd, cm);
+            H.raw(H.cl(n - 2), xs, rp);
+            cp2 = H.cl(n - 3);
+        }
         float Xcarry = 0.0f;
         float X2 = 0.0f, Y2 = 0.0f, Z2 = 0.0f;
         for (int i = M - 1; i >= 1; --i) {
             if (i >= ne) continue;
-            const CalHit prev = H.cal(i - 1, th, xs, sd, cm);
+            const float r0 = rp[0], r1 = rp[1], r2 = rp[2];
+            if (i >= 2) H.raw(cp2, xs, rp);
+            if (i >= 3) cp2 = H.cl(i - 3);
+            const CalHit prev = calibrate(th, r0, r1, r2, sd, cm);
             float p[5], C[15];
             load_ck(ckt, i - 1, p, C);
             const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};

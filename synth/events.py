@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -280,31 +281,58 @@ def make_config4(seed=CONFIG_SEEDS[4], n_instances=512):
                                        tracks_per_instance=ntrk.tolist()))
 
 
-def _sector_crossings(trk, max_turn=math.pi, n_turns=1, chunk=512):
-    """Crossings of tracks with the row planes of all 36 real 20-degree
-    sectors.  Returns (sector, row, y_local, z, label)."""
-    k_all = CURV_PER_QPT64 * trk["qpt"]
+def _crossings_chunk(trk, k_all, a, b, max_turn, n_turns):
     alphas = (np.arange(N_SECTORS_PER_SIDE) + 0.5) * SECTOR_WIDTH
     ylim = (ROW_X64 * TAN10)[None, None, :]
     X = ROW_X64[None, None, :]
     out = ([], [], [], [], [])
-    T = k_all.shape[0]
-    for a in range(0, T, chunk):
-        b = min(T, a + chunk)
-        sl = slice(a, b)
-        args = [trk[key][sl][:, None, None] for key in ("vx", "vy", "vz", "phi0", "tanl")]
-        k = k_all[sl][:, None, None]
-        for valid, yl, z, _ in helix_plane_point(*args, k, alphas[None, :, None], X,
-                                                  max_turn=max_turn, n_turns=n_turns):
-            m = valid & (np.abs(yl) <= ylim) & (np.abs(z) <= DRIFT_LEN)
-            ti, si, ri = np.nonzero(m)
-            zz = z[ti, si, ri]
-            out[0].append(si + N_SECTORS_PER_SIDE * (zz < 0))
-            out[1].append(ri)
-            out[2].append(yl[ti, si, ri])
-            out[3].append(zz)
-            out[4].append(ti + a)
+    sl = slice(a, b)
+    args = [trk[key][sl][:, None, None] for key in ("vx", "vy", "vz", "phi0", "tanl")]
+    k = k_all[sl][:, None, None]
+    for valid, yl, z, _ in helix_plane_point(*args, k, alphas[None, :, None], X,
+                                              max_turn=max_turn, n_turns=n_turns):
+        m = valid & (np.abs(yl) <= ylim) & (np.abs(z) <= DRIFT_LEN)
+        ti, si, ri = np.nonzero(m)
+        zz = z[ti, si, ri]
+        out[0].append(si + N_SECTORS_PER_SIDE * (zz < 0))
+        out[1].append(ri)
+        out[2].append(yl[ti, si, ri])
+        out[3].append(zz)
+        out[4].append(ti + a)
     return tuple(np.concatenate(v) for v in out)
+
+
+_POOL_STATE = {}
+
+
+def _crossings_task(args):
+    a, b = args
+    st = _POOL_STATE
+    return _crossings_chunk(st["trk"], st["k"], a, b, st["max_turn"], st["n_turns"])
+
+
+def _sector_crossings(trk, max_turn=math.pi, n_turns=1, chunk=512, workers=None):
+    """Crossings of tracks with the row planes of all 36 real 20-degree
+    sectors.  Returns (sector, row, y_local, z, label).  Pure geometry (no
+    random numbers): large track sets are split over forked worker
+    processes, the chunks joined in track order, so the result does not
+    depend on the number of workers."""
+    k_all = CURV_PER_QPT64 * trk["qpt"]
+    T = k_all.shape[0]
+    ranges = [(a, min(T, a + chunk)) for a in range(0, T, chunk)]
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if workers > 1 and len(ranges) >= 8:
+        import multiprocessing as mp
+        _POOL_STATE.update(trk=trk, k=k_all, max_turn=max_turn, n_turns=n_turns)
+        try:
+            with mp.get_context("fork").Pool(min(workers, len(ranges))) as pool:
+                parts = pool.map(_crossings_task, ranges)
+        finally:
+            _POOL_STATE.clear()
+    else:
+        parts = [_crossings_chunk(trk, k_all, a, b, max_turn, n_turns) for a, b in ranges]
+    return tuple(np.concatenate([p[i] for p in parts]) for i in range(5))
 
 
 def _secondaries(rng, n, pt_min=0.1):

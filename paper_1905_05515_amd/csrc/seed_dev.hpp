@@ -136,8 +136,13 @@ template <bool Staged>
 __device__ __forceinline__ int nb_id(const NbSrc& S, int k) { return Staged ? S.st->id[k] : S.idg[S.q0 + k]; }
 
 // best pair for one hit with its up candidates from U and down candidates
-// from D (positions relative to U.q0 / D.q0); same expressions and order as
-// neighbours_one
+// from D (positions relative to U.q0 / D.q0); same expressions as
+// neighbours_one.  The down candidates inside the window are gathered first
+// (up to kNbList, in registers), so that each up candidate is paired with
+// those only; a hit with more goes through the plain double scan.  The pair
+// is the lexicographic minimum of (D2, up id, down id), whatever the order.
+constexpr int kNbList = 8;
+
 template <bool SU, bool SD>
 __device__ __forceinline__ void nb_pairs(const NbSrc& U, const NbSrc& D, float y, float z,
                                          float yu_c, float yd_c, int iyu0, int iyu1, int iyd0,
@@ -147,12 +152,57 @@ __device__ __forceinline__ void nb_pairs(const NbSrc& U, const NbSrc& D, float y
     const float Wy = prm.nb_win_y, Wz = prm.nb_win_z, D2max = prm.nb_d2max;
     float best = 0.0f;
     int bidu = -1, bidd = -1;
+    float ly[kNbList], lz[kNbList];
+    int lid[kNbList], lpos[kNbList];
+    int nd = 0;
+    for (int izd = iz0; izd <= iz1; ++izd) {
+        const int pd1 = nb_first<SD>(D, izd, iyd1 + 1);
+        for (int pd = nb_first<SD>(D, izd, iyd0); pd < pd1; ++pd) {
+            const float yd = nb_y<SD>(D, pd), zd = nb_z<SD>(D, pd);
+            if (!(fabsf(yd - yd_c) <= Wy && fabsf(zd - z) <= Wz)) continue;
+#pragma unroll
+            for (int k = 0; k < kNbList; ++k)
+                if (k == nd) {
+                    ly[k] = yd;
+                    lz[k] = zd;
+                    lpos[k] = pd;
+                }
+            ++nd;
+        }
+    }
+    if (nd == 0) return;
+    const bool listed = nd <= kNbList;
+    if (listed) {
+#pragma unroll
+        for (int k = 0; k < kNbList; ++k)
+            if (k < nd) lid[k] = nb_id<SD>(D, lpos[k]);
+    }
     for (int izu = iz0; izu <= iz1; ++izu) {
         const int pu1 = nb_first<SU>(U, izu, iyu1 + 1);
         for (int pu = nb_first<SU>(U, izu, iyu0); pu < pu1; ++pu) {
             const float yu = nb_y<SU>(U, pu), zu = nb_z<SU>(U, pu);
             if (!(fabsf(yu - yu_c) <= Wy && fabsf(zu - z) <= Wz)) continue;
             const int idu = nb_id<SU>(U, pu);
+            if (listed) {
+#pragma unroll
+                for (int k = 0; k < kNbList; ++k) {
+                    if (k >= nd) break;
+                    const float dy = (yu + ly[k]) - (y + y);
+                    const float dz = (zu + lz[k]) - (z + z);
+                    const float d2 = dy * dy + dz * dz;
+                    if (!(d2 <= D2max)) continue;
+                    const int idd = lid[k];
+                    if (bu < 0 || d2 < best ||
+                        (d2 == best && (idu < bidu || (idu == bidu && idd < bidd)))) {
+                        best = d2;
+                        bu = U.q0 + pu;
+                        bd = D.q0 + lpos[k];
+                        bidu = idu;
+                        bidd = idd;
+                    }
+                }
+                continue;
+            }
             for (int izd = iz0; izd <= iz1; ++izd) {
                 const int pd1 = nb_first<SD>(D, izd, iyd1 + 1);
                 for (int pd = nb_first<SD>(D, izd, iyd0); pd < pd1; ++pd) {
@@ -245,21 +295,28 @@ __device__ __forceinline__ void neighbours_staged_one(
     down0[p] = bd;
 }
 
-// z bins per slab: about one block's worth of hits
-__device__ __forceinline__ int nb_slab(const tpc_sector& s, int n_rows)
-{
-    const int64_t n = s.end - s.begin;
-    const int64_t per_zbin = n / ((int64_t)n_rows * s.nbz) + 1;
-    int64_t zs = 256 / per_zbin;
-    if (zs < 1) zs = 1;
-    if (zs > s.nbz) zs = s.nbz;
-    return (int)zs;
-}
-
 // z-bin margin of the candidate windows
 __device__ __forceinline__ int nb_margin(const tpc_sector& s, const tpc_params& prm)
 {
     return (int)(prm.nb_win_z * TPC_WIDEN * s.inv_bz) + 2;
+}
+
+// z bins per slab: as many as the stage holds (bins, and the expected
+// candidates of a neighbouring row with room to spare), balanced over the
+// slabs of the row
+__device__ __forceinline__ int nb_slab(const tpc_sector& s, int n_rows, int m)
+{
+    const int64_t n = s.end - s.begin;
+    const int64_t per_row_zbin = n / ((int64_t)n_rows * s.nbz) + 1;
+    if ((int64_t)s.nby * s.nbz + 1 <= kNbBinCap && 2 * per_row_zbin * s.nbz <= kNbCap)
+        return s.nbz;                              // whole rows
+    int64_t zs = (kNbBinCap - 1) / s.nby - 2 * m;
+    const int64_t zc = kNbCap / (2 * per_row_zbin) - 2 * m;
+    if (zc < zs) zs = zc;
+    if (zs < 1) zs = 1;
+    if (zs >= s.nbz) return s.nbz;
+    const int64_t slabs = (s.nbz + zs - 1) / zs;
+    return (int)((s.nbz + slabs - 1) / slabs);
 }
 
 // all hits of row r (1 <= r <= n_rows - 2) of sector s, by one block
@@ -270,7 +327,7 @@ __device__ __forceinline__ void neighbours_row(
     const float* __restrict__ zg, const int32_t* __restrict__ idg, int32_t* __restrict__ up0,
     int32_t* __restrict__ down0)
 {
-    const int zs = nb_slab(s, n_rows), m = nb_margin(s, prm);
+    const int m = nb_margin(s, prm), zs = nb_slab(s, n_rows, m);
     const int g_r = s.bin_base + r * s.nbz * s.nby;
     for (int z0 = 0; z0 < s.nbz; z0 += zs) {
         const int z1 = z0 + zs < s.nbz ? z0 + zs : s.nbz;

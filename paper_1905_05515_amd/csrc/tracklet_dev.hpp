@@ -22,26 +22,14 @@ struct KState {
     float C[15];
 };
 
-// Transport from plane x1 to x1 + dx, in two parts: transport_begin moves
-// the parameters and the two covariance entries the search window needs
-// (C_yy, C_zz) and keeps B = F C; transport_end completes the other
-// covariance entries from B.  transport_begin returns false when |sin(phi)|
-// would reach s_max; the state is then meaningless (the caller stops the
-// pass) but every later index computed from it stays clamped.  There is no
-// branch between the parts, so a search window opened in between issues its
-// loads before the bulk of the covariance arithmetic.
-struct Transport {
-    float B[5][5];
-    float Fys, Fyw, Fzs, Fzt, Fzw, Fsw;
-};
-
-__device__ __forceinline__ bool transport_begin(KState& st, float dx, float curv, float s_max,
-                                                Transport& X)
+// Transport from plane x1 to x1 + dx.  Returns false (state untouched) when
+// |sin(phi)| would reach s_max.
+__device__ __forceinline__ bool propagate(KState& st, float dx, float curv, float s_max)
 {
     const float s = st.p[2], t = st.p[3], w = st.p[4];
     const float k = curv * w;
     const float s2 = s + k * dx;
-    const bool ok = fabsf(s2) < s_max;
+    if (!(fabsf(s2) < s_max)) return false;
     const float c1 = sqrtf((1.0f - s) * (1.0f + s));
     const float c2 = sqrtf((1.0f - s2) * (1.0f + s2));
     const float cc = c1 + c2;
@@ -58,43 +46,38 @@ __device__ __forceinline__ bool transport_begin(KState& st, float dx, float curv
     const float LT = dx * (T / q);
     const float G1 = 1.0f + a2 * (0.5f + a2 * ((3.0f / 8.0f) + a2 * (5.0f / 16.0f)));
     const float Sk = (L * (L * a)) * ((1.0f / 6.0f) + a2 * ((3.0f / 20.0f) + a2 * (15.0f / 112.0f)));
-    X.Fys = dx * Ts;
-    X.Fyw = dx * Tw;
-    X.Fzs = t * ((G1 * LT) * Ts);
-    X.Fzt = S;
-    X.Fzw = t * ((G1 * LT) * Tw + Sk * curv);
-    X.Fsw = kdx;
+    const float Fys = dx * Ts;
+    const float Fyw = dx * Tw;
+    const float Fzs = t * ((G1 * LT) * Ts);
+    const float Fzt = S;
+    const float Fzw = t * ((G1 * LT) * Tw + Sk * curv);
+    const float Fsw = kdx;
 
     // B = F C, then C' = B F^T, sums over the non-zero entries of F in
     // increasing column order
+    float B[5][5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         const float cy = st.C[lt(0, j)], cz = st.C[lt(1, j)], cs = st.C[lt(2, j)];
         const float ct = st.C[lt(3, j)], cw = st.C[lt(4, j)];
-        X.B[0][j] = (cy + X.Fys * cs) + X.Fyw * cw;
-        X.B[1][j] = ((cz + X.Fzs * cs) + X.Fzt * ct) + X.Fzw * cw;
-        X.B[2][j] = cs + X.Fsw * cw;
-        X.B[3][j] = ct;
-        X.B[4][j] = cw;
+        B[0][j] = (cy + Fys * cs) + Fyw * cw;
+        B[1][j] = ((cz + Fzs * cs) + Fzt * ct) + Fzw * cw;
+        B[2][j] = cs + Fsw * cw;
+        B[3][j] = ct;
+        B[4][j] = cw;
     }
-    st.C[0] = (X.B[0][0] + X.Fys * X.B[0][2]) + X.Fyw * X.B[0][4];
-    st.C[2] = ((X.B[1][1] + X.Fzs * X.B[1][2]) + X.Fzt * X.B[1][3]) + X.Fzw * X.B[1][4];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        st.C[lt(i, 0)] = (B[i][0] + Fys * B[i][2]) + Fyw * B[i][4];
+        if (i >= 1) st.C[lt(i, 1)] = ((B[i][1] + Fzs * B[i][2]) + Fzt * B[i][3]) + Fzw * B[i][4];
+        if (i >= 2) st.C[lt(i, 2)] = B[i][2] + Fsw * B[i][4];
+        if (i >= 3) st.C[lt(i, 3)] = B[i][3];
+        if (i >= 4) st.C[lt(i, 4)] = B[i][4];
+    }
     st.p[0] = st.p[0] + dx * T;
     st.p[1] = st.p[1] + t * S;
     st.p[2] = s2;
-    return ok;
-}
-
-__device__ __forceinline__ void transport_end(KState& st, const Transport& X)
-{
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        if (i >= 1) st.C[lt(i, 0)] = (X.B[i][0] + X.Fys * X.B[i][2]) + X.Fyw * X.B[i][4];
-        if (i >= 2) st.C[lt(i, 1)] = ((X.B[i][1] + X.Fzs * X.B[i][2]) + X.Fzt * X.B[i][3]) + X.Fzw * X.B[i][4];
-        if (i >= 2) st.C[lt(i, 2)] = X.B[i][2] + X.Fsw * X.B[i][4];
-        if (i >= 3) st.C[lt(i, 3)] = X.B[i][3];
-        if (i >= 4) st.C[lt(i, 4)] = X.B[i][4];
-    }
+    return true;
 }
 
 __device__ __forceinline__ float chi2_pred(const KState& st, float my, float mz, float sy2, float sz2)
@@ -147,65 +130,36 @@ __device__ __forceinline__ void reset_cov(KState& st, const tpc_params& prm)
     st.C[14] = prm.c_ww0;
 }
 
-// Search window of row r for the transported state: bins [iy0, iy1] x
-// [iz0, iz1] covering +-nsigma of the prediction (every hit passing the chi2
-// gate lies inside), and the bin bounds of its first two z rows.  Every lane
-// opens it right after the transport, before any branch, so that the loads
-// of the bounds overlap the rest of the transport arithmetic.
-struct Window {
-    int iy0, iy1, iz0, iz1, g;
-    int lo[2], hi[2];
-};
-
-__device__ __forceinline__ Window open_window(const KState& st, const tpc_sector& s, int r,
-                                              const tpc_params& prm,
-                                              const int32_t* __restrict__ bin_start)
+// Hit of least predicted chi2 <= chi2_max on row r of sector s, ties to the
+// lower cluster id; -1 if none, else its grid position with its coordinates
+// in (my, mz).  The bins scanned cover +-nsigma of the prediction (every hit
+// passing the gate lies inside); the gate decides.  Two z rows of bins are
+// opened at a time so that their bin bounds load together.
+__device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s, int r,
+                                          const tpc_params& prm, int& n_cand,
+                                          const int32_t* __restrict__ bin_start,
+                                          const float* __restrict__ yg,
+                                          const float* __restrict__ zg,
+                                          const int32_t* __restrict__ idg, float& my, float& mz)
 {
-    Window w;
     const float S00 = st.C[0] + prm.sigma_y2, S11 = st.C[2] + prm.sigma_z2;
     const float hy = prm.search_nsigma * sqrtf(S00) * TPC_WIDEN + 0.01f;
     const float hz = prm.search_nsigma * sqrtf(S11) * TPC_WIDEN + 0.01f;
-    w.iy0 = bin_of(st.p[0] - hy, s.y0, s.inv_by, s.nby);
-    w.iy1 = bin_of(st.p[0] + hy, s.y0, s.inv_by, s.nby);
-    w.iz0 = bin_of(st.p[1] - hz, s.z0, s.inv_bz, s.nbz);
-    w.iz1 = bin_of(st.p[1] + hz, s.z0, s.inv_bz, s.nbz);
-    w.g = s.bin_base + (r * s.nbz + w.iz0) * s.nby;
-    const bool two = w.iz0 + 1 <= w.iz1;
-    const int g1 = two ? w.g + s.nby : w.g;      // a valid address either way
-    w.lo[0] = bin_start[w.g + w.iy0];
-    w.hi[0] = bin_start[w.g + w.iy1 + 1];
-    const int lo1 = bin_start[g1 + w.iy0];
-    const int hi1 = bin_start[g1 + w.iy1 + 1];
-    w.lo[1] = two ? lo1 : 0;
-    w.hi[1] = two ? hi1 : 0;
-    return w;
-}
-
-// Hit of least predicted chi2 <= chi2_max in the window, ties to the lower
-// cluster id; -1 if none, else its grid position with its coordinates in
-// (my, mz).  The gate decides; the bins only bound the scan.  Further z rows
-// are opened two at a time so that their bin bounds load together.
-__device__ __forceinline__ int search_window(const KState& st, const tpc_sector& s,
-                                             const Window& w, const tpc_params& prm,
-                                             int& n_cand, const int32_t* __restrict__ bin_start,
-                                             const float* __restrict__ yg,
-                                             const float* __restrict__ zg,
-                                             const int32_t* __restrict__ idg, float& my,
-                                             float& mz)
-{
+    const int iy0 = bin_of(st.p[0] - hy, s.y0, s.inv_by, s.nby);
+    const int iy1 = bin_of(st.p[0] + hy, s.y0, s.inv_by, s.nby);
+    const int iz0 = bin_of(st.p[1] - hz, s.z0, s.inv_bz, s.nbz);
+    const int iz1 = bin_of(st.p[1] + hz, s.z0, s.inv_bz, s.nbz);
     float best = 0.0f;
     int bpos = -1;
-    int lo[2] = {w.lo[0], w.lo[1]}, hi[2] = {w.hi[0], w.hi[1]};
-    for (int iz = w.iz0; iz <= w.iz1; iz += 2) {
-        if (iz != w.iz0) {
-            const int g = w.g + (iz - w.iz0) * s.nby;
-            lo[0] = bin_start[g + w.iy0];
-            hi[0] = bin_start[g + w.iy1 + 1];
-            lo[1] = hi[1] = 0;
-            if (iz + 1 <= w.iz1) {
-                lo[1] = bin_start[g + s.nby + w.iy0];
-                hi[1] = bin_start[g + s.nby + w.iy1 + 1];
-            }
+    for (int iz = iz0; iz <= iz1; iz += 2) {
+        const int g = s.bin_base + (r * s.nbz + iz) * s.nby;
+        int lo[2], hi[2];
+        lo[0] = bin_start[g + iy0];
+        hi[0] = bin_start[g + iy1 + 1];
+        lo[1] = hi[1] = 0;
+        if (iz + 1 <= iz1) {
+            lo[1] = bin_start[g + s.nby + iy0];
+            hi[1] = bin_start[g + s.nby + iy1 + 1];
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -288,15 +242,11 @@ __device__ __forceinline__ void build_tracklet(
             cnn = up[cn];
         }
         ++n_prop;
-        Transport X;
-        const bool moved = transport_begin(st, xs[r] - xs[r - 1], prm.curv, prm.s_max, X);
-        const Window w = open_window(st, s, r, prm, bin_start);
-        transport_end(st, X);
-        if (!moved) break;
+        if (!propagate(st, xs[r] - xs[r - 1], prm.curv, prm.s_max)) break;
         int c = cc;
         float my = cy, mz = cz;
         if (!chain) {
-            c = search_window(st, s, w, prm, n_cand, bin_start, yg, zg, idg, my, mz);
+            c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg, my, mz);
             if (c < 0) {
                 if (++miss >= prm.max_miss) break;
                 continue;
@@ -349,16 +299,12 @@ __device__ __forceinline__ void build_tracklet(
             }
         }
         ++n_prop;
-        Transport X;
-        const bool moved = transport_begin(st, xs[r] - xs[r + 1], prm.curv, prm.s_max, X);
-        const Window w = open_window(st, s, r, prm, bin_start);
-        transport_end(st, X);
-        if (!moved) {
+        if (!propagate(st, xs[r] - xs[r + 1], prm.curv, prm.s_max)) {
             for (int q = r; q >= 0; --q) th[q * ths] = -1;
             break;
         }
         if (r < r0) {
-            c = search_window(st, s, w, prm, n_cand, bin_start, yg, zg, idg, my, mz);
+            c = search_row(st, s, r, prm, n_cand, bin_start, yg, zg, idg, my, mz);
             if (c < 0) {
                 if (++miss >= prm.max_miss) break;
                 continue;

@@ -1,54 +1,244 @@
 // Grid build: stable counting sort of each sector's clusters by
 // (row, z bin, y bin), ties by cluster id; clusters with an invalid row go to
 // the sector's last bin.  A sector's clusters occupy exactly its id range of
-// grid positions, so sectors can be built independently.
-//
-// count   one thread per cluster: bin histogram (atomics on the bin counts)
-// scan    exclusive scan of the counts -> bin_start
-// scatter one thread per cluster: claim a slot in its bin (any order)
-// rank    one thread per grid position: the final place of a cluster is its
-//         bin start plus the number of clusters in the bin with a smaller id,
-//         which restores id order inside every bin deterministically.
+// grid positions, so sectors can be built independently.  The staged form
+// partitions by row first (counts per tile in LDS), then sorts every row by
+// bin in LDS, so that no cluster needs a device-wide atomic; the persistent
+// kernel keeps the per-cluster form of grid_dev.hpp.
+#include "block_dev.hpp"
 #include "grid_dev.hpp"
 
 namespace tpc {
 
-__global__ __launch_bounds__(kBlock) void k_grid_count(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    const float* __restrict__ y, const float* __restrict__ z, int64_t begin, int64_t end,
-    int32_t* __restrict__ cnt, tpc_status* status)
-{
-    for (int64_t i = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < end;
-         i += (int64_t)gridDim.x * blockDim.x)
-        grid_count_one(sec, n_sec, n_rows, row, y, z, i, cnt, status);
-}
-
-__global__ __launch_bounds__(kBlock) void k_grid_scatter(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    const float* __restrict__ y, const float* __restrict__ z, int64_t begin, int64_t end,
-    const int32_t* __restrict__ bin_start, int32_t* __restrict__ fill, int32_t* __restrict__ tmp)
-{
-    for (int64_t i = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < end;
-         i += (int64_t)gridDim.x * blockDim.x)
-        grid_scatter_one(sec, n_sec, n_rows, row, y, z, i, bin_start, fill, tmp);
-}
-
-// grid positions [begin, end) (= the cluster ids of the sectors handled)
-__global__ __launch_bounds__(kBlock) void k_grid_rank(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    const float* __restrict__ y, const float* __restrict__ z,
-    const int32_t* __restrict__ bin_start, int64_t begin, int64_t end,
-    const int32_t* __restrict__ tmp, float* __restrict__ yg, float* __restrict__ zg,
-    int32_t* __restrict__ idg, int32_t* __restrict__ gsr)
-{
-    for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
-         p += (int64_t)gridDim.x * blockDim.x)
-        grid_rank_one(sec, n_sec, n_rows, row, y, z, bin_start, p, tmp, yg, zg, idg, gsr);
-}
-
 __global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) status->n_grid = n_grid;
+}
+
+// ---- staged grid build ------------------------------------------------------
+// 1. rows:     tiles of kRowTile consecutive clusters count them per
+//              (sector, row bucket) in LDS (bucket n_rows holds the invalid
+//              rows), one device atomic per non-empty bucket and tile;
+// 2. scan:     bucket starts (a sector's first bucket starts at its first id);
+// 3. scatter:  tiles claim a range per bucket and copy (id, y, z) there, in
+//              any order inside a bucket;
+// 4. bins:     one block per (sector, bucket) counts its clusters per bin in
+//              LDS, scans the counts into the bin starts and deals every
+//              cluster a slot of its bin (any order inside a bin);
+// 5. place:    the final place of a slot's cluster is its bin start plus the
+//              number of clusters of the bin with a smaller id.
+// No step depends on the order of atomics: the result is the stable sort.
+constexpr int kRowTile = kBlock * 8;
+constexpr int kTileSec = 8;          // sectors of one tile with LDS counters
+constexpr int kRowBinsLds = 8192;    // bins of one row counted in LDS
+
+__device__ __forceinline__ int tile_sector(int64_t i, const int64_t* ends, int ns)
+{
+    for (int k = 0; k < ns; ++k)
+        if (i < ends[k]) return k;
+    return -1;
+}
+
+// LDS: the tile's first sector, the ends of its first kTileSec sectors, and
+// zeroed bucket counters; returns the number of sectors with counters
+__device__ __forceinline__ int tile_setup(const tpc_sector* __restrict__ sec, int n_sec, int R,
+                                          int64_t i0, int* hist, int64_t* ends, int* sf_sh)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) *sf_sh = find_sector(sec, n_sec, i0);
+    for (int k = threadIdx.x; k < kTileSec * R; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    const int sf = *sf_sh;
+    const int ns = n_sec - sf < kTileSec ? n_sec - sf : kTileSec;
+    if ((int)threadIdx.x < ns) ends[threadIdx.x] = sec[sf + threadIdx.x].end;
+    __syncthreads();
+    return ns;
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_rows(
+    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
+    int64_t c0, int64_t c1, int32_t* __restrict__ rcnt, tpc_status* status)
+{
+    __shared__ int hist[kTileSec * 256];
+    __shared__ int64_t ends[kTileSec];
+    __shared__ int sf_sh;
+    __shared__ int64_t red[kBlock / kWave];
+    const int R = n_rows + 1;
+    const int64_t n_tiles = (c1 - c0 + kRowTile - 1) / kRowTile;
+    int64_t bad = 0;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t i0 = c0 + tile * kRowTile;
+        const int64_t i1 = i0 + kRowTile < c1 ? i0 + kRowTile : c1;
+        const int ns = tile_setup(sec, n_sec, R, i0, hist, ends, &sf_sh);
+        const int sf = sf_sh;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            int r = row[i];
+            if (r >= n_rows) {
+                ++bad;
+                r = n_rows;
+            }
+            const int k = tile_sector(i, ends, ns);
+            if (k >= 0) atomicAdd(&hist[k * R + r], 1);
+            else atomicAdd(&rcnt[find_sector(sec, n_sec, i) * R + r], 1);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < ns * R; k += blockDim.x)
+            if (hist[k]) atomicAdd(&rcnt[(sf + k / R) * R + k % R], hist[k]);
+    }
+    const int64_t tot = block_sum(bad, red);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&status->n_bad_rows,
+                                           (unsigned long long)tot);
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_rows_scatter(
+    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
+    const float* __restrict__ y, const float* __restrict__ z, int64_t c0, int64_t c1,
+    const int32_t* __restrict__ rstart, int32_t* __restrict__ rfill, int32_t* __restrict__ gid,
+    float* __restrict__ gy, float* __restrict__ gz)
+{
+    constexpr int kItems = kRowTile / kBlock;
+    __shared__ int hist[kTileSec * 256];
+    __shared__ int64_t ends[kTileSec];
+    __shared__ int sf_sh;
+    const int R = n_rows + 1;
+    const int64_t n_tiles = (c1 - c0 + kRowTile - 1) / kRowTile;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t i0 = c0 + tile * kRowTile;
+        const int64_t i1 = i0 + kRowTile < c1 ? i0 + kRowTile : c1;
+        const int ns = tile_setup(sec, n_sec, R, i0, hist, ends, &sf_sh);
+        const int sf = sf_sh;
+        int bucket[kItems], rank[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t i = i0 + threadIdx.x + (int64_t)j * kBlock;
+            bucket[j] = -1;
+            rank[j] = 0;
+            if (i >= i1) continue;
+            int r = row[i];
+            if (r >= n_rows) r = n_rows;
+            const int k = tile_sector(i, ends, ns);
+            if (k >= 0) {
+                bucket[j] = k * R + r;
+                rank[j] = atomicAdd(&hist[bucket[j]], 1);
+            } else {   // a sector beyond the tile's LDS counters: claim one slot
+                const int gb = find_sector(sec, n_sec, i) * R + r;
+                rank[j] = rstart[gb] + atomicAdd(&rfill[gb], 1);
+            }
+        }
+        __syncthreads();
+        // one range per non-empty bucket; the counter becomes the range start
+        for (int k = threadIdx.x; k < ns * R; k += blockDim.x) {
+            const int c = hist[k];
+            if (c) {
+                const int gb = (sf + k / R) * R + k % R;
+                hist[k] = rstart[gb] + atomicAdd(&rfill[gb], c);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t i = i0 + threadIdx.x + (int64_t)j * kBlock;
+            if (i >= i1) continue;
+            const int slot = bucket[j] >= 0 ? hist[bucket[j]] + rank[j] : rank[j];
+            gid[slot] = (int32_t)i;
+            gy[slot] = y[i];
+            gz[slot] = z[i];
+        }
+    }
+}
+
+__device__ __forceinline__ int ctr_load(const int* c, bool local)
+{
+    return local ? c[0] : __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// one block per (sector, row bucket) of sectors [sec_lo, ...)
+__global__ __launch_bounds__(kBlock) void k_grid_bins(
+    const tpc_sector* __restrict__ sec, int sec_lo, int n_rows,
+    const int32_t* __restrict__ rstart, const float* __restrict__ gy,
+    const float* __restrict__ gz, int32_t* __restrict__ bin_start, int32_t* __restrict__ cnt,
+    int32_t* __restrict__ gslot, int32_t* __restrict__ gbin)
+{
+    __shared__ int lds[kRowBinsLds];
+    __shared__ int red[kBlock / kWave];
+    const int R = n_rows + 1;
+    const int si = sec_lo + (int)(blockIdx.x / R);
+    const int r = (int)(blockIdx.x % R);
+    const tpc_sector s = sec[si];
+    const int a = rstart[si * R + r], n = rstart[si * R + r + 1] - a;
+    const int per_row = s.nbz * s.nby;
+    const int nbr = r < n_rows ? per_row : 1;
+    const int g_row = s.bin_base + r * per_row;
+    const bool local = nbr <= kRowBinsLds;
+    int* ctr = local ? lds : cnt + g_row;
+    for (int b = threadIdx.x; b < nbr; b += blockDim.x) ctr[b] = 0;
+    if (!local) __threadfence();
+    __syncthreads();
+    for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
+        const int b = r < n_rows ? bin_of(gz[j], s.z0, s.inv_bz, s.nbz) * s.nby +
+                                       bin_of(gy[j], s.y0, s.inv_by, s.nby)
+                                 : 0;
+        atomicAdd(&ctr[b], 1);
+    }
+    if (!local) __threadfence();
+    __syncthreads();
+    // bin starts: exclusive scan of the counts from the bucket start
+    int carry = a;
+    for (int b0 = 0; b0 < nbr; b0 += kScanTile) {
+        const int base = b0 + (int)threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < nbr ? ctr_load(ctr + base + k, local) : 0;
+            sum += v[k];
+        }
+        int tot;
+        int ex = block_excl_scan(sum, red, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < nbr) {
+                bin_start[g_row + base + k] = ex;
+                ctr[base + k] = ex;
+                ex += v[k];
+            }
+        carry += tot;
+    }
+    if (r == n_rows && threadIdx.x == 0) bin_start[g_row + 1] = a + n;
+    if (!local) __threadfence();
+    __syncthreads();
+    for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
+        const int b = r < n_rows ? bin_of(gz[j], s.z0, s.inv_bz, s.nbz) * s.nby +
+                                       bin_of(gy[j], s.y0, s.inv_by, s.nby)
+                                 : 0;
+        const int slot = atomicAdd(&ctr[b], 1);
+        gslot[slot] = j;
+        gbin[slot] = g_row + b;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_place(
+    const tpc_sector* __restrict__ sec, int n_sec, const uint8_t* __restrict__ row,
+    int64_t c0, int64_t c1, const int32_t* __restrict__ bin_start,
+    const int32_t* __restrict__ gid, const float* __restrict__ gy,
+    const float* __restrict__ gz, const int32_t* __restrict__ gslot,
+    const int32_t* __restrict__ gbin, float* __restrict__ yg, float* __restrict__ zg,
+    int32_t* __restrict__ idg, int32_t* __restrict__ gsr)
+{
+    for (int64_t q = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < c1;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int j = gslot[q];
+        const int g = gbin[q];
+        const int32_t id = gid[j];
+        const int32_t bs = bin_start[g], be = bin_start[g + 1];
+        int rank = 0;
+        for (int32_t u = bs; u < be; ++u) rank += gid[gslot[u]] < id;
+        const int32_t o = bs + rank;
+        yg[o] = gy[j];
+        zg[o] = gz[j];
+        idg[o] = id;
+        gsr[o] = (find_sector(sec, n_sec, q) << 8) | row[id];
+    }
 }
 
 // Build the grid of sectors [sec_lo, sec_hi).  The first call of an event
@@ -59,23 +249,26 @@ int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in
     const tpc_sector& a = p->h_sectors[sec_lo];
     const tpc_sector& b = p->h_sectors[sec_hi - 1];
     const int64_t c0 = a.begin, c1 = b.end;
-    const int64_t g0 = a.bin_base;
-    const int64_t g1 = (int64_t)b.bin_base + (int64_t)p->n_rows * b.nby * b.nbz + 1;
+    const int R = p->n_rows + 1;
+    const int64_t nbk = (int64_t)(sec_hi - sec_lo) * R;
     if (sec_lo == 0) launch_fill<int64_t>((int64_t*)ws.status, 0, sizeof(tpc_status) / 8, st);
-    launch_fill<int32_t>(ws.cnt + g0, 0, g1 - g0, st);
-    const unsigned gc = grid_for(c1 - c0);
-    TPC_LAUNCH(k_grid_count, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-               p->n_rows, in.row, in.y, in.z, c0, c1, ws.cnt, ws.status);
-    // the sectors' first bin starts at their first cluster id
-    launch_scan<int32_t>(ws.cnt + g0, out.bin_start + g0, g1 - g0, true, nullptr, nullptr,
-                         ws.partials, st, c0);
-    launch_fill<int32_t>(ws.cnt + g0, 0, g1 - g0, st);
-    TPC_LAUNCH(k_grid_scatter, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-               p->n_rows, in.row, in.y, in.z, c0, c1, (const int32_t*)out.bin_start, ws.cnt,
-               ws.tmp);
-    TPC_LAUNCH(k_grid_rank, dim3(gc), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors, p->n_rows,
-               in.row, in.y, in.z, (const int32_t*)out.bin_start, c0, c1,
-               (const int32_t*)ws.tmp, out.y, out.z, out.id, ws.gsr);
+    launch_fill<int32_t>(ws.rcnt + (int64_t)sec_lo * R, 0, nbk, st);
+    launch_fill<int32_t>(ws.rfill + (int64_t)sec_lo * R, 0, nbk, st);
+    const unsigned gt = grid_for_block(ceil_div(c1 - c0, kRowTile), 1, 4096);
+    TPC_LAUNCH(k_grid_rows, dim3(gt), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
+               p->n_rows, in.row, c0, c1, ws.rcnt, ws.status);
+    launch_scan<int32_t>(ws.rcnt + (int64_t)sec_lo * R, ws.rstart + (int64_t)sec_lo * R, nbk,
+                         true, nullptr, nullptr, ws.partials, st, c0);
+    TPC_LAUNCH(k_grid_rows_scatter, dim3(gt), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
+               p->n_rows, in.row, in.y, in.z, c0, c1, (const int32_t*)ws.rstart, ws.rfill,
+               ws.tmp, ws.gy, ws.gz);
+    TPC_LAUNCH(k_grid_bins, dim3((unsigned)nbk), dim3(kBlock), 0, st, p->d_sectors, sec_lo,
+               p->n_rows, (const int32_t*)ws.rstart, (const float*)ws.gy, (const float*)ws.gz,
+               out.bin_start, ws.cnt, ws.gslot, ws.gbin);
+    TPC_LAUNCH(k_grid_place, dim3(grid_for(c1 - c0)), dim3(kBlock), 0, st, p->d_sectors,
+               p->n_sectors, in.row, c0, c1, (const int32_t*)out.bin_start,
+               (const int32_t*)ws.tmp, (const float*)ws.gy, (const float*)ws.gz,
+               (const int32_t*)ws.gslot, (const int32_t*)ws.gbin, out.y, out.z, out.id, ws.gsr);
     TPC_LAUNCH(k_set_grid_status, dim3(1), dim3(1), 0, st, ws.status, c1);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }

@@ -126,6 +126,28 @@ __global__ void k_start_status(tpc_status* status, int64_t* sec_start, int sec_h
     if (status->n_starts > cap) status->overflow |= 1;
 }
 
+// First start of every sector strictly inside (sec_lo, sec_hi): starts are
+// stored in cluster-id order and a sector's starts are grid positions of its
+// own id range, so the sector of starts[t] grows with t and a binary search
+// for the first position at or beyond the sector's first id finds it.
+__global__ void k_sector_starts(const tpc_sector* __restrict__ sec, int sec_lo, int sec_hi,
+                                const int32_t* __restrict__ starts, int64_t cap,
+                                int64_t* __restrict__ sec_start)
+{
+    const int s = sec_lo + 1 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= sec_hi) return;
+    int64_t lo = sec_start[sec_lo], hi = sec_start[sec_hi];
+    if (hi > cap) hi = cap;
+    if (lo > hi) lo = hi;
+    const int64_t first = sec[s].begin;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (starts[mid] < first) lo = mid + 1;
+        else hi = mid;
+    }
+    sec_start[s] = lo;
+}
+
 // Seeding for sectors [sec_lo, sec_hi): their grid positions and cluster ids
 // are the same range.  Starts are appended in id order after those of the
 // earlier sectors.
@@ -153,6 +175,10 @@ int run_find_neighbours(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid g
                starts.capacity);
     TPC_LAUNCH(k_start_status, dim3(1), dim3(1), 0, st, ws.status, ws.sec_start, sec_hi,
                starts.capacity);
+    if (sec_hi - sec_lo > 1)
+        TPC_LAUNCH(k_sector_starts, dim3((unsigned)ceil_div(sec_hi - sec_lo - 1, kBlock)),
+                   dim3(kBlock), 0, st, p->d_sectors, sec_lo, sec_hi,
+                   (const int32_t*)starts.pos, starts.capacity, ws.sec_start);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

@@ -443,6 +443,47 @@ __device__ __forceinline__ void load_theta(const float* __restrict__ d_theta, fl
     __syncthreads();
 }
 
+// ---- staging of a wave's hits through LDS ---------------------------------
+// The 64 tracks of a wave are consecutive in the CSR, so hits [i0, i0 + K)
+// of all of them are 64 short contiguous runs.  The wave loads them
+// cooperatively (item e of a chunk: track e / K, hit i0 + e % K), K runs of
+// K hits per load instruction instead of 64 scattered words, and each lane
+// then reads its own hits from LDS.  Gradients leave the same way.
+constexpr int kChunk = 8;
+
+struct Stage {
+    float x[kChunk][kWave];   // raw plane position of the hit's row
+    float y[kChunk][kWave];
+    float z[kChunk][kWave];
+};
+
+// stage hits [i0, i0 + kChunk) of the wave's tracks (a, n of each lane);
+// flags a hit row >= n_rows in bad[lane of the track]
+__device__ __forceinline__ void stage_hits(Stage& S, int* bad, int i0, int a, int n,
+                                           const int32_t* __restrict__ idx,
+                                           const uint8_t* __restrict__ row,
+                                           const float* __restrict__ y,
+                                           const float* __restrict__ z, const float* xs,
+                                           int n_rows)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+        const int e = lane + kWave * j;
+        const int l = e / kChunk, k = e % kChunk;
+        const int al = __shfl(a, l, kWave), nl = __shfl(n, l, kWave);
+        const int i = i0 + k;
+        if (i < nl) {
+            const int c = idx ? idx[al + i] : al + i;
+            const int r = row[c];
+            if (r >= n_rows) bad[l] = 1;
+            S.x[k][l] = xs[r];
+            S.y[k][l] = y[c];
+            S.z[k][l] = z[c];
+        }
+    }
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kWave) void k_refit_fwd(
@@ -456,60 +497,67 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
 {
     __shared__ float th[16];
     __shared__ float xs[256];
+    __shared__ Stage S;
+    __shared__ int bad[kWave];
     load_theta(d_theta, th);
     for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
     __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int a = off[t], n = off[t + 1] - a;
-        HitRef H{idx, row, y, z, a};
+    // one wave per tile of 64 consecutive tracks
+    for (int64_t tb = blockIdx.x * (int64_t)kWave; tb < nt; tb += (int64_t)gridDim.x * kWave) {
+        const int64_t t = tb + lane;
+        int a = 0, n = 0;
+        if (t < nt) {
+            a = off[t];
+            n = off[t + 1] - a;
+        }
+        // tracks filtered: at least 3 hits, not more hits than rows (a hit
+        // row outside the table is found while staging)
+        const bool fit = t < nt && n >= 3 && n <= n_rows;
+        const int M = wave_max(t < nt && n >= 3 ? n : 0);
+        bad[lane] = 0;
         float p[5] = {0, 0, 0, 0, 0}, C[15];
 #pragma unroll
         for (int i = 0; i < 15; ++i) C[i] = 0.0f;
-        float chi2 = 0.0f;
+        float chi2 = 0.0f, xp = 0.0f;
+        bool alive = fit;
         int stat = 0;
-        bool rows_ok = true;
-        for (int i = 0; i < n; ++i) rows_ok &= H.row(i) < n_rows;
-        if (n < 3) {
-            stat = 1;
-        } else if (!rows_ok) {
-            stat = 3;
-        } else if (n > n_rows) {
-            stat = 4;
-        } else {
-            const float sd = side ? (float)side[t] : 1.0f;
-            const CalHit h0 = H.cal(0, th, xs, sd, cm);
-            const CalHit h2 = H.cal(2, th, xs, sd, cm);
-            const float dX = h2.x - h0.x;
-            const float T0 = (h2.y - h0.y) / dX;
-            const float q0 = sqrtf(1.0f + T0 * T0);
-            p[0] = h0.y;
-            p[1] = h0.z;
-            p[2] = T0 / q0;
-            p[3] = (h2.z - h0.z) / (dX * q0);
-            p[4] = 0.0f;
-            C[0] = prm.sigma_y2;
-            C[2] = prm.sigma_z2;
-            C[5] = prm.c_ss0;
-            C[9] = prm.c_tt0;
-            C[14] = prm.c_ww0;
-            float* ckt = ck ? ck_tile(ck, t, n_rows) : nullptr;
-            if (ckt) store_ck(ckt, 0, p, C);
-            float xp = h0.x;
-            // the raw hit of the next step and the index of the one after
-            // are loaded a step ahead, under the current step's arithmetic
-            float rn[3];
-            H.raw(H.cl(1), xs, rn);
-            int cn2 = H.cl(2);
-            for (int i = 1; i < n; ++i) {
-                const float r0 = rn[0], r1 = rn[1], r2 = rn[2];
-                if (i + 1 < n) H.raw(cn2, xs, rn);
-                if (i + 2 < n) cn2 = H.cl(i + 2);
-                const CalHit h = calibrate(th, r0, r1, r2, sd, cm);
+        const float sd = t < nt && side ? (float)side[t] : 1.0f;
+        float* ckt = ck && t < nt ? ck_tile(ck, t, n_rows) : nullptr;
+        for (int i0 = 0; i0 < M; i0 += kChunk) {
+            __syncthreads();      // the previous chunk is consumed
+            stage_hits(S, bad, i0, a, t < nt && n >= 3 ? n : 0, idx, row, y, z, xs, n_rows);
+            __syncthreads();
+            if (i0 == 0 && alive) {
+                // state from the first and third hits
+                const CalHit h0 = calibrate(th, S.x[0][lane], S.y[0][lane], S.z[0][lane], sd, cm);
+                const CalHit h2 = calibrate(th, S.x[2][lane], S.y[2][lane], S.z[2][lane], sd, cm);
+                const float dX = h2.x - h0.x;
+                const float T0 = (h2.y - h0.y) / dX;
+                const float q0 = sqrtf(1.0f + T0 * T0);
+                p[0] = h0.y;
+                p[1] = h0.z;
+                p[2] = T0 / q0;
+                p[3] = (h2.z - h0.z) / (dX * q0);
+                p[4] = 0.0f;
+                C[0] = prm.sigma_y2;
+                C[2] = prm.sigma_z2;
+                C[5] = prm.c_ss0;
+                C[9] = prm.c_tt0;
+                C[14] = prm.c_ww0;
+                if (ckt) store_ck(ckt, 0, p, C);
+                xp = h0.x;
+            }
+            const int i_end = i0 + kChunk < n ? i0 + kChunk : n;
+            for (int i = i0 > 1 ? i0 : 1; i < i_end; ++i) {
+                if (!alive) break;
+                const int k = i - i0;
+                const CalHit h = calibrate(th, S.x[k][lane], S.y[k][lane], S.z[k][lane], sd, cm);
                 Prop P;
                 if (!prop_fwd(p, C, h.x - xp, prm.curv, prm.s_max, P)) {
                     stat = 2;
+                    alive = false;
                     break;
                 }
                 Upd U;
@@ -518,12 +566,25 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
                 if (ckt && i + 1 < n) store_ck(ckt, i, p, C);
             }
         }
+        __syncthreads();
+        if (t < nt) {
+            if (n < 3) stat = 1;
+            else if (bad[lane]) stat = 3;
+            else if (n > n_rows) stat = 4;
+            if (stat == 1 || stat == 3 || stat == 4) {
+                chi2 = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) par[t * 5 + i] = p[i];
+                for (int i = 0; i < 5; ++i) p[i] = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 15; ++i) cov[t * 15 + i] = C[i];
-        chi2_out[t] = chi2;
-        status[t] = stat;
+                for (int i = 0; i < 15; ++i) C[i] = 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 5; ++i) par[t * 5 + i] = p[i];
+#pragma unroll
+            for (int i = 0; i < 15; ++i) cov[t * 15 + i] = C[i];
+            chi2_out[t] = chi2;
+            status[t] = stat;
+        }
     }
 }
 
@@ -539,6 +600,9 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
 {
     __shared__ float th[16];
     __shared__ float xs[256];
+    __shared__ Stage S;
+    __shared__ float Gy[kChunk][kWave], Gz[kChunk][kWave];
+    __shared__ int bad[kWave];
     load_theta(d_theta, th);
     for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
     __syncthreads();
@@ -549,7 +613,8 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
     const int lane = threadIdx.x & (kWave - 1);
     // one wave per tile of 64 tracks; the reverse sweep runs over the slots
     // of the tile in lockstep (slot i is active in the lanes whose track has
-    // more than i hits), so that checkpoint loads are whole lines
+    // more than i hits), so that checkpoint loads are whole lines; hits come
+    // through LDS in chunks, from the top down
     for (int64_t tb = blockIdx.x * (int64_t)kWave; tb < nt; tb += (int64_t)gridDim.x * kWave) {
         const int64_t t = tb + lane;
         int a = 0, n = 0;
@@ -574,46 +639,58 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
 #pragma unroll
         for (int i = 0; i < 15; ++i) G[i] = 0.0f;
         CalHit cur{};
-        // raw hit i - 1 of the coming step and the index of hit i - 2, one
-        // step ahead
-        float rp[3] = {0.0f, 0.0f, 0.0f};
-        int cp2 = 0;
-        if (fit) {
-            cur = H.cal(n - 1, th, xs, sd, cm);
-            H.raw(H.cl(n - 2), xs, rp);
-            cp2 = H.cl(n - 3);
-        }
+        if (fit) cur = H.cal(n - 1, th, xs, sd, cm);
         float Xcarry = 0.0f;
         float X2 = 0.0f, Y2 = 0.0f, Z2 = 0.0f;
-        for (int i = M - 1; i >= 1; --i) {
-            if (i >= ne) continue;
-            const float r0 = rp[0], r1 = rp[1], r2 = rp[2];
-            if (i >= 2) H.raw(cp2, xs, rp);
-            if (i >= 3) cp2 = H.cl(i - 3);
-            const CalHit prev = calibrate(th, r0, r1, r2, sd, cm);
-            float p[5], C[15];
-            load_ck(ckt, i - 1, p, C);
-            const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};
-            Prop P;
-            prop_fwd(p, C, cur.x - prev.x, prm.curv, prm.s_max, P);
-            Upd U;
-            upd_fwd(p, C, cur.y, cur.z, prm.sigma_y2, prm.sigma_z2, U);
-            float myb, mzb;
-            upd_adj(U, cb, pb, G, myb, mzb);
-            const float dxb = prop_adj(P, p0, nullptr, prm.curv, pb, G);
-            const float Xi = Xcarry + dxb;
-            if (i == 2) {
-                X2 = Xi;
-                Y2 = myb;
-                Z2 = mzb;
-            } else {
-                float gyr, gzr;
-                calibrate_adj(th, cur, sd, cm, Xi, myb, mzb, gth, gyr, gzr);
-                gy[a + i] = gyr;
-                gz[a + i] = gzr;
+        // steps i = top .. lo need hits lo - 1 .. top - 1 (the previous hit)
+        for (int top = M - 1; top >= 1;) {
+            const int lo = top - kChunk + 1 > 1 ? top - kChunk + 1 : 1;
+            __syncthreads();
+            stage_hits(S, bad, lo - 1, a, ne, idx, row, y, z, xs, n_rows);
+            __syncthreads();
+            for (int i = top; i >= lo; --i) {
+                if (i >= ne) continue;
+                const int k = i - lo;             // slot of hit i - 1
+                const CalHit prev = calibrate(th, S.x[k][lane], S.y[k][lane], S.z[k][lane], sd, cm);
+                float p[5], C[15];
+                load_ck(ckt, i - 1, p, C);
+                const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};
+                Prop P;
+                prop_fwd(p, C, cur.x - prev.x, prm.curv, prm.s_max, P);
+                Upd U;
+                upd_fwd(p, C, cur.y, cur.z, prm.sigma_y2, prm.sigma_z2, U);
+                float myb, mzb;
+                upd_adj(U, cb, pb, G, myb, mzb);
+                const float dxb = prop_adj(P, p0, nullptr, prm.curv, pb, G);
+                const float Xi = Xcarry + dxb;
+                if (i == 2) {
+                    X2 = Xi;
+                    Y2 = myb;
+                    Z2 = mzb;
+                } else {
+                    float gyr, gzr;
+                    calibrate_adj(th, cur, sd, cm, Xi, myb, mzb, gth, gyr, gzr);
+                    Gy[i - lo][lane] = gyr;
+                    Gz[i - lo][lane] = gzr;
+                }
+                Xcarry = -dxb;
+                cur = prev;
             }
-            Xcarry = -dxb;
-            cur = prev;
+            __syncthreads();
+            // write the chunk's hit gradients (hits lo .. top, but hit 2),
+            // the same runs as the staging
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                const int e = lane + kWave * j;
+                const int l = e / kChunk, kk = e % kChunk;
+                const int al = __shfl(a, l, kWave), nl = __shfl(ne, l, kWave);
+                const int i = lo + kk;
+                if (i <= top && i < nl && i != 2) {
+                    gy[al + i] = Gy[kk][l];
+                    gz[al + i] = Gz[kk][l];
+                }
+            }
+            top = lo - 1;
         }
         if (!fit) continue;
         // initial state: y, z of hit 0, direction from hit 0 to hit 2

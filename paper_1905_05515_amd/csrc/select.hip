@@ -7,41 +7,74 @@
 
 namespace tpc {
 
-// Staged kernels: item (t, blockIdx.y) handles rows [8 y, 8 y + 8) of
-// tracklet t; consecutive threads take consecutive tracklets, so every row
-// load of a chunk is one coalesced line per wave.
-__global__ __launch_bounds__(kBlock) void k_sel_keys(
-    int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
-    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
-    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
-    unsigned long long* __restrict__ hitkey)
-{
-    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
-    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
-    const int ra = blockIdx.y * kSelRows;
-    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        if (key) sel_keys_chunk(t, ra, n_rows, key, t_hits, cap, hitkey);
-    }
-}
+// Ownership keys by (sector, chunk of kSelRows pad rows): a tracklet's hits
+// on those rows are grid positions of one contiguous range, so one block
+// keeps the range's keys in LDS (64-bit LDS atomic max, no device-wide
+// atomics), writes them out, and counts for every tracklet of the sector the
+// hits of the chunk it keeps.  A range larger than the LDS table uses the
+// device-wide keys instead.
+constexpr int kSelLds = 6144;
 
-__global__ __launch_bounds__(kBlock) void k_sel_count(
-    int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
+__global__ __launch_bounds__(kBlock) void k_sel_chunk(
+    const tpc_sector* __restrict__ sec, int sec_lo, int n_rows, tpc_params prm,
+    const int32_t* __restrict__ bin_start, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
-    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, uint8_t* __restrict__ ccnt)
+    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ sec_start,
+    int64_t count_cap, int64_t cap, unsigned long long* __restrict__ hitkey,
+    uint8_t* __restrict__ ccnt)
 {
-    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
-    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
-    const int ra = blockIdx.y * kSelRows;
-    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    __shared__ unsigned long long kl[kSelLds];
+    const int nq = (n_rows + kSelRows - 1) / kSelRows;
+    const int si = sec_lo + (int)(blockIdx.x / nq);
+    const int q = (int)(blockIdx.x % nq);
+    const tpc_sector s = sec[si];
+    const int ra = q * kSelRows, rb = ra + kSelRows < n_rows ? ra + kSelRows : n_rows;
+    const int per_row = s.nbz * s.nby;
+    const int p0 = bin_start[s.bin_base + ra * per_row];
+    const int np = bin_start[s.bin_base + rb * per_row] - p0;
+    int64_t lo = sec_start[si], hi = sec_start[si + 1];
+    if (hi > count_cap) hi = count_cap;
+    if (lo < 0) lo = 0;
+    if (lo > hi) lo = hi;
+    const bool local = np <= kSelLds;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+        if (local) kl[k] = 0ull;
+        else hitkey[p0 + k] = 0ull;
+    }
+    if (!local) __threadfence();
+    __syncthreads();
+    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
         const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        ccnt[blockIdx.y * count_cap + t] =
-            key ? (uint8_t)sel_count_chunk(t, ra, n_rows, key, t_hits, cap, hitkey) : 0;
+        if (!key) continue;
+        int c[kSelRows];
+        load_chunk(t, ra, n_rows, t_hits, cap, c);
+#pragma unroll
+        for (int k = 0; k < kSelRows; ++k) {
+            const unsigned o = (unsigned)(c[k] - p0);
+            if (c[k] < 0 || o >= (unsigned)np) continue;
+            if (local) atomicMax(&kl[o], (unsigned long long)key);
+            else atomicMax(&hitkey[c[k]], (unsigned long long)key);
+        }
+    }
+    if (!local) __threadfence();
+    __syncthreads();
+    if (local)
+        for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[p0 + k] = kl[k];
+    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        int kept = 0;
+        if (key) {
+            int c[kSelRows];
+            load_chunk(t, ra, n_rows, t_hits, cap, c);
+#pragma unroll
+            for (int k = 0; k < kSelRows; ++k) {
+                const unsigned o = (unsigned)(c[k] - p0);
+                if (c[k] < 0 || o >= (unsigned)np) continue;
+                const unsigned long long h = local ? kl[o] : hitkey[c[k]];
+                kept += h == key;
+            }
+        }
+        ccnt[q * count_cap + t] = (uint8_t)kept;
     }
 }
 
@@ -116,15 +149,11 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
     const int nq = sel_chunks(p->n_rows);
     const int64_t* lo = ws.sec_start + sec_lo;
     const int64_t* hi = ws.sec_start + sec_hi;
-    launch_fill<uint64_t>(ws.hitkey + c0, 0ull, c1 - c0, st);
-    TPC_LAUNCH(k_sel_keys, dim3(gx, nq), dim3(kBlock), 0, st, p->n_rows, p->params,
+    TPC_LAUNCH(k_sel_chunk, dim3((unsigned)((sec_hi - sec_lo) * nq)), dim3(kBlock), 0, st,
+               p->d_sectors, sec_lo, p->n_rows, p->params, (const int32_t*)grid.bin_start,
                (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
-               (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
-               (unsigned long long*)ws.hitkey);
-    TPC_LAUNCH(k_sel_count, dim3(gx, nq), dim3(kBlock), 0, st, p->n_rows, p->params,
-               (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
-               (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
-               (const unsigned long long*)ws.hitkey, ws.ccnt);
+               (const int32_t*)trl.nhits, (const int64_t*)ws.sec_start, count_cap,
+               trl.capacity, (unsigned long long*)ws.hitkey, ws.ccnt);
     TPC_LAUNCH(k_sel_len, dim3(gx), dim3(kBlock), 0, st, nq, p->params, lo, hi, count_cap,
                (const uint8_t*)ws.ccnt, ws.tlen);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;

@@ -1,7 +1,8 @@
 // Device code of the tracklet selection, shared by the staged kernels and
-// the persistent kernel.  The staged kernels split every tracklet's rows
-// into chunks of kSelRows so that one item loads its chunk's hits at once;
-// the persistent kernel walks all chunks of a tracklet in one thread.
+// the persistent kernel.  Every tracklet's rows are read in chunks of
+// kSelRows so that one item loads its chunk's hits at once; the staged
+// kernels give each (sector, chunk) a block, the persistent kernel walks all
+// chunks of a tracklet in one thread.
 #pragma once
 #include "tpc_internal.hpp"
 

@@ -31,6 +31,15 @@ struct Workspace {
     uint64_t* tlen;        // [start_cap + 1] per tracklet: accepted << 32 | kept
     uint64_t* toff;        // [start_cap + 1] exclusive scan of tlen
     uint8_t* ccnt;         // [row chunks * start_cap] kept hits per tracklet and row chunk
+    // grid build: clusters per (sector, row bucket), their running fill and
+    // starts; the row-partitioned copy of the clusters; the binned order
+    int32_t* rcnt;         // [n_sectors * (n_rows + 1)]
+    int32_t* rfill;        // [n_sectors * (n_rows + 1)]
+    int32_t* rstart;       // [n_sectors * (n_rows + 1) + 1]
+    float* gy;             // [n]
+    float* gz;             // [n]
+    int32_t* gslot;        // [n] row-partitioned index of the cluster at a binned slot
+    int32_t* gbin;         // [n] global bin of a binned slot
     int64_t* sec_start;    // [n_sectors + 1] first start of each sector
     int32_t* pq;           // persistent form: [1] queue head, [kPhases * n_sectors] done counts
     int64_t* scnt;         // persistent form: [n_sectors] starts per sector

@@ -131,6 +131,8 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
 {
     const int64_t n = p->n_clusters, nb = p->n_bins;
     int64_t scan_n = n > nb + 1 ? n : nb + 1;
+    const int64_t nrb1 = (int64_t)p->n_sectors * (p->n_rows + 1) + 1;
+    if (nrb1 > scan_n) scan_n = nrb1;
     if (start_cap + 1 > scan_n) scan_n = start_cap + 1;
     int64_t max_tiles = ceil_div(scan_n, kScanTile) + 1;
     char* b = (char*)base;
@@ -151,6 +153,15 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->pq = (int32_t*)take(sizeof(int32_t) * (size_t)(1 + kPhases * p->n_sectors));
     ws->scnt = (int64_t*)take(sizeof(int64_t) * (size_t)p->n_sectors);
     ws->tsum = (uint64_t*)take(sizeof(uint64_t) * (size_t)p->n_sectors);
+    const size_t nrb = (size_t)p->n_sectors * (size_t)(p->n_rows + 1);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    ws->rcnt = (int32_t*)take(sizeof(int32_t) * nrb);
+    ws->rfill = (int32_t*)take(sizeof(int32_t) * nrb);
+    ws->rstart = (int32_t*)take(sizeof(int32_t) * (nrb + 1));
+    ws->gy = (float*)take(sizeof(float) * nn);
+    ws->gz = (float*)take(sizeof(float) * nn);
+    ws->gslot = (int32_t*)take(sizeof(int32_t) * nn);
+    ws->gbin = (int32_t*)take(sizeof(int32_t) * nn);
     // scratch of single calls, sized by the start capacity
     ws->partials = (int64_t*)take(sizeof(int64_t) * (size_t)max_tiles);
     ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));

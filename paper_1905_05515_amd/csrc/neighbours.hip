@@ -11,36 +11,17 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
     const int32_t* __restrict__ gsr, int64_t begin, int64_t end,
     int32_t* __restrict__ up0, int32_t* __restrict__ down0)
 {
-    for (int64_t p = begin + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < end;
-         p += (int64_t)gridDim.x * blockDim.x)
-        neighbours_one(p, sec, n_rows, row_x, prm, bin_start, yg, zg, idg, gsr, up0, down0);
-}
-
-// One block per (sector, row r in [0, n_rows]); rows 1..n_rows-2 search
-// their neighbours with LDS-staged candidate rows; rows 0, n_rows-1 and the
-// invalid-row bin (r = n_rows) get no links.
-__global__ __launch_bounds__(kBlock) void k_neighbours_rows(
-    const tpc_sector* __restrict__ sec, int sec_lo, int n_rows, const float* __restrict__ row_x,
-    tpc_params prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
-    const float* __restrict__ zg, const int32_t* __restrict__ idg, int32_t* __restrict__ up0,
-    int32_t* __restrict__ down0)
-{
-    __shared__ NbRowStage stu, std_;
-    const int w = xcd_remap(blockIdx.x, gridDim.x);
-    const int si = sec_lo + w / (n_rows + 1);
-    const int r = w % (n_rows + 1);
-    const tpc_sector s = sec[si];
-    if (r == 0 || r >= n_rows - 1) {
-        const int per_row = s.nbz * s.nby;
-        const int g0 = s.bin_base + r * per_row;
-        const int g1 = r < n_rows ? g0 + per_row : g0 + 1;
-        for (int64_t p = bin_start[g0] + threadIdx.x; p < bin_start[g1]; p += blockDim.x) {
-            up0[p] = -1;
-            down0[p] = -1;
-        }
-        return;
+    // work blocks dealt to the XCDs in contiguous ranges (one sector's rows
+    // share an L2)
+    const int64_t nblk = (end - begin + blockDim.x - 1) / blockDim.x;
+    for (int64_t b0 = 0; b0 < nblk; b0 += gridDim.x) {
+        const int64_t chunk = nblk - b0 < (int64_t)gridDim.x ? nblk - b0 : (int64_t)gridDim.x;
+        if ((int64_t)blockIdx.x >= chunk) break;
+        const int64_t p = begin + (b0 + xcd_remap(blockIdx.x, (int)chunk)) * blockDim.x +
+                          threadIdx.x;
+        if (p < end)
+            neighbours_one(p, sec, n_rows, row_x, prm, bin_start, yg, zg, idg, gsr, up0, down0);
     }
-    neighbours_row(&stu, &std_, s, r, n_rows, row_x, prm, bin_start, yg, zg, idg, up0, down0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_clean(
@@ -157,10 +138,10 @@ int run_find_neighbours(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid g
     const int64_t c0 = p->h_sectors[sec_lo].begin, c1 = p->h_sectors[sec_hi - 1].end;
     const int64_t n = c1 - c0;
     const unsigned gn = grid_for(n);
-    const unsigned nrb = (unsigned)((sec_hi - sec_lo) * (p->n_rows + 1));
-    TPC_LAUNCH(k_neighbours_rows, dim3(nrb), dim3(kBlock), 0, st, p->d_sectors, sec_lo, p->n_rows,
-               p->d_row_x, p->params, (const int32_t*)grid.bin_start, (const float*)grid.y,
-               (const float*)grid.z, (const int32_t*)grid.id, links.up0, links.down0);
+    TPC_LAUNCH(k_neighbours, dim3(grid_for(n, 65536)), dim3(kBlock), 0, st, p->d_sectors,
+               p->n_rows, p->d_row_x, p->params, (const int32_t*)grid.bin_start,
+               (const float*)grid.y, (const float*)grid.z, (const int32_t*)grid.id,
+               (const int32_t*)ws.gsr, c0, c1, links.up0, links.down0);
     launch_fill<int32_t>(ws.tmp + c0, -1, n, st);
     TPC_LAUNCH(k_clean, dim3(gn), dim3(kBlock), 0, st, (const int32_t*)links.up0,
                (const int32_t*)links.down0, (const int32_t*)grid.id, c0, c1, links.up, links.down,

@@ -159,7 +159,7 @@ def main():
     n_cl = ev.n_clusters
     n_hits_trk = int(st["n_track_hits"])
     roof = roofline(dom, kernels[dom]["avg_ms"], st, n_cl, n_hits_trk)
-    roof["traffic"] = counter_traffic(dom, "central_event")
+    roof["traffic"] = counter_traffic(dom.split("<")[0], "central_event")
     roof["source_sha256"] = source_hash()
 
     extra = {}
@@ -209,29 +209,36 @@ def main():
 def roofline(name, avg_ms, st, n_cl, n_trk_hits):
     """Algorithmic traffic (bytes) or operations per launch of a kernel."""
     sec = avg_ms * 1e-3
+    base = name.split("<")[0]
     bytes_per_cluster = {
-        # reads row, y, z (9 B); atomics on the bin counts
-        "k_grid_count": 9, "k_grid_scatter": 13, "k_grid_rank": 33,
+        # row bucket counts: row (1 B)
+        "k_grid_rows": 1,
+        # row partition: read row, y, z (9 B), write id, y, z (12 B)
+        "k_grid_rows_scatter": 21,
+        # per-row bin sort: read y, z (8 B), write slot and bin (8 B)
+        "k_grid_bins": 16,
+        # final place: read slot, bin, id, y, z (20 B), write y, z, id, gsr (16 B)
+        "k_grid_place": 36,
         # reads y, z, gsr (12 B) writes up0, down0 (8 B)
         "k_neighbours": 20,
         # reads up0, down0, idg (12 B), writes up, down (8 B)
         "k_clean": 20,
     }
-    if name in bytes_per_cluster:
-        b = bytes_per_cluster[name] * n_cl
+    if base in bytes_per_cluster:
+        b = bytes_per_cluster[base] * n_cl
         gbs = b / sec / 1e9
         return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                 "units_per_launch": n_cl, "unit_name": "cluster",
-                "algorithmic_bytes_per_unit": bytes_per_cluster[name]}
-    if name == "k_tracklets":
+                "algorithmic_bytes_per_unit": bytes_per_cluster[base]}
+    if base == "k_tracklets":
         fl = FLOPS_PROPAGATE * st["n_propagations"] + FLOPS_UPDATE * st["n_updates"]
         tf = fl / sec / 1e12
         return {"kernel": name, "bound": "alu", "achieved": tf, "peak": ALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": tf / ALU_PEAK_TFLOPS, "traffic": None,
                 "flops_per_launch": fl, "propagations": st["n_propagations"],
                 "updates": st["n_updates"], "candidates": st["n_candidates"]}
-    if name in ("k_refit_fwd", "k_refit_adj"):
+    if base in ("k_refit_fwd", "k_refit_adj"):
         per_hit = 4 + 9 + (80 if name == "k_refit_fwd" else 88)
         b = per_hit * n_trk_hits
         gbs = b / sec / 1e9

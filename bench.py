@@ -160,7 +160,7 @@ def main():
     n_hits_trk = int(st["n_track_hits"])
     roof = roofline(dom, kernels[dom]["avg_ms"], st, n_cl, n_hits_trk)
     roof["traffic"] = counter_traffic(dom.split("<")[0], "central_event")
-    roof["source_sha256"] = source_hash()
+    roof["source_sha256"] = source_hash(dom.split("<")[0])
 
     extra = {}
     if not args.no_batch_bench:
@@ -250,16 +250,28 @@ def roofline(name, avg_ms, st, n_cl, n_trk_hits):
             "frac": None, "traffic": None}
 
 
-def source_hash():
-    """SHA-256 over the library's kernel sources and header: a counter
-    summary applies to the kernels only while this is unchanged."""
+# sources a kernel is built from (a counter summary applies while they are
+# unchanged)
+KERNEL_SOURCES = {
+    "k_tracklets": ["tracklets.hip", "tracklet_dev.hpp", "tpc_internal.hpp"],
+    "k_refit_fwd": ["refit.hip", "tpc_internal.hpp"],
+    "k_refit_adj": ["refit.hip", "tpc_internal.hpp"],
+}
+
+
+def source_hash(kernel=None):
+    """SHA-256 over the sources of `kernel` (all kernel sources when it has
+    no entry) and the header."""
     import glob
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1905_05515_amd", "csrc")
+    if kernel in KERNEL_SOURCES:
+        files = [os.path.join(csrc, f) for f in KERNEL_SOURCES[kernel]]
+    else:
+        files = sorted(glob.glob(os.path.join(csrc, "*.hip")) +
+                       glob.glob(os.path.join(csrc, "*.hpp")))
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1905_05515_amd", "csrc", "*.hip")) +
-                   glob.glob(os.path.join(ROOT, "paper_1905_05515_amd", "csrc", "*.hpp")) +
-                   [os.path.join(ROOT, "include", "tpc.h")])
-    for f in files:
+    for f in files + [os.path.join(ROOT, "include", "tpc.h")]:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
@@ -280,7 +292,7 @@ def counter_traffic(kernel, workload):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != source_hash():
+    if kv.get("source_sha256") != source_hash(kernel):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])

@@ -400,31 +400,36 @@ __device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const 
 }
 
 // Checkpoints are kept in tiles of 64 tracks (one wave): slot i of the
-// track in lane l of tile g holds 20 floats (p, C) at
-// ck[((g * n_rows + i) * 20 + k) * 64 + l].  The lanes of a wave that stand
-// at the same slot store and load whole 256-byte lines, and one wave's
-// checkpoints are one contiguous block.
-__device__ __forceinline__ float* ck_tile(float* ck, int64_t t, int n_rows)
+// track in lane l of tile g holds 20 floats (p, C) as five float4 at
+// ck4[((g * n_rows + i) * 5 + q) * 64 + l].  The lanes of a wave that stand
+// at the same slot store and load five contiguous 1 KB blocks, and one
+// wave's checkpoints are one contiguous block.
+__device__ __forceinline__ float4* ck_tile(float* ck, int64_t t, int n_rows)
 {
-    return ck + (t / kWave) * (int64_t)n_rows * 20 * kWave + (t & (kWave - 1));
+    return reinterpret_cast<float4*>(ck) + (t / kWave) * (int64_t)n_rows * 5 * kWave +
+           (t & (kWave - 1));
 }
 
-__device__ __forceinline__ void store_ck(float* o, int i, const float* p, const float* C)
+__device__ __forceinline__ void store_ck(float4* o, int i, const float* p, const float* C)
 {
-    o += (int64_t)i * 20 * kWave;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) o[k * kWave] = p[k];
-#pragma unroll
-    for (int k = 0; k < 15; ++k) o[(5 + k) * kWave] = C[k];
+    o += (int64_t)i * 5 * kWave;
+    o[0 * kWave] = make_float4(p[0], p[1], p[2], p[3]);
+    o[1 * kWave] = make_float4(p[4], C[0], C[1], C[2]);
+    o[2 * kWave] = make_float4(C[3], C[4], C[5], C[6]);
+    o[3 * kWave] = make_float4(C[7], C[8], C[9], C[10]);
+    o[4 * kWave] = make_float4(C[11], C[12], C[13], C[14]);
 }
 
-__device__ __forceinline__ void load_ck(const float* o, int i, float* p, float* C)
+__device__ __forceinline__ void load_ck(const float4* o, int i, float* p, float* C)
 {
-    o += (int64_t)i * 20 * kWave;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) p[k] = o[k * kWave];
-#pragma unroll
-    for (int k = 0; k < 15; ++k) C[k] = o[(5 + k) * kWave];
+    o += (int64_t)i * 5 * kWave;
+    const float4 a = o[0 * kWave], b = o[1 * kWave], c = o[2 * kWave], d = o[3 * kWave],
+                 e = o[4 * kWave];
+    p[0] = a.x; p[1] = a.y; p[2] = a.z; p[3] = a.w;
+    p[4] = b.x; C[0] = b.y; C[1] = b.z; C[2] = b.w;
+    C[3] = c.x; C[4] = c.y; C[5] = c.z; C[6] = c.w;
+    C[7] = d.x; C[8] = d.y; C[9] = d.z; C[10] = d.w;
+    C[11] = e.x; C[12] = e.y; C[13] = e.z; C[14] = e.w;
 }
 
 __device__ __forceinline__ int wave_max(int v)
@@ -524,7 +529,7 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
         bool alive = fit;
         int stat = 0;
         const float sd = t < nt && side ? (float)side[t] : 1.0f;
-        float* ckt = ck && t < nt ? ck_tile(ck, t, n_rows) : nullptr;
+        float4* ckt = ck && t < nt ? ck_tile(ck, t, n_rows) : nullptr;
         for (int i0 = 0; i0 < M; i0 += kChunk) {
             __syncthreads();      // the previous chunk is consumed
             stage_hits(S, bad, i0, a, t < nt && n >= 3 ? n : 0, idx, row, y, z, xs, n_rows);
@@ -632,7 +637,7 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
         const int M = wave_max(ne);
         if (M == 0) continue;
         HitRef H{idx, row, y, z, a};
-        const float* ckt = ck_tile(const_cast<float*>(ck), tb + lane, n_rows);
+        const float4* ckt = ck_tile(const_cast<float*>(ck), tb + lane, n_rows);
         const float sd = fit && side ? (float)side[t] : 1.0f;
         const float cb = fit ? gchi2[t] : 0.0f;
         float pb[5] = {0, 0, 0, 0, 0}, G[15];

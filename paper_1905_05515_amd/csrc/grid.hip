@@ -156,8 +156,10 @@ __device__ __forceinline__ int ctr_load(const int* c, bool local)
 __global__ __launch_bounds__(kBlock) void k_grid_bins(
     const tpc_sector* __restrict__ sec, int sec_lo, int n_rows,
     const int32_t* __restrict__ rstart, const float* __restrict__ gy,
-    const float* __restrict__ gz, int32_t* __restrict__ bin_start, int32_t* __restrict__ cnt,
-    int32_t* __restrict__ gslot, int32_t* __restrict__ gbin)
+    const float* __restrict__ gz, const int32_t* __restrict__ gid,
+    const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start,
+    int32_t* __restrict__ cnt, int32_t* __restrict__ gslot, int32_t* __restrict__ gbin,
+    int32_t* __restrict__ gtag)
 {
     __shared__ int lds[kRowBinsLds];
     __shared__ int red[kBlock / kWave];
@@ -214,16 +216,18 @@ __global__ __launch_bounds__(kBlock) void k_grid_bins(
         const int slot = atomicAdd(&ctr[b], 1);
         gslot[slot] = j;
         gbin[slot] = g_row + b;
+        // invalid rows keep their raw row value
+        gtag[slot] = (si << 8) | (r < n_rows ? r : (int)row[gid[j]]);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_place(
-    const tpc_sector* __restrict__ sec, int n_sec, const uint8_t* __restrict__ row,
     int64_t c0, int64_t c1, const int32_t* __restrict__ bin_start,
     const int32_t* __restrict__ gid, const float* __restrict__ gy,
     const float* __restrict__ gz, const int32_t* __restrict__ gslot,
-    const int32_t* __restrict__ gbin, float* __restrict__ yg, float* __restrict__ zg,
-    int32_t* __restrict__ idg, int32_t* __restrict__ gsr)
+    const int32_t* __restrict__ gbin, const int32_t* __restrict__ gtag,
+    float* __restrict__ yg, float* __restrict__ zg, int32_t* __restrict__ idg,
+    int32_t* __restrict__ gsr)
 {
     for (int64_t q = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < c1;
          q += (int64_t)gridDim.x * blockDim.x) {
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_place(
         yg[o] = gy[j];
         zg[o] = gz[j];
         idg[o] = id;
-        gsr[o] = (find_sector(sec, n_sec, q) << 8) | row[id];
+        gsr[o] = gtag[q];
     }
 }
 
@@ -264,11 +268,12 @@ int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in
                ws.tmp, ws.gy, ws.gz);
     TPC_LAUNCH(k_grid_bins, dim3((unsigned)nbk), dim3(kBlock), 0, st, p->d_sectors, sec_lo,
                p->n_rows, (const int32_t*)ws.rstart, (const float*)ws.gy, (const float*)ws.gz,
-               out.bin_start, ws.cnt, ws.gslot, ws.gbin);
-    TPC_LAUNCH(k_grid_place, dim3(grid_for(c1 - c0)), dim3(kBlock), 0, st, p->d_sectors,
-               p->n_sectors, in.row, c0, c1, (const int32_t*)out.bin_start,
-               (const int32_t*)ws.tmp, (const float*)ws.gy, (const float*)ws.gz,
-               (const int32_t*)ws.gslot, (const int32_t*)ws.gbin, out.y, out.z, out.id, ws.gsr);
+               (const int32_t*)ws.tmp, in.row, out.bin_start, ws.cnt, ws.gslot, ws.gbin,
+               ws.gtag);
+    TPC_LAUNCH(k_grid_place, dim3(grid_for(c1 - c0)), dim3(kBlock), 0, st, c0, c1,
+               (const int32_t*)out.bin_start, (const int32_t*)ws.tmp, (const float*)ws.gy,
+               (const float*)ws.gz, (const int32_t*)ws.gslot, (const int32_t*)ws.gbin,
+               (const int32_t*)ws.gtag, out.y, out.z, out.id, ws.gsr);
     TPC_LAUNCH(k_set_grid_status, dim3(1), dim3(1), 0, st, ws.status, c1);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }

@@ -420,16 +420,20 @@ __device__ __forceinline__ void store_ck(float4* o, int i, const float* p, const
     o[4 * kWave] = make_float4(C[11], C[12], C[13], C[14]);
 }
 
-__device__ __forceinline__ void load_ck(const float4* o, int i, float* p, float* C)
+__device__ __forceinline__ void load_ck(const float4* o, int i, float4* q)
 {
     o += (int64_t)i * 5 * kWave;
-    const float4 a = o[0 * kWave], b = o[1 * kWave], c = o[2 * kWave], d = o[3 * kWave],
-                 e = o[4 * kWave];
-    p[0] = a.x; p[1] = a.y; p[2] = a.z; p[3] = a.w;
-    p[4] = b.x; C[0] = b.y; C[1] = b.z; C[2] = b.w;
-    C[3] = c.x; C[4] = c.y; C[5] = c.z; C[6] = c.w;
-    C[7] = d.x; C[8] = d.y; C[9] = d.z; C[10] = d.w;
-    C[11] = e.x; C[12] = e.y; C[13] = e.z; C[14] = e.w;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) q[k] = o[k * kWave];
+}
+
+__device__ __forceinline__ void unpack_ck(const float4* q, float* p, float* C)
+{
+    p[0] = q[0].x; p[1] = q[0].y; p[2] = q[0].z; p[3] = q[0].w;
+    p[4] = q[1].x; C[0] = q[1].y; C[1] = q[1].z; C[2] = q[1].w;
+    C[3] = q[2].x; C[4] = q[2].y; C[5] = q[2].z; C[6] = q[2].w;
+    C[7] = q[3].x; C[8] = q[3].y; C[9] = q[3].z; C[10] = q[3].w;
+    C[11] = q[4].x; C[12] = q[4].y; C[13] = q[4].z; C[14] = q[4].w;
 }
 
 __device__ __forceinline__ int wave_max(int v)
@@ -644,7 +648,12 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
 #pragma unroll
         for (int i = 0; i < 15; ++i) G[i] = 0.0f;
         CalHit cur{};
-        if (fit) cur = H.cal(n - 1, th, xs, sd, cm);
+        // checkpoint of the coming step (slot i - 1), loaded a step ahead
+        float4 ck4[5];
+        if (fit) {
+            cur = H.cal(n - 1, th, xs, sd, cm);
+            load_ck(ckt, n - 2, ck4);
+        }
         float Xcarry = 0.0f;
         float X2 = 0.0f, Y2 = 0.0f, Z2 = 0.0f;
         // steps i = top .. lo need hits lo - 1 .. top - 1 (the previous hit)
@@ -658,7 +667,8 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
                 const int k = i - lo;             // slot of hit i - 1
                 const CalHit prev = calibrate(th, S.x[k][lane], S.y[k][lane], S.z[k][lane], sd, cm);
                 float p[5], C[15];
-                load_ck(ckt, i - 1, p, C);
+                unpack_ck(ck4, p, C);
+                if (i >= 2) load_ck(ckt, i - 2, ck4);
                 const float p0[5] = {p[0], p[1], p[2], p[3], p[4]};
                 Prop P;
                 prop_fwd(p, C, cur.x - prev.x, prm.curv, prm.s_max, P);

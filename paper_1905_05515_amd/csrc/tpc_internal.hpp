@@ -40,6 +40,7 @@ struct Workspace {
     float* gz;             // [n]
     int32_t* gslot;        // [n] row-partitioned index of the cluster at a binned slot
     int32_t* gbin;         // [n] global bin of a binned slot
+    int32_t* gtag;         // [n] sector << 8 | row of a binned slot
     int64_t* sec_start;    // [n_sectors + 1] first start of each sector
     int32_t* pq;           // persistent form: [1] queue head, [kPhases * n_sectors] done counts
     int64_t* scnt;         // persistent form: [n_sectors] starts per sector

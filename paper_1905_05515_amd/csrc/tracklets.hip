@@ -66,16 +66,23 @@ inline size_t tracklet_lds_bytes(int n_rows, bool lds)
 }
 
 // work blocks of the LDS form that are resident on the whole device at once
+// (kept per device and row count: the query is not free and the per-sector
+// form asks once per sector)
 static int64_t tracklet_lds_capacity(int n_rows)
 {
+    constexpr int kDevs = 16;
+    static int64_t cache[kDevs][256];
     int dev = 0, n_cu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev >= 0 && dev < kDevs && cache[dev][n_rows] > 0) return cache[dev][n_rows];
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tracklets<true>, kWave,
                                                      tracklet_lds_bytes(n_rows, true)) !=
             hipSuccess)
         return 0;
-    return (int64_t)n_cu * per_cu;
+    const int64_t v = (int64_t)n_cu * per_cu;
+    if (dev >= 0 && dev < kDevs) cache[dev][n_rows] = v;
+    return v;
 }
 
 // Tracklets of the starts of sectors [sec_lo, sec_hi) (the start range that

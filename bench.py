@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-refit-bench", action="store_true")
     ap.add_argument("--no-batch-bench", action="store_true")
+    ap.add_argument("--no-slice-bench", action="store_true",
+                    help="skip the continuous read-out slice (100 collisions)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference size for scaling the HBM byte counters) and exit")
@@ -165,6 +167,8 @@ def main():
     extra = {}
     if not args.no_batch_bench:
         extra["batched_vs_per_sector"] = batch_bench(args, api, synth, ctx, stream, prm)
+    if not args.no_slice_bench:
+        extra["continuous_readout"] = slice_bench(args, api, synth, ctx, stream, prm)
     if not args.no_refit_bench:
         extra["refit_adjoint"] = refit_bench(args, api, synth, ctx, stream, prm, dev)
     cpu = None if args.no_cpu else cpu_baseline(ev, prm, args, tuned["occupancy"])
@@ -346,32 +350,86 @@ def batch_bench(args, api, synth, ctx, stream, prm):
     per = {k: ms / steps for k, (n, ms) in kt.items()}
     res["staged_kernels_us"] = {k: round(v * 1e3, 1) for k, v in
                                 sorted(per.items(), key=lambda kv: -kv[1])}
-    # grid build to chain starts alone: the two entry points that run them
-    with torch.cuda.stream(stream):
-        api.build_grid(ctx, e, stream)
-        api.find_neighbours(ctx, e, stream)
-        a = torch.cuda.Event(enable_timing=True)
-        b_ = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(steps):
-            api.build_grid(ctx, e, stream)
-            api.find_neighbours(ctx, e, stream)
-        b_.record(stream)
-        torch.cuda.synchronize()
-    seed_ms = a.elapsed_time(b_) / steps
-    b = SEEDING_BYTES_PER_CLUSTER * ev.n_clusters
-    res["roofline_grid_to_starts"] = {
-        "bound": "hbm", "kernels": "tpc_build_grid + tpc_find_neighbours (grid, neighbours, "
-                                   "cleaning, starts), eager launches",
-        "achieved": b / (seed_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": b / (seed_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": seed_ms,
-        "algorithmic_bytes_per_cluster": SEEDING_BYTES_PER_CLUSTER}
-    log(f"[bench]   grid..starts {seed_ms * 1e3:.1f} us, "
+    res["roofline_grid_to_starts"] = seeding_roofline(api, ctx, e, stream, steps,
+                                                      ev.n_clusters)
+    log(f"[bench]   grid..starts {res['roofline_grid_to_starts']['ms'] * 1e3:.1f} us, "
         f"{res['roofline_grid_to_starts']['frac'] * 100:.1f}% of HBM peak at "
         f"{SEEDING_BYTES_PER_CLUSTER} B/cluster")
     res["workload"] = ("512 single-sector instances, half pp-like (20-200 tracks), half "
                        "Pb-Pb-like (50-800), log-uniform, shuffled (seed 40040000)")
     res["clusters"] = ev.n_clusters
+    return res
+
+
+def seeding_roofline(api, ctx, e, stream, steps, n_clusters):
+    """Grid build to chain starts alone (tpc_build_grid + tpc_find_neighbours,
+    eager launches, HIP events) against the HBM peak."""
+    import torch
+    with torch.cuda.stream(stream):
+        api.build_grid(ctx, e, stream)
+        api.find_neighbours(ctx, e, stream)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            api.build_grid(ctx, e, stream)
+            api.find_neighbours(ctx, e, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    by = SEEDING_BYTES_PER_CLUSTER * n_clusters
+    return {"bound": "hbm", "kernels": "tpc_build_grid + tpc_find_neighbours (grid, neighbours, "
+                                       "cleaning, starts), eager launches",
+            "achieved": by / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": ms,
+            "algorithmic_bytes_per_cluster": SEEDING_BYTES_PER_CLUSTER}
+
+
+def slice_bench(args, api, synth, ctx, stream, prm):
+    """The continuous read-out slice: 100 collisions at 50 kHz, time turned
+    into z with the drift velocity, loopers up to three turns."""
+    import torch
+    t0 = time.time()
+    ev = synth.make_config3()
+    log(f"[bench] continuous read-out slice: {ev.n_clusters} clusters, generated in "
+        f"{time.time() - t0:.1f}s")
+    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
+                       sector_side=ev.sector_side)
+    res = {"grid_layout": pick_layout(args, api, ctx, e, stream)}
+    steps = max(2, args.steps // 4)
+    with torch.cuda.stream(stream):
+        api.track_batch(ctx, e, mode="staged", use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            api.track_batch(ctx, e, mode="staged", use_graph=True, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        api.timing_enable(ctx, True)
+        api.track_batch(ctx, e, mode="staged", use_graph=False, stream=stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    st = api.get_status(e, stream)
+    res.update({
+        "workload": "100 collisions, Poisson arrivals at 50 kHz, multiplicity U(5%, 100%) of the "
+                    "central event, pT >= 0.05 GeV, loopers up to 3 turns, z* = z - vd t "
+                    "(seed 3003)",
+        "clusters": ev.n_clusters, "ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3),
+        "launch_form": "staged, HIP graph", "starts": int(st["n_starts"]),
+        "tracks": int(st["n_tracks"]), "overflow": int(st["overflow"]),
+        "kernels_us": {k: round(ms_ / n * 1e3, 1) for k, (n, ms_) in
+                       sorted(kt.items(), key=lambda kv: -kv[1][1])},
+        "roofline_grid_to_starts": seeding_roofline(api, ctx, e, stream, steps, ev.n_clusters),
+    })
+    log(f"[bench]   slice {ms:.3f} ms  {ev.n_clusters / (ms * 1e-3):.3e} clusters/s, tracks "
+        f"{st['n_tracks']}; grid..starts {res['roofline_grid_to_starts']['ms'] * 1e3:.0f} us, "
+        f"{res['roofline_grid_to_starts']['frac'] * 100:.1f}% of HBM peak")
+    del e
+    torch.cuda.empty_cache()
     return res
 
 

@@ -281,55 +281,76 @@ def make_config4(seed=CONFIG_SEEDS[4], n_instances=512):
                                        tracks_per_instance=ntrk.tolist()))
 
 
-def _crossings_chunk(trk, k_all, a, b, max_turn, n_turns):
+def _crossings_chunk(trk, k_all, a, b, max_turn, n_turns, offset=0, chunk=512):
+    if b - a > chunk:
+        parts = [_crossings_chunk(trk, k_all, c, min(b, c + chunk), max_turn, n_turns, offset)
+                 for c in range(a, b, chunk)]
+        return tuple(np.concatenate([p[i] for p in parts]) for i in range(5))
     alphas = (np.arange(N_SECTORS_PER_SIDE) + 0.5) * SECTOR_WIDTH
-    ylim = (ROW_X64 * TAN10)[None, None, :]
-    X = ROW_X64[None, None, :]
-    out = ([], [], [], [], [])
+    ylim_row = ROW_X64 * TAN10
     sl = slice(a, b)
-    args = [trk[key][sl][:, None, None] for key in ("vx", "vy", "vz", "phi0", "tanl")]
-    k = k_all[sl][:, None, None]
-    for valid, yl, z, _ in helix_plane_point(*args, k, alphas[None, :, None], X,
+    k = k_all[sl]
+    vx, vy, vz = trk["vx"][sl], trk["vy"][sl], trk["vz"][sl]
+    phi0, tanl = trk["phi0"][sl], trk["tanl"][sl]
+    # (track, sector) pairs whose circle can reach the sector's rows: the
+    # circle's local x extent must meet [x_0, x_last] and its y extent the
+    # widest acceptance (a necessary condition; the exact tests follow)
+    xc = vx - np.sin(phi0) / k
+    yc = vy + np.cos(phi0) / k
+    ca, sa = np.cos(alphas), np.sin(alphas)
+    xcl = xc[:, None] * ca[None, :] + yc[:, None] * sa[None, :]
+    ycl = -xc[:, None] * sa[None, :] + yc[:, None] * ca[None, :]
+    R = (1.0 / np.abs(k))[:, None]
+    ymax = float(ylim_row[-1])
+    keep = ((xcl + R >= ROW_X64[0]) & (xcl - R <= ROW_X64[-1]) &
+            (ycl + R >= -ymax) & (ycl - R <= ymax))
+    ti, si = np.nonzero(keep)
+    out = ([], [], [], [], [])
+    if ti.shape[0] == 0:
+        return tuple(np.zeros(0, d) for d in (np.int64, np.int64, np.float64, np.float64,
+                                              np.int64))
+    col = lambda v: v[ti][:, None]
+    for valid, yl, z, _ in helix_plane_point(col(vx), col(vy), col(vz), col(phi0), col(tanl),
+                                              col(k), alphas[si][:, None], ROW_X64[None, :],
                                               max_turn=max_turn, n_turns=n_turns):
-        m = valid & (np.abs(yl) <= ylim) & (np.abs(z) <= DRIFT_LEN)
-        ti, si, ri = np.nonzero(m)
-        zz = z[ti, si, ri]
-        out[0].append(si + N_SECTORS_PER_SIDE * (zz < 0))
+        m = valid & (np.abs(yl) <= ylim_row[None, :]) & (np.abs(z) <= DRIFT_LEN)
+        pi, ri = np.nonzero(m)
+        zz = z[pi, ri]
+        out[0].append(si[pi] + N_SECTORS_PER_SIDE * (zz < 0))
         out[1].append(ri)
-        out[2].append(yl[ti, si, ri])
+        out[2].append(yl[pi, ri])
         out[3].append(zz)
-        out[4].append(ti + a)
+        out[4].append(ti[pi] + a + offset)
     return tuple(np.concatenate(v) for v in out)
 
 
-_POOL_STATE = {}
-
-
 def _crossings_task(args):
-    a, b = args
-    st = _POOL_STATE
-    return _crossings_chunk(st["trk"], st["k"], a, b, st["max_turn"], st["n_turns"])
+    trk, k_all, a, max_turn, n_turns = args
+    return _crossings_chunk(trk, k_all, 0, k_all.shape[0], max_turn, n_turns, offset=a)
 
 
 def _sector_crossings(trk, max_turn=math.pi, n_turns=1, chunk=512, workers=None):
     """Crossings of tracks with the row planes of all 36 real 20-degree
     sectors.  Returns (sector, row, y_local, z, label).  Pure geometry (no
-    random numbers): large track sets are split over forked worker
-    processes, the chunks joined in track order, so the result does not
-    depend on the number of workers."""
+    random numbers): large track sets are split over worker processes
+    (started fresh, so that a parent process that uses a GPU is never
+    forked), the chunks joined in track order, so the result does not depend
+    on the number of workers."""
     k_all = CURV_PER_QPT64 * trk["qpt"]
     T = k_all.shape[0]
     ranges = [(a, min(T, a + chunk)) for a in range(0, T, chunk)]
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
-    if workers > 1 and len(ranges) >= 8:
+    if workers > 1 and len(ranges) >= 16:
         import multiprocessing as mp
-        _POOL_STATE.update(trk=trk, k=k_all, max_turn=max_turn, n_turns=n_turns)
-        try:
-            with mp.get_context("fork").Pool(min(workers, len(ranges))) as pool:
-                parts = pool.map(_crossings_task, ranges)
-        finally:
-            _POOL_STATE.clear()
+        keys = ("vx", "vy", "vz", "phi0", "tanl")
+        per = -(-len(ranges) // (4 * workers))          # ranges per task
+        tasks = []
+        for i in range(0, len(ranges), per):
+            a, b = ranges[i][0], ranges[min(i + per, len(ranges)) - 1][1]
+            tasks.append(({k: trk[k][a:b] for k in keys}, k_all[a:b], a, max_turn, n_turns))
+        with mp.get_context("spawn").Pool(min(workers, len(tasks))) as pool:
+            parts = pool.map(_crossings_task, tasks)
     else:
         parts = [_crossings_chunk(trk, k_all, a, b, max_turn, n_turns) for a, b in ranges]
     return tuple(np.concatenate([p[i] for p in parts]) for i in range(5))
@@ -372,8 +393,9 @@ def make_event(rng, n_primary, sec_frac=0.10, noise_frac=0.05, pt_min=0.1):
 
 def _pack_sectors(rng, sector, row, y, z, lab, trk, zranges, meta):
     n_sec = 2 * N_SECTORS_PER_SIDE
-    key = sector.astype(np.int64)
-    # group by sector, random order inside each sector
+    key = sector.astype(np.uint8)
+    # group by sector, random order inside each sector (a stable sort of a
+    # uint8 key is a radix sort)
     perm = rng.permutation(key.shape[0])
     order = perm[np.argsort(key[perm], kind="stable")]
     counts = np.bincount(key, minlength=n_sec)
@@ -403,23 +425,34 @@ def make_config3(seed=CONFIG_SEEDS[3], n_collisions=100, rate_khz=50.0,
     """Continuous read-out slice: n_collisions collisions with Poisson
     arrival times at rate_khz, multiplicity U(5%, 100%) of the central event,
     loopers followed up to max_turns turns; the tracker sees
-    z* = z - sgn(z) * vd * t_collision."""
+    z* = z - sgn(z) * vd * t_collision.  Random draws: arrival times, then
+    every collision's tracks, then per collision its smearing and noise (the
+    crossings of all tracks are computed in between, in one parallel pass)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t_us = np.cumsum(rng.exponential(1e3 / rate_khz, n_collisions))
     t_us -= t_us[0]
-    parts = []
-    tracks = None
-    base = 0
+    colls = []
     for c in range(n_collisions):
         f = rng.uniform(0.05, 1.0)
         n_p = int(round(f * n_primary_central))
         prim = _sample_tracks(rng, n_p, 0.0, 2 * math.pi, -0.9, 0.9, pt_min)
         sec = _secondaries(rng, int(round(0.1 * n_p)), pt_min)
         trk = _concat_tracks(prim, sec)
-        sector, row, y, z, lab = _sector_crossings(trk, max_turn=2 * math.pi * max_turns,
-                                                   n_turns=max_turns)
-        y = _smear32(rng, y)
-        z = _smear32(rng, z)
+        trk["t_us"] = np.full(trk["qpt"].shape[0], t_us[c])
+        colls.append(trk)
+    tracks = {k: np.concatenate([t[k] for t in colls]) for k in colls[0]}
+    first = np.zeros(n_collisions + 1, np.int64)
+    first[1:] = np.cumsum([t["qpt"].shape[0] for t in colls])
+    x_sector, x_row, x_y, x_z, x_lab = _sector_crossings(
+        tracks, max_turn=2 * math.pi * max_turns, n_turns=max_turns)
+    # crossings come in track order
+    bounds = np.searchsorted(x_lab, first)
+    parts = []
+    for c in range(n_collisions):
+        a, b = bounds[c], bounds[c + 1]
+        sector, row, lab = x_sector[a:b], x_row[a:b], x_lab[a:b]
+        y = _smear32(rng, x_y[a:b])
+        z = _smear32(rng, x_z[a:b])
         n_noise = int(round(0.05 * row.shape[0]))
         ns = rng.integers(0, 2 * N_SECTORS_PER_SIDE, n_noise)
         nr = rng.integers(0, N_ROWS, n_noise)
@@ -432,11 +465,8 @@ def make_config3(seed=CONFIG_SEEDS[3], n_collisions=100, rate_khz=50.0,
         zz = np.concatenate([z, nz]).astype(np.float64)
         shift = VD_CM_PER_US * t_us[c]
         zstar = np.where(sector >= N_SECTORS_PER_SIDE, zz + shift, zz - shift)
-        lab = np.concatenate([lab + base, -np.ones(n_noise, np.int64)])
+        lab = np.concatenate([lab, -np.ones(n_noise, np.int64)])
         parts.append((sector, row, np.concatenate([y, ny]), zstar.astype(np.float32), lab))
-        base += trk["qpt"].shape[0]
-        trk["t_us"] = np.full(trk["qpt"].shape[0], t_us[c])
-        tracks = trk if tracks is None else _concat_tracks(tracks, trk)
     sector, row, y, z, lab = (np.concatenate([p[i] for p in parts]) for i in range(5))
     zmin = -VD_CM_PER_US * float(t_us[-1])
     zr = [(zmin, DRIFT_LEN)] * N_SECTORS_PER_SIDE + [(-DRIFT_LEN, -zmin)] * N_SECTORS_PER_SIDE

@@ -1,0 +1,123 @@
+"""The continuous read-out slice at full size (100 overlapping collisions,
+tens of millions of clusters) through the launch form the benchmark times
+(staged stages, graph replay).  The oracle cannot track the whole slice in
+seconds, but sectors are independent for every step, so the oracle run on
+single sectors must reproduce the library's outputs for those sectors bit
+for bit; properties that hold at any size are checked over the whole
+slice."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import assert_same_tracking, ctx
+from paper_1905_05515_amd import api
+from paper_1905_05515_amd.layout import grid_layout
+
+pytestmark = pytest.mark.gpu
+
+SAMPLED_SECTORS = (3, 30)
+
+
+@pytest.fixture(scope="module")
+def slice_run():
+    t0 = time.time()
+    ev = synth.make_config3()
+    print(f"case c3 n={ev.n_clusters} generated in {time.time() - t0:.1f}s", flush=True)
+    prm = synth.default_params()
+    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
+                       sector_side=ev.sector_side)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for _ in range(2):                   # capture, then replay
+            api.track_batch(ctx(), e, mode="staged", use_graph=True, stream=side)
+    side.synchronize()
+    st = api.get_status(e, side)
+    print(f"case c3 tracked: starts {st['n_starts']} tracks {st['n_tracks']}", flush=True)
+    return ev, e, st, prm
+
+
+def _sector_slice(ev, e, st, s):
+    """The library's outputs for sector s, in the coordinates of the sector
+    as a stand-alone event (ids and positions minus its first id)."""
+    t = e.t
+    b0, b1 = int(ev.sector_offsets[s]), int(ev.sector_offsets[s + 1])
+    tab, _ = e.layout
+    bb0 = int(tab[s]["bin_base"])
+    nb = e.n_rows * int(tab[s]["nby"]) * int(tab[s]["nbz"]) + 1
+    cpu = lambda x: x.cpu().numpy()
+
+    def shift(a):
+        return np.where(a >= 0, a - b0, -1).astype(np.int32)
+
+    out = dict(status=dict(st))
+    out["bin_start"] = cpu(t["bin_start"][bb0:bb0 + nb + 1]) - b0
+    out["yg"] = cpu(t["yg"][b0:b1])
+    out["zg"] = cpu(t["zg"][b0:b1])
+    out["idg"] = cpu(t["idg"][b0:b1]) - b0
+    for k in ("up0", "down0", "up", "down"):
+        out[k] = shift(cpu(t[k][b0:b1]))
+    m = min(int(st["n_starts"]), e.start_capacity)
+    starts = cpu(t["starts"][:m])
+    t_lo, t_hi = np.searchsorted(starts >= b0, True), np.searchsorted(starts >= b1, True)
+    # starts are in id order, so the sector's starts are one block
+    assert np.all((starts[t_lo:t_hi] >= b0) & (starts[t_lo:t_hi] < b1))
+    out["starts"] = starts[t_lo:t_hi] - b0
+    hits = cpu(t["t_hits"].view(e.n_rows, e.start_capacity)[:, t_lo:t_hi]).T
+    out["t_hits"] = shift(np.ascontiguousarray(hits))
+    for k, w in (("t_nhits", 1), ("t_rin", 1), ("t_chi2", 1)):
+        out[k] = cpu(t[k][t_lo:t_hi])
+    out["t_par"] = cpu(t["t_par"][t_lo * 5:t_hi * 5]).reshape(-1, 5)
+    out["t_cov"] = cpu(t["t_cov"][t_lo * 15:t_hi * 15]).reshape(-1, 15)
+    nt = min(int(st["n_tracks"]), e.track_capacity)
+    trk_t = cpu(t["trk_tracklet"][:nt])
+    k_lo, k_hi = np.searchsorted(trk_t, t_lo), np.searchsorted(trk_t, t_hi)
+    off = cpu(t["trk_off"][k_lo:k_hi + 1])
+    out["trk_off"] = (off - off[0]).astype(np.int32)
+    out["trk_hits"] = cpu(t["trk_hits"][int(off[0]):int(off[-1])]) - b0
+    out["trk_tracklet"] = (trk_t[k_lo:k_hi] - t_lo).astype(np.int32)
+    out["status"]["n_grid"] = b1 - b0
+    return out
+
+
+def test_slice_status_and_any_size_properties(slice_run):
+    ev, e, st, _ = slice_run
+    assert st["overflow"] == 0
+    assert st["n_grid"] == ev.n_clusters
+    assert 0 < st["n_tracks"] <= st["n_starts"] <= e.start_capacity
+    nt = int(st["n_tracks"])
+    off = e.t["trk_off"][:nt + 1].cpu().numpy()
+    ids = e.t["trk_hits"][:int(off[-1])].cpu().numpy()
+    # every cluster is in at most one track; every track has hits of one
+    # sector only, at increasing rows
+    assert np.unique(ids).shape[0] == ids.shape[0]
+    sec = np.searchsorted(ev.sector_offsets, ids, side="right") - 1
+    first = np.repeat(sec[off[:-1]], np.diff(off))
+    assert np.array_equal(sec, first)
+    rows = ev.row[ids].astype(np.int64)
+    inc = np.diff(rows)
+    inner = np.ones(ids.shape[0] - 1, bool)
+    inner[off[1:-1] - 1] = False
+    assert np.all(inc[inner] > 0)
+
+
+@pytest.mark.parametrize("s", SAMPLED_SECTORS)
+def test_sampled_sectors_match_the_oracle(slice_run, s):
+    ev, e, st, prm = slice_run
+    sub = ev.sector(s)
+    print(f"case c3 sector {s} n={sub.n_clusters}", flush=True)
+    tab, nb = grid_layout(sub.sector_offsets, sub.sector_range, occupancy=e.occupancy,
+                          sides=sub.sector_side)
+    full_tab, _ = e.layout
+    for f in ("y0", "z0", "inv_by", "inv_bz", "nby", "nbz"):
+        assert tab[0][f] == full_tab[s][f], f
+    o = oracle.track_event(sub.row, sub.y, sub.z, tab, nb, sub.row_x, prm)
+    g = _sector_slice(ev, e, st, s)
+    # the work counters are whole-slice totals: compare them as the oracle's
+    g["status"]["n_propagations"], g["status"]["n_updates"], g["status"]["n_candidates"] = \
+        o["tracklets"]["work"]
+    assert_same_tracking(g, o, sub.n_clusters)

@@ -17,8 +17,9 @@ __global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)
 
 // ---- staged grid build ------------------------------------------------------
 // 1. rows:     tiles of kRowTile consecutive clusters count them per
-//              (sector, row bucket) in LDS (bucket n_rows holds the invalid
-//              rows), one device atomic per non-empty bucket and tile;
+//              (sector, row bucket) in LDS (a bucket is a z slab of a pad
+//              row, or the invalid rows), one device atomic per non-empty
+//              bucket and tile;
 // 2. scan:     bucket starts (a sector's first bucket starts at its first id);
 // 3. scatter:  tiles claim a range per bucket and copy (id, y, z) there, in
 //              any order inside a bucket;
@@ -29,8 +30,7 @@ __global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)
 //              number of clusters of the bin with a smaller id.
 // No step depends on the order of atomics: the result is the stable sort.
 constexpr int kRowTile = kBlock * 8;
-constexpr int kTileSec = 8;          // sectors of one tile with LDS counters
-constexpr int kRowBinsLds = 8192;    // bins of one row counted in LDS
+constexpr int kTileCounters = 4096;  // LDS bucket counters of one tile
 
 __device__ __forceinline__ int tile_sector(int64_t i, const int64_t* ends, int ns)
 {
@@ -39,51 +39,64 @@ __device__ __forceinline__ int tile_sector(int64_t i, const int64_t* ends, int n
     return -1;
 }
 
-// LDS: the tile's first sector, the ends of its first kTileSec sectors, and
-// zeroed bucket counters; returns the number of sectors with counters
-__device__ __forceinline__ int tile_setup(const tpc_sector* __restrict__ sec, int n_sec, int R,
-                                          int64_t i0, int* hist, int64_t* ends, int* sf_sh)
+// bucket of a cluster inside its sector
+__device__ __forceinline__ int cluster_bucket(const tpc_sector& s, int n_rows, int S, int r,
+                                              float z)
+{
+    if (r >= n_rows) return n_rows * S;
+    const int iz = bin_of(z, s.z0, s.inv_bz, s.nbz);
+    return r * S + iz / slab_zbins(s);
+}
+
+// LDS: the tile's first sector, the ends of its first ts sectors, and zeroed
+// bucket counters; returns the number of sectors with counters
+__device__ __forceinline__ int tile_setup(const tpc_sector* __restrict__ sec, int n_sec, int Rb,
+                                          int ts, int64_t i0, int* hist, int64_t* ends,
+                                          int* sf_sh)
 {
     __syncthreads();
     if (threadIdx.x == 0) *sf_sh = find_sector(sec, n_sec, i0);
-    for (int k = threadIdx.x; k < kTileSec * R; k += blockDim.x) hist[k] = 0;
+    for (int k = threadIdx.x; k < ts * Rb; k += blockDim.x) hist[k] = 0;
     __syncthreads();
     const int sf = *sf_sh;
-    const int ns = n_sec - sf < kTileSec ? n_sec - sf : kTileSec;
+    const int ns = n_sec - sf < ts ? n_sec - sf : ts;
     if ((int)threadIdx.x < ns) ends[threadIdx.x] = sec[sf + threadIdx.x].end;
     __syncthreads();
     return ns;
 }
 
+constexpr int kTileSecMax = 8;
+
+// ts: sectors of a tile with LDS counters (Rb * ts <= kTileCounters)
 __global__ __launch_bounds__(kBlock) void k_grid_rows(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    int64_t c0, int64_t c1, int32_t* __restrict__ rcnt, tpc_status* status)
+    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, int S, int ts,
+    const uint8_t* __restrict__ row, const float* __restrict__ z, int64_t c0, int64_t c1,
+    int32_t* __restrict__ rcnt, tpc_status* status)
 {
-    __shared__ int hist[kTileSec * 256];
-    __shared__ int64_t ends[kTileSec];
+    __shared__ int hist[kTileCounters];
+    __shared__ int64_t ends[kTileSecMax];
     __shared__ int sf_sh;
     __shared__ int64_t red[kBlock / kWave];
-    const int R = n_rows + 1;
+    const int Rb = (n_rows + 1) * S;
     const int64_t n_tiles = (c1 - c0 + kRowTile - 1) / kRowTile;
     int64_t bad = 0;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t i0 = c0 + tile * kRowTile;
         const int64_t i1 = i0 + kRowTile < c1 ? i0 + kRowTile : c1;
-        const int ns = tile_setup(sec, n_sec, R, i0, hist, ends, &sf_sh);
+        const int ns = tile_setup(sec, n_sec, Rb, ts, i0, hist, ends, &sf_sh);
         const int sf = sf_sh;
         for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-            int r = row[i];
-            if (r >= n_rows) {
-                ++bad;
-                r = n_rows;
-            }
+            const int r = row[i];
+            if (r >= n_rows) ++bad;
             const int k = tile_sector(i, ends, ns);
-            if (k >= 0) atomicAdd(&hist[k * R + r], 1);
-            else atomicAdd(&rcnt[find_sector(sec, n_sec, i) * R + r], 1);
+            const int si = k >= 0 ? sf + k : find_sector(sec, n_sec, i);
+            const int bk = cluster_bucket(sec[si], n_rows, S, r, z[i]);
+            if (k >= 0) atomicAdd(&hist[k * Rb + bk], 1);
+            else atomicAdd(&rcnt[(int64_t)si * Rb + bk], 1);
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < ns * R; k += blockDim.x)
-            if (hist[k]) atomicAdd(&rcnt[(sf + k / R) * R + k % R], hist[k]);
+        for (int k = threadIdx.x; k < ns * Rb; k += blockDim.x)
+            if (hist[k]) atomicAdd(&rcnt[(int64_t)(sf + k / Rb) * Rb + k % Rb], hist[k]);
     }
     const int64_t tot = block_sum(bad, red);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&status->n_bad_rows,
@@ -91,21 +104,21 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows(
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_rows_scatter(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    const float* __restrict__ y, const float* __restrict__ z, int64_t c0, int64_t c1,
-    const int32_t* __restrict__ rstart, int32_t* __restrict__ rfill, int32_t* __restrict__ gid,
-    float* __restrict__ gy, float* __restrict__ gz)
+    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, int S, int ts,
+    const uint8_t* __restrict__ row, const float* __restrict__ y, const float* __restrict__ z,
+    int64_t c0, int64_t c1, const int32_t* __restrict__ rstart, int32_t* __restrict__ rfill,
+    int32_t* __restrict__ gid, float* __restrict__ gy, float* __restrict__ gz)
 {
     constexpr int kItems = kRowTile / kBlock;
-    __shared__ int hist[kTileSec * 256];
-    __shared__ int64_t ends[kTileSec];
+    __shared__ int hist[kTileCounters];
+    __shared__ int64_t ends[kTileSecMax];
     __shared__ int sf_sh;
-    const int R = n_rows + 1;
+    const int Rb = (n_rows + 1) * S;
     const int64_t n_tiles = (c1 - c0 + kRowTile - 1) / kRowTile;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t i0 = c0 + tile * kRowTile;
         const int64_t i1 = i0 + kRowTile < c1 ? i0 + kRowTile : c1;
-        const int ns = tile_setup(sec, n_sec, R, i0, hist, ends, &sf_sh);
+        const int ns = tile_setup(sec, n_sec, Rb, ts, i0, hist, ends, &sf_sh);
         const int sf = sf_sh;
         int bucket[kItems], rank[kItems];
 #pragma unroll
@@ -114,23 +127,23 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows_scatter(
             bucket[j] = -1;
             rank[j] = 0;
             if (i >= i1) continue;
-            int r = row[i];
-            if (r >= n_rows) r = n_rows;
             const int k = tile_sector(i, ends, ns);
+            const int si = k >= 0 ? sf + k : find_sector(sec, n_sec, i);
+            const int bk = cluster_bucket(sec[si], n_rows, S, row[i], z[i]);
             if (k >= 0) {
-                bucket[j] = k * R + r;
+                bucket[j] = k * Rb + bk;
                 rank[j] = atomicAdd(&hist[bucket[j]], 1);
             } else {   // a sector beyond the tile's LDS counters: claim one slot
-                const int gb = find_sector(sec, n_sec, i) * R + r;
+                const int64_t gb = (int64_t)si * Rb + bk;
                 rank[j] = rstart[gb] + atomicAdd(&rfill[gb], 1);
             }
         }
         __syncthreads();
         // one range per non-empty bucket; the counter becomes the range start
-        for (int k = threadIdx.x; k < ns * R; k += blockDim.x) {
+        for (int k = threadIdx.x; k < ns * Rb; k += blockDim.x) {
             const int c = hist[k];
             if (c) {
-                const int gb = (sf + k / R) * R + k % R;
+                const int64_t gb = (int64_t)(sf + k / Rb) * Rb + k % Rb;
                 hist[k] = rstart[gb] + atomicAdd(&rfill[gb], c);
             }
         }
@@ -152,9 +165,9 @@ __device__ __forceinline__ int ctr_load(const int* c, bool local)
     return local ? c[0] : __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// one block per (sector, row bucket) of sectors [sec_lo, ...)
+// one block per (sector, bucket) of sectors [sec_lo, ...)
 __global__ __launch_bounds__(kBlock) void k_grid_bins(
-    const tpc_sector* __restrict__ sec, int sec_lo, int n_rows,
+    const tpc_sector* __restrict__ sec, int sec_lo, int n_rows, int S,
     const int32_t* __restrict__ rstart, const float* __restrict__ gy,
     const float* __restrict__ gz, const int32_t* __restrict__ gid,
     const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start,
@@ -163,21 +176,26 @@ __global__ __launch_bounds__(kBlock) void k_grid_bins(
 {
     __shared__ int lds[kRowBinsLds];
     __shared__ int red[kBlock / kWave];
-    const int R = n_rows + 1;
-    const int si = sec_lo + (int)(blockIdx.x / R);
-    const int r = (int)(blockIdx.x % R);
+    const int Rb = (n_rows + 1) * S;
+    const int si = sec_lo + (int)(blockIdx.x / Rb);
+    const int bk = (int)(blockIdx.x % Rb);
+    const int r = bk / S, slab = bk % S;
     const tpc_sector s = sec[si];
-    const int a = rstart[si * R + r], n = rstart[si * R + r + 1] - a;
+    const int zs = slab_zbins(s);
+    if (slab >= (r < n_rows ? slab_count(s) : 1)) return;    // no such slab: no clusters
+    const int a = rstart[(int64_t)si * Rb + bk], n = rstart[(int64_t)si * Rb + bk + 1] - a;
     const int per_row = s.nbz * s.nby;
-    const int nbr = r < n_rows ? per_row : 1;
-    const int g_row = s.bin_base + r * per_row;
+    const int z_lo = slab * zs;
+    const int z_hi = z_lo + zs < s.nbz ? z_lo + zs : s.nbz;
+    const int nbr = r < n_rows ? (z_hi - z_lo) * s.nby : 1;
+    const int g0 = s.bin_base + r * per_row + (r < n_rows ? z_lo * s.nby : 0);
     const bool local = nbr <= kRowBinsLds;
-    int* ctr = local ? lds : cnt + g_row;
+    int* ctr = local ? lds : cnt + g0;
     for (int b = threadIdx.x; b < nbr; b += blockDim.x) ctr[b] = 0;
     if (!local) __threadfence();
     __syncthreads();
     for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
-        const int b = r < n_rows ? bin_of(gz[j], s.z0, s.inv_bz, s.nbz) * s.nby +
+        const int b = r < n_rows ? (bin_of(gz[j], s.z0, s.inv_bz, s.nbz) - z_lo) * s.nby +
                                        bin_of(gy[j], s.y0, s.inv_by, s.nby)
                                  : 0;
         atomicAdd(&ctr[b], 1);
@@ -200,22 +218,22 @@ __global__ __launch_bounds__(kBlock) void k_grid_bins(
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k)
             if (base + k < nbr) {
-                bin_start[g_row + base + k] = ex;
+                bin_start[g0 + base + k] = ex;
                 ctr[base + k] = ex;
                 ex += v[k];
             }
         carry += tot;
     }
-    if (r == n_rows && threadIdx.x == 0) bin_start[g_row + 1] = a + n;
+    if (r == n_rows && threadIdx.x == 0) bin_start[g0 + 1] = a + n;
     if (!local) __threadfence();
     __syncthreads();
     for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
-        const int b = r < n_rows ? bin_of(gz[j], s.z0, s.inv_bz, s.nbz) * s.nby +
+        const int b = r < n_rows ? (bin_of(gz[j], s.z0, s.inv_bz, s.nbz) - z_lo) * s.nby +
                                        bin_of(gy[j], s.y0, s.inv_by, s.nby)
                                  : 0;
         const int slot = atomicAdd(&ctr[b], 1);
         gslot[slot] = j;
-        gbin[slot] = g_row + b;
+        gbin[slot] = g0 + b;
         // invalid rows keep their raw row value
         gtag[slot] = (si << 8) | (r < n_rows ? r : (int)row[gid[j]]);
     }
@@ -253,21 +271,26 @@ int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in
     const tpc_sector& a = p->h_sectors[sec_lo];
     const tpc_sector& b = p->h_sectors[sec_hi - 1];
     const int64_t c0 = a.begin, c1 = b.end;
-    const int R = p->n_rows + 1;
-    const int64_t nbk = (int64_t)(sec_hi - sec_lo) * R;
+    const int S = grid_slabs(p);
+    const int Rb = (p->n_rows + 1) * S;
+    int ts = kTileCounters / Rb;
+    if (ts > kTileSecMax) ts = kTileSecMax;
+    if (ts < 1) ts = 1;
+    if (Rb > kTileCounters) return TPC_ERR_UNSUPPORTED;
+    const int64_t nbk = (int64_t)(sec_hi - sec_lo) * Rb;
     if (sec_lo == 0) launch_fill<int64_t>((int64_t*)ws.status, 0, sizeof(tpc_status) / 8, st);
-    launch_fill<int32_t>(ws.rcnt + (int64_t)sec_lo * R, 0, nbk, st);
-    launch_fill<int32_t>(ws.rfill + (int64_t)sec_lo * R, 0, nbk, st);
+    launch_fill<int32_t>(ws.rcnt + (int64_t)sec_lo * Rb, 0, nbk, st);
+    launch_fill<int32_t>(ws.rfill + (int64_t)sec_lo * Rb, 0, nbk, st);
     const unsigned gt = grid_for_block(ceil_div(c1 - c0, kRowTile), 1, 4096);
     TPC_LAUNCH(k_grid_rows, dim3(gt), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-               p->n_rows, in.row, c0, c1, ws.rcnt, ws.status);
-    launch_scan<int32_t>(ws.rcnt + (int64_t)sec_lo * R, ws.rstart + (int64_t)sec_lo * R, nbk,
+               p->n_rows, S, ts, in.row, in.z, c0, c1, ws.rcnt, ws.status);
+    launch_scan<int32_t>(ws.rcnt + (int64_t)sec_lo * Rb, ws.rstart + (int64_t)sec_lo * Rb, nbk,
                          true, nullptr, nullptr, ws.partials, st, c0);
     TPC_LAUNCH(k_grid_rows_scatter, dim3(gt), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-               p->n_rows, in.row, in.y, in.z, c0, c1, (const int32_t*)ws.rstart, ws.rfill,
-               ws.tmp, ws.gy, ws.gz);
+               p->n_rows, S, ts, in.row, in.y, in.z, c0, c1, (const int32_t*)ws.rstart,
+               ws.rfill, ws.tmp, ws.gy, ws.gz);
     TPC_LAUNCH(k_grid_bins, dim3((unsigned)nbk), dim3(kBlock), 0, st, p->d_sectors, sec_lo,
-               p->n_rows, (const int32_t*)ws.rstart, (const float*)ws.gy, (const float*)ws.gz,
+               p->n_rows, S, (const int32_t*)ws.rstart, (const float*)ws.gy, (const float*)ws.gz,
                (const int32_t*)ws.tmp, in.row, out.bin_start, ws.cnt, ws.gslot, ws.gbin,
                ws.gtag);
     TPC_LAUNCH(k_grid_place, dim3(grid_for(c1 - c0)), dim3(kBlock), 0, st, c0, c1,

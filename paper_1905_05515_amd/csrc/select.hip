@@ -15,6 +15,14 @@ namespace tpc {
 // device-wide keys instead.
 constexpr int kSelLds = 6144;
 
+// Sectors whose row chunks would not fit the LDS table on average take the
+// tracklet-parallel form with device-wide atomics instead (same keys and
+// counts); host and device decide alike from the sector's size.
+__host__ __device__ inline bool sel_big(const tpc_sector& s, int n_rows)
+{
+    return (s.end - s.begin) * (int64_t)kSelRows > (int64_t)(kSelLds / 2) * n_rows;
+}
+
 __global__ __launch_bounds__(kBlock) void k_sel_chunk(
     const tpc_sector* __restrict__ sec, int sec_lo, int n_rows, tpc_params prm,
     const int32_t* __restrict__ bin_start, const int32_t* __restrict__ idg,
@@ -37,6 +45,10 @@ __global__ __launch_bounds__(kBlock) void k_sel_chunk(
     if (lo < 0) lo = 0;
     if (lo > hi) lo = hi;
     const bool local = np <= kSelLds;
+    if (sel_big(s, n_rows)) {   // the tracklet-parallel kernels take this sector
+        for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[p0 + k] = 0ull;
+        return;
+    }
     for (int k = threadIdx.x; k < np; k += blockDim.x) {
         if (local) kl[k] = 0ull;
         else hitkey[p0 + k] = 0ull;
@@ -75,6 +87,48 @@ __global__ __launch_bounds__(kBlock) void k_sel_chunk(
             }
         }
         ccnt[q * count_cap + t] = (uint8_t)kept;
+    }
+}
+
+// Tracklet-parallel form for big sectors: item (t, blockIdx.y) handles rows
+// [8 y, 8 y + 8) of tracklet t, consecutive threads on consecutive
+// tracklets; tracklets of other sectors are left to k_sel_chunk.
+__global__ __launch_bounds__(kBlock) void k_sel_keys_big(
+    const tpc_sector* __restrict__ sec, int n_rows, tpc_params prm,
+    const int32_t* __restrict__ idg, const int32_t* __restrict__ gsr,
+    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
+    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
+    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
+    unsigned long long* __restrict__ hitkey)
+{
+    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
+    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
+    const int ra = blockIdx.y * kSelRows;
+    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (!sel_big(sec[gsr[t_start[t]] >> 8], n_rows)) continue;
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        if (key) sel_keys_chunk(t, ra, n_rows, key, t_hits, cap, hitkey);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_count_big(
+    const tpc_sector* __restrict__ sec, int n_rows, tpc_params prm,
+    const int32_t* __restrict__ idg, const int32_t* __restrict__ gsr,
+    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
+    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
+    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
+    const unsigned long long* __restrict__ hitkey, uint8_t* __restrict__ ccnt)
+{
+    const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
+    const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
+    const int ra = blockIdx.y * kSelRows;
+    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (!sel_big(sec[gsr[t_start[t]] >> 8], n_rows)) continue;
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        ccnt[blockIdx.y * count_cap + t] =
+            key ? (uint8_t)sel_count_chunk(t, ra, n_rows, key, t_hits, cap, hitkey) : 0;
     }
 }
 
@@ -154,6 +208,20 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
                (const int32_t*)grid.id, (const int32_t*)trl.start, (const int32_t*)trl.hits,
                (const int32_t*)trl.nhits, (const int64_t*)ws.sec_start, count_cap,
                trl.capacity, (unsigned long long*)ws.hitkey, ws.ccnt);
+    bool any_big = false;
+    for (int s = sec_lo; s < sec_hi && !any_big; ++s) any_big = sel_big(p->h_sectors[s], p->n_rows);
+    if (any_big) {
+        TPC_LAUNCH(k_sel_keys_big, dim3(gx, nq), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
+                   p->params, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
+                   (const int32_t*)trl.start, (const int32_t*)trl.hits,
+                   (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
+                   (unsigned long long*)ws.hitkey);
+        TPC_LAUNCH(k_sel_count_big, dim3(gx, nq), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
+                   p->params, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
+                   (const int32_t*)trl.start, (const int32_t*)trl.hits,
+                   (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
+                   (const unsigned long long*)ws.hitkey, ws.ccnt);
+    }
     TPC_LAUNCH(k_sel_len, dim3(gx), dim3(kBlock), 0, st, nq, p->params, lo, hi, count_cap,
                (const uint8_t*)ws.ccnt, ws.tlen);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;

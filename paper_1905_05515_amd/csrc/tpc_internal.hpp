@@ -33,9 +33,9 @@ struct Workspace {
     uint8_t* ccnt;         // [row chunks * start_cap] kept hits per tracklet and row chunk
     // grid build: clusters per (sector, row bucket), their running fill and
     // starts; the row-partitioned copy of the clusters; the binned order
-    int32_t* rcnt;         // [n_sectors * (n_rows + 1)]
-    int32_t* rfill;        // [n_sectors * (n_rows + 1)]
-    int32_t* rstart;       // [n_sectors * (n_rows + 1) + 1]
+    int32_t* rcnt;         // [n_sectors * (n_rows + 1) * S]
+    int32_t* rfill;        // [n_sectors * (n_rows + 1) * S]
+    int32_t* rstart;       // [n_sectors * (n_rows + 1) * S + 1]
     float* gy;             // [n]
     float* gz;             // [n]
     int32_t* gslot;        // [n] row-partitioned index of the cluster at a binned slot
@@ -47,6 +47,25 @@ struct Workspace {
     uint64_t* tsum;        // persistent form: [n_sectors] tracks << 32 | hits per sector
     size_t bytes;
 };
+
+// Row buckets of the staged grid build.  Every pad row of a sector is cut
+// into z slabs of at most kRowBinsLds bins (so that one block counts a
+// slab's bins in LDS); bucket (row, slab) of a sector has index
+// row * S + slab, S the largest slab count of the problem; the clusters of
+// invalid rows form bucket (n_rows, 0).
+constexpr int kRowBinsLds = 8192;
+__host__ __device__ inline int slab_zbins(const tpc_sector& s)
+{
+    const int z = kRowBinsLds / (s.nby > 0 ? s.nby : 1);
+    return z < 1 ? 1 : z;
+}
+__host__ __device__ inline int slab_count(const tpc_sector& s)
+{
+    const int zs = slab_zbins(s);
+    return (s.nbz + zs - 1) / zs;
+}
+// S of a problem (host)
+int grid_slabs(const tpc_problem* p);
 
 // Rows of a tracklet handled by one selection work item.
 constexpr int kSelRows = 8;

@@ -127,11 +127,21 @@ template void launch_scan<uint64_t>(const uint64_t*, uint64_t*, int64_t, bool, i
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+int grid_slabs(const tpc_problem* p)
+{
+    int S = 1;
+    for (int i = 0; i < p->n_sectors; ++i) {
+        const int c = slab_count(p->h_sectors[i]);
+        if (c > S) S = c;
+    }
+    return S;
+}
+
 bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Workspace* ws)
 {
     const int64_t n = p->n_clusters, nb = p->n_bins;
     int64_t scan_n = n > nb + 1 ? n : nb + 1;
-    const int64_t nrb1 = (int64_t)p->n_sectors * (p->n_rows + 1) + 1;
+    const int64_t nrb1 = (int64_t)p->n_sectors * (p->n_rows + 1) * grid_slabs(p) + 1;
     if (nrb1 > scan_n) scan_n = nrb1;
     if (start_cap + 1 > scan_n) scan_n = start_cap + 1;
     int64_t max_tiles = ceil_div(scan_n, kScanTile) + 1;
@@ -153,7 +163,7 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->pq = (int32_t*)take(sizeof(int32_t) * (size_t)(1 + kPhases * p->n_sectors));
     ws->scnt = (int64_t*)take(sizeof(int64_t) * (size_t)p->n_sectors);
     ws->tsum = (uint64_t*)take(sizeof(uint64_t) * (size_t)p->n_sectors);
-    const size_t nrb = (size_t)p->n_sectors * (size_t)(p->n_rows + 1);
+    const size_t nrb = (size_t)p->n_sectors * (size_t)(p->n_rows + 1) * (size_t)grid_slabs(p);
     const size_t nn = (size_t)(n > 0 ? n : 1);
     ws->rcnt = (int32_t*)take(sizeof(int32_t) * nrb);
     ws->rfill = (int32_t*)take(sizeof(int32_t) * nrb);

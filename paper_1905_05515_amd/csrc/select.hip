@@ -15,12 +15,15 @@ namespace tpc {
 // device-wide keys instead.
 constexpr int kSelLds = 6144;
 
-// Sectors whose row chunks would not fit the LDS table on average take the
-// tracklet-parallel form with device-wide atomics instead (same keys and
-// counts); host and device decide alike from the sector's size.
+// Sectors whose row chunks hold on average several times more positions
+// than the LDS table take the tracklet-parallel form with device-wide
+// atomics instead (same keys and counts): one block per chunk would loop
+// over too many tracklets.  A chunk just over the table still uses its
+// block (with device-wide keys).  Host and device decide alike from the
+// sector's size.
 __host__ __device__ inline bool sel_big(const tpc_sector& s, int n_rows)
 {
-    return (s.end - s.begin) * (int64_t)kSelRows > (int64_t)(kSelLds / 2) * n_rows;
+    return (s.end - s.begin) * (int64_t)kSelRows > (int64_t)(8 * kSelLds) * n_rows;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sel_chunk(

@@ -4,16 +4,11 @@
 // grid positions, so sectors can be built independently.  The staged form
 // partitions by row first (counts per tile in LDS), then sorts every row by
 // bin in LDS, so that no cluster needs a device-wide atomic; the persistent
-// kernel keeps the per-cluster form of grid_dev.hpp.
+// kernel runs the same steps as tasks (grid_dev.hpp).
 #include "block_dev.hpp"
 #include "grid_dev.hpp"
 
 namespace tpc {
-
-__global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) status->n_grid = n_grid;
-}
 
 // ---- staged grid build ------------------------------------------------------
 // 1. rows:     tiles of kRowTile consecutive clusters count them per
@@ -37,15 +32,6 @@ __device__ __forceinline__ int tile_sector(int64_t i, const int64_t* ends, int n
     for (int k = 0; k < ns; ++k)
         if (i < ends[k]) return k;
     return -1;
-}
-
-// bucket of a cluster inside its sector
-__device__ __forceinline__ int cluster_bucket(const tpc_sector& s, int n_rows, int S, int r,
-                                              float z)
-{
-    if (r >= n_rows) return n_rows * S;
-    const int iz = bin_of(z, s.z0, s.inv_bz, s.nbz);
-    return r * S + iz / slab_zbins(s);
 }
 
 // LDS: the tile's first sector, the ends of its first ts sectors, and zeroed
@@ -160,11 +146,6 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows_scatter(
     }
 }
 
-__device__ __forceinline__ int ctr_load(const int* c, bool local)
-{
-    return local ? c[0] : __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // one block per (sector, bucket) of sectors [sec_lo, ...)
 __global__ __launch_bounds__(kBlock) void k_grid_bins(
     const tpc_sector* __restrict__ sec, int sec_lo, int n_rows, int S,
@@ -179,64 +160,9 @@ __global__ __launch_bounds__(kBlock) void k_grid_bins(
     const int Rb = (n_rows + 1) * S;
     const int si = sec_lo + (int)(blockIdx.x / Rb);
     const int bk = (int)(blockIdx.x % Rb);
-    const int r = bk / S, slab = bk % S;
     const tpc_sector s = sec[si];
-    const int zs = slab_zbins(s);
-    if (slab >= (r < n_rows ? slab_count(s) : 1)) return;    // no such slab: no clusters
-    const int a = rstart[(int64_t)si * Rb + bk], n = rstart[(int64_t)si * Rb + bk + 1] - a;
-    const int per_row = s.nbz * s.nby;
-    const int z_lo = slab * zs;
-    const int z_hi = z_lo + zs < s.nbz ? z_lo + zs : s.nbz;
-    const int nbr = r < n_rows ? (z_hi - z_lo) * s.nby : 1;
-    const int g0 = s.bin_base + r * per_row + (r < n_rows ? z_lo * s.nby : 0);
-    const bool local = nbr <= kRowBinsLds;
-    int* ctr = local ? lds : cnt + g0;
-    for (int b = threadIdx.x; b < nbr; b += blockDim.x) ctr[b] = 0;
-    if (!local) __threadfence();
-    __syncthreads();
-    for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
-        const int b = r < n_rows ? (bin_of(gz[j], s.z0, s.inv_bz, s.nbz) - z_lo) * s.nby +
-                                       bin_of(gy[j], s.y0, s.inv_by, s.nby)
-                                 : 0;
-        atomicAdd(&ctr[b], 1);
-    }
-    if (!local) __threadfence();
-    __syncthreads();
-    // bin starts: exclusive scan of the counts from the bucket start
-    int carry = a;
-    for (int b0 = 0; b0 < nbr; b0 += kScanTile) {
-        const int base = b0 + (int)threadIdx.x * kScanItems;
-        int v[kScanItems];
-        int sum = 0;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            v[k] = base + k < nbr ? ctr_load(ctr + base + k, local) : 0;
-            sum += v[k];
-        }
-        int tot;
-        int ex = block_excl_scan(sum, red, &tot) + carry;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k)
-            if (base + k < nbr) {
-                bin_start[g0 + base + k] = ex;
-                ctr[base + k] = ex;
-                ex += v[k];
-            }
-        carry += tot;
-    }
-    if (r == n_rows && threadIdx.x == 0) bin_start[g0 + 1] = a + n;
-    if (!local) __threadfence();
-    __syncthreads();
-    for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
-        const int b = r < n_rows ? (bin_of(gz[j], s.z0, s.inv_bz, s.nbz) - z_lo) * s.nby +
-                                       bin_of(gy[j], s.y0, s.inv_by, s.nby)
-                                 : 0;
-        const int slot = atomicAdd(&ctr[b], 1);
-        gslot[slot] = j;
-        gbin[slot] = g0 + b;
-        // invalid rows keep their raw row value
-        gtag[slot] = (si << 8) | (r < n_rows ? r : (int)row[gid[j]]);
-    }
+    grid_bins_bucket(s, si, bk, n_rows, S, rstart, gy, gz, gid, row, bin_start, cnt, gslot, gbin,
+                     gtag, lds, red);
 }
 
 __global__ __launch_bounds__(kBlock) void k_grid_place(
@@ -248,19 +174,13 @@ __global__ __launch_bounds__(kBlock) void k_grid_place(
     int32_t* __restrict__ gsr)
 {
     for (int64_t q = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < c1;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int j = gslot[q];
-        const int g = gbin[q];
-        const int32_t id = gid[j];
-        const int32_t bs = bin_start[g], be = bin_start[g + 1];
-        int rank = 0;
-        for (int32_t u = bs; u < be; ++u) rank += gid[gslot[u]] < id;
-        const int32_t o = bs + rank;
-        yg[o] = gy[j];
-        zg[o] = gz[j];
-        idg[o] = id;
-        gsr[o] = gtag[q];
-    }
+         q += (int64_t)gridDim.x * blockDim.x)
+        grid_place_one(q, bin_start, gid, gy, gz, gslot, gbin, gtag, yg, zg, idg, gsr);
+}
+
+__global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) status->n_grid = n_grid;
 }
 
 // Build the grid of sectors [sec_lo, sec_hi).  The first call of an event

@@ -1,55 +1,116 @@
-// Per-item device code of the grid build, shared by the staged kernels and
-// the persistent kernel.
+// Device code of the grid build shared by the staged kernels (grid.hip) and
+// the persistent kernel: the bucket of a cluster (a z slab of its pad row),
+// the per-bucket bin sort of one block, and the final placement.
 #pragma once
-#include "tpc_internal.hpp"
+#include "block_dev.hpp"
 
 namespace tpc {
 
-__device__ __forceinline__ void grid_count_one(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    const float* __restrict__ y, const float* __restrict__ z, int64_t i,
-    int32_t* __restrict__ cnt, tpc_status* status)
+// bucket of a cluster inside its sector
+__device__ __forceinline__ int cluster_bucket(const tpc_sector& s, int n_rows, int S, int r,
+                                              float z)
 {
-    const int r = row[i];
-    if (r >= n_rows) atomicAdd((unsigned long long*)&status->n_bad_rows, 1ull);
-    const tpc_sector& s = sec[find_sector(sec, n_sec, i)];
-    atomicAdd(&cnt[global_bin(s, n_rows, r, y[i], z[i])], 1);
+    if (r >= n_rows) return n_rows * S;
+    const int iz = bin_of(z, s.z0, s.inv_bz, s.nbz);
+    return r * S + iz / slab_zbins(s);
 }
 
-__device__ __forceinline__ void grid_scatter_one(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    const float* __restrict__ y, const float* __restrict__ z, int64_t i,
-    const int32_t* __restrict__ bin_start, int32_t* __restrict__ fill, int32_t* __restrict__ tmp)
+__device__ __forceinline__ int ctr_load(const int* c, bool local)
 {
-    const tpc_sector& s = sec[find_sector(sec, n_sec, i)];
-    const int g = global_bin(s, n_rows, row[i], y[i], z[i]);
-    const int slot = atomicAdd(&fill[g], 1);
-    tmp[bin_start[g] + slot] = (int32_t)i;
+    return local ? c[0] : __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// final place of the cluster at staging position p: its bin start plus the
-// number of clusters of the bin with a smaller id
-__device__ __forceinline__ void grid_rank_one(
-    const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const uint8_t* __restrict__ row,
-    const float* __restrict__ y, const float* __restrict__ z,
-    const int32_t* __restrict__ bin_start, int64_t p, const int32_t* __restrict__ tmp,
-    float* __restrict__ yg, float* __restrict__ zg, int32_t* __restrict__ idg,
-    int32_t* __restrict__ gsr)
+// One block: bucket bk of sector si.  Counts the bucket's clusters per bin
+// (in LDS, lds[kRowBinsLds]; in the device-wide counters cnt when the
+// bucket has more bins), scans the counts into the bin starts and deals
+// every cluster a slot of its bin (any order inside a bin).
+__device__ __forceinline__ void grid_bins_bucket(
+    const tpc_sector& s, int si, int bk, int n_rows, int S, const int32_t* __restrict__ rstart,
+    const float* __restrict__ gy, const float* __restrict__ gz, const int32_t* __restrict__ gid,
+    const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start, int32_t* __restrict__ cnt,
+    int32_t* __restrict__ gslot, int32_t* __restrict__ gbin, int32_t* __restrict__ gtag,
+    int* lds, int* red)
 {
-    const int32_t id = tmp[p];
-    const int si = find_sector(sec, n_sec, id);
-    const tpc_sector& s = sec[si];
-    const int r = row[id];
-    const float yy = y[id], zz = z[id];
-    const int g = global_bin(s, n_rows, r, yy, zz);
+    const int Rb = (n_rows + 1) * S;
+    const int r = bk / S, slab = bk % S;
+    const int zs = slab_zbins(s);
+    if (slab >= (r < n_rows ? slab_count(s) : 1)) return;    // no such slab: no clusters
+    const int a = rstart[(int64_t)si * Rb + bk], n = rstart[(int64_t)si * Rb + bk + 1] - a;
+    const int per_row = s.nbz * s.nby;
+    const int z_lo = slab * zs;
+    const int z_hi = z_lo + zs < s.nbz ? z_lo + zs : s.nbz;
+    const int nbr = r < n_rows ? (z_hi - z_lo) * s.nby : 1;
+    const int g0 = s.bin_base + r * per_row + (r < n_rows ? z_lo * s.nby : 0);
+    const bool local = nbr <= kRowBinsLds;
+    int* ctr = local ? lds : cnt + g0;
+    for (int b = threadIdx.x; b < nbr; b += blockDim.x) ctr[b] = 0;
+    if (!local) __threadfence();
+    __syncthreads();
+    for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
+        const int b = r < n_rows ? (bin_of(gz[j], s.z0, s.inv_bz, s.nbz) - z_lo) * s.nby +
+                                       bin_of(gy[j], s.y0, s.inv_by, s.nby)
+                                 : 0;
+        atomicAdd(&ctr[b], 1);
+    }
+    if (!local) __threadfence();
+    __syncthreads();
+    // bin starts: exclusive scan of the counts from the bucket start
+    int carry = a;
+    for (int b0 = 0; b0 < nbr; b0 += kScanTile) {
+        const int base = b0 + (int)threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < nbr ? ctr_load(ctr + base + k, local) : 0;
+            sum += v[k];
+        }
+        int tot;
+        int ex = block_excl_scan(sum, red, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < nbr) {
+                bin_start[g0 + base + k] = ex;
+                ctr[base + k] = ex;
+                ex += v[k];
+            }
+        carry += tot;
+    }
+    if (r == n_rows && threadIdx.x == 0) bin_start[g0 + 1] = a + n;
+    if (!local) __threadfence();
+    __syncthreads();
+    for (int j = a + threadIdx.x; j < a + n; j += blockDim.x) {
+        const int b = r < n_rows ? (bin_of(gz[j], s.z0, s.inv_bz, s.nbz) - z_lo) * s.nby +
+                                       bin_of(gy[j], s.y0, s.inv_by, s.nby)
+                                 : 0;
+        const int slot = atomicAdd(&ctr[b], 1);
+        gslot[slot] = j;
+        gbin[slot] = g0 + b;
+        // invalid rows keep their raw row value
+        gtag[slot] = (si << 8) | (r < n_rows ? r : (int)row[gid[j]]);
+    }
+}
+
+// final place of the cluster at binned slot q: its bin start plus the number
+// of clusters of the bin with a smaller id
+__device__ __forceinline__ void grid_place_one(
+    int64_t q, const int32_t* __restrict__ bin_start, const int32_t* __restrict__ gid,
+    const float* __restrict__ gy, const float* __restrict__ gz,
+    const int32_t* __restrict__ gslot, const int32_t* __restrict__ gbin,
+    const int32_t* __restrict__ gtag, float* __restrict__ yg, float* __restrict__ zg,
+    int32_t* __restrict__ idg, int32_t* __restrict__ gsr)
+{
+    const int j = gslot[q];
+    const int g = gbin[q];
+    const int32_t id = gid[j];
     const int32_t bs = bin_start[g], be = bin_start[g + 1];
     int rank = 0;
-    for (int32_t q = bs; q < be; ++q) rank += tmp[q] < id;
+    for (int32_t u = bs; u < be; ++u) rank += gid[gslot[u]] < id;
     const int32_t o = bs + rank;
-    yg[o] = yy;
-    zg[o] = zz;
+    yg[o] = gy[j];
+    zg[o] = gz[j];
     idg[o] = id;
-    gsr[o] = (si << 8) | r;
+    gsr[o] = gtag[q];
 }
 
 }  // namespace tpc

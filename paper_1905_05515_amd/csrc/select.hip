@@ -7,14 +7,6 @@
 
 namespace tpc {
 
-// Ownership keys by (sector, chunk of kSelRows pad rows): a tracklet's hits
-// on those rows are grid positions of one contiguous range, so one block
-// keeps the range's keys in LDS (64-bit LDS atomic max, no device-wide
-// atomics), writes them out, and counts for every tracklet of the sector the
-// hits of the chunk it keeps.  A range larger than the LDS table uses the
-// device-wide keys instead.
-constexpr int kSelLds = 6144;
-
 // Sectors whose row chunks hold on average several times more positions
 // than the LDS table take the tracklet-parallel form with device-wide
 // atomics instead (same keys and counts): one block per chunk would loop
@@ -26,6 +18,7 @@ __host__ __device__ inline bool sel_big(const tpc_sector& s, int n_rows)
     return (s.end - s.begin) * (int64_t)kSelRows > (int64_t)(8 * kSelLds) * n_rows;
 }
 
+// one block per (sector, row chunk) of sectors [sec_lo, ...)
 __global__ __launch_bounds__(kBlock) void k_sel_chunk(
     const tpc_sector* __restrict__ sec, int sec_lo, int n_rows, tpc_params prm,
     const int32_t* __restrict__ bin_start, const int32_t* __restrict__ idg,
@@ -39,58 +32,18 @@ __global__ __launch_bounds__(kBlock) void k_sel_chunk(
     const int si = sec_lo + (int)(blockIdx.x / nq);
     const int q = (int)(blockIdx.x % nq);
     const tpc_sector s = sec[si];
-    const int ra = q * kSelRows, rb = ra + kSelRows < n_rows ? ra + kSelRows : n_rows;
-    const int per_row = s.nbz * s.nby;
-    const int p0 = bin_start[s.bin_base + ra * per_row];
-    const int np = bin_start[s.bin_base + rb * per_row] - p0;
-    int64_t lo = sec_start[si], hi = sec_start[si + 1];
-    if (hi > count_cap) hi = count_cap;
-    if (lo < 0) lo = 0;
-    if (lo > hi) lo = hi;
-    const bool local = np <= kSelLds;
     if (sel_big(s, n_rows)) {   // the tracklet-parallel kernels take this sector
+        const int ra = q * kSelRows, rb = ra + kSelRows < n_rows ? ra + kSelRows : n_rows;
+        const int per_row = s.nbz * s.nby;
+        const int p0 = bin_start[s.bin_base + ra * per_row];
+        const int np = bin_start[s.bin_base + rb * per_row] - p0;
         for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[p0 + k] = 0ull;
         return;
     }
-    for (int k = threadIdx.x; k < np; k += blockDim.x) {
-        if (local) kl[k] = 0ull;
-        else hitkey[p0 + k] = 0ull;
-    }
-    if (!local) __threadfence();
-    __syncthreads();
-    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        if (!key) continue;
-        int c[kSelRows];
-        load_chunk(t, ra, n_rows, t_hits, cap, c);
-#pragma unroll
-        for (int k = 0; k < kSelRows; ++k) {
-            const unsigned o = (unsigned)(c[k] - p0);
-            if (c[k] < 0 || o >= (unsigned)np) continue;
-            if (local) atomicMax(&kl[o], (unsigned long long)key);
-            else atomicMax(&hitkey[c[k]], (unsigned long long)key);
-        }
-    }
-    if (!local) __threadfence();
-    __syncthreads();
-    if (local)
-        for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[p0 + k] = kl[k];
-    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        int kept = 0;
-        if (key) {
-            int c[kSelRows];
-            load_chunk(t, ra, n_rows, t_hits, cap, c);
-#pragma unroll
-            for (int k = 0; k < kSelRows; ++k) {
-                const unsigned o = (unsigned)(c[k] - p0);
-                if (c[k] < 0 || o >= (unsigned)np) continue;
-                const unsigned long long h = local ? kl[o] : hitkey[c[k]];
-                kept += h == key;
-            }
-        }
-        ccnt[q * count_cap + t] = (uint8_t)kept;
-    }
+    int64_t lo = sec_start[si], hi = sec_start[si + 1];
+    if (lo < 0) lo = 0;
+    sel_chunk_block(s, q, n_rows, prm, bin_start, idg, t_start, t_hits, t_nhits, lo, hi,
+                    count_cap, cap, hitkey, ccnt, kl, kSelLds);
 }
 
 // Tracklet-parallel form for big sectors: item (t, blockIdx.y) handles rows

@@ -1,8 +1,6 @@
 // Device code of the tracklet selection, shared by the staged kernels and
 // the persistent kernel.  Every tracklet's rows are read in chunks of
-// kSelRows so that one item loads its chunk's hits at once; the staged
-// kernels give each (sector, chunk) a block, the persistent kernel walks all
-// chunks of a tracklet in one thread.
+// kSelRows so that one item loads its chunk's hits at once.
 #pragma once
 #include "tpc_internal.hpp"
 
@@ -92,47 +90,80 @@ __device__ __forceinline__ void sel_write_track(
     }
 }
 
-// ---- whole tracklet in one thread (persistent kernel) -----------------------
+// Ownership keys by (sector, chunk of kSelRows pad rows): a tracklet's hits
+// on those rows are grid positions of one contiguous range, so one block
+// keeps the range's keys in LDS (kl[lds_cap], 64-bit LDS atomic max, no
+// device-wide atomics), writes them out, and counts for every tracklet of
+// the sector the hits of the chunk it keeps (ccnt[q * count_cap + t]).  A
+// range larger than the LDS table uses the device-wide keys instead.
+constexpr int kSelLds = 6144;   // LDS table of the staged kernel
 
-__device__ __forceinline__ void sel_keys_one(
-    int64_t t, int n_rows, const tpc_params& prm, const int32_t* __restrict__ idg,
+// tracklets [lo, hi) of the sector
+__device__ __forceinline__ void sel_chunk_block(
+    const tpc_sector& s, int q, int n_rows, const tpc_params& prm,
+    const int32_t* __restrict__ bin_start, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, int64_t cap, unsigned long long* __restrict__ hitkey)
+    const int32_t* __restrict__ t_nhits, int64_t lo, int64_t hi, int64_t count_cap,
+    int64_t cap, unsigned long long* __restrict__ hitkey, uint8_t* __restrict__ ccnt,
+    unsigned long long* kl, int lds_cap)
 {
-    const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-    if (!key) return;
-    for (int ra = 0; ra < n_rows; ra += kSelRows)
-        sel_keys_chunk(t, ra, n_rows, key, t_hits, cap, hitkey);
+    const int ra = q * kSelRows, rb = ra + kSelRows < n_rows ? ra + kSelRows : n_rows;
+    const int per_row = s.nbz * s.nby;
+    const int p0 = bin_start[s.bin_base + ra * per_row];
+    const int np = bin_start[s.bin_base + rb * per_row] - p0;
+    if (hi > count_cap) hi = count_cap;
+    if (lo < 0) lo = 0;
+    if (lo > hi) lo = hi;
+    const bool local = np <= lds_cap;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+        if (local) kl[k] = 0ull;
+        else hitkey[p0 + k] = 0ull;
+    }
+    if (!local) __threadfence();
+    __syncthreads();
+    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        if (!key) continue;
+        int c[kSelRows];
+        load_chunk(t, ra, n_rows, t_hits, cap, c);
+#pragma unroll
+        for (int k = 0; k < kSelRows; ++k) {
+            const unsigned o = (unsigned)(c[k] - p0);
+            if (c[k] < 0 || o >= (unsigned)np) continue;
+            if (local) atomicMax(&kl[o], (unsigned long long)key);
+            else atomicMax(&hitkey[c[k]], (unsigned long long)key);
+        }
+    }
+    if (!local) __threadfence();
+    __syncthreads();
+    if (local)
+        for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[p0 + k] = kl[k];
+    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
+        int kept = 0;
+        if (key) {
+            int c[kSelRows];
+            load_chunk(t, ra, n_rows, t_hits, cap, c);
+#pragma unroll
+            for (int k = 0; k < kSelRows; ++k) {
+                const unsigned o = (unsigned)(c[k] - p0);
+                if (c[k] < 0 || o >= (unsigned)np) continue;
+                const unsigned long long h = local ? kl[o] : hitkey[c[k]];
+                kept += h == key;
+            }
+        }
+        ccnt[q * count_cap + t] = (uint8_t)kept;
+    }
 }
 
-// 1 << 32 | kept hits if tracklet t becomes a track, else 0
-__device__ __forceinline__ uint64_t sel_count_one(
-    int64_t t, int n_rows, const tpc_params& prm, const int32_t* __restrict__ idg,
+// the kept hits of tracklet t (cluster ids, row order) from hit offset o on
+__device__ __forceinline__ void sel_write_hits(
+    int64_t t, int64_t o, int n_rows, const tpc_params& prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, int64_t cap,
-    const unsigned long long* __restrict__ hitkey)
+    const unsigned long long* __restrict__ hitkey, int32_t* __restrict__ trk_hits,
+    int64_t hit_cap)
 {
-    const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-    if (!key) return 0ull;
-    int kept = 0;
-    for (int ra = 0; ra < n_rows; ra += kSelRows)
-        kept += sel_count_chunk(t, ra, n_rows, key, t_hits, cap, hitkey);
-    return kept >= prm.min_track_hits ? ((1ull << 32) | (uint64_t)kept) : 0ull;
-}
-
-// write track k = toff >> 32 of tracklet t at hit offset toff & (2^32 - 1)
-__device__ __forceinline__ void sel_write_one(
-    int64_t t, uint64_t toff, int n_rows, const tpc_params& prm,
-    const int32_t* __restrict__ idg, const int32_t* __restrict__ t_start,
-    const int32_t* __restrict__ t_hits, const int32_t* __restrict__ t_nhits, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, const tpc_sector* __restrict__ sec,
-    const int32_t* __restrict__ gsr, int32_t* __restrict__ trk_off,
-    int32_t* __restrict__ trk_hits, int32_t* __restrict__ trk_tracklet,
-    int8_t* __restrict__ trk_side, int64_t trk_cap, int64_t hit_cap)
-{
-    int64_t o = (int64_t)(toff & 0xFFFFFFFFull);
-    sel_write_track(t, (int64_t)(toff >> 32), o, t_start, sec, gsr, trk_off, trk_tracklet,
-                    trk_side, trk_cap);
     const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
     for (int ra = 0; ra < n_rows; ra += kSelRows)
         o = sel_write_chunk(t, ra, n_rows, key, o, idg, t_hits, cap, hitkey, trk_hits, hit_cap);

@@ -19,7 +19,7 @@ constexpr int kBlock = 256;          // threads per block of the streaming kerne
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kScanItems = 8;        // items per thread in the scans
 constexpr int kScanTile = kBlock * kScanItems;
-constexpr int kPhases = 14;          // phases of the persistent form
+constexpr int kPhases = 16;          // phases of the persistent form
 
 struct Workspace {
     tpc_status* status;
@@ -45,6 +45,8 @@ struct Workspace {
     int32_t* pq;           // persistent form: [1] queue head, [kPhases * n_sectors] done counts
     int64_t* scnt;         // persistent form: [n_sectors] starts per sector
     uint64_t* tsum;        // persistent form: [n_sectors] tracks << 32 | hits per sector
+    int64_t* ptile;        // persistent form: starts per counting tile
+    int32_t* pchunk;       // persistent form: [n_sectors] next tracklet chunk of each sector
     size_t bytes;
 };
 

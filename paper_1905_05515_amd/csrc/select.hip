@@ -46,45 +46,72 @@ __global__ __launch_bounds__(kBlock) void k_sel_chunk(
                     count_cap, cap, hitkey, ccnt, kl, kSelLds);
 }
 
-// Tracklet-parallel form for big sectors: item (t, blockIdx.y) handles rows
-// [8 y, 8 y + 8) of tracklet t, consecutive threads on consecutive
-// tracklets; tracklets of other sectors are left to k_sel_chunk.
+// Tracklet-parallel form for big sectors.  Keys: one thread per tracklet
+// claims its hits with device-wide 64-bit atomics, reading its rows upwards
+// from its innermost hit until all its hits are seen (every hit row lies in
+// [t_rin, last hit row]), and records that row span.  Tracklets of other
+// sectors are left to k_sel_chunk.
+constexpr uint16_t kSpanOther = 0xFFFE;   // tracklet of a sector that is not big
+constexpr uint16_t kSpanNone = 0xFFFF;    // takes no part in the selection
+
 __global__ __launch_bounds__(kBlock) void k_sel_keys_big(
     const tpc_sector* __restrict__ sec, int n_rows, tpc_params prm,
     const int32_t* __restrict__ idg, const int32_t* __restrict__ gsr,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
-    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
-    unsigned long long* __restrict__ hitkey)
+    const int32_t* __restrict__ t_nhits, const int32_t* __restrict__ t_rin,
+    const int64_t* __restrict__ t_lo, const int64_t* __restrict__ t_hi, int64_t count_cap,
+    int64_t cap, unsigned long long* __restrict__ hitkey, uint16_t* __restrict__ tspan)
 {
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
-    const int ra = blockIdx.y * kSelRows;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
          t += (int64_t)gridDim.x * blockDim.x) {
-        if (!sel_big(sec[gsr[t_start[t]] >> 8], n_rows)) continue;
+        if (!sel_big(sec[gsr[t_start[t]] >> 8], n_rows)) {
+            tspan[t] = kSpanOther;
+            continue;
+        }
         const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        if (key) sel_keys_chunk(t, ra, n_rows, key, t_hits, cap, hitkey);
+        const int nh = t_nhits[t];
+        int r = t_rin[t];
+        if (!key || r < 0 || r >= n_rows) {
+            tspan[t] = kSpanNone;
+            continue;
+        }
+        const int first = r;
+        int last = r, seen = 0;
+        for (; r < n_rows && seen < nh; ++r) {
+            const int h = t_hits[(int64_t)r * cap + t];
+            if (h < 0) continue;
+            atomicMax(&hitkey[h], (unsigned long long)key);
+            ++seen;
+            last = r;
+        }
+        tspan[t] = (uint16_t)(first | (last << 8));
     }
 }
 
+// Counts: item (t, blockIdx.y) handles rows [8 y, 8 y + 8) of tracklet t;
+// a chunk outside the tracklet's row span is zero without a load.
 __global__ __launch_bounds__(kBlock) void k_sel_count_big(
-    const tpc_sector* __restrict__ sec, int n_rows, tpc_params prm,
-    const int32_t* __restrict__ idg, const int32_t* __restrict__ gsr,
+    int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
     const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, uint8_t* __restrict__ ccnt)
+    const unsigned long long* __restrict__ hitkey, const uint16_t* __restrict__ tspan,
+    uint8_t* __restrict__ ccnt)
 {
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
     const int ra = blockIdx.y * kSelRows;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
          t += (int64_t)gridDim.x * blockDim.x) {
-        if (!sel_big(sec[gsr[t_start[t]] >> 8], n_rows)) continue;
-        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        ccnt[blockIdx.y * count_cap + t] =
-            key ? (uint8_t)sel_count_chunk(t, ra, n_rows, key, t_hits, cap, hitkey) : 0;
+        const int sp = tspan[t];
+        if (sp == kSpanOther) continue;
+        int kept = 0;
+        if (sp != kSpanNone && ra + kSelRows > (sp & 255) && ra <= (sp >> 8))
+            kept = sel_count_chunk(t, ra, n_rows, key_of(t, prm, idg, t_start, t_nhits), t_hits,
+                                   cap, hitkey);
+        ccnt[blockIdx.y * count_cap + t] = (uint8_t)kept;
     }
 }
 
@@ -167,16 +194,16 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
     bool any_big = false;
     for (int s = sec_lo; s < sec_hi && !any_big; ++s) any_big = sel_big(p->h_sectors[s], p->n_rows);
     if (any_big) {
-        TPC_LAUNCH(k_sel_keys_big, dim3(gx, nq), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
+        TPC_LAUNCH(k_sel_keys_big, dim3(gx), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
                    p->params, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
                    (const int32_t*)trl.start, (const int32_t*)trl.hits,
-                   (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
-                   (unsigned long long*)ws.hitkey);
-        TPC_LAUNCH(k_sel_count_big, dim3(gx, nq), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
-                   p->params, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
-                   (const int32_t*)trl.start, (const int32_t*)trl.hits,
-                   (const int32_t*)trl.nhits, lo, hi, count_cap, trl.capacity,
-                   (const unsigned long long*)ws.hitkey, ws.ccnt);
+                   (const int32_t*)trl.nhits, (const int32_t*)trl.row_inner, lo, hi, count_cap,
+                   trl.capacity, (unsigned long long*)ws.hitkey, ws.tspan);
+        TPC_LAUNCH(k_sel_count_big, dim3(gx, nq), dim3(kBlock), 0, st, p->n_rows, p->params,
+                   (const int32_t*)grid.id, (const int32_t*)trl.start,
+                   (const int32_t*)trl.hits, (const int32_t*)trl.nhits, lo, hi, count_cap,
+                   trl.capacity, (const unsigned long long*)ws.hitkey,
+                   (const uint16_t*)ws.tspan, ws.ccnt);
     }
     TPC_LAUNCH(k_sel_len, dim3(gx), dim3(kBlock), 0, st, nq, p->params, lo, hi, count_cap,
                (const uint8_t*)ws.ccnt, ws.tlen);

@@ -31,6 +31,7 @@ struct Workspace {
     uint64_t* tlen;        // [start_cap + 1] per tracklet: accepted << 32 | kept
     uint64_t* toff;        // [start_cap + 1] exclusive scan of tlen
     uint8_t* ccnt;         // [row chunks * start_cap] kept hits per tracklet and row chunk
+    uint16_t* tspan;       // [start_cap] selection, big sectors: hit rows first | last << 8
     // grid build: clusters per (sector, row bucket), their running fill and
     // starts; the row-partitioned copy of the clusters; the binned order
     int32_t* rcnt;         // [n_sectors * (n_rows + 1) * S]

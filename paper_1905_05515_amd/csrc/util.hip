@@ -180,6 +180,7 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));
     ws->toff = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 2));
     ws->ccnt = (uint8_t*)take((size_t)sel_chunks(p->n_rows) * (size_t)(start_cap > 0 ? start_cap : 1));
+    ws->tspan = (uint16_t*)take(sizeof(uint16_t) * (size_t)(start_cap > 0 ? start_cap : 1));
     ws->bytes = o;
     return true;
 }

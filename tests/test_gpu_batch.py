@@ -94,3 +94,23 @@ def test_batched_uneven_instances_full_size():
     _same(r[("staged", True)], r[("persistent", True)])
     o = run_oracle(ev)
     assert_same_tracking(r[("staged", True)], o, ev.n_clusters)
+
+
+@pytest.mark.timeout(600)
+def test_persistent_tile_scales():
+    """The persistent form grows its tiles with the clusters per resident
+    block (scale 1, 2 or 4).  The central event and the full 512-instance set
+    cover the smallest and the largest scale on this part; the first
+    instances of the set, about 4.5M clusters, the middle one.  Every scale
+    gives the staged form's outputs."""
+    ev = synth.make_config4()
+    k = int(np.searchsorted(ev.sector_offsets, 4_500_000))
+    n = int(ev.sector_offsets[k])
+    sub = synth.Event(ev.row[:n], ev.y[:n], ev.z[:n], ev.charge[:n],
+                      ev.sector_offsets[:k + 1].copy(), ev.sector_range[:k].copy(), ev.row_x,
+                      ev.label[:n], ev.tracks, {}, ev.sector_side[:k].copy())
+    print(f"case c4 first {k} instances n={n}", flush=True)
+    r = _forms(sub, [("staged", False), ("persistent", False), ("persistent", True)])
+    assert r[("persistent", False)]["status"]["overflow"] == 0
+    _same(r[("staged", False)], r[("persistent", False)])
+    _same(r[("staged", False)], r[("persistent", True)])

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from gpu_common import assert_same_tracking, ctx
+from gpu_common import assert_same_tracking, ctx, run_gpu, run_oracle
 from paper_1905_05515_amd import api
 from paper_1905_05515_amd.layout import grid_layout
 
@@ -121,3 +121,25 @@ def test_sampled_sectors_match_the_oracle(slice_run, s):
     g["status"]["n_propagations"], g["status"]["n_updates"], g["status"]["n_candidates"] = \
         o["tracklets"]["work"]
     assert_same_tracking(g, o, sub.n_clusters)
+
+
+@pytest.mark.timeout(600)
+def test_big_sector_between_small_ones(slice_run):
+    """A sector of the slice (millions of clusters: the selection takes its
+    tracklet-parallel form there) between two central-event sectors (row
+    chunks in LDS) in one problem: staged and per-sector launches equal the
+    oracle."""
+    ev3 = slice_run[0]
+    ev2 = synth.make_config2()
+    parts = [ev2.sector(0), ev3.sector(SAMPLED_SECTORS[0]), ev2.sector(1)]
+    cat = lambda f: np.concatenate([getattr(p, f) for p in parts])
+    offs = np.concatenate([[0], np.cumsum([p.n_clusters for p in parts])]).astype(np.int64)
+    ev = synth.Event(cat("row"), cat("y"), cat("z"), cat("charge"), offs,
+                     np.concatenate([p.sector_range for p in parts]), ev2.row_x, cat("label"),
+                     ev2.tracks, {}, cat("sector_side"))
+    print(f"case mixed sectors n={ev.n_clusters} sizes={np.diff(offs).tolist()}", flush=True)
+    o = run_oracle(ev)
+    for mode in ("staged", "per_sector"):
+        _, g = run_gpu(ev, mode=mode)
+        assert g["status"]["overflow"] == 0
+        assert_same_tracking(g, o, ev.n_clusters)

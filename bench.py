@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference size for scaling the HBM byte counters) and exit")
+    ap.add_argument("--seeding-probe", action="store_true",
+                    help="only build the grid and find the chain starts of the 512-instance "
+                         "set three times (eager launches; the workload of the HBM byte "
+                         "counters of those stages) and exit")
     ap.add_argument("--occupancy", default="auto",
                     help="clusters per grid bin, or 'auto' (autotuned per workload before "
                          "the timed region; the tracks do not depend on it)")
@@ -99,6 +103,18 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] copied {4 * n} bytes 3 times")
+        return
+    if args.seeding_probe:
+        ev = synth.make_config4()
+        occ = 0.125 if args.occupancy == "auto" else float(args.occupancy)
+        e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x,
+                           synth.default_params(), occupancy=occ, sector_side=ev.sector_side)
+        ctx = api.Context(0)
+        for _ in range(3):
+            api.build_grid(ctx, e)
+            api.find_neighbours(ctx, e)
+        torch.cuda.synchronize()
+        log(f"[bench] grid and starts of {ev.n_clusters} clusters, occupancy {occ}, 3 times")
         return
     dev = torch.device("cuda:0")
     t0 = time.time()
@@ -260,6 +276,9 @@ KERNEL_SOURCES = {
     "k_tracklets": ["tracklets.hip", "tracklet_dev.hpp", "tpc_internal.hpp"],
     "k_refit_fwd": ["refit.hip", "tpc_internal.hpp"],
     "k_refit_adj": ["refit.hip", "tpc_internal.hpp"],
+    # every kernel that tpc_build_grid and tpc_find_neighbours launch
+    "grid_to_starts": ["grid.hip", "grid_dev.hpp", "neighbours.hip", "seed_dev.hpp",
+                       "block_dev.hpp", "util.hip", "tpc_internal.hpp"],
 }
 
 
@@ -351,7 +370,7 @@ def batch_bench(args, api, synth, ctx, stream, prm):
     res["staged_kernels_us"] = {k: round(v * 1e3, 1) for k, v in
                                 sorted(per.items(), key=lambda kv: -kv[1])}
     res["roofline_grid_to_starts"] = seeding_roofline(api, ctx, e, stream, steps,
-                                                      ev.n_clusters)
+                                                      ev.n_clusters, "batched_set")
     log(f"[bench]   grid..starts {res['roofline_grid_to_starts']['ms'] * 1e3:.1f} us, "
         f"{res['roofline_grid_to_starts']['frac'] * 100:.1f}% of HBM peak at "
         f"{SEEDING_BYTES_PER_CLUSTER} B/cluster")
@@ -361,7 +380,7 @@ def batch_bench(args, api, synth, ctx, stream, prm):
     return res
 
 
-def seeding_roofline(api, ctx, e, stream, steps, n_clusters):
+def seeding_roofline(api, ctx, e, stream, steps, n_clusters, workload=None):
     """Grid build to chain starts alone (tpc_build_grid + tpc_find_neighbours,
     eager launches, HIP events) against the HBM peak."""
     import torch
@@ -382,7 +401,8 @@ def seeding_roofline(api, ctx, e, stream, steps, n_clusters):
                                        "cleaning, starts), eager launches",
             "achieved": by / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": ms,
-            "algorithmic_bytes_per_cluster": SEEDING_BYTES_PER_CLUSTER}
+            "algorithmic_bytes_per_cluster": SEEDING_BYTES_PER_CLUSTER,
+            "traffic": counter_traffic("grid_to_starts", workload) if workload else None}
 
 
 def slice_bench(args, api, synth, ctx, stream, prm):

@@ -130,6 +130,8 @@ __device__ __forceinline__ void reset_cov(KState& st, const tpc_params& prm)
     st.C[14] = prm.c_ww0;
 }
 
+constexpr int kCandBatch = 4;   // candidate loads issued together
+
 // Hit of least predicted chi2 <= chi2_max on row r of sector s, ties to the
 // lower cluster id; -1 if none, else its grid position with its coordinates
 // in (my, mz).  The bins scanned cover +-nsigma of the prediction (every hit
@@ -161,19 +163,36 @@ __device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s,
             lo[1] = bin_start[g + s.nby + iy0];
             hi[1] = bin_start[g + s.nby + iy1 + 1];
         }
+        // the candidates of both z rows as one stream (row iz first, each in
+        // grid order: the order of evaluation decides nothing but ties,
+        // which go to the lower id anyway), loaded kCandBatch at a time so
+        // that one memory round trip serves several candidates
+        const int n0 = hi[0] - lo[0] > 0 ? hi[0] - lo[0] : 0;
+        const int n1 = hi[1] - lo[1] > 0 ? hi[1] - lo[1] : 0;
+        n_cand += n0 + n1;
+        for (int b = 0; b < n0 + n1; b += kCandBatch) {
+            float yb[kCandBatch], zb[kCandBatch];
+            int pb[kCandBatch];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            n_cand += hi[k] - lo[k] > 0 ? hi[k] - lo[k] : 0;
-            for (int pc = lo[k]; pc < hi[k]; ++pc) {
-                const float y = yg[pc], z = zg[pc];
-                const float c2 = chi2_pred(st, y, z, prm.sigma_y2, prm.sigma_z2);
+            for (int j = 0; j < kCandBatch; ++j) {
+                const int e = b + j;
+                pb[j] = e < n0 ? lo[0] + e : lo[1] + (e - n0);
+                if (e < n0 + n1) {
+                    yb[j] = yg[pb[j]];
+                    zb[j] = zg[pb[j]];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kCandBatch; ++j) {
+                if (b + j >= n0 + n1) break;
+                const float c2 = chi2_pred(st, yb[j], zb[j], prm.sigma_y2, prm.sigma_z2);
                 if (!(c2 <= prm.chi2_max)) continue;
                 // equal chi2 (rare): the lower cluster id wins
-                if (bpos < 0 || c2 < best || (c2 == best && idg[pc] < idg[bpos])) {
+                if (bpos < 0 || c2 < best || (c2 == best && idg[pb[j]] < idg[bpos])) {
                     best = c2;
-                    bpos = pc;
-                    my = y;
-                    mz = z;
+                    bpos = pb[j];
+                    my = yb[j];
+                    mz = zb[j];
                 }
             }
         }

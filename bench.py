@@ -60,6 +60,9 @@ def parse():
                     help="only build the grid and find the chain starts of the 512-instance "
                          "set three times (eager launches; the workload of the HBM byte "
                          "counters of those stages) and exit")
+    ap.add_argument("--inflight", default="auto",
+                    help="events in flight in the timed step loop (each on its own stream "
+                         "with its own buffers), or 'auto' (1-3, the fastest; the box runs four hardware queues per process)")
     ap.add_argument("--occupancy", default="auto",
                     help="clusters per grid bin, or 'auto' (autotuned per workload before "
                          "the timed region; the tracks do not depend on it)")
@@ -127,43 +130,98 @@ def main():
                        sector_side=ev.sector_side)
     tuned = pick_layout(args, api, ctx, e, stream)
     th = torch.as_tensor(synth.make_config5(n_tracks=1).theta_eval).to(dev)
-    hits = api.found_track_hits(e)
     gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
-    bufs = {"fwd": None, "adj": {}}
 
-    def step(graph=True):
-        api.track_batch(ctx, e, mode="staged", use_graph=graph, stream=stream)
-        bufs["fwd"] = api.refit(ctx, hits, e.t["row_x"], prm, th, stream=stream, out=bufs["fwd"])
-        api.refit_adjoint(ctx, hits, e.t["row_x"], prm, th, bufs["fwd"], gchi2, stream=stream,
-                          out=bufs["adj"])
+    # Events in flight: lane k owns an event's buffers, a context (whose
+    # cached graph is that event's) and a stream; step i runs on lane
+    # i % depth.  A lane's steps follow each other on its stream, so no
+    # buffer is shared between steps in flight; lanes overlap on the GPU (one
+    # central event keeps only a fraction of the chip busy).
+    lanes = [dict(ctx=ctx, e=e, stream=stream, hits=api.found_track_hits(e),
+                  fwd=None, adj={})]
 
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step()
+    def lane(k):
+        while len(lanes) <= k:
+            e_k = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range,
+                                 ev.row_x, prm, sector_side=ev.sector_side)
+            api.relayout(e_k, tuned["occupancy"])
+            lanes.append(dict(ctx=api.Context(0), e=e_k, stream=torch.cuda.Stream(),
+                              hits=api.found_track_hits(e_k), fwd=None, adj={}))
+        return lanes[k]
+
+    def step(L, graph=True):
+        with torch.cuda.stream(L["stream"]):
+            api.track_batch(L["ctx"], L["e"], mode="staged", use_graph=graph,
+                            stream=L["stream"])
+            L["fwd"] = api.refit(L["ctx"], L["hits"], L["e"].t["row_x"], prm, th,
+                                 stream=L["stream"], out=L["fwd"])
+            api.refit_adjoint(L["ctx"], L["hits"], L["e"].t["row_x"], prm, th, L["fwd"], gchi2,
+                              stream=L["stream"], out=L["adj"])
+
+    def run(depth, n_steps):
+        """n_steps steps over `depth` lanes; GPU ms between two events that
+        bracket all of them, and host wall seconds."""
+        ls = [lane(k) for k in range(depth)]
         torch.cuda.synchronize()
-        # timed region 1: graph replay of the tracking + refit + adjoint
-        t_start = time.perf_counter()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(args.steps):
-            step()
-        ev1.record(stream)
+        t0 = time.perf_counter()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(ls[0]["stream"])
+        for L in ls[1:]:
+            L["stream"].wait_event(a)
+        for i in range(n_steps):
+            step(ls[i % depth])
+        for L in ls[1:]:
+            done = torch.cuda.Event()
+            done.record(L["stream"])
+            ls[0]["stream"].wait_event(done)
+        b.record(ls[0]["stream"])
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t_start
-        gpu_ms = ev0.elapsed_time(ev1)
+        return a.elapsed_time(b), time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        step(lanes[0])
+    torch.cuda.synchronize()
+    # one event at a time: the latency of a step
+    lat_ms = run(1, args.steps)[0] / args.steps
+    if args.inflight == "auto":
+        tried = {}
+        for d in (1, 2, 3):
+            run(d, 2 * d)                               # warm-up (graph capture per lane)
+            tried[d] = run(d, max(args.steps // 2, 2 * d))[0] / max(args.steps // 2, 2 * d)
+        depth = min(tried, key=tried.get)
+        log(f"[bench] events in flight: {depth} "
+            f"({', '.join(f'{d}: {v:.3f} ms' for d, v in tried.items())})")
+    else:
+        depth = int(args.inflight)
+        tried = None
+        run(depth, 2 * depth)
+    # timed region 1: graph replay of the tracking + refit + adjoint
+    gpu_ms, wall = run(depth, args.steps)
+    # every lane produced the same tracks
+    same = True
+    ref = None
+    for L in lanes[:depth]:
+        r = api.results(L["e"], L["stream"])
+        key = (r["trk_off"].tobytes(), r["trk_hits"].tobytes())
+        ref = key if ref is None else ref
+        same &= key == ref
     st = api.get_status(e, stream)
     ms_per_step = gpu_ms / args.steps
-    log(f"[bench] step {ms_per_step:.3f} ms (wall {1e3 * wall / args.steps:.3f} ms), "
-        f"tracks {st['n_tracks']}, starts {st['n_starts']}")
+    log(f"[bench] step {ms_per_step:.3f} ms with {depth} in flight (wall "
+        f"{1e3 * wall / args.steps:.3f} ms; one at a time {lat_ms:.3f} ms), "
+        f"tracks {st['n_tracks']}, starts {st['n_starts']}, lanes equal {same}")
+
+    def step_eager():
+        step(lanes[0], graph=False)
 
     # timed region 2: the same step with eager launches and per-kernel events
     with torch.cuda.stream(stream):
-        step(graph=False)
+        step_eager()
         torch.cuda.synchronize()
         api.timing_enable(ctx, True)
         for _ in range(args.steps):
-            step(graph=False)
+            step_eager()
         torch.cuda.synchronize()
         kt = api.timing_report(ctx)
         api.timing_enable(ctx, False)
@@ -212,6 +270,11 @@ def main():
             "tracks_found": int(st["n_tracks"]),
             "track_hits": n_hits_trk,
             "launch_form": "staged stages over all sectors, HIP graph",
+            "events_in_flight": depth,
+            "events_in_flight_tried_ms": ({str(k): round(v, 4) for k, v in tried.items()}
+                                          if tried else None),
+            "ms_per_step_one_at_a_time": lat_ms,
+            "lanes_equal_output": bool(same),
             "grid_layout": tuned,
             "parallelism": "single GPU",
         },

@@ -163,6 +163,33 @@ def select_tracks(n_clusters, prm, tracklets, starts, n_rows=152):
     return dict(trk_off=off, trk_hits=th[:off[-1]].copy(), trk_tracklet=tt[:nt].copy())
 
 
+def attach_clusters(sector_offsets, row, y, z, row_x, prm, trk_off, trk_hits, par, rin,
+                    radius=1.5, pt_good=0.05, n_rows=152):
+    """Track-based cluster attachment (section 5).  par/rin: the state of
+    each track (5 floats at the plane of row rin).  Returns (track, state)
+    per cluster id: owning or adjacent track (-1 none); state bits 1
+    attached, 2 adjacent, 4 protected, 8 removed."""
+    L = lib()
+    offs = np.ascontiguousarray(sector_offsets, np.int64)
+    n = row.shape[0]
+    nt = trk_off.shape[0] - 1
+    track = np.empty(max(n, 1), np.int32)
+    state = np.empty(max(n, 1), np.uint8)
+    P = params(prm)
+    w_good = np.float32(1.0) / np.float32(pt_good)
+    L.orc_attach_clusters(C.c_int(offs.shape[0] - 1), _p(offs), C.c_int(n_rows),
+                          _p(np.ascontiguousarray(row_x, np.float32)), C.byref(P),
+                          _p(np.ascontiguousarray(row, np.uint8)),
+                          _p(np.ascontiguousarray(y, np.float32)),
+                          _p(np.ascontiguousarray(z, np.float32)), C.c_int64(n), C.c_int64(nt),
+                          _p(np.ascontiguousarray(trk_off, np.int32)),
+                          _p(np.ascontiguousarray(trk_hits, np.int32)),
+                          _p(np.ascontiguousarray(par, np.float32)),
+                          _p(np.ascontiguousarray(rin, np.int32)), C.c_float(radius),
+                          C.c_float(w_good), _p(track), _p(state))
+    return track[:n], state[:n]
+
+
 def track_event(row, y, z, layout, n_bins, row_x, prm, n_rows=152, brute=False):
     """The whole chain: grid, neighbours, cleaning, starts, tracklets,
     selection.  Returns a dict of every intermediate (id space)."""

@@ -635,3 +635,96 @@ void orc_calibrate64(const double* th, double xr, double yr, double zr, double s
     calibrate_d(th, xr, yr, zr, side, cm->drift_len, cm->vd, cm->tan_half, cm->u_centre,
                 cm->u_scale, out3, out3 + 1, out3 + 2);
 }
+
+/* ---- track-based cluster attachment (section 5, cluster rejection) -------
+ * The tracker lays a tube of fixed radius around every track and marks each
+ * cluster that no track owns as adjacent to the track of highest transverse
+ * momentum whose tube holds it.  Readings: the tube of track k covers the
+ * pad rows from its first to its last hit; at row r its axis is the point
+ * (y_r, z_r) of the track's state (at the plane of row rin[k], the output of
+ * the inward pass) transported outwards row by row (the tracker's own
+ * transport, stopping where |sin(phi)| reaches s_max); a cluster of the
+ * track's sector on row r lies in the tube when dy*dy + dz*dz <= radius^2
+ * (float32, in that order).  Highest pT = least |q/pT|, ties to the lower
+ * track index.  Protected: in the tube of, or attached to, a track with
+ * |q/pT| <= w_good; removed: attached or adjacent and not protected.
+ * Brute force over the clusters of each row of the sector.
+ * track[c]: owning track, else the adjacent track, else -1;
+ * state[c]: 1 attached, 2 adjacent, | 4 protected, | 8 removed. */
+void orc_attach_clusters(int n_sec, const int64_t* sector_offsets, int n_rows,
+                         const float* row_x, const orc_params* prm, const uint8_t* row,
+                         const float* y, const float* z, int64_t n_clusters, int64_t n_tracks,
+                         const int* trk_off, const int* trk_hits, const float* par,
+                         const int* rin, float radius, float w_good, int* track,
+                         uint8_t* state)
+{
+    const float r2 = radius * radius;
+    /* clusters of every (sector, row), in id order */
+    int64_t n_lists = (int64_t)n_sec * n_rows;
+    int64_t* first = (int64_t*)calloc((size_t)n_lists + 1, sizeof(int64_t));
+    int64_t* members = (int64_t*)malloc((size_t)(n_clusters > 0 ? n_clusters : 1) * sizeof(int64_t));
+    int64_t* fill = (int64_t*)calloc((size_t)n_lists + 1, sizeof(int64_t));
+    float* best_w = (float*)malloc((size_t)(n_clusters > 0 ? n_clusters : 1) * sizeof(float));
+    int s = 0;
+    for (int64_t c = 0; c < n_clusters; c++) {
+        while (s + 1 < n_sec && c >= sector_offsets[s + 1]) s++;
+        if (row[c] < n_rows) first[(int64_t)s * n_rows + row[c] + 1]++;
+    }
+    for (int64_t k = 0; k < n_lists; k++) first[k + 1] += first[k];
+    s = 0;
+    for (int64_t c = 0; c < n_clusters; c++) {
+        while (s + 1 < n_sec && c >= sector_offsets[s + 1]) s++;
+        if (row[c] < n_rows) {
+            int64_t l = (int64_t)s * n_rows + row[c];
+            members[first[l] + fill[l]++] = c;
+        }
+    }
+    for (int64_t c = 0; c < n_clusters; c++) {
+        track[c] = -1;
+        state[c] = 0;
+        best_w[c] = 0.0f;
+    }
+    for (int64_t k = 0; k < n_tracks; k++)
+        for (int i = trk_off[k]; i < trk_off[k + 1]; i++) {
+            track[trk_hits[i]] = (int)k;
+            state[trk_hits[i]] = 1;
+        }
+    for (int64_t k = 0; k < n_tracks; k++) {
+        if (trk_off[k + 1] <= trk_off[k]) continue;
+        int c0 = trk_hits[trk_off[k]];
+        int sk = 0;
+        while (sk + 1 < n_sec && c0 >= sector_offsets[sk + 1]) sk++;
+        int r_first = row[c0], r_last = row[trk_hits[trk_off[k + 1] - 1]];
+        float p[5], C[15];
+        for (int i = 0; i < 5; i++) p[i] = par[5 * k + i];
+        for (int i = 0; i < 15; i++) C[i] = 0.0f;
+        float w = fabsf(p[4]);
+        int good = w <= w_good;
+        for (int r = rin[k]; r <= r_last; r++) {
+            if (r > rin[k] && !propagate_f(p, C, row_x[r] - row_x[r - 1], prm->curv, prm->s_max))
+                break;
+            if (r < r_first) continue;
+            int64_t l = (int64_t)sk * n_rows + r;
+            for (int64_t m = first[l]; m < first[l + 1]; m++) {
+                int64_t c = members[m];
+                float dy = y[c] - p[0], dz = z[c] - p[1];
+                if (!(dy * dy + dz * dz <= r2)) continue;
+                if (good) state[c] |= 4;
+                if (state[c] & 1) continue;
+                if (track[c] < 0 || w < best_w[c] || (w == best_w[c] && (int)k < track[c])) {
+                    track[c] = (int)k;
+                    best_w[c] = w;
+                }
+            }
+        }
+    }
+    for (int64_t c = 0; c < n_clusters; c++) {
+        if (track[c] >= 0 && !(state[c] & 1)) state[c] |= 2;
+        if ((state[c] & 1) && fabsf(par[5 * track[c] + 4]) <= w_good) state[c] |= 4;
+        if ((state[c] & 3) && !(state[c] & 4)) state[c] |= 8;
+    }
+    free(first);
+    free(members);
+    free(fill);
+    free(best_w);
+}

@@ -131,6 +131,20 @@ void orc_refit64_fd_grad(int64_t n_tracks, const int* trk_off, const uint8_t* ro
                          const double* g, double h_hit, double h_theta,
                          double* grad_y, double* grad_z, double* grad_theta);
 
+/* Track-based cluster attachment (section 5): tube of `radius` around
+ * every track over the rows of its hits, its axis the track state par[5k]
+ * (at the plane of row rin[k]) transported outwards row by row; unowned
+ * clusters in a tube are adjacent to the track of least |q/pT| (ties to the
+ * lower index).  track[c]: owning or adjacent track, else -1; state[c]: 1
+ * attached, 2 adjacent, |4 protected (tube or track of |q/pT| <= w_good),
+ * |8 removed (attached or adjacent, not protected). */
+void orc_attach_clusters(int n_sec, const int64_t* sector_offsets, int n_rows,
+                         const float* row_x, const orc_params* prm, const uint8_t* row,
+                         const float* y, const float* z, int64_t n_clusters, int64_t n_tracks,
+                         const int* trk_off, const int* trk_hits, const float* par,
+                         const int* rin, float radius, float w_good, int* track,
+                         uint8_t* state);
+
 /* Single steps, exposed for the tests. */
 int orc_propagate32(float* p, float* C, float dx, float curv, float s_max);
 int orc_propagate64(double* p, double* C, double dx, double curv, double s_max);

@@ -82,7 +82,12 @@ __global__ __launch_bounds__(kBlock) void k_sel_keys_big(
         for (; r < n_rows && seen < nh; ++r) {
             const int h = t_hits[(int64_t)r * cap + t];
             if (h < 0) continue;
-            atomicMax(&hitkey[h], (unsigned long long)key);
+            // keys only grow: a value seen here is a lower bound of the
+            // current one, so a hit that already holds a key >= ours needs
+            // no atomic (most hits are claimed by several tracklets)
+            const unsigned long long seen_key =
+                __hip_atomic_load(&hitkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (seen_key < key) atomicMax(&hitkey[h], (unsigned long long)key);
             ++seen;
             last = r;
         }

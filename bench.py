@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-batch-bench", action="store_true")
     ap.add_argument("--no-slice-bench", action="store_true",
                     help="skip the continuous read-out slice (100 collisions)")
+    ap.add_argument("--no-attach-bench", action="store_true",
+                    help="skip the track-based cluster attachment of the central event")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference size for scaling the HBM byte counters) and exit")
@@ -239,6 +241,8 @@ def main():
     roof["source_sha256"] = source_hash(dom.split("<")[0])
 
     extra = {}
+    if not args.no_attach_bench:
+        extra["cluster_attachment"] = attach_bench(args, api, ctx, e, ev, stream)
     if not args.no_batch_bench:
         extra["batched_vs_per_sector"] = batch_bench(args, api, synth, ctx, stream, prm)
     if not args.no_slice_bench:
@@ -440,6 +444,64 @@ def batch_bench(args, api, synth, ctx, stream, prm):
     res["workload"] = ("512 single-sector instances, half pp-like (20-200 tracks), half "
                        "Pb-Pb-like (50-800), log-uniform, shuffled (seed 40040000)")
     res["clusters"] = ev.n_clusters
+    return res
+
+
+def attach_bench(args, api, ctx, e, ev, stream):
+    """Track-based cluster attachment (1.5 cm tubes) of the central event's
+    found tracks: time per event, per-kernel times, the tube kernel against
+    the ALU ceiling (transport operations counted from the tracks' row
+    spans), and the attachment figures with truth-label fake rates."""
+    import numpy as np
+    import torch
+    steps = max(args.steps, 2)
+    with torch.cuda.stream(stream):
+        api.track_batch(ctx, e, mode="staged", use_graph=False, stream=stream)
+        api.attach_clusters(ctx, e, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            track, state = api.attach_clusters(ctx, e, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        api.timing_enable(ctx, True)
+        for _ in range(steps):
+            api.attach_clusters(ctx, e, stream=stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    per = {k: ms_ / n for k, (n, ms_) in kt.items()}
+    r = api.results(e, stream)
+    track = track.cpu().numpy()
+    state = state.cpu().numpy()
+    off, hits, tt = r["trk_off"], r["trk_hits"], r["trk_tracklet"]
+    nt = len(off) - 1
+    last_row = ev.row[hits[off[1:] - 1]].astype(np.int64) if nt else np.zeros(0, np.int64)
+    rows = int(np.sum(np.maximum(last_row - r["t_rin"][tt], 0))) if nt else 0
+    tube_ms = per.get("k_attach_tube", ms)
+    fl = FLOPS_PROPAGATE * rows
+    maj = np.array([np.bincount(np.maximum(ev.label[hits[off[k]:off[k + 1]]], 0)).argmax()
+                    for k in range(nt)], np.int64)
+    att, adj = (state & 1) != 0, (state & 2) != 0
+    fake = lambda m: float(np.mean(ev.label[m] != maj[track[m]])) if m.any() else None
+    res = {"workload": "tubes of 1.5 cm around the found tracks of the central event, "
+                       "protection above 0.05 GeV",
+           "ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3), "tracks": nt,
+           "kernels_us": {k: round(v * 1e3, 1) for k, v in per.items()},
+           "roofline_tube": {"kernel": "k_attach_tube", "bound": "alu",
+                             "achieved": fl / (tube_ms * 1e-3) / 1e12, "peak": ALU_PEAK_TFLOPS,
+                             "unit": "TFLOP/s",
+                             "frac": fl / (tube_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                             "flops_per_launch": fl, "row_transports": rows},
+           "attached": int(att.sum()), "adjacent": int(adj.sum()),
+           "protected": int(((state & 4) != 0).sum()), "removed": int(((state & 8) != 0).sum()),
+           "fake_attached": fake(att), "fake_adjacent": fake(adj)}
+    log(f"[bench] attachment {ms:.3f} ms ({nt} tracks): attached {res['attached']} "
+        f"(fake {res['fake_attached']}), adjacent {res['adjacent']} (fake "
+        f"{res['fake_adjacent']}), removed {res['removed']}")
     return res
 
 

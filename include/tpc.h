@@ -251,6 +251,35 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
                     tpc_tracklets tracklets, tpc_tracks tracks, void* d_ws,
                     size_t ws_bytes, int mode, int use_graph, void* stream);
 
+/* ---- track-based cluster attachment -------------------------------------- */
+
+/* Cluster attachment and rejection marks (section 5).  Every track of the
+ * selection gets a tube of `radius` cm over the pad rows from its first to
+ * its last hit; its axis is the state of the track's tracklet (par, at the
+ * plane of row row_inner) transported outwards row by row as in tracklet
+ * construction, stopping where |sin(phi)| would reach s_max.  A cluster of
+ * the track's sector on such a row lies in the tube when
+ * dy*dy + dz*dz <= radius*radius (float32, in that order).  Per cluster id:
+ *   track[c]: the track that owns c, else the track of least |q/pT| (ties to
+ *             the lower index) whose tube holds c, else -1;
+ *   state[c]: 1 attached (owned) | 2 adjacent (in a tube, not owned) |
+ *             4 protected (in the tube of, or owned by, a track with
+ *             |q/pT| <= 1/pt_good in float32) | 8 removed (attached or
+ *             adjacent and not protected).
+ * in, grid, tracklets and tracks are those of the tracking calls on the
+ * same problem; d_n_tracks (device) holds the track count (the status
+ * block's n_tracks; tracks beyond tracks.capacity do not exist).  track
+ * and state are device arrays of n_clusters entries, owned by the caller.
+ * d_ws: tpc_attach_workspace_size bytes of device scratch.  Returns
+ * TPC_ERR_INVALID_ARG for a null pointer, radius or pt_good not > 0, or a
+ * short workspace; asynchronous on stream. */
+int tpc_attach_workspace_size(const tpc_problem* h_prob, size_t* h_bytes);
+int tpc_attach_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in,
+                        tpc_grid grid, tpc_tracklets tracklets, tpc_tracks tracks,
+                        const int64_t* d_n_tracks, float radius, float pt_good,
+                        int32_t* track, uint8_t* state, void* d_ws, size_t ws_bytes,
+                        void* stream);
+
 /* ---- calibrated refit ---------------------------------------------------- */
 
 /* Calibration model.  For a cluster of a sector on z side `side` (+1/-1) on

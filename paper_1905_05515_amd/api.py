@@ -262,6 +262,31 @@ def track_batch(ctx: Context, ev: Event, mode="staged", use_graph=False, stream=
                                     1 if use_graph else 0, _stream(stream)), "tpc_track_batch")
 
 
+def attach_clusters(ctx: Context, ev: Event, radius: float = 1.5, pt_good: float = 0.05,
+                    stream=None):
+    """Track-based cluster attachment of the event's found tracks (after
+    the tracking calls): returns device tensors (track int32, state uint8)
+    per cluster id; state bits 1 attached, 2 adjacent, 4 protected, 8
+    removed."""
+    n = ev.problem.n_clusters
+    dev = ev.t["row"].device
+    need = C.c_size_t(0)
+    L.check(L.lib().tpc_attach_workspace_size(C.byref(ev.problem), C.byref(need)),
+            "tpc_attach_workspace_size")
+    ws = ev.t.get("attach_ws")
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=dev)
+        ev.t["attach_ws"] = ws
+    track = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    state = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    L.check(L.lib().tpc_attach_clusters(ctx.handle, C.byref(ev.problem), _clusters(ev), _grid(ev),
+                                        _tracklets(ev), _tracks(ev), status_count_ptr(ev),
+                                        float(radius), float(pt_good), _ptr(track), _ptr(state),
+                                        _ptr(ws), ws.numel(), _stream(stream)),
+            "tpc_attach_clusters")
+    return track[:n], state[:n]
+
+
 def get_status(ev: Event, stream=None) -> dict:
     st = L.Status()
     L.check(L.lib().tpc_get_status(_ptr(ev.t["ws"]), C.byref(st), _stream(stream)),

@@ -19,10 +19,13 @@ namespace tpc {
 // 3. scatter:  tiles claim a range per bucket and copy (id, y, z) there, in
 //              any order inside a bucket;
 // 4. bins:     one block per (sector, bucket) counts its clusters per bin in
-//              LDS, scans the counts into the bin starts and deals every
-//              cluster a slot of its bin (any order inside a bin);
-// 5. place:    the final place of a slot's cluster is its bin start plus the
-//              number of clusters of the bin with a smaller id.
+//              LDS and scans the counts into the bin starts; a bucket that
+//              fits in LDS (grid_bins_place_fused) is also placed there: the
+//              final place of a cluster is its bin start plus the number of
+//              clusters of its bin with a smaller id; a larger one deals every
+//              cluster a slot of its bin (any order inside a bin) and joins
+//              the list of step 5;
+// 5. place:    for the listed buckets, the same rule over the slots.
 // No step depends on the order of atomics: the result is the stable sort.
 constexpr int kRowTile = kBlock * 8;
 constexpr int kTileCounters = 4096;  // LDS bucket counters of one tile
@@ -57,8 +60,9 @@ constexpr int kTileSecMax = 8;
 __global__ __launch_bounds__(kBlock) void k_grid_rows(
     const tpc_sector* __restrict__ sec, int n_sec, int n_rows, int S, int ts,
     const uint8_t* __restrict__ row, const float* __restrict__ z, int64_t c0, int64_t c1,
-    int32_t* __restrict__ rcnt, tpc_status* status)
+    int32_t* __restrict__ rcnt, tpc_status* status, int32_t* __restrict__ bigq)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) bigq[0] = 0;   // the list of step 5
     __shared__ int hist[kTileCounters];
     __shared__ int64_t ends[kTileSecMax];
     __shared__ int sf_sh;
@@ -153,29 +157,40 @@ __global__ __launch_bounds__(kBlock) void k_grid_bins(
     const float* __restrict__ gz, const int32_t* __restrict__ gid,
     const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start,
     int32_t* __restrict__ cnt, int32_t* __restrict__ gslot, int32_t* __restrict__ gbin,
-    int32_t* __restrict__ gtag)
+    int32_t* __restrict__ gtag, float* __restrict__ yg, float* __restrict__ zg,
+    int32_t* __restrict__ idg, int32_t* __restrict__ gsr, int32_t* __restrict__ bigq)
 {
-    __shared__ int lds[kRowBinsLds];
+    constexpr int kLds = kFuseLds > kRowBinsLds ? kFuseLds : kRowBinsLds;
+    __shared__ int lds[kLds];
     __shared__ int red[kBlock / kWave];
     const int Rb = (n_rows + 1) * S;
     const int si = sec_lo + (int)(blockIdx.x / Rb);
     const int bk = (int)(blockIdx.x % Rb);
     const tpc_sector s = sec[si];
+    if (grid_bins_place_fused(s, si, bk, n_rows, S, rstart, gy, gz, gid, row, bin_start, yg, zg,
+                              idg, gsr, lds, red))
+        return;
     grid_bins_bucket(s, si, bk, n_rows, S, rstart, gy, gz, gid, row, bin_start, cnt, gslot, gbin,
                      gtag, lds, red);
+    if (threadIdx.x == 0) bigq[1 + atomicAdd(&bigq[0], 1)] = si * Rb + bk;
 }
 
+// the listed buckets (one block each, any order)
 __global__ __launch_bounds__(kBlock) void k_grid_place(
-    int64_t c0, int64_t c1, const int32_t* __restrict__ bin_start,
-    const int32_t* __restrict__ gid, const float* __restrict__ gy,
-    const float* __restrict__ gz, const int32_t* __restrict__ gslot,
-    const int32_t* __restrict__ gbin, const int32_t* __restrict__ gtag,
-    float* __restrict__ yg, float* __restrict__ zg, int32_t* __restrict__ idg,
-    int32_t* __restrict__ gsr)
+    const int32_t* __restrict__ bigq, const int32_t* __restrict__ rstart,
+    const int32_t* __restrict__ bin_start, const int32_t* __restrict__ gid,
+    const float* __restrict__ gy, const float* __restrict__ gz,
+    const int32_t* __restrict__ gslot, const int32_t* __restrict__ gbin,
+    const int32_t* __restrict__ gtag, float* __restrict__ yg, float* __restrict__ zg,
+    int32_t* __restrict__ idg, int32_t* __restrict__ gsr)
 {
-    for (int64_t q = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < c1;
-         q += (int64_t)gridDim.x * blockDim.x)
-        grid_place_one(q, bin_start, gid, gy, gz, gslot, gbin, gtag, yg, zg, idg, gsr);
+    const int nq = bigq[0];
+    for (int e = blockIdx.x; e < nq; e += gridDim.x) {
+        const int gb = bigq[1 + e];
+        const int a = rstart[gb], b = rstart[gb + 1];
+        for (int q = a + threadIdx.x; q < b; q += blockDim.x)
+            grid_place_one(q, bin_start, gid, gy, gz, gslot, gbin, gtag, yg, zg, idg, gsr);
+    }
 }
 
 __global__ void k_set_grid_status(tpc_status* status, int64_t n_grid)
@@ -203,7 +218,7 @@ int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in
     launch_fill<int32_t>(ws.rfill + (int64_t)sec_lo * Rb, 0, nbk, st);
     const unsigned gt = grid_for_block(ceil_div(c1 - c0, kRowTile), 1, 4096);
     TPC_LAUNCH(k_grid_rows, dim3(gt), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
-               p->n_rows, S, ts, in.row, in.z, c0, c1, ws.rcnt, ws.status);
+               p->n_rows, S, ts, in.row, in.z, c0, c1, ws.rcnt, ws.status, ws.bigq);
     launch_scan<int32_t>(ws.rcnt + (int64_t)sec_lo * Rb, ws.rstart + (int64_t)sec_lo * Rb, nbk,
                          true, nullptr, nullptr, ws.partials, st, c0);
     TPC_LAUNCH(k_grid_rows_scatter, dim3(gt), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
@@ -212,8 +227,9 @@ int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in
     TPC_LAUNCH(k_grid_bins, dim3((unsigned)nbk), dim3(kBlock), 0, st, p->d_sectors, sec_lo,
                p->n_rows, S, (const int32_t*)ws.rstart, (const float*)ws.gy, (const float*)ws.gz,
                (const int32_t*)ws.tmp, in.row, out.bin_start, ws.cnt, ws.gslot, ws.gbin,
-               ws.gtag);
-    TPC_LAUNCH(k_grid_place, dim3(grid_for(c1 - c0)), dim3(kBlock), 0, st, c0, c1,
+               ws.gtag, out.y, out.z, out.id, ws.gsr, ws.bigq);
+    TPC_LAUNCH(k_grid_place, dim3(grid_for_block(nbk, 1, 2048)), dim3(kBlock), 0, st,
+               (const int32_t*)ws.bigq, (const int32_t*)ws.rstart,
                (const int32_t*)out.bin_start, (const int32_t*)ws.tmp, (const float*)ws.gy,
                (const float*)ws.gz, (const int32_t*)ws.gslot, (const int32_t*)ws.gbin,
                (const int32_t*)ws.gtag, out.y, out.z, out.id, ws.gsr);

@@ -91,6 +91,98 @@ __device__ __forceinline__ void grid_bins_bucket(
     }
 }
 
+// Bucket sort and placement in one block, for buckets of at most
+// kFuseMax clusters over at most kFuseBins bins: the clusters, their bins,
+// the bin counters and the binned order stay in LDS (smem[kFuseLds] ints);
+// every cluster's place is its bin start plus the number of clusters of its
+// bin with a smaller id (the stable order), as in the two-pass form.
+// Returns false, touching nothing, when the bucket is larger.
+constexpr int kFuseBins = 4096;
+constexpr int kFuseMax = 1024;
+constexpr int kFuseLds = kFuseBins + 5 * kFuseMax;
+
+__device__ __forceinline__ bool grid_bins_place_fused(
+    const tpc_sector& s, int si, int bk, int n_rows, int S, const int32_t* __restrict__ rstart,
+    const float* __restrict__ gy, const float* __restrict__ gz, const int32_t* __restrict__ gid,
+    const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start, float* __restrict__ yg,
+    float* __restrict__ zg, int32_t* __restrict__ idg, int32_t* __restrict__ gsr, int* smem,
+    int* red)
+{
+    const int Rb = (n_rows + 1) * S;
+    const int r = bk / S, slab = bk % S;
+    if (slab >= (r < n_rows ? slab_count(s) : 1)) return true;   // no such slab: nothing
+    const int zs = slab_zbins(s);
+    const int a = rstart[(int64_t)si * Rb + bk], n = rstart[(int64_t)si * Rb + bk + 1] - a;
+    const int per_row = s.nbz * s.nby;
+    const int z_lo = slab * zs;
+    const int z_hi = z_lo + zs < s.nbz ? z_lo + zs : s.nbz;
+    const int nbr = r < n_rows ? (z_hi - z_lo) * s.nby : 1;
+    if (n > kFuseMax || nbr > kFuseBins) return false;
+    const int g0 = s.bin_base + r * per_row + (r < n_rows ? z_lo * s.nby : 0);
+    int* ctr = smem;                                   // [kFuseBins]
+    int* lid = smem + kFuseBins;                       // [kFuseMax] cluster ids
+    float* ly = reinterpret_cast<float*>(lid + kFuseMax);
+    float* lz = ly + kFuseMax;
+    int* lb = reinterpret_cast<int*>(lz + kFuseMax);   // bins
+    int* mem = lb + kFuseMax;                          // binned order
+    for (int b = threadIdx.x; b < nbr; b += blockDim.x) ctr[b] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float y = gy[a + i], z = gz[a + i];
+        const int b = r < n_rows ? (bin_of(z, s.z0, s.inv_bz, s.nbz) - z_lo) * s.nby +
+                                       bin_of(y, s.y0, s.inv_by, s.nby)
+                                 : 0;
+        lid[i] = gid[a + i];
+        ly[i] = y;
+        lz[i] = z;
+        lb[i] = b;
+        atomicAdd(&ctr[b], 1);
+    }
+    __syncthreads();
+    // bin starts: exclusive scan of the counts from the bucket start
+    int carry = a;
+    for (int b0 = 0; b0 < nbr; b0 += kScanTile) {
+        const int base = b0 + (int)threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < nbr ? ctr[base + k] : 0;
+            sum += v[k];
+        }
+        int tot;
+        int ex = block_excl_scan(sum, red, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < nbr) {
+                bin_start[g0 + base + k] = ex;
+                ctr[base + k] = ex;
+                ex += v[k];
+            }
+        carry += tot;
+    }
+    if (r == n_rows && threadIdx.x == 0) bin_start[g0 + 1] = a + n;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mem[atomicAdd(&ctr[lb[i]], 1) - a] = i;
+    __syncthreads();
+    // ctr[b] is now the end of bin b, i.e. the start of bin b + 1
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int i = mem[q];
+        const int b = lb[i];
+        const int bs = (b > 0 ? ctr[b - 1] : a) - a, be = ctr[b] - a;
+        const int id = lid[i];
+        int rank = 0;
+        for (int u = bs; u < be; ++u) rank += lid[mem[u]] < id;
+        const int o = a + bs + rank;
+        yg[o] = ly[i];
+        zg[o] = lz[i];
+        idg[o] = id;
+        // invalid rows keep their raw row value
+        gsr[o] = (si << 8) | (r < n_rows ? r : (int)row[id]);
+    }
+    return true;
+}
+
 // final place of the cluster at binned slot q: its bin start plus the number
 // of clusters of the bin with a smaller id
 __device__ __forceinline__ void grid_place_one(

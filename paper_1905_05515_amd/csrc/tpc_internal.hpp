@@ -42,6 +42,8 @@ struct Workspace {
     int32_t* gslot;        // [n] row-partitioned index of the cluster at a binned slot
     int32_t* gbin;         // [n] global bin of a binned slot
     int32_t* gtag;         // [n] sector << 8 | row of a binned slot
+    int32_t* bigq;         // [n_sectors * (n_rows + 1) * S + 1] count, then the buckets
+                           // the staged grid build places in a pass of their own
     int64_t* sec_start;    // [n_sectors + 1] first start of each sector
     int32_t* pq;           // persistent form: [1] queue head, [kPhases * n_sectors] done counts
     int64_t* scnt;         // persistent form: [n_sectors] starts per sector

@@ -175,6 +175,7 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->gslot = (int32_t*)take(sizeof(int32_t) * nn);
     ws->gbin = (int32_t*)take(sizeof(int32_t) * nn);
     ws->gtag = (int32_t*)take(sizeof(int32_t) * nn);
+    ws->bigq = (int32_t*)take(sizeof(int32_t) * (nrb + 1));
     // scratch of single calls, sized by the start capacity
     ws->partials = (int64_t*)take(sizeof(int64_t) * (size_t)max_tiles);
     ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));

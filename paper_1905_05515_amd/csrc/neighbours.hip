@@ -11,6 +11,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
     const int32_t* __restrict__ gsr, int64_t begin, int64_t end,
     int32_t* __restrict__ up0, int32_t* __restrict__ down0)
 {
+    __shared__ float nb_l[3 * kNbList * kBlock];
+    const NbList L{nb_l, nb_l + kNbList * kBlock,
+                   reinterpret_cast<int*>(nb_l + 2 * kNbList * kBlock)};
     // work blocks dealt to the XCDs in contiguous ranges (one sector's rows
     // share an L2)
     const int64_t nblk = (end - begin + blockDim.x - 1) / blockDim.x;
@@ -20,7 +23,8 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
         const int64_t p = begin + (b0 + xcd_remap(blockIdx.x, (int)chunk)) * blockDim.x +
                           threadIdx.x;
         if (p < end)
-            neighbours_one(p, sec, n_rows, row_x, prm, bin_start, yg, zg, idg, gsr, up0, down0);
+            neighbours_one(p, sec, n_rows, row_x, prm, bin_start, yg, zg, idg, gsr, up0, down0,
+                           L);
     }
 }
 

@@ -324,13 +324,20 @@ void k_persistent(PArgs a)
                 grid_place_one(q, a.grid.bin_start, a.ws.tmp, a.ws.gy, a.ws.gz, a.ws.gslot,
                                a.ws.gbin, a.ws.gtag, a.grid.y, a.grid.z, a.grid.id, a.ws.gsr);
             break;
-        case P_NEIGH:
+        case P_NEIGH: {
+            // the down-candidate lists in the task scratch
+            static_assert(3 * kNbList * kBlock <= 2 * kPersistLds, "neighbour lists");
+            float* nbf = reinterpret_cast<float*>(pbuf);
+            const NbList nbl{nbf, nbf + kNbList * kBlock,
+                             reinterpret_cast<int*>(nbf + 2 * kNbList * kBlock)};
             for (int64_t k = c0 + i0 + threadIdx.x; k < c1 && k < c0 + i0 + items; k += kBlock) {
                 neighbours_one(k, a.sec, n_rows, a.row_x, a.prm, a.grid.bin_start, a.grid.y,
-                               a.grid.z, a.grid.id, a.ws.gsr, a.links.up0, a.links.down0);
+                               a.grid.z, a.grid.id, a.ws.gsr, a.links.up0, a.links.down0,
+                               nbl);
                 a.ws.tmp[k] = -1;   // start flags (the staging array is free again)
             }
             break;
+        }
         case P_CLEAN:
             for (int64_t k = c0 + i0 + threadIdx.x; k < c1 && k < c0 + i0 + items; k += kBlock)
                 clean_one(k, a.links.up0, a.links.down0, a.grid.id, a.links.up, a.links.down,

@@ -18,66 +18,75 @@ struct NbSrc {
 
 // best pair for one hit with its up candidates from U and down candidates
 // from D.  The down candidates inside the window are gathered first (up to
-// kNbList, in registers), so that each up candidate is paired with those
-// only; a hit with more goes through the plain double scan.  The pair is the
-// lexicographic minimum of (D2, up id, down id), whatever the order.
+// kNbList, in the lane's column of an LDS list), so that each up candidate
+// is paired with those only; a hit with more goes through the plain double
+// scan.  The pair is the lexicographic minimum of (D2, up id, down id),
+// whatever the order; the ids are read only to break an exact tie of D2.
 constexpr int kNbList = 8;
+
+// down-candidate list of one lane: entry k at [k * blockDim.x + lane]
+struct NbList {
+    float* y;
+    float* z;
+    int* pos;
+    __device__ __forceinline__ int at(int k) const
+    {
+        return k * (int)blockDim.x + (int)threadIdx.x;
+    }
+};
+
+// does pair (pu, pd) at deviation d2 improve on the best (bu, bd) at best?
+__device__ __forceinline__ bool nb_better(float d2, int pu, int pd, float best, int bu, int bd,
+                                          const NbSrc& U, const NbSrc& D)
+{
+    if (bu < 0 || d2 < best) return true;
+    if (!(d2 == best)) return false;
+    const int idu = U.idg[pu], bidu = U.idg[bu];
+    if (idu != bidu) return idu < bidu;
+    return D.idg[pd] < D.idg[bd];
+}
 
 __device__ __forceinline__ void nb_pairs(const NbSrc& U, const NbSrc& D, float y, float z,
                                          float yu_c, float yd_c, int iyu0, int iyu1, int iyd0,
                                          int iyd1, int iz0, int iz1, const tpc_params& prm,
-                                         int& bu, int& bd)
+                                         const NbList& L, int& bu, int& bd)
 {
     const float Wy = prm.nb_win_y, Wz = prm.nb_win_z, D2max = prm.nb_d2max;
     float best = 0.0f;
-    int bidu = -1, bidd = -1;
-    float ly[kNbList], lz[kNbList];
-    int lid[kNbList], lpos[kNbList];
     int nd = 0;
     for (int izd = iz0; izd <= iz1; ++izd) {
         const int pd1 = D.first(izd, iyd1 + 1);
         for (int pd = D.first(izd, iyd0); pd < pd1; ++pd) {
             const float yd = D.yg[pd], zd = D.zg[pd];
             if (!(fabsf(yd - yd_c) <= Wy && fabsf(zd - z) <= Wz)) continue;
-#pragma unroll
-            for (int k = 0; k < kNbList; ++k)
-                if (k == nd) {
-                    ly[k] = yd;
-                    lz[k] = zd;
-                    lpos[k] = pd;
-                }
+            if (nd < kNbList) {
+                const int e = L.at(nd);
+                L.y[e] = yd;
+                L.z[e] = zd;
+                L.pos[e] = pd;
+            }
             ++nd;
         }
     }
     if (nd == 0) return;
     const bool listed = nd <= kNbList;
-    if (listed) {
-#pragma unroll
-        for (int k = 0; k < kNbList; ++k)
-            if (k < nd) lid[k] = D.idg[lpos[k]];
-    }
     for (int izu = iz0; izu <= iz1; ++izu) {
         const int pu1 = U.first(izu, iyu1 + 1);
         for (int pu = U.first(izu, iyu0); pu < pu1; ++pu) {
             const float yu = U.yg[pu], zu = U.zg[pu];
             if (!(fabsf(yu - yu_c) <= Wy && fabsf(zu - z) <= Wz)) continue;
-            const int idu = U.idg[pu];
             if (listed) {
-#pragma unroll
-                for (int k = 0; k < kNbList; ++k) {
-                    if (k >= nd) break;
-                    const float dy = (yu + ly[k]) - (y + y);
-                    const float dz = (zu + lz[k]) - (z + z);
+                for (int k = 0; k < nd; ++k) {
+                    const int e = L.at(k);
+                    const float dy = (yu + L.y[e]) - (y + y);
+                    const float dz = (zu + L.z[e]) - (z + z);
                     const float d2 = dy * dy + dz * dz;
                     if (!(d2 <= D2max)) continue;
-                    const int idd = lid[k];
-                    if (bu < 0 || d2 < best ||
-                        (d2 == best && (idu < bidu || (idu == bidu && idd < bidd)))) {
+                    const int pd = L.pos[e];
+                    if (nb_better(d2, pu, pd, best, bu, bd, U, D)) {
                         best = d2;
                         bu = pu;
-                        bd = lpos[k];
-                        bidu = idu;
-                        bidd = idd;
+                        bd = pd;
                     }
                 }
                 continue;
@@ -91,14 +100,10 @@ __device__ __forceinline__ void nb_pairs(const NbSrc& U, const NbSrc& D, float y
                     const float dz = (zu + zd) - (z + z);
                     const float d2 = dy * dy + dz * dz;
                     if (!(d2 <= D2max)) continue;
-                    const int idd = D.idg[pd];
-                    if (bu < 0 || d2 < best ||
-                        (d2 == best && (idu < bidu || (idu == bidu && idd < bidd)))) {
+                    if (nb_better(d2, pu, pd, best, bu, bd, U, D)) {
                         best = d2;
                         bu = pu;
                         bd = pd;
-                        bidu = idu;
-                        bidd = idd;
                     }
                 }
             }
@@ -115,7 +120,8 @@ __device__ __forceinline__ void neighbours_one(
     int64_t p, const tpc_sector* __restrict__ sec, int n_rows, const float* __restrict__ row_x,
     const tpc_params& prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
     const float* __restrict__ zg, const int32_t* __restrict__ idg,
-    const int32_t* __restrict__ gsr, int32_t* __restrict__ up0, int32_t* __restrict__ down0)
+    const int32_t* __restrict__ gsr, int32_t* __restrict__ up0, int32_t* __restrict__ down0,
+    const NbList& L)
 {
     const float Wy = prm.nb_win_y, Wz = prm.nb_win_z;
     const int v = gsr[p];
@@ -136,7 +142,7 @@ __device__ __forceinline__ void neighbours_one(
         const int per_row = s.nbz * s.nby;
         const NbSrc U{s.bin_base + (r + 1) * per_row, s.nby, bin_start, yg, zg, idg};
         const NbSrc D{s.bin_base + (r - 1) * per_row, s.nby, bin_start, yg, zg, idg};
-        nb_pairs(U, D, y, z, yu_c, yd_c, iyu0, iyu1, iyd0, iyd1, iz0, iz1, prm, bu, bd);
+        nb_pairs(U, D, y, z, yu_c, yd_c, iyu0, iyu1, iyd0, iyd1, iz0, iz1, prm, L, bu, bd);
     }
     up0[p] = bu;
     down0[p] = bd;

@@ -157,11 +157,11 @@ __device__ __noinline__ void write_track_hits(
     int64_t t, int64_t o, int n_rows, const tpc_params& prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, int32_t* __restrict__ trk_hits,
-    int64_t hit_cap)
+    const unsigned long long* __restrict__ hitkey, const uint8_t* __restrict__ ccnt,
+    int64_t count_cap, int32_t* __restrict__ trk_hits, int64_t hit_cap)
 {
-    sel_write_hits(t, o, n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey, trk_hits,
-                   hit_cap);
+    sel_write_hits(t, o, n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey, ccnt,
+                   count_cap, trk_hits, hit_cap);
 }
 
 __global__ __launch_bounds__(kBlock)
@@ -445,6 +445,7 @@ void k_persistent(PArgs a)
                     write_track_hits(t, (int64_t)(a.ws.toff[t] & 0xFFFFFFFFull), n_rows, a.prm,
                                    a.grid.id, a.trl.start, a.trl.hits, a.trl.nhits,
                                    a.trl.capacity, (const unsigned long long*)a.ws.hitkey,
+                                     a.ws.ccnt, count_cap,
                                    a.trk.hits, a.trk.hit_capacity);
             break;
         }

@@ -158,6 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(
         if (q == 0)
             sel_write_track(t, (int64_t)(to >> 32), o, t_start, sec, gsr, trk_off, trk_tracklet,
                             trk_side, trk_cap);
+        if (!ccnt[q * count_cap + t]) continue;     // the chunk keeps nothing
         for (int j = 0; j < q; ++j) o += ccnt[j * count_cap + t];
         const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
         sel_write_chunk(t, q * kSelRows, n_rows, key, o, idg, t_hits, cap, hitkey, trk_hits,

@@ -156,17 +156,23 @@ __device__ __forceinline__ void sel_chunk_block(
     }
 }
 
-// the kept hits of tracklet t (cluster ids, row order) from hit offset o on
+// the kept hits of tracklet t (cluster ids, row order) from hit offset o on;
+// ccnt[q * count_cap + t]: kept hits of row chunk q (chunks without any are
+// skipped)
 __device__ __forceinline__ void sel_write_hits(
     int64_t t, int64_t o, int n_rows, const tpc_params& prm, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, int32_t* __restrict__ trk_hits,
-    int64_t hit_cap)
+    const unsigned long long* __restrict__ hitkey, const uint8_t* __restrict__ ccnt,
+    int64_t count_cap, int32_t* __restrict__ trk_hits, int64_t hit_cap)
 {
     const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-    for (int ra = 0; ra < n_rows; ra += kSelRows)
-        o = sel_write_chunk(t, ra, n_rows, key, o, idg, t_hits, cap, hitkey, trk_hits, hit_cap);
+    for (int ra = 0, q = 0; ra < n_rows; ra += kSelRows, ++q) {
+        const int kept = ccnt[q * count_cap + t];
+        if (kept)
+            sel_write_chunk(t, ra, n_rows, key, o, idg, t_hits, cap, hitkey, trk_hits, hit_cap);
+        o += kept;
+    }
 }
 
 }  // namespace tpc

@@ -533,7 +533,12 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
         bool alive = fit;
         int stat = 0;
         const float sd = t < nt && side ? (float)side[t] : 1.0f;
-        float4* ckt = ck && t < nt ? ck_tile(ck, t, n_rows) : nullptr;
+        // every lane of a tile stores every slot up to the wave's longest
+        // track (a lane past its own track stores its unchanged state, which
+        // nothing reads), so that each store writes whole lines; the tile of
+        // the last, partial wave is allocated in full
+        float4* ckt = ck ? ck_tile(ck, t, n_rows) : nullptr;
+        const int M_ck = M < n_rows ? M : n_rows;
         for (int i0 = 0; i0 < M; i0 += kChunk) {
             __syncthreads();      // the previous chunk is consumed
             stage_hits(S, bad, i0, a, t < nt && n >= 3 ? n : 0, idx, row, y, z, xs, n_rows);
@@ -555,24 +560,26 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
                 C[5] = prm.c_ss0;
                 C[9] = prm.c_tt0;
                 C[14] = prm.c_ww0;
-                if (ckt) store_ck(ckt, 0, p, C);
                 xp = h0.x;
             }
-            const int i_end = i0 + kChunk < n ? i0 + kChunk : n;
-            for (int i = i0 > 1 ? i0 : 1; i < i_end; ++i) {
-                if (!alive) break;
-                const int k = i - i0;
-                const CalHit h = calibrate(th, S.x[k][lane], S.y[k][lane], S.z[k][lane], sd, cm);
-                Prop P;
-                if (!prop_fwd(p, C, h.x - xp, prm.curv, prm.s_max, P)) {
-                    stat = 2;
-                    alive = false;
-                    break;
+            if (i0 == 0 && ckt && M_ck > 1) store_ck(ckt, 0, p, C);
+            const int i_hi = i0 + kChunk < M ? i0 + kChunk : M;
+            for (int i = i0 > 1 ? i0 : 1; i < i_hi; ++i) {
+                if (alive && i < n) {
+                    const int k = i - i0;
+                    const CalHit h =
+                        calibrate(th, S.x[k][lane], S.y[k][lane], S.z[k][lane], sd, cm);
+                    Prop P;
+                    if (prop_fwd(p, C, h.x - xp, prm.curv, prm.s_max, P)) {
+                        Upd U;
+                        chi2 += upd_fwd(p, C, h.y, h.z, prm.sigma_y2, prm.sigma_z2, U);
+                        xp = h.x;
+                    } else {
+                        stat = 2;
+                        alive = false;
+                    }
                 }
-                Upd U;
-                chi2 += upd_fwd(p, C, h.y, h.z, prm.sigma_y2, prm.sigma_z2, U);
-                xp = h.x;
-                if (ckt && i + 1 < n) store_ck(ckt, i, p, C);
+                if (ckt && i + 1 < M_ck) store_ck(ckt, i, p, C);
             }
         }
         __syncthreads();

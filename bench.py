@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-refit-bench", action="store_true")
     ap.add_argument("--no-batch-bench", action="store_true")
+    ap.add_argument("--no-per-sector", action="store_true",
+                    help="time the batched set in the staged and persistent forms only")
     ap.add_argument("--no-slice-bench", action="store_true",
                     help="skip the continuous read-out slice (100 collisions)")
     ap.add_argument("--no-attach-bench", action="store_true",
@@ -404,7 +406,9 @@ def batch_bench(args, api, synth, ctx, stream, prm):
     res = {"grid_layout": pick_layout(args, api, ctx, e, stream)}
     ref = None
     steps = max(2, args.steps // 4)
-    for mode, graph in (("staged", True), ("persistent", True), ("per_sector", False)):
+    forms = (("staged", True), ("persistent", True)) + (() if args.no_per_sector else
+                                                       (("per_sector", False),))
+    for mode, graph in forms:
         with torch.cuda.stream(stream):
             api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
             torch.cuda.synchronize()

@@ -66,7 +66,8 @@ def parse():
                          "counters of those stages) and exit")
     ap.add_argument("--inflight", default="auto",
                     help="events in flight in the timed step loop (each on its own stream "
-                         "with its own buffers), or 'auto' (1-3, the fastest; the box runs four hardware queues per process)")
+                         "with its own buffers), or 'auto' (1-3, the fastest; with four "
+                         "hardware queues per process more streams serialise)")
     ap.add_argument("--occupancy", default="auto",
                     help="clusters per grid bin, or 'auto' (autotuned per workload before "
                          "the timed region; the tracks do not depend on it)")
@@ -78,7 +79,8 @@ def pick_layout(args, api, ctx, e, stream, mode="staged"):
     for the JSON line."""
     if args.occupancy == "auto":
         best, times = api.autotune(ctx, e, mode=mode, stream=stream)
-        log(f"[bench] autotuned occupancy {best} ({', '.join(f'{k}: {v:.3f} ms' for k, v in times.items())})")
+        tried = ", ".join(f"{k}: {v:.3f} ms" for k, v in times.items())
+        log(f"[bench] autotuned occupancy {best} ({tried})")
         return {"occupancy": best, "tried_ms": {str(k): round(v, 4) for k, v in times.items()}}
     api.relayout(e, float(args.occupancy))
     return {"occupancy": float(args.occupancy)}
@@ -91,7 +93,7 @@ def log(*a):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
               "runs on a single MI355X and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
@@ -255,7 +257,8 @@ def main():
 
     value = n_cl / (ms_per_step * 1e-3)
     line = {
-        "metric": "TPC clusters/s tracked on 1 MI355X (batched vs per-sector); refit+adjoint tracks/s",
+        "metric": ("TPC clusters/s tracked on 1 MI355X (batched vs per-sector); "
+                   "refit+adjoint tracks/s"),
         "value": value,
         "unit": "clusters/s",
         "n_gpus": 1,

@@ -190,6 +190,57 @@ def attach_clusters(sector_offsets, row, y, z, row_x, prm, trk_off, trk_hits, pa
     return track[:n], state[:n]
 
 
+MERGE_WINDOWS = (3.0, 2.0, 0.1, 0.02, 2.0)   # y, z [cm], sin(phi), tan(lambda), q/pT
+
+
+def merge_windows_inv(windows=MERGE_WINDOWS):
+    """Inverse window widths as float32 (the form both sides take)."""
+    return (np.float32(1.0) / np.asarray(windows, np.float32)).astype(np.float32)
+
+
+def sector_width_cs(width_deg=20.0):
+    """cos and sin of the sector width as float32 inputs."""
+    import math
+    w = math.radians(width_deg)
+    return np.float32(math.cos(w)), np.float32(math.sin(w))
+
+
+def merge_transform(pj, xj, c, sd, x_to, curv, s_max=0.95):
+    """One state rotated into a frame turned by D (cos c, sin sd) and
+    transported to the plane x_to; None where invalid."""
+    out = np.empty(5, np.float32)
+    ok = lib().orc_merge_transform(_p(np.ascontiguousarray(pj, np.float32)), C.c_float(xj),
+                                   C.c_float(c), C.c_float(sd), C.c_float(x_to),
+                                   C.c_float(curv), C.c_float(s_max), _p(out))
+    return out if ok else None
+
+
+def merge_sector_tracks(sector_offsets, sectors_per_side, row_x, prm, trk_off, trk_hits, par,
+                        rin, iw=None, cos_w=None, sin_w=None):
+    """Sector-track merging (sections 2 and 3).  par/rin: the state of every
+    track.  Returns (link_up, link_dn, group) per track."""
+    offs = np.ascontiguousarray(sector_offsets, np.int64)
+    n_sec = offs.shape[0] - 1
+    if sectors_per_side < 3 or n_sec % sectors_per_side:
+        raise ValueError("sectors must form sides of at least 3 sectors")
+    if cos_w is None:
+        cos_w, sin_w = sector_width_cs(360.0 / sectors_per_side)
+    iw = merge_windows_inv() if iw is None else np.ascontiguousarray(iw, np.float32)
+    nt = trk_off.shape[0] - 1
+    up = np.empty(max(nt, 1), np.int32)
+    dn = np.empty(max(nt, 1), np.int32)
+    grp = np.empty(max(nt, 1), np.int32)
+    P = params(prm)
+    lib().orc_merge_sector_tracks(C.c_int(n_sec), _p(offs), C.c_int(sectors_per_side),
+                                  _p(np.ascontiguousarray(row_x, np.float32)), C.byref(P),
+                                  C.c_int64(nt), _p(np.ascontiguousarray(trk_off, np.int32)),
+                                  _p(np.ascontiguousarray(trk_hits, np.int32)),
+                                  _p(np.ascontiguousarray(par, np.float32)),
+                                  _p(np.ascontiguousarray(rin, np.int32)), C.c_float(cos_w),
+                                  C.c_float(sin_w), _p(iw), _p(up), _p(dn), _p(grp))
+    return up[:nt], dn[:nt], grp[:nt]
+
+
 def track_event(row, y, z, layout, n_bins, row_x, prm, n_rows=152, brute=False):
     """The whole chain: grid, neighbours, cleaning, starts, tracklets,
     selection.  Returns a dict of every intermediate (id space)."""

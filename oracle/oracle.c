@@ -728,3 +728,121 @@ void orc_attach_clusters(int n_sec, const int64_t* sector_offsets, int n_rows,
     free(fill);
     free(best_w);
 }
+
+/* ---- sector-track merging (section 2: the first fit of the sector tracks
+ * serves to find the whole track; section 3: sector boundaries) -----------
+ * Readings: the sector of a track is that of its first hit.  Sector s lies
+ * on side s / sps at index i = s % sps; its frame is rotated by
+ * (i + 1/2) * width; its up neighbour is index (i + 1) % sps on the same
+ * side, its down neighbour (i + sps - 1) % sps.  The state of track j (par
+ * at the plane x_j = row_x[rin[j]] of its sector's frame) is taken into the
+ * frame of a sector rotated by D = alpha_j - alpha_k (cos D = c, sin D =
+ * sd: +sin(width) when j's sector is the up neighbour of k's, -sin(width)
+ * when it is the down neighbour):
+ *   x' = x c - y sd,  y' = x sd + y c,  sin' = sin c + cos sd,
+ *   cos' = cos c - sin sd  (cos = sqrt((1 - sin)(1 + sin))),
+ * valid when cos' > 0 and |sin'| < s_max; z, tan(lambda) and q/pT do not
+ * change.  It is then transported to x_k with the tracker's transport (no
+ * candidate where that stops).  Distance: d2 = sum over the five
+ * parameters, in order, of ((p'_i - p_k,i) * iw_i)^2; a candidate needs
+ * d2 < 1.  Best partner per direction: least d2, ties to the lower index.
+ * Tracks k and j (j in the up neighbour of k's sector) are linked when each
+ * is the other's best partner in that direction.  group[k]: the least track
+ * index over the chain of links through k. */
+int orc_merge_transform(const float* pj, float xj, float c, float sd, float x_to, float curv,
+                        float s_max, float* out5)
+{
+    float y = pj[0], s = pj[2];
+    float cs = sqrtf((1.0f - s) * (1.0f + s));
+    float xr = xj * c - y * sd;
+    float p[5], C[15];
+    p[0] = xj * sd + y * c;
+    p[1] = pj[1];
+    p[2] = s * c + cs * sd;
+    p[3] = pj[3];
+    p[4] = pj[4];
+    float cr = cs * c - s * sd;
+    if (!(cr > 0.0f) || !(fabsf(p[2]) < s_max)) return 0;
+    for (int i = 0; i < 15; i++) C[i] = 0.0f;
+    if (!propagate_f(p, C, x_to - xr, curv, s_max)) return 0;
+    for (int i = 0; i < 5; i++) out5[i] = p[i];
+    return 1;
+}
+
+void orc_merge_sector_tracks(int n_sec, const int64_t* sector_offsets, int sps,
+                             const float* row_x, const orc_params* prm, int64_t n_tracks,
+                             const int* trk_off, const int* trk_hits, const float* par,
+                             const int* rin, float cos_w, float sin_w, const float* iw,
+                             int* link_up, int* link_dn, int* group)
+{
+    int64_t nt1 = n_tracks > 0 ? n_tracks : 1;
+    int* sec = (int*)malloc((size_t)nt1 * sizeof(int));
+    int* best = (int*)malloc((size_t)nt1 * 2 * sizeof(int));
+    int64_t* first = (int64_t*)calloc((size_t)n_sec + 1, sizeof(int64_t));
+    int64_t* fill = (int64_t*)calloc((size_t)n_sec + 1, sizeof(int64_t));
+    int64_t* members = (int64_t*)malloc((size_t)nt1 * sizeof(int64_t));
+    for (int64_t k = 0; k < n_tracks; k++) {
+        sec[k] = -1;
+        if (trk_off[k + 1] > trk_off[k]) {
+            int c0 = trk_hits[trk_off[k]];
+            int s = 0;
+            while (s + 1 < n_sec && c0 >= sector_offsets[s + 1]) s++;
+            sec[k] = s;
+            first[s + 1]++;
+        }
+    }
+    for (int s = 0; s < n_sec; s++) first[s + 1] += first[s];
+    for (int64_t k = 0; k < n_tracks; k++)
+        if (sec[k] >= 0) members[first[sec[k]] + fill[sec[k]]++] = k;
+    /* best partner of every track in its up (d = 0) and down (d = 1) neighbour */
+    for (int64_t k = 0; k < n_tracks; k++)
+        for (int d = 0; d < 2; d++) {
+            best[2 * k + d] = -1;
+            if (sec[k] < 0) continue;
+            int side = sec[k] / sps, i = sec[k] % sps;
+            int nb = side * sps + (d == 0 ? (i + 1) % sps : (i + sps - 1) % sps);
+            float sd = d == 0 ? sin_w : -sin_w;
+            float xk = row_x[rin[k]];
+            float best_d2 = 0.0f;
+            for (int64_t m = first[nb]; m < first[nb + 1]; m++) {
+                int64_t j = members[m];
+                float q[5];
+                if (!orc_merge_transform(par + 5 * j, row_x[rin[j]], cos_w, sd, xk, prm->curv,
+                                         prm->s_max, q))
+                    continue;
+                float d2 = 0.0f;
+                for (int e = 0; e < 5; e++) {
+                    float r = (q[e] - par[5 * k + e]) * iw[e];
+                    d2 = d2 + r * r;
+                }
+                if (!(d2 < 1.0f)) continue;
+                if (best[2 * k + d] < 0 || d2 < best_d2) {
+                    best[2 * k + d] = (int)j;
+                    best_d2 = d2;
+                }
+            }
+        }
+    for (int64_t k = 0; k < n_tracks; k++) {
+        int j = best[2 * k];
+        link_up[k] = (j >= 0 && best[2 * j + 1] == (int)k) ? j : -1;
+        j = best[2 * k + 1];
+        link_dn[k] = (j >= 0 && best[2 * j] == (int)k) ? j : -1;
+    }
+    for (int64_t k = 0; k < n_tracks; k++) {
+        int g = (int)k;
+        for (int d = 0; d < 2; d++) {
+            const int* lk = d == 0 ? link_up : link_dn;
+            int j = lk[k];
+            for (int step = 0; j >= 0 && j != (int)k && step < n_sec; step++) {
+                if (j < g) g = j;
+                j = lk[j];
+            }
+        }
+        group[k] = g;
+    }
+    free(sec);
+    free(best);
+    free(first);
+    free(fill);
+    free(members);
+}

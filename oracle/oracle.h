@@ -145,6 +145,26 @@ void orc_attach_clusters(int n_sec, const int64_t* sector_offsets, int n_rows,
                          const int* rin, float radius, float w_good, int* track,
                          uint8_t* state);
 
+/* Sector-track merging (sections 2 and 3): tracks in neighbouring sectors
+ * of one side (n_sec = sides * sps, sps >= 3) are linked when each is the
+ * other's best partner: track j's state (par[5j] at row rin[j]) rotated
+ * into the frame of k's sector (cos_w, sin_w: the sector width) and
+ * transported to k's plane must lie within d2 = sum ((p'_i - p_k,i) iw_i)^2
+ * < 1, least d2 (ties to the lower index) in each direction.  link_up[k]:
+ * the linked track in the next sector of the side (index + 1 mod sps),
+ * link_dn[k]: in the previous one, -1 none; group[k]: least index on k's
+ * chain of links. */
+void orc_merge_sector_tracks(int n_sec, const int64_t* sector_offsets, int sps,
+                             const float* row_x, const orc_params* prm, int64_t n_tracks,
+                             const int* trk_off, const int* trk_hits, const float* par,
+                             const int* rin, float cos_w, float sin_w, const float* iw,
+                             int* link_up, int* link_dn, int* group);
+/* One state into a frame rotated by D (c = cos D, sd = sin D) and
+ * transported to the plane x_to; 0 where the rotated state is invalid or the
+ * transport stops. */
+int orc_merge_transform(const float* pj, float xj, float c, float sd, float x_to, float curv,
+                        float s_max, float* out5);
+
 /* Single steps, exposed for the tests. */
 int orc_propagate32(float* p, float* C, float dx, float curv, float s_max);
 int orc_propagate64(double* p, double* C, double dx, double curv, double s_max);

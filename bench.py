@@ -57,6 +57,8 @@ def parse():
                     help="skip the continuous read-out slice (100 collisions)")
     ap.add_argument("--no-attach-bench", action="store_true",
                     help="skip the track-based cluster attachment of the central event")
+    ap.add_argument("--no-merge-bench", action="store_true",
+                    help="skip the sector-track merging of the central event")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference size for scaling the HBM byte counters) and exit")
@@ -247,6 +249,8 @@ def main():
     extra = {}
     if not args.no_attach_bench:
         extra["cluster_attachment"] = attach_bench(args, api, ctx, e, ev, stream)
+    if not args.no_merge_bench:
+        extra["sector_merging"] = merge_bench(args, api, ctx, e, ev, stream)
     if not args.no_batch_bench:
         extra["batched_vs_per_sector"] = batch_bench(args, api, synth, ctx, stream, prm)
     if not args.no_slice_bench:
@@ -509,6 +513,69 @@ def attach_bench(args, api, ctx, e, ev, stream):
     log(f"[bench] attachment {ms:.3f} ms ({nt} tracks): attached {res['attached']} "
         f"(fake {res['fake_attached']}), adjacent {res['adjacent']} (fake "
         f"{res['fake_adjacent']}), removed {res['removed']}")
+    return res
+
+
+# float operations of one candidate pair in k_merge_best: the transport's
+# parameter part (dx, k, sin, two cosines, chord slope, chord, series of the
+# arc, y and z: 33) and the windowed distance (5 x 4)
+FLOPS_MERGE_PAIR = 53
+
+
+def merge_bench(args, api, ctx, e, ev, stream):
+    """Sector-track merging of the central event's found tracks: time per
+    event, per-kernel times, the pair kernel against the ALU ceiling
+    (candidate pairs counted from the tracks' sectors), links and their
+    truth-label purity."""
+    import numpy as np
+    import torch
+    steps = max(args.steps, 2)
+    with torch.cuda.stream(stream):
+        api.track_batch(ctx, e, mode="staged", use_graph=False, stream=stream)
+        api.merge_sector_tracks(ctx, e, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            up, dn, grp = api.merge_sector_tracks(ctx, e, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        api.timing_enable(ctx, True)
+        for _ in range(steps):
+            api.merge_sector_tracks(ctx, e, stream=stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    per = {k: ms_ / n for k, (n, ms_) in kt.items()}
+    r = api.results(e, stream)
+    off, hits = r["trk_off"], r["trk_hits"]
+    nt = len(off) - 1
+    up = up[:nt].cpu().numpy()
+    grp = grp[:nt].cpu().numpy()
+    sec = np.searchsorted(ev.sector_offsets, hits[off[:-1]], side="right") - 1
+    cnt = np.bincount(sec, minlength=len(ev.sector_offsets) - 1)
+    side, idx = sec // 18, sec % 18
+    pairs = int(np.sum(cnt[side * 18 + (idx + 1) % 18] + cnt[side * 18 + (idx + 17) % 18]))
+    best_ms = per.get("k_merge_best", ms)
+    fl = FLOPS_MERGE_PAIR * pairs
+    maj = np.array([np.bincount(np.maximum(ev.label[hits[off[k]:off[k + 1]]], 0)).argmax()
+                    for k in range(nt)], np.int64)
+    k = np.nonzero(up >= 0)[0]
+    res = {"workload": "sector-track merging of the found tracks of the central event "
+                       "(18 sectors per side, windows 3 cm, 2 cm, 0.1, 0.02, 2 c/GeV)",
+           "ms": ms, "tracks_per_s": nt / (ms * 1e-3), "tracks": nt,
+           "kernels_us": {k_: round(v * 1e3, 1) for k_, v in per.items()},
+           "roofline_pairs": {"kernel": "k_merge_best", "bound": "alu",
+                              "achieved": fl / (best_ms * 1e-3) / 1e12,
+                              "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": fl / (best_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                              "flops_per_launch": fl, "candidate_pairs": pairs},
+           "links": int(len(k)), "groups": int(len(np.unique(grp))),
+           "link_purity": float(np.mean(maj[k] == maj[up[k]])) if len(k) else None}
+    log(f"[bench] merging {ms:.3f} ms ({nt} tracks, {pairs} pairs): {res['links']} links, "
+        f"purity {res['link_purity']}, {res['groups']} groups")
     return res
 
 

@@ -280,6 +280,56 @@ int tpc_attach_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_cluster
                         int32_t* track, uint8_t* state, void* d_ws, size_t ws_bytes,
                         void* stream);
 
+/* ---- sector-track merging ------------------------------------------------ */
+
+/* Cuts of the merging.  Sectors form sides of sectors_per_side (>= 3)
+ * sectors; sector s lies on side s / sectors_per_side at index
+ * i = s % sectors_per_side, its frame turned by (i + 1/2) times the sector
+ * width, whose cosine and sine (float32) are cos_width and sin_width.
+ * inv_window: inverse window widths of y, z [1/cm], sin(phi), tan(lambda)
+ * and q/pT (finite, >= 0). */
+typedef struct tpc_merge_cuts {
+    int32_t sectors_per_side;
+    float cos_width, sin_width;
+    float inv_window[5];
+} tpc_merge_cuts;
+
+/* Sector-track merging (section 2: the first fit of the sector tracks serves
+ * to find the whole track; section 3: sector boundaries).  The sector of a
+ * track is that of its first hit; the up neighbour of index i is
+ * (i + 1) % sectors_per_side on the same side, the down neighbour
+ * (i + sectors_per_side - 1) % sectors_per_side.  For track k and a track j
+ * of a neighbour sector, j's state (its tracklet's par at the plane of
+ * row_inner, x_j) is turned into the frame of k's sector by D (cos D =
+ * cos_width, sin D = +sin_width when j lies in the up neighbour, -sin_width
+ * in the down one):
+ *   x' = x c - y sd, y' = x sd + y c, sin' = sin c + cos sd,
+ *   cos' = cos c - sin sd (cos = sqrt((1 - sin)(1 + sin))),
+ * valid when cos' > 0 and |sin'| < s_max, and transported to x_k as in
+ * tracklet construction (no candidate where that stops).  With
+ * r_i = (p'_i - p_k,i) * inv_window[i], d2 = ((((r0^2 + r1^2) + r2^2) +
+ * r3^2) + r4^2) in float32; a candidate needs d2 < 1.  In each direction the
+ * best partner has the least d2, ties to the lower index; k and j are linked
+ * when each is the other's best partner.  Per track k (device arrays of
+ * tracks.capacity entries, owned by the caller; entries from the track
+ * count on are not written):
+ *   link_up[k]: the linked track in the up neighbour, else -1;
+ *   link_dn[k]: the linked track in the down neighbour, else -1;
+ *   group[k]:   the least track index on k's chain of links.
+ * tracklets and tracks are those of the tracking calls on the same problem,
+ * in any track order; d_n_tracks (device) holds the track count, tracks
+ * beyond tracks.capacity do not exist.  d_ws: tpc_merge_workspace_size
+ * bytes of device scratch for tracks.capacity tracks.  Returns
+ * TPC_ERR_INVALID_ARG for a null pointer, a capacity outside [0, 2^31), a
+ * sector count that is not a multiple of sectors_per_side, sectors_per_side
+ * < 3, a non-finite cut or a short workspace; asynchronous on stream. */
+int tpc_merge_workspace_size(const tpc_problem* h_prob, int64_t track_capacity, size_t* h_bytes);
+int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
+                            tpc_tracklets tracklets, tpc_tracks tracks,
+                            const int64_t* d_n_tracks, tpc_merge_cuts cuts, int32_t* link_up,
+                            int32_t* link_dn, int32_t* group, void* d_ws, size_t ws_bytes,
+                            void* stream);
+
 /* ---- calibrated refit ---------------------------------------------------- */
 
 /* Calibration model.  For a cluster of a sector on z side `side` (+1/-1) on

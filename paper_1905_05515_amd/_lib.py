@@ -61,6 +61,11 @@ class CalibModel(C.Structure):
     _fields_ = [(n, F32) for n in ("drift_len", "vd", "tan_half", "u_centre", "u_scale")]
 
 
+class MergeCuts(C.Structure):
+    _fields_ = [("sectors_per_side", C.c_int32), ("cos_width", C.c_float),
+                ("sin_width", C.c_float), ("inv_window", C.c_float * 5)]
+
+
 class TrackHits(C.Structure):
     _fields_ = [("off", P), ("idx", P), ("row", P), ("y", P), ("z", P), ("side", P),
                 ("d_count", P), ("n_tracks", I64), ("n_hits", I64)]
@@ -90,6 +95,9 @@ EXPORTS = {
     "tpc_attach_workspace_size": (C.c_int, [C.POINTER(Problem), C.POINTER(C.c_size_t)]),
     "tpc_attach_clusters": (C.c_int, [P, C.POINTER(Problem), Clusters, Grid, Tracklets, Tracks,
                                       P, F32, F32, P, P, P, C.c_size_t, P]),
+    "tpc_merge_workspace_size": (C.c_int, [C.POINTER(Problem), I64, C.POINTER(C.c_size_t)]),
+    "tpc_merge_sector_tracks": (C.c_int, [P, C.POINTER(Problem), Tracklets, Tracks, P, MergeCuts,
+                                          P, P, P, P, C.c_size_t, P]),
     "tpc_status_string": (C.c_char_p, [C.c_int]),
     "tpc_timing_enable": (C.c_int, [P, C.c_int]),
     "tpc_timing_report": (C.c_int, [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(I64),

@@ -4,6 +4,7 @@ kernels; nothing here computes the method."""
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -285,6 +286,47 @@ def attach_clusters(ctx: Context, ev: Event, radius: float = 1.5, pt_good: float
                                         _ptr(ws), ws.numel(), _stream(stream)),
             "tpc_attach_clusters")
     return track[:n], state[:n]
+
+
+MERGE_WINDOWS = (3.0, 2.0, 0.1, 0.02, 2.0)   # y, z [cm], sin(phi), tan(lambda), q/pT
+
+
+def merge_cuts(sectors_per_side: int = 18, windows=MERGE_WINDOWS) -> "L.MergeCuts":
+    """Cuts of the sector-track merging: the sector width is the full turn
+    over sectors_per_side; cos, sin and the inverse windows in float32."""
+    w = math.radians(360.0 / sectors_per_side)
+    iw = np.float32(1.0) / np.asarray(windows, np.float32)
+    cuts = L.MergeCuts()
+    cuts.sectors_per_side = int(sectors_per_side)
+    cuts.cos_width = float(np.float32(math.cos(w)))
+    cuts.sin_width = float(np.float32(math.sin(w)))
+    for i in range(5):
+        cuts.inv_window[i] = float(iw[i])
+    return cuts
+
+
+def merge_sector_tracks(ctx: Context, ev: Event, sectors_per_side: int = 18,
+                        windows=MERGE_WINDOWS, stream=None):
+    """Sector-track merging of the event's found tracks (after the tracking
+    calls): returns device tensors (link_up, link_dn, group) of
+    tracks.capacity entries; the first n_tracks of them are written."""
+    dev = ev.t["row"].device
+    cap = ev.track_capacity
+    need = C.c_size_t(0)
+    L.check(L.lib().tpc_merge_workspace_size(C.byref(ev.problem), cap, C.byref(need)),
+            "tpc_merge_workspace_size")
+    ws = ev.t.get("merge_ws")
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=dev)
+        ev.t["merge_ws"] = ws
+    out = [torch.empty(max(cap, 1), dtype=torch.int32, device=dev) for _ in range(3)]
+    L.check(L.lib().tpc_merge_sector_tracks(ctx.handle, C.byref(ev.problem), _tracklets(ev),
+                                            _tracks(ev), status_count_ptr(ev),
+                                            merge_cuts(sectors_per_side, windows),
+                                            *[_ptr(o) for o in out], _ptr(ws), ws.numel(),
+                                            _stream(stream)),
+            "tpc_merge_sector_tracks")
+    return tuple(out)
 
 
 def get_status(ev: Event, stream=None) -> dict:

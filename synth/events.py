@@ -335,12 +335,14 @@ def _sector_crossings(trk, max_turn=math.pi, n_turns=1, chunk=512, workers=None)
     random numbers): large track sets are split over worker processes
     (started fresh, so that a parent process that uses a GPU is never
     forked), the chunks joined in track order, so the result does not depend
-    on the number of workers."""
+    on the number of workers; TPC_SYNTH_WORKERS sets it)."""
     k_all = CURV_PER_QPT64 * trk["qpt"]
     T = k_all.shape[0]
     ranges = [(a, min(T, a + chunk)) for a in range(0, T, chunk)]
     if workers is None:
-        workers = min(16, os.cpu_count() or 1)
+        # TPC_SYNTH_WORKERS=1 keeps the work in this process (for runs under a
+        # profiler that instruments every child process)
+        workers = int(os.environ.get("TPC_SYNTH_WORKERS", min(16, os.cpu_count() or 1)))
     if workers > 1 and len(ranges) >= 16:
         import multiprocessing as mp
         keys = ("vx", "vy", "vz", "phi0", "tanl")

@@ -305,15 +305,22 @@ def _crossings_chunk(trk, k_all, a, b, max_turn, n_turns, offset=0, chunk=512):
     keep = ((xcl + R >= ROW_X64[0]) & (xcl - R <= ROW_X64[-1]) &
             (ycl + R >= -ymax) & (ycl - R <= ymax))
     ti, si = np.nonzero(keep)
+    # later turns only for helices that stay inside the outer radius of the
+    # drift volume; any other track leaves it within its first half turn
+    r_out = ROW_X64[-1] / math.cos(SECTOR_WIDTH / 2)
+    contained = np.hypot(xc, yc) + 1.0 / np.abs(k) <= r_out
+    tmax = np.where(contained, max_turn, min(max_turn, math.pi))
     out = ([], [], [], [], [])
     if ti.shape[0] == 0:
         return tuple(np.zeros(0, d) for d in (np.int64, np.int64, np.float64, np.float64,
                                               np.int64))
     col = lambda v: v[ti][:, None]
-    for valid, yl, z, _ in helix_plane_point(col(vx), col(vy), col(vz), col(phi0), col(tanl),
-                                              col(k), alphas[si][:, None], ROW_X64[None, :],
-                                              max_turn=max_turn, n_turns=n_turns):
-        m = valid & (np.abs(yl) <= ylim_row[None, :]) & (np.abs(z) <= DRIFT_LEN)
+    for valid, yl, z, turn in helix_plane_point(col(vx), col(vy), col(vz), col(phi0),
+                                                 col(tanl), col(k), alphas[si][:, None],
+                                                 ROW_X64[None, :], max_turn=max_turn,
+                                                 n_turns=n_turns):
+        m = (valid & (turn <= col(tmax)) & (np.abs(yl) <= ylim_row[None, :]) &
+             (np.abs(z) <= DRIFT_LEN))
         pi, ri = np.nonzero(m)
         zz = z[pi, ri]
         out[0].append(si[pi] + N_SECTORS_PER_SIDE * (zz < 0))

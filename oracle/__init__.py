@@ -241,6 +241,19 @@ def merge_sector_tracks(sector_offsets, sectors_per_side, row_x, prm, trk_off, t
     return up[:nt], dn[:nt], grp[:nt]
 
 
+def track_t0(par, x_in, side, prm, vd=2.58):
+    """Interaction time of every track (section 2, continuous read-out):
+    returns (z0, y0, t0, ok) at the plane x = 0 of each track's frame."""
+    par = np.ascontiguousarray(par, np.float32).reshape(-1, 5)
+    n = par.shape[0]
+    out = [np.empty(max(n, 1), np.float32) for _ in range(3)]
+    ok = np.empty(max(n, 1), np.int8)
+    lib().orc_track_t0(C.c_int64(n), _p(par), _p(np.ascontiguousarray(x_in, np.float32)),
+                       _p(np.ascontiguousarray(side, np.int8)), C.c_float(prm["curv"]),
+                       C.c_float(prm["s_max"]), C.c_float(vd), *[_p(o) for o in out], _p(ok))
+    return out[0][:n], out[1][:n], out[2][:n], ok[:n]
+
+
 def track_event(row, y, z, layout, n_bins, row_x, prm, n_rows=152, brute=False):
     """The whole chain: grid, neighbours, cleaning, starts, tracklets,
     selection.  Returns a dict of every intermediate (id space)."""

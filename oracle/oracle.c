@@ -846,3 +846,33 @@ void orc_merge_sector_tracks(int n_sec, const int64_t* sector_offsets, int sps,
     free(fill);
     free(members);
 }
+
+/* ---- per-track interaction time (section 2: continuous read-out; the z of
+ * a hit depends on the unknown time of its collision) -----------------------
+ * Readings: a primary track comes from the beam axis at z = 0; the tracker
+ * sees z* = z - side * vd * t for a collision at time t (side +1 for z > 0,
+ * -1 for z < 0).  The track's state (par at the plane x = row_x[rin]) is
+ * transported to the plane x = 0 of its sector frame, which contains the
+ * beam axis, with the tracker's transport: there y0 is the distance from
+ * the axis (0 for a primary) and z0 = -side * vd * t, so the estimate is
+ * t0 = (side > 0 ? -z0 : z0) / vd (float32).  ok = 0 (and z0, y0, t0 = 0)
+ * where the transport stops. */
+void orc_track_t0(int64_t n_tracks, const float* par, const float* x_in,
+                  const signed char* side, float curv, float s_max, float vd, float* z0,
+                  float* y0, float* t0, signed char* ok)
+{
+    for (int64_t k = 0; k < n_tracks; k++) {
+        float p[5], C[15];
+        for (int i = 0; i < 5; i++) p[i] = par[5 * k + i];
+        for (int i = 0; i < 15; i++) C[i] = 0.0f;
+        if (!propagate_f(p, C, 0.0f - x_in[k], curv, s_max)) {
+            z0[k] = y0[k] = t0[k] = 0.0f;
+            ok[k] = 0;
+            continue;
+        }
+        y0[k] = p[0];
+        z0[k] = p[1];
+        t0[k] = (side[k] > 0 ? -p[1] : p[1]) / vd;
+        ok[k] = 1;
+    }
+}

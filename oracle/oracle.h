@@ -165,6 +165,14 @@ void orc_merge_sector_tracks(int n_sec, const int64_t* sector_offsets, int sps,
 int orc_merge_transform(const float* pj, float xj, float c, float sd, float x_to, float curv,
                         float s_max, float* out5);
 
+/* Interaction time of every track (section 2, continuous read-out): the
+ * state (par[5k] at x_in[k]) transported to the plane x = 0 of its sector
+ * frame; y0, z0 there and t0 = (side > 0 ? -z0 : z0) / vd; ok 0 (zeros)
+ * where the transport stops. */
+void orc_track_t0(int64_t n_tracks, const float* par, const float* x_in,
+                  const signed char* side, float curv, float s_max, float vd, float* z0,
+                  float* y0, float* t0, signed char* ok);
+
 /* Single steps, exposed for the tests. */
 int orc_propagate32(float* p, float* C, float dx, float curv, float s_max);
 int orc_propagate64(double* p, double* C, double dx, double curv, double s_max);

@@ -1,0 +1,122 @@
+"""Pins of the oracle's per-track interaction time (section 2: in continuous
+read-out the z of a hit depends on the unknown time of its collision; the
+first fit of a track, assumed primary, improves the z estimate).
+
+Pinned against helix geometry: a helix from the beam axis seen at any
+sector-local plane, with its z shifted by the drift of a collision at time
+t, must come back to z = -side * vd * t and y = 0 at the plane x = 0 (both
+sides, both charges); a straight track from a displaced vertex has the
+closed-form intercept; the transport's stop gives no estimate; and on a
+seeded continuous read-out slice the primaries' estimates recover their
+collisions' times."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.events import CURV_PER_QPT64, VD_CM_PER_US
+
+W = math.radians(20.0)
+CURV = float(CURV_PER_QPT64)
+X = synth.ROW_X.astype(np.float64)
+PRM = synth.default_params()
+
+
+def _state(phi0, qpt, tanl, alpha, x, vz=0.0):
+    """Closed-form state of the helix from (0, 0, vz) at plane x of the frame
+    turned by alpha (outgoing branch)."""
+    k = CURV * qpt
+    xc, yc = -math.sin(phi0) / k, math.cos(phi0) / k
+    xcl = xc * math.cos(alpha) + yc * math.sin(alpha)
+    ycl = -xc * math.sin(alpha) + yc * math.cos(alpha)
+    s = k * (x - xcl)
+    phi = math.asin(s)
+    y = ycl - math.cos(phi) / k
+    arc = (phi - math.remainder(phi0 - alpha, 2 * math.pi)) / k
+    assert arc > 0
+    return np.array([y, vz + tanl * arc, s, tanl, qpt])
+
+
+def test_primaries_come_back_to_the_collision_time():
+    rng = np.random.default_rng(5)
+    par, xin, side, t_true = [], [], [], []
+    for _ in range(300):
+        i = int(rng.integers(0, 18))
+        phi0 = (i + 0.5) * W + rng.uniform(-0.1, 0.1)
+        qpt = rng.choice([-1, 1]) / rng.uniform(0.5, 5.0)
+        sd = int(rng.choice([-1, 1]))
+        tanl = sd * rng.uniform(0.02, 1.0)
+        r = int(rng.integers(0, 152))
+        t = rng.uniform(0.0, 90.0)
+        p = _state(phi0, qpt, tanl, (i + 0.5) * W, X[r])
+        p[1] -= sd * VD_CM_PER_US * t          # the drift of a collision at t
+        par.append(p)
+        xin.append(synth.ROW_X[r])
+        side.append(sd)
+        t_true.append(t)
+    z0, y0, t0, ok = oracle.track_t0(np.array(par), np.array(xin), np.array(side), PRM,
+                                     vd=VD_CM_PER_US)
+    assert ok.all()
+    t_true = np.array(t_true)
+    np.testing.assert_allclose(y0, 0.0, atol=5e-3)
+    np.testing.assert_allclose(z0, -np.array(side) * VD_CM_PER_US * t_true, atol=5e-3)
+    np.testing.assert_allclose(t0, t_true, atol=2e-3)
+
+
+def test_straight_track_from_a_displaced_vertex():
+    # q/pT = 0: the line through (x_in, y_in) with slope s/c meets x = 0 at
+    # y_in - x_in s/c, z_in - x_in t/c
+    p = np.array([[3.0, 50.0, 0.2, 0.4, 0.0], [-2.0, -30.0, -0.1, -0.3, 0.0]], np.float32)
+    xin = np.array([120.0, 200.0], np.float32)
+    z0, y0, t0, ok = oracle.track_t0(p, xin, np.array([1, -1]), PRM, vd=2.5)
+    c = np.sqrt(1 - p[:, 2].astype(np.float64) ** 2)
+    np.testing.assert_allclose(y0, p[:, 0] - xin * p[:, 2] / c, atol=1e-4)
+    np.testing.assert_allclose(z0, p[:, 1] - xin * p[:, 3] / c, atol=1e-4)
+    np.testing.assert_allclose(t0, [-z0[0] / 2.5, z0[1] / 2.5], rtol=1e-6)
+    assert ok.all()
+
+
+def test_transport_stop_gives_no_estimate():
+    # sin(phi) = 0.9 at x = 200 with a curvature that reaches 0.95 before x = 0
+    qpt = 0.5 / (CURV * 200.0)
+    p = np.array([[0.0, 10.0, 0.9, 0.1, -qpt]], np.float32)
+    z0, y0, t0, ok = oracle.track_t0(p, np.array([200.0], np.float32), np.array([1]), PRM)
+    assert ok[0] == 0 and z0[0] == 0 and t0[0] == 0
+
+
+def test_empty():
+    z0, y0, t0, ok = oracle.track_t0(np.zeros((0, 5), np.float32), np.zeros(0, np.float32),
+                                     np.zeros(0, np.int8), PRM)
+    assert len(z0) == len(ok) == 0
+
+
+@pytest.mark.timeout(600)
+def test_slice_primaries_recover_their_collision_times():
+    from paper_1905_05515_amd.layout import grid_layout
+    ev = synth.make_config3(n_collisions=3)
+    tab, nb = grid_layout(ev.sector_offsets, ev.sector_range, occupancy=0.25,
+                          sides=ev.sector_side)
+    o = oracle.track_event(ev.row, ev.y, ev.z, tab, nb, ev.row_x, PRM)
+    trk, trl = o["tracks"], o["tracklets"]
+    tt = trk["trk_tracklet"]
+    off, hits = trk["trk_off"], trk["trk_hits"]
+    sec = np.searchsorted(ev.sector_offsets, hits[off[:-1]], side="right") - 1
+    z0, y0, t0, ok = oracle.track_t0(trl["par"][tt], ev.row_x[trl["row_inner"][tt]],
+                                     ev.sector_side[sec], PRM, vd=VD_CM_PER_US)
+    maj = np.array([np.bincount(np.maximum(ev.label[hits[off[k]:off[k + 1]]], 0)).argmax()
+                    for k in range(len(off) - 1)])
+    T = ev.tracks
+    prim = (T["vx"][maj] == 0) & (T["vy"][maj] == 0) & (np.abs(T["qpt"][maj]) < 1 / 0.3)
+    sel = ok.astype(bool) & prim
+    t_true = T["t_us"][maj]
+    d = np.abs(t0[sel] - t_true[sel])
+    assert sel.sum() > 5000
+    assert np.median(d) < 0.05 and np.quantile(d, 0.9) < 0.5
+    for tc in np.unique(t_true[sel]):
+        m = sel & (t_true == tc)
+        assert abs(np.median(t0[m]) - tc) < 0.02
+    # primaries pass close to the axis, secondaries (vertices up to 50 cm) do not
+    assert np.median(np.abs(y0[sel])) < 0.5
+    assert np.median(np.abs(y0[ok.astype(bool) & ~prim & (T["vx"][maj] != 0)])) > 5

@@ -633,9 +633,13 @@ def slice_bench(args, api, synth, ctx, stream, prm):
         kt = api.timing_report(ctx)
         api.timing_enable(ctx, False)
     st = api.get_status(e, stream)
+    # before the seeding probe, which runs the grid and neighbour calls again
+    # and so resets the event's track count
+    res["track_t0"] = slice_t0(api, ctx, e, ev, stream, steps, int(st["n_tracks"]))
     res.update({
         "workload": "100 collisions, Poisson arrivals at 50 kHz, multiplicity U(5%, 100%) of the "
-                    "central event, pT >= 0.05 GeV, loopers up to 3 turns, z* = z - vd t "
+                    "central event, pT >= 0.05 GeV, loopers inside the drift volume up to 3 "
+                    "turns, z* = z - vd t "
                     "(seed 3003)",
         "clusters": ev.n_clusters, "ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3),
         "launch_form": "staged, HIP graph", "starts": int(st["n_starts"]),
@@ -649,6 +653,46 @@ def slice_bench(args, api, synth, ctx, stream, prm):
         f"{res['roofline_grid_to_starts']['frac'] * 100:.1f}% of HBM peak")
     del e
     torch.cuda.empty_cache()
+    return res
+
+
+def slice_t0(api, ctx, e, ev, stream, steps, n_tracks):
+    """Interaction time of every found track of the slice: time per call and
+    the resolution on primaries above 0.3 GeV/c (truth: the generating track
+    of the track's first hit)."""
+    import numpy as np
+    import torch
+    from synth.events import VD_CM_PER_US
+    with torch.cuda.stream(stream):
+        api.track_t0(ctx, e, VD_CM_PER_US, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            z0, y0, t0, ok = api.track_t0(ctx, e, VD_CM_PER_US, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    nt = min(n_tracks, e.track_capacity)
+    off = e.t["trk_off"][:nt + 1].cpu().numpy()
+    hits = e.t["trk_hits"]
+    idx = np.clip(off[:-1], 0, hits.numel() - 1)
+    first = hits[torch.as_tensor(idx, device=hits.device).long()]
+    lab = ev.label[first.cpu().numpy()]
+    t0, ok = t0[:nt].cpu().numpy(), ok[:nt].cpu().numpy().astype(bool)
+    T = ev.tracks
+    li = np.maximum(lab, 0)
+    prim = (lab >= 0) & (T["vx"][li] == 0) & (T["vy"][li] == 0) & (np.abs(T["qpt"][li]) < 1 / 0.3)
+    sel = ok & prim
+    d = np.abs(t0[sel] - T["t_us"][li][sel])
+    res = {"ms": ms, "tracks_per_s": nt / (ms * 1e-3), "tracks": nt,
+           "ok_fraction": float(ok.mean()) if nt else None,
+           "primaries_above_0.3_GeV": int(sel.sum()),
+           "abs_dt_us_median": float(np.median(d)) if len(d) else None,
+           "abs_dt_us_q90": float(np.quantile(d, 0.9)) if len(d) else None}
+    log(f"[bench]   slice t0 {ms * 1e3:.1f} us for {nt} tracks; primaries |dt| median "
+        f"{res['abs_dt_us_median']} us, q90 {res['abs_dt_us_q90']} us")
     return res
 
 

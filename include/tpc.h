@@ -330,6 +330,27 @@ int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
                             int32_t* link_dn, int32_t* group, void* d_ws, size_t ws_bytes,
                             void* stream);
 
+/* ---- per-track interaction time ----------------------------------------- */
+
+/* Interaction time of every track in continuous read-out (section 2: the z
+ * of a hit depends on the unknown time of its collision).  A primary comes
+ * from the beam axis at z = 0; a collision at time t shifts the z the
+ * tracker sees by -side * vd * t (side of the track's sector: that of its
+ * first hit; +1 for a track without hits).  The state of the track's
+ * tracklet (par at the plane of row_inner, x_in) is transported to the
+ * plane x = 0 of its sector frame with the tracklet transport (one step,
+ * dx = 0 - x_in).  Per track k (device arrays of tracks.capacity entries,
+ * owned by the caller; entries from the track count on are not written):
+ *   y0[k], z0[k]: the state's y and z at x = 0 (y0 is 0 for a primary);
+ *   t0[k]: (side > 0 ? -z0 : z0) / vd, float32 [time unit of vd];
+ *   ok[k]: 1, or 0 (and zeros) where |sin(phi)| would reach s_max.
+ * d_n_tracks (device) holds the track count.  Returns TPC_ERR_INVALID_ARG
+ * for a null pointer, vd not finite and > 0 or a negative capacity;
+ * asynchronous on stream. */
+int tpc_track_t0(tpc_context* ctx, const tpc_problem* h_prob, tpc_tracklets tracklets,
+                 tpc_tracks tracks, const int64_t* d_n_tracks, float vd, float* z0, float* y0,
+                 float* t0, int8_t* ok, void* stream);
+
 /* ---- calibrated refit ---------------------------------------------------- */
 
 /* Calibration model.  For a cluster of a sector on z side `side` (+1/-1) on

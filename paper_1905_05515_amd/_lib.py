@@ -98,6 +98,7 @@ EXPORTS = {
     "tpc_merge_workspace_size": (C.c_int, [C.POINTER(Problem), I64, C.POINTER(C.c_size_t)]),
     "tpc_merge_sector_tracks": (C.c_int, [P, C.POINTER(Problem), Tracklets, Tracks, P, MergeCuts,
                                           P, P, P, P, C.c_size_t, P]),
+    "tpc_track_t0": (C.c_int, [P, C.POINTER(Problem), Tracklets, Tracks, P, F32, P, P, P, P, P]),
     "tpc_status_string": (C.c_char_p, [C.c_int]),
     "tpc_timing_enable": (C.c_int, [P, C.c_int]),
     "tpc_timing_report": (C.c_int, [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(I64),

@@ -329,6 +329,21 @@ def merge_sector_tracks(ctx: Context, ev: Event, sectors_per_side: int = 18,
     return tuple(out)
 
 
+def track_t0(ctx: Context, ev: Event, vd: float = 2.58, stream=None):
+    """Interaction time of the event's found tracks in continuous read-out
+    (after the tracking calls): device tensors (z0, y0, t0 float32, ok int8)
+    of tracks.capacity entries; the first n_tracks of them are written."""
+    dev = ev.t["row"].device
+    cap = max(ev.track_capacity, 1)
+    out = [torch.empty(cap, dtype=torch.float32, device=dev) for _ in range(3)]
+    ok = torch.empty(cap, dtype=torch.int8, device=dev)
+    L.check(L.lib().tpc_track_t0(ctx.handle, C.byref(ev.problem), _tracklets(ev), _tracks(ev),
+                                 status_count_ptr(ev), float(vd), *[_ptr(o) for o in out],
+                                 _ptr(ok), _stream(stream)),
+            "tpc_track_t0")
+    return out[0], out[1], out[2], ok
+
+
 def get_status(ev: Event, stream=None) -> dict:
     st = L.Status()
     L.check(L.lib().tpc_get_status(_ptr(ev.t["ws"]), C.byref(st), _stream(stream)),

@@ -555,9 +555,20 @@ def merge_bench(args, api, ctx, e, ev, stream):
     up = up[:nt].cpu().numpy()
     grp = grp[:nt].cpu().numpy()
     sec = np.searchsorted(ev.sector_offsets, hits[off[:-1]], side="right") - 1
-    cnt = np.bincount(sec, minlength=len(ev.sector_offsets) - 1)
+    # candidate pairs the pair kernel evaluates: the tracks of each neighbour
+    # sector whose tan(lambda) lies within the window of the track's
+    tl = r["t_par"][r["trk_tracklet"], 3].astype(np.float32)
+    iw3 = np.float32(1.0) / np.float32(api.MERGE_WINDOWS[3])
     side, idx = sec // 18, sec % 18
-    pairs = int(np.sum(cnt[side * 18 + (idx + 1) % 18] + cnt[side * 18 + (idx + 17) % 18]))
+    srt = {s_: np.sort(tl[sec == s_]) for s_ in range(len(ev.sector_offsets) - 1)}
+    pairs = 0
+    for nb in ((side * 18 + (idx + 1) % 18), (side * 18 + (idx + 17) % 18)):
+        for s_ in np.unique(nb):
+            m = nb == s_
+            c = srt[s_]
+            lo = np.searchsorted(c, tl[m] - np.float32(1.0) / iw3, side="right")
+            hi = np.searchsorted(c, tl[m] + np.float32(1.0) / iw3, side="left")
+            pairs += int(np.sum(hi - lo))
     best_ms = per.get("k_merge_best", ms)
     fl = FLOPS_MERGE_PAIR * pairs
     maj = np.array([np.bincount(np.maximum(ev.label[hits[off[k]:off[k + 1]]], 0)).argmax()
@@ -571,7 +582,8 @@ def merge_bench(args, api, ctx, e, ev, stream):
                               "achieved": fl / (best_ms * 1e-3) / 1e12,
                               "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": fl / (best_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
-                              "flops_per_launch": fl, "candidate_pairs": pairs},
+                              "flops_per_launch": fl,
+                              "candidate_pairs_in_tan_lambda_windows": pairs},
            "links": int(len(k)), "groups": int(len(np.unique(grp))),
            "link_purity": float(np.mean(maj[k] == maj[up[k]])) if len(k) else None}
     log(f"[bench] merging {ms:.3f} ms ({nt} tracks, {pairs} pairs): {res['links']} links, "
@@ -636,6 +648,7 @@ def slice_bench(args, api, synth, ctx, stream, prm):
     # before the seeding probe, which runs the grid and neighbour calls again
     # and so resets the event's track count
     res["track_t0"] = slice_t0(api, ctx, e, ev, stream, steps, int(st["n_tracks"]))
+    res["track_merging"] = slice_merge(api, ctx, e, stream, steps, int(st["n_tracks"]))
     res.update({
         "workload": "100 collisions, Poisson arrivals at 50 kHz, multiplicity U(5%, 100%) of the "
                     "central event, pT >= 0.05 GeV, loopers inside the drift volume up to 3 "
@@ -653,6 +666,34 @@ def slice_bench(args, api, synth, ctx, stream, prm):
         f"{res['roofline_grid_to_starts']['frac'] * 100:.1f}% of HBM peak")
     del e
     torch.cuda.empty_cache()
+    return res
+
+
+def slice_merge(api, ctx, e, stream, steps, n_tracks):
+    """Sector-track merging of every found track of the slice (buckets
+    sorted by tan(lambda), windowed candidate ranges)."""
+    import torch
+    with torch.cuda.stream(stream):
+        api.merge_sector_tracks(ctx, e, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            up, dn, grp = api.merge_sector_tracks(ctx, e, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        api.timing_enable(ctx, True)
+        api.merge_sector_tracks(ctx, e, stream=stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    ms = a.elapsed_time(b) / steps
+    nt = min(n_tracks, e.track_capacity)
+    links = int((up[:nt] >= 0).sum().item())
+    res = {"ms": ms, "tracks": nt, "tracks_per_s": nt / (ms * 1e-3), "links": links,
+           "kernels_us": {k: round(ms_ / n * 1e3, 1) for k, (n, ms_) in kt.items()}}
+    log(f"[bench]   slice merging {ms:.3f} ms for {nt} tracks, {links} links")
     return res
 
 

@@ -11,13 +11,21 @@
 // bucket of every sector stores, per candidate, its state already turned
 // into the frames of both neighbour sectors (the turn does not depend on
 // the track it is compared with), 32 bytes per direction, so the pair loop
-// streams contiguous records.  The pair loop is split over kSlices threads
+// streams contiguous records.  Every bucket is sorted by tan(lambda), which
+// neither the turn nor the transport changes: a candidate passes only if
+// r3 = (tl_j - tl_k) / win_3 lies in (-1, 1) (else r3^2 >= 1 and so
+// d2 >= 1), and r3 grows with tl_j, so the candidates that can pass form one
+// range of the sorted bucket, found by two binary searches with the same
+// float expression; the result is the brute-force one.  The pair loop over
+// that range is split over kSlices threads
 // per (track, direction), each taking every kSlices-th candidate, with the
 // lanes of a wave on consecutive tracks of one sector reading the same
 // record; the slices' minima meet in a 64-bit atomic min of the key
 // (bits(d2) << 32 | index): d2 >= +0 orders like its bit pattern, so the
 // least key is the least d2 and, among equal ones, the lower index, and the
 // result does not depend on the bucket order or the order of the atomics.
+#include <hipcub/hipcub.hpp>
+
 #include "tracklet_dev.hpp"
 
 namespace tpc {
@@ -33,12 +41,20 @@ struct MergeWs {
     int32_t* fill;             // [n_sec + 1] bucket fill counters
     int32_t* first;            // [n_sec + 1] first bucket slot of every sector
     unsigned long long* key;   // [2 * cap] best partner key per (track, direction)
-    float4* rec;               // [2][cap][2] bucketed candidate records
+    float4* rec;               // [2][cap][2] bucketed candidate records (fill order)
+    float4* rec_s;             // [2][cap][2] the same, each bucket sorted by tan(lambda)
+    float* tl;                 // [cap] sorted tan(lambda) (NaN as +inf)
+    uint32_t* key_in;          // [cap] order-preserving bits of tan(lambda)
+    uint32_t* key_out;
+    int32_t* val_in;           // [cap] fill slot
+    int32_t* val_out;
+    void* sort_tmp;            // segmented radix sort scratch
+    size_t sort_bytes;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-void layout_merge(const tpc_problem* p, int64_t cap, void* base, MergeWs* w, size_t* bytes)
+bool layout_merge(const tpc_problem* p, int64_t cap, void* base, MergeWs* w, size_t* bytes)
 {
     const size_t c = (size_t)(cap > 0 ? cap : 1);
     const size_t ns = (size_t)p->n_sectors + 1;
@@ -47,6 +63,18 @@ void layout_merge(const tpc_problem* p, int64_t cap, void* base, MergeWs* w, siz
     const size_t o_rec = o;  o += align256(sizeof(float4) * 4 * c);
     const size_t o_sec = o;  o += align256(sizeof(int32_t) * c);
     const size_t o_cnt = o;  o += align256(sizeof(int32_t) * 3 * ns);
+    const size_t o_rs = o;   o += align256(sizeof(float4) * 4 * c);
+    const size_t o_tl = o;   o += align256(sizeof(float) * c);
+    const size_t o_ki = o;   o += align256(sizeof(uint32_t) * c);
+    const size_t o_ko = o;   o += align256(sizeof(uint32_t) * c);
+    const size_t o_vi = o;   o += align256(sizeof(int32_t) * c);
+    const size_t o_vo = o;   o += align256(sizeof(int32_t) * c);
+    size_t sort_bytes = 0;
+    const hipError_t q = hipcub::DeviceSegmentedRadixSort::SortPairs(
+        nullptr, sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+        (const int32_t*)nullptr, (int32_t*)nullptr, (int)c, p->n_sectors, (const int32_t*)nullptr,
+        (const int32_t*)nullptr, 0, 32, (hipStream_t)0);
+    const size_t o_st = o;   o += align256(sort_bytes > 0 ? sort_bytes : 1);
     *bytes = o;
     if (w) {
         char* b = (char*)base;
@@ -56,7 +84,16 @@ void layout_merge(const tpc_problem* p, int64_t cap, void* base, MergeWs* w, siz
         w->cnt = (int32_t*)(b + o_cnt);
         w->fill = w->cnt + ns;
         w->first = w->fill + ns;
+        w->rec_s = (float4*)(b + o_rs);
+        w->tl = (float*)(b + o_tl);
+        w->key_in = (uint32_t*)(b + o_ki);
+        w->key_out = (uint32_t*)(b + o_ko);
+        w->val_in = (int32_t*)(b + o_vi);
+        w->val_out = (int32_t*)(b + o_vo);
+        w->sort_tmp = (void*)(b + o_st);
+        w->sort_bytes = sort_bytes;
     }
+    return q == hipSuccess;
 }
 
 __device__ __forceinline__ int64_t n_tracks_of(const int64_t* d_n, int64_t cap)
@@ -164,25 +201,63 @@ __global__ __launch_bounds__(kBlock) void k_merge_fill(
             r[0] = make_float4(xr, yr, z, sr);
             r[1] = make_float4(tl, qp, ok ? 1.0f : 0.0f, __int_as_float((int32_t)k));
         }
+        // bits that order like the value: sign bit set for >= +0, all bits
+        // flipped for negatives; NaN last (it is read as +inf below)
+        const uint32_t u = __float_as_uint(tl);
+        w.key_in[slot] = tl != tl ? 0xFFFFFFFFu : (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+        w.val_in[slot] = (int32_t)slot;
     }
 }
 
+// bucket records into tan(lambda) order (both directions)
+__global__ __launch_bounds__(kBlock) void k_merge_gather(int n_sec, int64_t cap, MergeWs w)
+{
+    const int64_t total = w.first[n_sec];
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < total;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t src = w.val_out[m];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const float4* a = w.rec + ((int64_t)d * cap + src) * 2;
+            float4* b = w.rec_s + ((int64_t)d * cap + m) * 2;
+            b[0] = a[0];
+            b[1] = a[1];
+        }
+        const float t = w.rec[src * 2 + 1].x;
+        w.tl[m] = t != t ? __int_as_float(0x7f800000) : t;
+    }
+}
+
+// first m in [lo, hi) with pred(m), pred monotone (false ... true)
+template <typename P>
+__device__ __forceinline__ int first_true(int lo, int hi, P pred)
+{
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (pred(mid)) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 // (track, direction, slice): the least key over every kSlices-th candidate
-// of the neighbour sector's bucket.
+// of the neighbour sector's bucket.  Threads walk the tracks in sorted
+// bucket order, so the lanes of a wave hold tracks of one sector with close
+// tan(lambda) and nearly the same candidate range.
 __global__ __launch_bounds__(kWave) void k_merge_best(
-    int sps, const float* __restrict__ row_x, float curv, float s_max,
+    int n_sec, int sps, const float* __restrict__ row_x, float curv, float s_max,
     const int32_t* __restrict__ trk_tracklet, const float* __restrict__ t_par,
     const int32_t* __restrict__ t_rin, const int64_t* __restrict__ d_n_tracks, int64_t cap,
     float iw0, float iw1, float iw2, float iw3, float iw4, MergeWs w)
 {
     const int slice = blockIdx.y, d = blockIdx.z;
-    const int64_t nt = n_tracks_of(d_n_tracks, cap);
     const float iw[5] = {iw0, iw1, iw2, iw3, iw4};
-    const float4* rec = w.rec + (int64_t)d * cap * 2;
-    for (int64_t k = blockIdx.x * (int64_t)kWave + threadIdx.x; k < nt;
-         k += (int64_t)gridDim.x * kWave) {
+    const float4* rec = w.rec_s + (int64_t)d * cap * 2;
+    const int64_t total = w.first[n_sec];
+    const float4* own = w.rec_s;      // direction 0 records carry the track index
+    for (int64_t q = blockIdx.x * (int64_t)kWave + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * kWave) {
+        const int64_t k = __float_as_int(own[q * 2 + 1].w);
         const int s = w.sec[k];
-        if (s < 0) continue;
         const int nb = neighbour(s, d, sps);
         const int32_t t = trk_tracklet[k];
         const float xk = row_x[t_rin[t]];
@@ -190,8 +265,19 @@ __global__ __launch_bounds__(kWave) void k_merge_best(
 #pragma unroll
         for (int i = 0; i < 5; ++i) pk[i] = t_par[(int64_t)t * 5 + i];
         unsigned long long best = ~0ull;
-        const int m1 = w.first[nb + 1];
-        for (int m = w.first[nb] + slice; m < m1; m += kSlices) {
+        // candidates with r3 = (tl_j - tl_k) * iw3 in (-1, 1); a window
+        // without a tan(lambda) cut takes the whole bucket, a NaN track none
+        int m0 = w.first[nb], m1 = w.first[nb + 1];
+        if (pk[3] != pk[3]) {
+            m1 = m0;
+        } else if (iw[3] != 0.0f) {
+            const float* tl = w.tl;
+            const float tk = pk[3], i3 = iw[3];
+            const int a = first_true(m0, m1, [&](int m) { return (tl[m] - tk) * i3 > -1.0f; });
+            m1 = first_true(a, m1, [&](int m) { return (tl[m] - tk) * i3 >= 1.0f; });
+            m0 = a;
+        }
+        for (int m = m0 + slice; m < m1; m += kSlices) {
             const float4 a = rec[(int64_t)m * 2], b = rec[(int64_t)m * 2 + 1];
             if (!(b.z != 0.0f)) continue;
             // the transport's covariance part is dead code here and drops out
@@ -276,8 +362,8 @@ int tpc_merge_workspace_size(const tpc_problem* h_prob, int64_t track_capacity, 
     if (!h_bytes || track_capacity < 0) return TPC_ERR_INVALID_ARG;
     const int e = tpc_check_problem(h_prob);
     if (e) return e;
-    tpc::layout_merge(h_prob, track_capacity, nullptr, nullptr, h_bytes);
-    return TPC_OK;
+    return tpc::layout_merge(h_prob, track_capacity, nullptr, nullptr, h_bytes) ? TPC_OK
+                                                                                : TPC_ERR_HIP;
 }
 
 int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
@@ -303,7 +389,7 @@ int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
     const int64_t cap = tracks.capacity;
     size_t need = 0;
     tpc::MergeWs w;
-    tpc::layout_merge(h_prob, cap, d_ws, &w, &need);
+    if (!tpc::layout_merge(h_prob, cap, d_ws, &w, &need)) return TPC_ERR_HIP;
     if (need > ws_bytes) return TPC_ERR_INVALID_ARG;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return TPC_ERR_HIP;
@@ -322,9 +408,16 @@ int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
                    h_prob->d_row_x, prm.s_max, (const int32_t*)tracks.tracklet,
                    (const float*)tracklets.par, (const int32_t*)tracklets.row_inner, d_n_tracks,
                    cap, cuts.cos_width, cuts.sin_width, w);
+        if (hipcub::DeviceSegmentedRadixSort::SortPairs(
+                w.sort_tmp, w.sort_bytes, (const uint32_t*)w.key_in, w.key_out,
+                (const int32_t*)w.val_in, w.val_out, (int)cap, n_sec, (const int32_t*)w.first,
+                (const int32_t*)(w.first + 1), 0, 32, st) != hipSuccess)
+            return TPC_ERR_HIP;
+        TPC_LAUNCH(tpc::k_merge_gather, dim3(tpc::grid_for(cap)), dim3(tpc::kBlock), 0, st, n_sec,
+                   cap, w);
         TPC_LAUNCH(tpc::k_merge_best,
                    dim3(tpc::grid_for_block(cap, tpc::kWave, tpc::kMergeRows), tpc::kSlices, 2),
-                   dim3(tpc::kWave), 0, st, sps, h_prob->d_row_x, prm.curv, prm.s_max,
+                   dim3(tpc::kWave), 0, st, n_sec, sps, h_prob->d_row_x, prm.curv, prm.s_max,
                    (const int32_t*)tracks.tracklet, (const float*)tracklets.par,
                    (const int32_t*)tracklets.row_inner, d_n_tracks, cap, cuts.inv_window[0],
                    cuts.inv_window[1], cuts.inv_window[2], cuts.inv_window[3],

@@ -57,6 +57,16 @@ def test_merging_other_windows_and_a_smaller_event():
     _check(ev, windows=(30.0, 20.0, 1.0, 0.2, 20.0))
 
 
+@pytest.mark.timeout(600)
+def test_merging_continuous_slice_matches_the_oracle():
+    """Three collisions of continuous read-out (several collisions' tracks
+    in every sector bucket; the oracle compares every pair)."""
+    ev = synth.make_config3(n_collisions=3)
+    print(f"case merge c3 3 collisions n={ev.n_clusters}", flush=True)
+    _check(ev)
+    _check(ev, windows=(3.0, 2.0, 0.1, float("inf"), 2.0))     # no tan(lambda) cut
+
+
 def test_merging_without_tracks_and_bad_arguments():
     rng = np.random.default_rng(3)
     n = 720

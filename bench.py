@@ -66,10 +66,12 @@ def parse():
                     help="only build the grid and find the chain starts of the 512-instance "
                          "set three times (eager launches; the workload of the HBM byte "
                          "counters of those stages) and exit")
-    ap.add_argument("--inflight", default="auto",
+    ap.add_argument("--inflight", default="3",
                     help="events in flight in the timed step loop (each on its own stream "
-                         "with its own buffers), or 'auto' (1-3, the fastest; with four "
-                         "hardware queues per process more streams serialise)")
+                         "with its own buffers; with four hardware queues per process more "
+                         "than three streams serialise), or 'auto' (times 1-3 first and "
+                         "takes the fastest; after those trials the timed region has run "
+                         "2.5x slower in most runs, so a fixed depth is the default)")
     ap.add_argument("--occupancy", default="auto",
                     help="clusters per grid bin, or 'auto' (autotuned per workload before "
                          "the timed region; the tracks do not depend on it)")

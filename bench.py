@@ -699,6 +699,9 @@ def slice_merge(api, ctx, e, stream, steps, n_tracks):
     return res
 
 
+T0_BYTES_PER_TRACK = 4 + 4 + 4 + 20 + 4 + 13
+
+
 def slice_t0(api, ctx, e, ev, stream, steps, n_tracks):
     """Interaction time of every found track of the slice: time per call and
     the resolution on primaries above 0.3 GeV/c (truth: the generating track
@@ -716,7 +719,15 @@ def slice_t0(api, ctx, e, ev, stream, steps, n_tracks):
             z0, y0, t0, ok = api.track_t0(ctx, e, VD_CM_PER_US, stream=stream)
         b.record(stream)
         torch.cuda.synchronize()
+        api.timing_enable(ctx, True)
+        for _ in range(steps):
+            api.track_t0(ctx, e, VD_CM_PER_US, stream=stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
     ms = a.elapsed_time(b) / steps
+    n_k, ms_k = kt.get("k_track_t0", (1, ms))
+    k_ms = ms_k / max(n_k, 1)
     nt = min(n_tracks, e.track_capacity)
     off = e.t["trk_off"][:nt + 1].cpu().numpy()
     hits = e.t["trk_hits"]
@@ -729,7 +740,13 @@ def slice_t0(api, ctx, e, ev, stream, steps, n_tracks):
     prim = (lab >= 0) & (T["vx"][li] == 0) & (T["vy"][li] == 0) & (np.abs(T["qpt"][li]) < 1 / 0.3)
     sel = ok & prim
     d = np.abs(t0[sel] - T["t_us"][li][sel])
+    # algorithmic bytes per track: off, first hit, tracklet index, state (20),
+    # innermost row; z0, y0, t0 and ok written
+    gbs = T0_BYTES_PER_TRACK * nt / (k_ms * 1e-3) / 1e9
     res = {"ms": ms, "tracks_per_s": nt / (ms * 1e-3), "tracks": nt,
+           "roofline": {"kernel": "k_track_t0", "bound": "hbm", "achieved": gbs,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                        "kernel_ms": k_ms, "bytes_per_track": T0_BYTES_PER_TRACK},
            "ok_fraction": float(ok.mean()) if nt else None,
            "primaries_above_0.3_GeV": int(sel.sum()),
            "abs_dt_us_median": float(np.median(d)) if len(d) else None,

@@ -246,8 +246,8 @@ __device__ __forceinline__ int first_true(int lo, int hi, P pred)
 __global__ __launch_bounds__(kWave) void k_merge_best(
     int n_sec, int sps, const float* __restrict__ row_x, float curv, float s_max,
     const int32_t* __restrict__ trk_tracklet, const float* __restrict__ t_par,
-    const int32_t* __restrict__ t_rin, const int64_t* __restrict__ d_n_tracks, int64_t cap,
-    float iw0, float iw1, float iw2, float iw3, float iw4, MergeWs w)
+    const int32_t* __restrict__ t_rin, int64_t cap, float iw0, float iw1, float iw2, float iw3,
+    float iw4, MergeWs w)
 {
     const int slice = blockIdx.y, d = blockIdx.z;
     const float iw[5] = {iw0, iw1, iw2, iw3, iw4};
@@ -419,7 +419,7 @@ int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
                    dim3(tpc::grid_for_block(cap, tpc::kWave, tpc::kMergeRows), tpc::kSlices, 2),
                    dim3(tpc::kWave), 0, st, n_sec, sps, h_prob->d_row_x, prm.curv, prm.s_max,
                    (const int32_t*)tracks.tracklet, (const float*)tracklets.par,
-                   (const int32_t*)tracklets.row_inner, d_n_tracks, cap, cuts.inv_window[0],
+                   (const int32_t*)tracklets.row_inner, cap, cuts.inv_window[0],
                    cuts.inv_window[1], cuts.inv_window[2], cuts.inv_window[3],
                    cuts.inv_window[4], w);
         TPC_LAUNCH(tpc::k_merge_link, dim3(tpc::grid_for(cap)), dim3(tpc::kBlock), 0, st,

@@ -35,11 +35,15 @@ SECTOR_DTYPE = np.dtype([
 
 
 def lib():
+    """The oracle library; TPC_ORACLE_SO names another build of oracle.c
+    (for checking that a pin fails under a deliberate change of the
+    oracle)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.SO):
+        so = os.environ.get("TPC_ORACLE_SO") or _build.SO
+        if so == _build.SO and not os.path.exists(so):
             _build.build()
-        _lib = C.CDLL(_build.SO)
+        _lib = C.CDLL(so)
     return _lib
 
 
@@ -165,7 +169,7 @@ def select_tracks(n_clusters, prm, tracklets, starts, n_rows=152):
 
 def attach_clusters(sector_offsets, row, y, z, row_x, prm, trk_off, trk_hits, par, rin,
                     radius=1.5, pt_good=0.05, n_rows=152):
-    """Track-based cluster attachment (section 5).  par/rin: the state of
+    """Track-based cluster attachment (section 6).  par/rin: the state of
     each track (5 floats at the plane of row rin).  Returns (track, state)
     per cluster id: owning or adjacent track (-1 none); state bits 1
     attached, 2 adjacent, 4 protected, 8 removed."""

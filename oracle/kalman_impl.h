@@ -36,13 +36,16 @@ typedef struct {
 } FN(jac_t);
 
 /* Propagate p, C from plane x1 to x2 = x1 + dx.  Returns 0 (and leaves
- * p, C untouched) when |sin(phi)| would reach s_max. */
+ * p, C untouched) when |sin(phi)| at either end of the step is not below
+ * s_max: at the far end the track turns back before x2, at the near end an
+ * update has pushed the state past the transport's domain (|s| >= 1 would
+ * take the square root of a negative number). */
 static int FN(propagate)(REAL* p, REAL* C, REAL dx, REAL curv, REAL s_max)
 {
     REAL s = p[2], t = p[3], w = p[4];
     REAL k = curv * w;
     REAL s2 = s + k * dx;
-    if (!(FABS(s2) < s_max)) return 0;
+    if (!(FABS(s) < s_max) || !(FABS(s2) < s_max)) return 0;
     REAL c1 = SQRT((R1 - s) * (R1 + s));
     REAL c2 = SQRT((R1 - s2) * (R1 + s2));
     REAL cc = c1 + c2;

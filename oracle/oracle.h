@@ -131,7 +131,7 @@ void orc_refit64_fd_grad(int64_t n_tracks, const int* trk_off, const uint8_t* ro
                          const double* g, double h_hit, double h_theta,
                          double* grad_y, double* grad_z, double* grad_theta);
 
-/* Track-based cluster attachment (section 5): tube of `radius` around
+/* Track-based cluster attachment (section 6): tube of `radius` around
  * every track over the rows of its hits, its axis the track state par[5k]
  * (at the plane of row rin[k]) transported outwards row by row; unowned
  * clusters in a tube are adjacent to the track of least |q/pT| (ties to the

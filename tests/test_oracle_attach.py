@@ -1,4 +1,4 @@
-"""Pins of the oracle's track-based cluster attachment (section 5: tubes of
+"""Pins of the oracle's track-based cluster attachment (section 6: tubes of
 1.5 cm around the tracks; an unowned cluster in a tube is adjacent to the
 track of highest transverse momentum; clusters in tubes of good tracks are
 protected, attached or adjacent ones that are not are removed).

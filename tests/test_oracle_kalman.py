@@ -92,6 +92,78 @@ def test_propagate_stops_at_s_max():
     assert not ok and np.all(p2 == p)
 
 
+def test_propagate_stops_on_an_incoming_state_past_s_max():
+    """An update can leave |sin(phi)| >= s_max (even > 1); a transport from
+    there stops (state untouched) even when the step's curvature would bring
+    sin(phi) back below s_max: no square root of a negative number."""
+    for s in (0.95, 0.97, 1.02, -1.02):
+        w = -np.sign(s) * 60.0 / abs(CURV) / 1.0596026 * 0.1     # k dx pulls s back by 0.1
+        p = np.array([0.0, 0.0, s, 0.1, w])
+        for fp64 in (True, False):
+            ok, p2, C2 = oracle.propagate(p, lower(np.eye(5)), 1.0596026, CURV, 0.95, fp64=fp64)
+            assert not ok and np.all(p2 == p.astype(p2.dtype)) and np.isfinite(C2).all()
+
+
+def test_straight_line_kalman_equals_least_squares():
+    """B = 0 (curv = 0), the track in the plane y = 0 (so sin(phi) stays
+    exactly 0 and the filter's transport is linear): the filter run plane by
+    plane over measurements with noisy z (and y = 0) equals the regularised
+    least-squares fit with the same Gaussian prior -- mean, full covariance
+    and the sum of the update chi2 (= the minimum of the objective), in
+    float64 to 1e-10.  The y, sin(phi) block is pinned through the
+    covariance, the z, tan(lambda) block through mean and covariance."""
+    rng = np.random.default_rng(8)
+    sy2, sz2 = 0.01, 0.02
+    for _ in range(20):
+        n = int(rng.integers(3, 40))
+        xs = 85.0 + np.cumsum(rng.uniform(0.5, 3.0, n))
+        x0 = 85.0 - rng.uniform(0.0, 5.0)
+        t_true, z_true = rng.uniform(-1, 1), rng.uniform(-50, 50)
+        zm = z_true + t_true * (xs - x0) + rng.normal(0, math.sqrt(sz2), n)
+        # prior: block diagonal {y, s}, {z, t}, {w}
+        Ays = rng.normal(size=(2, 2)) * [[0.2], [0.02]]
+        Azt = rng.normal(size=(2, 2)) * [[0.3], [0.05]]
+        P0 = np.zeros((5, 5))
+        P0[np.ix_([0, 2], [0, 2])] = Ays @ Ays.T + np.diag([0.01, 1e-4])
+        P0[np.ix_([1, 3], [1, 3])] = Azt @ Azt.T + np.diag([0.01, 1e-4])
+        P0[4, 4] = rng.uniform(1, 100)
+        mu0 = np.array([0.0, z_true + rng.normal(0, 0.3), 0.0, t_true + rng.normal(0, 0.05),
+                        rng.normal(0, 3)])
+        p, Cl = mu0.copy(), lower(P0)
+        xp, csum = x0, 0.0
+        for i in range(n):
+            ok, p, Cl = oracle.propagate(p, Cl, xs[i] - xp, 0.0, 0.95)
+            assert ok
+            c2, p, Cl = oracle.update(p, Cl, 0.0, zm[i], sy2, sz2)
+            csum += c2
+            xp = xs[i]
+        # least squares for the state at x0: y_i = y + d_i s, z_i = z + d_i t
+        d = xs - x0
+        H = np.zeros((2 * n, 5))
+        H[0::2, 0] = 1.0
+        H[0::2, 2] = d
+        H[1::2, 1] = 1.0
+        H[1::2, 3] = d
+        m = np.zeros(2 * n)
+        m[1::2] = zm
+        Ri = np.tile([1.0 / sy2, 1.0 / sz2], n)
+        P0i = np.linalg.inv(P0)
+        A = P0i + H.T @ (Ri[:, None] * H)
+        mu = np.linalg.solve(A, P0i @ mu0 + H.T @ (Ri * m))
+        cov = np.linalg.inv(A)
+        r = m - H @ mu
+        jmin = (mu - mu0) @ P0i @ (mu - mu0) + r @ (Ri * r)
+        # carried to the last plane
+        D = xs[-1] - x0
+        T = np.eye(5)
+        T[0, 2] = T[1, 3] = D
+        mu_n, cov_n = T @ mu, T @ cov @ T.T
+        np.testing.assert_allclose(p, mu_n, rtol=1e-10, atol=1e-10)
+        scale = np.sqrt(np.outer(np.diag(cov_n), np.diag(cov_n)))
+        assert np.all(np.abs(full(Cl) - cov_n) <= 1e-10 * scale)
+        assert abs(csum - jmin) <= 1e-10 * max(1.0, jmin)
+
+
 def test_transport_jacobian_matches_central_differences():
     """Covariance transport C' = F C F^T: the F it applies (read off by
     transporting unit covariances) equals the central-difference Jacobian of

@@ -65,6 +65,47 @@ def test_primaries_come_back_to_the_collision_time():
     np.testing.assert_allclose(t0, t_true, atol=2e-3)
 
 
+def test_low_pt_primaries_come_back_to_the_collision_time():
+    """Helices of 0.08-0.3 GeV/c (radius 53-200 cm) from any pad row they
+    reach: over the whole distance to the axis plane the arc-length series
+    of one step would be off by up to ~1e-3 of the arc (cm in z0); the
+    transport in steps of at most 20 cm keeps z0 within 5e-3 cm."""
+    rng = np.random.default_rng(11)
+    par, xin, side, t_true = [], [], [], []
+    while len(par) < 300:
+        i = int(rng.integers(0, 18))
+        alpha = (i + 0.5) * W
+        phi0 = alpha + rng.uniform(-0.1, 0.1)
+        pt = rng.uniform(0.08, 0.3)
+        qpt = rng.choice([-1, 1]) / pt
+        reach = 2.0 * pt / abs(CURV)             # diameter of the circle [cm]
+        rows = np.nonzero(X < 0.9 * reach)[0]
+        if rows.size == 0:
+            continue
+        r = int(rng.choice(rows))
+        sd = int(rng.choice([-1, 1]))
+        tanl = sd * rng.uniform(0.02, 1.0)
+        t = rng.uniform(0.0, 90.0)
+        try:
+            p = _state(phi0, qpt, tanl, alpha, X[r])
+        except (ValueError, AssertionError):      # plane not reached on the outgoing branch
+            continue
+        if abs(p[2]) > 0.9:
+            continue
+        p[1] -= sd * VD_CM_PER_US * t
+        par.append(p)
+        xin.append(synth.ROW_X[r])
+        side.append(sd)
+        t_true.append(t)
+    z0, y0, t0, ok = oracle.track_t0(np.array(par), np.array(xin), np.array(side), PRM,
+                                     vd=VD_CM_PER_US)
+    assert ok.all()
+    t_true = np.array(t_true)
+    np.testing.assert_allclose(y0, 0.0, atol=5e-3)
+    np.testing.assert_allclose(z0, -np.array(side) * VD_CM_PER_US * t_true, atol=5e-3)
+    np.testing.assert_allclose(t0, t_true, atol=2e-3)
+
+
 def test_straight_track_from_a_displaced_vertex():
     # q/pT = 0: the line through (x_in, y_in) with slope s/c meets x = 0 at
     # y_in - x_in s/c, z_in - x_in t/c

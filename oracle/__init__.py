@@ -315,6 +315,27 @@ def refit_fd_grad(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None,
     return gy, gz, gt
 
 
+def refit_adjoint64(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None):
+    """Gradient of L = sum_t g_t chi2_t of the float64 refit with respect to
+    the raw hit y, z and the 16 calibration parameters, by reverse-mode
+    differentiation of the float64 forward (a recorded tape)."""
+    L = lib()
+    P = params(prm)
+    cm = cm or calib_model()
+    n = trk_off.shape[0] - 1
+    nh = row.shape[0]
+    gy = np.zeros(nh, np.float64)
+    gz = np.zeros(nh, np.float64)
+    gt = np.zeros(16, np.float64)
+    sd = None if side is None else np.ascontiguousarray(side, np.int8)
+    L.orc_refit64_adjoint(C.c_int64(n), _p(np.ascontiguousarray(trk_off, np.int32)), _p(row),
+                          _p(np.ascontiguousarray(y, np.float64)),
+                          _p(np.ascontiguousarray(z, np.float64)), _p(sd), _p(row_x),
+                          C.byref(P), C.byref(cm), _p(np.ascontiguousarray(theta, np.float64)),
+                          _p(np.ascontiguousarray(g, np.float64)), _p(gy), _p(gz), _p(gt))
+    return gy, gz, gt
+
+
 def propagate(p, Cov, dx, curv, s_max=0.95, fp64=True):
     """One propagation step; returns (ok, p', C')."""
     dt = np.float64 if fp64 else np.float32

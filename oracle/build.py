@@ -1,19 +1,30 @@
-"""Build the oracle shared library with gcc (test infrastructure only)."""
+"""Build the oracle shared library with gcc/g++ (test infrastructure only):
+oracle.c (the plain C oracle) and adjoint.cc (the double-precision refit
+differentiated by a recorded tape)."""
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "liboracle.so")
-CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-          "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard"]
+FPFLAGS = ["-O2", "-Wall", "-Wextra", "-fPIC", "-ffp-contract=off", "-fno-fast-math"]
 
 
 def build(verbose=False):
-    cmd = ["gcc", *CFLAGS, "-o", SO + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    c_obj = os.path.join(objdir, "oracle.o")
+    cc_obj = os.path.join(objdir, "adjoint.o")
+    cmds = [
+        ["gcc", "-std=c11", *FPFLAGS, "-fexcess-precision=standard", "-c", os.path.join(HERE, "oracle.c"), "-o", c_obj],
+        ["g++", "-std=c++17", *FPFLAGS, "-Wno-unused-function", "-c",
+         os.path.join(HERE, "adjoint.cc"), "-o", cc_obj],
+        ["g++", "-shared", "-fPIC", "-o", SO + ".tmp", c_obj, cc_obj, "-lm"],
+    ]
+    for cmd in cmds:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(SO + ".tmp", SO)
     return SO
 

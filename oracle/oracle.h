@@ -131,6 +131,15 @@ void orc_refit64_fd_grad(int64_t n_tracks, const int* trk_off, const uint8_t* ro
                          const double* g, double h_hit, double h_theta,
                          double* grad_y, double* grad_z, double* grad_theta);
 
+/* Gradient of sum_t g_t chi2_t of the double refit, by reverse-mode
+ * differentiation of the same forward code on a recorded tape (adjoint.cc):
+ * grad_y, grad_z per hit, grad_theta summed over tracks. */
+void orc_refit64_adjoint(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                         const double* y, const double* z, const signed char* side,
+                         const float* row_x, const orc_params* prm,
+                         const orc_calib_model* cm, const double* theta, const double* g,
+                         double* grad_y, double* grad_z, double* grad_theta);
+
 /* Track-based cluster attachment (section 6): tube of `radius` around
  * every track over the rows of its hits, its axis the track state par[5k]
  * (at the plane of row rin[k]) transported outwards row by row; unowned

@@ -511,17 +511,20 @@ def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: 
 def refit_adjoint(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
                   theta: torch.Tensor, fwd: dict, grad_chi2: torch.Tensor, cm=None, stream=None,
                   y=None, z=None, out=None):
-    """Gradients of sum_k grad_chi2[k] chi2[k]: (grad_y, grad_z, grad_theta).
-    `out` (dict with ws, gy, gz, gt of an earlier call) is reused."""
+    """Gradients of sum_k grad_chi2[k] chi2[k]: (grad_y, grad_z, grad_theta),
+    grad_y/grad_z per hit entry of the track list.  `out` (dict with ws, gy,
+    gz, gt of an earlier call, or any of them) is reused; entries of tracks
+    past the device track count are not written."""
     dev = hits.row.device
     nb = C.c_size_t()
     L.check(L.lib().tpc_refit_workspace_size(hits.n_tracks, C.byref(nb)), "workspace")
-    if out is None:
-        out = {}
+    out = {} if out is None else out
     if "ws" not in out:
         out["ws"] = torch.empty(max(int(nb.value), 64), dtype=torch.uint8, device=dev)
+    if "gy" not in out:
         out["gy"] = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
         out["gz"] = torch.empty(max(hits.n_hits, 1), dtype=torch.float32, device=dev)
+    if "gt" not in out:
         out["gt"] = torch.zeros(16, dtype=torch.float32, device=dev)
     ws, gy, gz, gt = out["ws"], out["gy"], out["gz"], out["gt"]
     P = params_struct(prm)

@@ -12,7 +12,8 @@ OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-    # binary32 decisions with a fixed association order: no contraction,
+    # binary32 with a fixed association order everywhere (the tracking's
+    # decisions and the refit's toleranced outputs alike): no contraction,
     # IEEE division and square root, denormals kept
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-fno-gpu-flush-denormals-to-zero",
@@ -21,26 +22,9 @@ FLAGS = [
 ]
 
 
-# The refit feeds tolerance-checked outputs only (no decision depends on
-# it): hardware reciprocal and square root there instead of the correctly
-# rounded sequences.
-FILE_FLAGS = {
-    "refit.hip": ("-fhip-fp32-correctly-rounded-divide-sqrt",
-                  "-fno-hip-fp32-correctly-rounded-divide-sqrt"),
-}
-
-
-def _flags(src):
-    f = list(FLAGS)
-    swap = FILE_FLAGS.get(os.path.basename(src))
-    if swap:
-        f[f.index(swap[0])] = swap[1]
-    return f
-
-
 def _compile(src, verbose):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *_flags(src), "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

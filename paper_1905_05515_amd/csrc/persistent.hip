@@ -548,33 +548,46 @@ uint64_t sectors_key(const tpc_problem* p, int scale)
 
 }  // namespace
 
+namespace {
+
+const tpc_context::TaskTable* find_table(const tpc_context* ctx, uint64_t key)
+{
+    for (int i = 0; i < ctx->n_tables; ++i)
+        if (ctx->tables[i].key == key) return &ctx->tables[i];
+    return nullptr;
+}
+
+}  // namespace
+
 int prepare_persistent(tpc_context* ctx, const tpc_problem* p)
 {
     const int scale = tile_scale(p, persistent_blocks(ctx));
     const uint64_t key = sectors_key(p, scale);
-    if (!ctx->d_tasks || ctx->tasks_key != key) {
-        // the table depends on the sector table only: built once per problem
-        // shape, outside any timed or captured sequence
-        std::vector<int4> task;
-        std::vector<int32_t> pre;
-        if (!build_tasks(p, scale, task, pre)) return TPC_ERR_INVALID_ARG;
-        const size_t tbytes = task.size() * sizeof(int4);
-        const size_t bytes = tbytes + pre.size() * sizeof(int32_t);
-        if (bytes > ctx->tasks_cap) {
-            if (ctx->d_tasks) (void)hipFree(ctx->d_tasks);
-            ctx->d_tasks = nullptr;
-            ctx->tasks_cap = 0;
-            if (hipMalloc(&ctx->d_tasks, bytes) != hipSuccess) return TPC_ERR_HIP;
-            ctx->tasks_cap = bytes;
-        }
-        if (hipMemcpy(ctx->d_tasks, task.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy((char*)ctx->d_tasks + tbytes, pre.data(), pre.size() * sizeof(int32_t),
-                      hipMemcpyHostToDevice) != hipSuccess)
-            return TPC_ERR_HIP;
-        const int64_t n_tasks = (int64_t)task.size();
-        ctx->tasks_key = key;
-        ctx->n_tasks = n_tasks;
+    if (find_table(ctx, key)) return TPC_OK;
+    // the table depends on the sector table only: built once per problem
+    // shape, outside any timed or captured sequence
+    std::vector<int4> task;
+    std::vector<int32_t> pre;
+    if (!build_tasks(p, scale, task, pre)) return TPC_ERR_INVALID_ARG;
+    const size_t tbytes = task.size() * sizeof(int4);
+    const size_t bytes = tbytes + pre.size() * sizeof(int32_t);
+    if (ctx->n_tables == tpc_context::kTaskTables) {
+        // a launch on any stream may still read the oldest table
+        if (hipDeviceSynchronize() != hipSuccess) return TPC_ERR_HIP;
+        (void)hipFree(ctx->tables[0].d);
+        for (int i = 1; i < ctx->n_tables; ++i) ctx->tables[i - 1] = ctx->tables[i];
+        --ctx->n_tables;
     }
+    int32_t* d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return TPC_ERR_HIP;
+    // a fresh allocation: no launch reads it yet
+    if (hipMemcpy(d, task.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((char*)d + tbytes, pre.data(), pre.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return TPC_ERR_HIP;
+    }
+    ctx->tables[ctx->n_tables++] = tpc_context::TaskTable{key, d, (int64_t)task.size()};
     return TPC_OK;
 }
 
@@ -584,7 +597,8 @@ int run_persistent(tpc_context* ctx, const tpc_problem* p, tpc_clusters in, tpc_
 {
     const int64_t resident = persistent_blocks(ctx);
     const int scale = tile_scale(p, resident);
-    if (!ctx->d_tasks || ctx->tasks_key != sectors_key(p, scale)) return TPC_ERR_INVALID_ARG;
+    const tpc_context::TaskTable* tab = find_table(ctx, sectors_key(p, scale));
+    if (!tab) return TPC_ERR_INVALID_ARG;
     PArgs a;
     a.scale = scale;
     a.sec = p->d_sectors;
@@ -602,10 +616,10 @@ int run_persistent(tpc_context* ctx, const tpc_problem* p, tpc_clusters in, tpc_
     a.trl = trl;
     a.trk = trk;
     a.ws = ws;
-    a.task = reinterpret_cast<const int4*>(ctx->d_tasks);
-    a.tiles = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(ctx->d_tasks) +
-                                               ctx->n_tasks * sizeof(int4));
-    a.n_tasks = ctx->n_tasks;
+    a.task = reinterpret_cast<const int4*>(tab->d);
+    a.tiles = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(tab->d) +
+                                               tab->n_tasks * sizeof(int4));
+    a.n_tasks = tab->n_tasks;
     TPC_LAUNCH(k_persist_setup, dim3(64), dim3(kBlock), 0, st, ws, p->n_sectors);
     int64_t blocks = resident;
     if (blocks > a.n_tasks) blocks = a.n_tasks;

@@ -15,10 +15,6 @@
 // gradient is reduced per block in a fixed order, then over blocks.
 #include "tpc_internal.hpp"
 
-// The refit feeds tolerance-checked outputs only: contraction allowed (and
-// the library builds this file with hardware reciprocal and square root).
-#pragma clang fp contract(fast)
-
 namespace tpc {
 
 namespace {
@@ -112,7 +108,8 @@ struct Prop {
     float FC[5][5];                 // F C
 };
 
-// transport of (p, C) by dx; fills the intermediates; false on |s| stop
+// transport of (p, C) by dx; fills the intermediates; false when |s| at
+// either end of the step is not below s_max
 __device__ __forceinline__ bool prop_fwd(float* p, float* C, float dx, float curv, float s_max,
                                          Prop& P)
 {
@@ -120,7 +117,7 @@ __device__ __forceinline__ bool prop_fwd(float* p, float* C, float dx, float cur
     P.dx = dx;
     P.k = curv * w;
     P.s2 = s + P.k * dx;
-    if (!(fabsf(P.s2) < s_max)) return false;
+    if (!(fabsf(s) < s_max) || !(fabsf(P.s2) < s_max)) return false;
     P.c1 = sqrtf((1.0f - s) * (1.0f + s));
     P.c2 = sqrtf((1.0f - P.s2) * (1.0f + P.s2));
     P.cc = P.c1 + P.c2;

@@ -9,8 +9,7 @@
 
 // All decisions are taken in binary32 with the association order written in
 // the source; contraction into FMA is off for the whole library (also passed
-// on the command line).  The refit, which only feeds tolerance-checked
-// outputs, enables contraction locally.
+// on the command line), the refit included.
 #pragma clang fp contract(off)
 
 namespace tpc {
@@ -192,11 +191,18 @@ struct tpc_context {
     hipGraphExec_t graph_exec;
     uint64_t graph_key;
     bool graph_valid;
-    // task table of the persistent form (device copy), keyed on the sectors
-    int32_t* d_tasks;
-    size_t tasks_cap;
-    uint64_t tasks_key;
-    int64_t n_tasks;
+    // task tables of the persistent form (device copies), one per sector
+    // table seen, keyed on it.  A table is never rewritten, so a launch still
+    // running on any stream keeps reading its own; the oldest is freed (after
+    // a device synchronisation) when a new one does not fit.
+    struct TaskTable {
+        uint64_t key;
+        int32_t* d;
+        int64_t n_tasks;
+    };
+    static constexpr int kTaskTables = 8;
+    TaskTable tables[kTaskTables];
+    int n_tables;
 };
 
 // stage launchers (stream-ordered, no host synchronisation); the sector

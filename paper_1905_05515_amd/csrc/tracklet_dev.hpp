@@ -23,13 +23,15 @@ struct KState {
 };
 
 // Transport from plane x1 to x1 + dx.  Returns false (state untouched) when
-// |sin(phi)| would reach s_max.
+// |sin(phi)| at either end of the step is not below s_max: at the far end
+// the track turns back before the plane, at the near end an update has
+// pushed the state out of the transport's domain (|s| >= 1 has no cosine).
 __device__ __forceinline__ bool propagate(KState& st, float dx, float curv, float s_max)
 {
     const float s = st.p[2], t = st.p[3], w = st.p[4];
     const float k = curv * w;
     const float s2 = s + k * dx;
-    if (!(fabsf(s2) < s_max)) return false;
+    if (!(fabsf(s) < s_max) || !(fabsf(s2) < s_max)) return false;
     const float c1 = sqrtf((1.0f - s) * (1.0f + s));
     const float c2 = sqrtf((1.0f - s2) * (1.0f + s2));
     const float cc = c1 + c2;

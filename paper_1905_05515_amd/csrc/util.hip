@@ -276,10 +276,7 @@ int tpc_context_create(tpc_context** out, int device)
     c->graph_key = 0;
     c->graph_valid = false;
     c->timer = nullptr;
-    c->d_tasks = nullptr;
-    c->tasks_cap = 0;
-    c->tasks_key = 0;
-    c->n_tasks = 0;
+    c->n_tables = 0;
     *out = c;
     return TPC_OK;
 }
@@ -288,7 +285,7 @@ int tpc_context_destroy(tpc_context* ctx)
 {
     if (!ctx) return TPC_ERR_INVALID_ARG;
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->d_tasks) (void)hipFree(ctx->d_tasks);
+    for (int i = 0; i < ctx->n_tables; ++i) (void)hipFree(ctx->tables[i].d);
     delete ctx->timer;
     delete ctx;
     return TPC_OK;

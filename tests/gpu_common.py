@@ -81,6 +81,10 @@ def assert_same_tracking(g, o, n_clusters):
         assert np.array_equal(gi[k], o[k]), k
     assert np.array_equal(gi["starts"], o["starts"])
     tr = o["tracklets"]
+    # the transport stops on |sin(phi)| >= s_max at either end of a step, so
+    # no state leaves its domain and no output is NaN
+    for k in ("par", "cov", "chi2"):
+        assert np.isfinite(tr[k]).all(), k
     assert np.array_equal(gi["hits"], tr["hits"])
     assert np.array_equal(g["t_nhits"], tr["nhits"])
     assert np.array_equal(g["t_rin"], tr["row_inner"])

@@ -1,9 +1,12 @@
 """GPU refit and adjoint against the float64 oracle, through the C ABI.
 
-Forward: track parameters relative 1e-4 of max(|p|, floor, sigma) (a few
-tracks up to the float filter's own rounding, 1e-3), chi2 relative 1e-4.
-Adjoint: against float64 central differences of the oracle refit, relative
-1e-3 per gradient block (hit y, hit z, theta), plus exact chain-rule
+Forward: every track's parameters within relative 1e-4 of max(|p|, floor)
+(floors 1 cm, 1 cm, 0.01, 0.01, 0.1 c/GeV for parameters near zero), chi2
+relative 1e-4.
+Adjoint: against the float64 reverse-mode gradient of the oracle refit on
+every hit of 10k tracks and against float64 central differences on a few
+tracks, relative 1e-3 per gradient block (hit y, hit z, theta) and per
+component to 1e-3 of the block's largest entry, plus exact chain-rule
 identities of the calibration model at full size."""
 import numpy as np
 import pytest
@@ -42,9 +45,8 @@ def _fwd(rs):
     return h, rx, th, out
 
 
-def _par_errors(par32, cov64, par64):
-    sig = np.sqrt(cov64[:, [0, 2, 5, 9, 14]])
-    scale = np.maximum(np.maximum(np.abs(par64), FLOOR), sig)
+def _par_errors(par32, par64):
+    scale = np.maximum(np.abs(par64), FLOOR)
     return (np.abs(par32.astype(np.float64) - par64) / scale).max(1)
 
 
@@ -56,8 +58,8 @@ def test_refit_forward_matches_fp64():
     st = out["status"].cpu().numpy()
     assert np.array_equal(st, o["status"])
     ok = st == 0
-    err = _par_errors(out["par"].cpu().numpy()[ok], o["cov"][ok], o["par"][ok])
-    assert np.mean(err > 1e-4) < 0.02 and err.max() < 1e-3, (np.mean(err > 1e-4), err.max())
+    err = _par_errors(out["par"].cpu().numpy()[ok], o["par"][ok])
+    assert err.max() <= 1e-4, (np.mean(err > 1e-4), err.max())
     c32 = out["chi2"].cpu().numpy()[ok]
     assert np.allclose(c32, o["chi2"][ok], rtol=1e-4, atol=1e-3)
 
@@ -84,6 +86,30 @@ def test_adjoint_matches_fp64_central_differences():
         assert np.all(np.abs(a - b) <= 1e-3 * np.abs(b).max() + 3e-3 * np.abs(b))
 
 
+@pytest.mark.timeout(600)
+def test_adjoint_matches_fp64_adjoint_on_10k_tracks():
+    rs = synth.make_config5(n_tracks=10000)
+    print(f"case adjoint 10k tracks hits={rs.n_hits}", flush=True)
+    h, rx, th, out = _fwd(rs)
+    g = torch.linspace(0.5, 1.5, rs.n_tracks, device="cuda")
+    gy, gz, gt = api.refit_adjoint(ctx(), h, rx, synth.default_params(), th, out, g)
+    st = out["status"].cpu().numpy()
+    ok = st == 0
+    assert ok.mean() > 0.99
+    # stopped tracks carry no gradient on the library's side
+    g64 = g.cpu().numpy().astype(np.float64) * ok
+    ry, rz, rt = oracle.refit_adjoint64(rs.trk_off, rs.row, rs.y, rs.z, rs.row_x,
+                                        synth.default_params(),
+                                        rs.theta_eval.astype(np.float64), g64)
+    hit_ok = np.repeat(ok, np.diff(rs.trk_off))
+    gy, gz, gt = (x.cpu().numpy().astype(np.float64) for x in (gy, gz, gt))
+    assert np.all(gy[~hit_ok] == 0) and np.all(gz[~hit_ok] == 0)
+    for name, a, b in (("y", gy, ry), ("z", gz, rz), ("theta", gt, rt)):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        worst = np.abs(a - b).max() / np.abs(b).max()
+        assert rel <= 1e-3 and worst <= 1e-3, (name, rel, worst)
+
+
 def test_autograd_function_uses_the_adjoint():
     rs = synth.make_config5(n_tracks=64)
     h = _hits(rs)
@@ -98,6 +124,44 @@ def test_autograd_function_uses_the_adjoint():
     gy, gz, gt = api.refit_adjoint(ctx(), h, rx, synth.default_params(), th.detach(), out, w)
     assert torch.equal(y.grad, gy) and torch.equal(z.grad, gz) and torch.equal(th.grad, gt)
     assert torch.equal(chi2, out["chi2"])
+
+
+def test_autograd_through_the_trackers_own_tracks():
+    """The differentiable refit on the tracker's output (track entries are
+    cluster ids, y and z are per cluster): autograd returns per-cluster
+    gradients, the ABI adjoint's per-entry gradients summed onto clusters."""
+    from gpu_common import run_gpu
+    ev = synth.make_config1()
+    print(f"case autograd found tracks n={ev.n_clusters}", flush=True)
+    e, g = run_gpu(ev)
+    hits = api.found_track_hits(e)
+    rx = e.t["row_x"]
+    prm = synth.default_params()
+    th = torch.as_tensor(rs_theta()).cuda().requires_grad_(True)
+    y = e.t["y"].clone().requires_grad_(True)
+    z = e.t["z"].clone().requires_grad_(True)
+    chi2, status = refit_chi2(ctx(), hits, rx, prm, y, z, th)
+    n_trk = len(g["trk_off"]) - 1
+    w = torch.zeros_like(chi2)
+    w[:n_trk] = torch.linspace(0.5, 1.5, n_trk, device="cuda")
+    (chi2 * w).sum().backward()
+    assert y.grad.shape == y.shape and z.grad.shape == z.shape
+    out = api.refit(ctx(), hits, rx, prm, th.detach())
+    gy, gz, gt = api.refit_adjoint(ctx(), hits, rx, prm, th.detach(), out, w)
+    m = int(g["trk_off"][-1])
+    ids = torch.as_tensor(g["trk_hits"][:m].astype(np.int64)).cuda()
+    ey = torch.zeros_like(y).index_add_(0, ids, gy[:m])
+    ez = torch.zeros_like(z).index_add_(0, ids, gz[:m])
+    assert torch.equal(y.grad, ey) and torch.equal(z.grad, ez) and torch.equal(th.grad, gt)
+    assert float(y.grad.abs().sum()) > 0.0
+    # clusters on no track get no gradient
+    on = torch.zeros(y.shape[0], dtype=torch.bool, device="cuda")
+    on[ids] = True
+    assert not bool((y.grad[~on] != 0).any())
+
+
+def rs_theta():
+    return synth.make_config5(n_tracks=1).theta_eval
 
 
 @pytest.mark.timeout(900)
@@ -118,8 +182,8 @@ def test_full_size_refit_and_adjoint_properties():
     o = oracle.refit(sub.trk_off, sub.row, sub.y, sub.z, sub.row_x, synth.default_params(),
                      rs.theta_eval.astype(np.float64), fp64=True)
     ok = (o["status"] == 0) & (st[idx] == 0)
-    err = _par_errors(out["par"].cpu().numpy()[idx][ok], o["cov"][ok], o["par"][ok])
-    assert np.mean(err > 1e-4) < 0.02 and err.max() < 1e-3
+    err = _par_errors(out["par"].cpu().numpy()[idx][ok], o["par"][ok])
+    assert err.max() <= 1e-4, (np.mean(err > 1e-4), err.max())
     assert np.allclose(out["chi2"].cpu().numpy()[idx][ok], o["chi2"][ok], rtol=1e-4, atol=1e-3)
     cm = api.CALIB_MODEL
     vd = float(np.float32(cm["vd"]))

@@ -9,6 +9,9 @@ scale, t0 and 14 smooth distortion coefficients).  Pinned here:
   * exact chain-rule identities of the model: z_raw enters only through
     the drift length d = (1 + vd_scale)(d_raw - vd t0), so the t0 and
     vd-scale gradients are fixed sums of the z_raw gradients;
+  * the reverse-mode (tape) gradient of the double refit, the reference
+    for the library's adjoint, equals the converged central differences to
+    1e-6 per block and per component, for both z sides;
   * float and double refits agree to the float filter's rounding;
   * chi2 at the true calibration is the smear's chi2 (ndf about 2n - 5), and
     a distortion the helix cannot absorb raises it.
@@ -54,6 +57,36 @@ def test_gradient_chain_rule_identities(small_set):
     d_raw = dl - side * rs.z.astype(np.float64)
     expect = np.sum(gz * (d_raw - vd * th[1]) / (-side * (1.0 + th[0])))
     assert abs(gt[0] - expect) <= 1e-6 * np.sum(np.abs(gz * d_raw))
+
+
+def test_tape_adjoint_matches_central_differences(small_set):
+    rs = small_set
+    prm = synth.default_params()
+    g = np.linspace(0.5, 1.5, rs.n_tracks)
+    th = rs.theta_eval.astype(np.float64)
+    side = np.where(np.arange(rs.n_tracks) % 3 == 0, -1, 1).astype(np.int8)
+    ad = oracle.refit_adjoint64(rs.trk_off, rs.row, rs.y, rs.z, rs.row_x, prm, th, g, side=side)
+    fd = oracle.refit_fd_grad(rs.trk_off, rs.row, rs.y, rs.z, rs.row_x, prm, th, g, side=side)
+    for a, b in zip(ad, fd):
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b)
+        assert np.all(np.abs(a - b) <= 1e-6 * np.abs(b).max())
+
+
+def test_tape_adjoint_chain_rule_identities(small_set):
+    """z_raw enters only through the drift length, so the t0 and vd-scale
+    gradients are exact sums of the z_raw gradients (to double rounding)."""
+    rs = small_set
+    prm = synth.default_params()
+    th = rs.theta_eval.astype(np.float64)
+    gy, gz, gt = oracle.refit_adjoint64(rs.trk_off, rs.row, rs.y, rs.z, rs.row_x, prm, th,
+                                        np.ones(rs.n_tracks))
+    cm = oracle.calib_model()
+    vd = float(np.float32(cm.vd))
+    dl = float(np.float32(cm.drift_len))
+    assert abs(gt[1] - vd * gz.sum()) <= 1e-12 * np.abs(vd * gz).sum()
+    d_raw = dl - rs.z.astype(np.float64)
+    expect = np.sum(gz * (d_raw - vd * th[1]) / (-(1.0 + th[0])))
+    assert abs(gt[0] - expect) <= 1e-12 * np.sum(np.abs(gz * d_raw))
 
 
 def test_float_refit_matches_double(small_set):

@@ -1,17 +1,22 @@
 """Benchmark of the TPC track-finding hot path on one MI355X.
 
-Workload: one central Pb-Pb-like event (36 sectors, 8000 primaries + 10%
-secondaries + 5% noise, ~1.32M float32 clusters, seed 2002), all inputs
-resident in HBM.  One step = the whole hot path over the event:
-  grid -> neighbours -> cleaning/starts -> tracklets -> selection
-  (tpc_track_batch, one HIP graph replay)
-  -> calibrated refit of the found tracks -> adjoint (dchi2 / d(hits, theta)).
-value = clusters of the event / step time (clusters/s).
+Workload: the batched uneven set, 512 independent single-sector instances
+(half pp-like with 20-200 tracks, half Pb-Pb-like with 50-800, log-uniform,
+shuffled; ~10.9M float32 clusters, seed 40040000), all inputs resident in
+HBM.  One step = the whole hot path over the batch:
+  grid -> neighbours -> cleaning/starts -> tracklets -> selection of every
+  instance (tpc_track_batch, one launch sequence over all instances, one HIP
+  graph replay) -> calibrated refit of the found tracks -> adjoint.
+value = clusters of the batch / step time (clusters/s).
 
 Also reported (same JSON line): per-kernel durations from HIP events over a
-second timed region (eager launches, same step), the roofline of the
-dominant kernel, the refit+adjoint throughput on 1M tracks (tracks/s), and
-the oracle timed on the host (cpu_baseline).
+second timed region (eager launches, same step) and the roofline of the
+dominant kernel; tracking alone in each launch form (batched staged and
+batched persistent, per-sector in a graph and eager) with equal outputs;
+the grid-to-starts stages against the HBM peak; the oracle timed on the
+host on one core and on all cores (cpu_baseline) with the paper's
+GPU-equivalent cores; and as extras the central event, the continuous
+read-out slice and the refit+adjoint throughput on 1M tracks (tracks/s).
 """
 from __future__ import annotations
 
@@ -26,11 +31,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector ALU: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T simple ops/s for
-# unpacked, uncontracted float arithmetic (the tracklet kernel's mix); the
-# published 157.3 TFLOP/s counts packed FMA as 4 flops per lane and cycle.
-ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
-ALU_PEAK_FMA_TFLOPS = 157.3
+# FP32 vector peak as published (packed FMA: 4 flops per lane and cycle);
+# the float work here is unpacked and uncontracted, for which the issue
+# ceiling is 256 CUs x 64 lanes x 2.4 GHz = 39.3 T operations/s (reported
+# beside it, labelled)
+ALU_PEAK_TFLOPS = 157.3
+ALU_ISSUE_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic float operations per call, counted from the formulas
 # (division and square root count as one operation each)
 FLOPS_PROPAGATE = 179
@@ -50,9 +56,8 @@ def parse():
     ap.add_argument("--refit-tracks", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-refit-bench", action="store_true")
-    ap.add_argument("--no-batch-bench", action="store_true")
-    ap.add_argument("--no-per-sector", action="store_true",
-                    help="time the batched set in the staged and persistent forms only")
+    ap.add_argument("--no-central-bench", action="store_true",
+                    help="skip the central event (events in flight, attachment, merging)")
     ap.add_argument("--no-slice-bench", action="store_true",
                     help="skip the continuous read-out slice (100 collisions)")
     ap.add_argument("--no-attach-bench", action="store_true",
@@ -67,7 +72,7 @@ def parse():
                          "set three times (eager launches; the workload of the HBM byte "
                          "counters of those stages) and exit")
     ap.add_argument("--inflight", default="3",
-                    help="events in flight in the timed step loop (each on its own stream "
+                    help="central event: events in flight in its timed step loop (each on its own stream "
                          "with its own buffers; with four hardware queues per process more "
                          "than three streams serialise), or 'auto' (times 1-3 first and "
                          "takes the fastest; after those trials the timed region has run "
@@ -107,7 +112,8 @@ def main():
     import synth
     from paper_1905_05515_amd import api
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe or args.seeding_probe:
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe:
         n = 1 << 28
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -130,18 +136,219 @@ def main():
         log(f"[bench] grid and starts of {ev.n_clusters} clusters, occupancy {occ}, 3 times")
         return
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    ev = synth.make_config2()
     prm = synth.default_params()
-    log(f"[bench] event: {ev.n_clusters} clusters, generated in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    ev = synth.make_config4()
+    log(f"[bench] batched set: {ev.n_sectors} instances, {ev.n_clusters} clusters, generated "
+        f"in {time.time() - t0:.1f}s")
+    # the oracle first: its worker processes fork before the GPU is touched
+    cpu = None if args.no_cpu else cpu_baseline(args, ev, prm)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = api.Context(0)
     stream = torch.cuda.Stream()      # default priority; graphs need a non-default stream
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
                        sector_side=ev.sector_side)
     tuned = pick_layout(args, api, ctx, e, stream)
-    th = torch.as_tensor(synth.make_config5(n_tracks=1).theta_eval).to(dev)
+    th = torch.as_tensor(synth_theta()).to(dev)
     gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
+    hits = api.found_track_hits(e)
+    S = dict(fwd=None, adj={})
 
+    def step(mode="staged", graph=True):
+        """One pass of the hot path over the batch: tracking of every
+        instance (one launch sequence over all of them, HIP graph), then the
+        calibrated refit of the found tracks and its adjoint."""
+        with torch.cuda.stream(stream):
+            api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
+            S["fwd"] = api.refit(ctx, hits, e.t["row_x"], prm, th, stream=stream, out=S["fwd"])
+            api.refit_adjoint(ctx, hits, e.t["row_x"], prm, th, S["fwd"], gchi2, stream=stream,
+                              out=S["adj"])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # timed region: K steps between two events on the step's stream
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    ru0 = host_cpu_seconds()
+    w0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(args.steps):
+        step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    host_cpu = host_cpu_seconds() - ru0
+    ms_per_step = a.elapsed_time(b) / args.steps
+    st = api.get_status(e, stream)
+    log(f"[bench] step {ms_per_step:.3f} ms ({ev.n_clusters / (ms_per_step * 1e-3):.3e} "
+        f"clusters/s; wall {1e3 * wall / args.steps:.3f} ms, host CPU "
+        f"{1e3 * host_cpu / args.steps:.3f} ms per step), tracks {st['n_tracks']}")
+
+    # the same step with eager launches and HIP events around every kernel
+    with torch.cuda.stream(stream):
+        step(graph=False)
+        torch.cuda.synchronize()
+        api.timing_enable(ctx, True)
+        for _ in range(args.steps):
+            step(graph=False)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    kernels = {k: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / args.steps}
+               for k, (n, ms) in kt.items()}
+    eager_ms = sum(v["ms_per_step"] for v in kernels.values())
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        log(f"[bench]   {k:28s} {v['avg_ms'] * 1e3:9.1f} us x {v['launches'] // args.steps}")
+    n_cl = ev.n_clusters
+    n_hits_trk = int(st["n_track_hits"])
+    roof = roofline(dom, kernels[dom]["avg_ms"], st, n_cl, n_hits_trk)
+    roof["traffic"] = counter_traffic(dom.split("<")[0], "batched_set")
+    roof["source_sha256"] = source_hash(dom.split("<")[0])
+
+    forms = forms_bench(args, api, ctx, e, ev, stream)
+    extra = {"launch_forms": forms}
+    if cpu is not None:
+        cpu["gpu_equivalent_cores"] = gpu_equivalent_cores(cpu, forms, ms_per_step, host_cpu,
+                                                           args.steps)
+    extra["grid_to_starts"] = seeding_roofline(api, ctx, e, stream, max(2, args.steps // 4),
+                                               n_cl, "batched_set")
+    log(f"[bench] grid..starts {extra['grid_to_starts']['ms'] * 1e3:.1f} us, "
+        f"{extra['grid_to_starts']['frac'] * 100:.1f}% of HBM peak at "
+        f"{SEEDING_BYTES_PER_CLUSTER} B/cluster")
+    if not args.no_central_bench:
+        extra["central_event"] = central_bench(args, api, synth, prm, dev, tuned)
+    if not args.no_slice_bench:
+        extra["continuous_readout"] = slice_bench(args, api, synth, ctx, stream, prm)
+    if not args.no_refit_bench:
+        extra["refit_adjoint"] = refit_bench(args, api, synth, ctx, stream, prm, dev)
+
+    line = {
+        "metric": ("TPC clusters/s tracked on 1 MI355X (batched vs per-sector); "
+                   "refit+adjoint tracks/s"),
+        "value": n_cl / (ms_per_step * 1e-3),
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched uneven set: 512 independent single-sector instances, half "
+                        "pp-like (20-200 tracks), half Pb-Pb-like (50-800 tracks), log-uniform, "
+                        "shuffled, 5% noise, float32 SoA clusters (seed 40040000); step = grid, "
+                        "neighbours, cleaning, starts, tracklets, selection of every instance "
+                        "(one launch sequence over all instances, HIP graph) + calibrated refit "
+                        "and adjoint of the found tracks",
+            "clusters": n_cl,
+            "instances": ev.n_sectors,
+            "tracks_found": int(st["n_tracks"]),
+            "track_hits": n_hits_trk,
+            "launch_form": "batched: staged stages over all instances, HIP graph",
+            "wall_ms_per_step": 1e3 * wall / args.steps,
+            "host_cpu_ms_per_step": 1e3 * host_cpu / args.steps,
+            "grid_layout": tuned,
+            "parallelism": "single GPU",
+        },
+        "roofline": roof,
+        "kernels": {k: {"avg_us": round(v["avg_ms"] * 1e3, 2),
+                        "launches_per_step": v["launches"] // args.steps}
+                    for k, v in kernels.items()},
+        "eager_kernel_ms_per_step": eager_ms,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def host_cpu_seconds():
+    """User + system CPU time of this process and its finished children."""
+    import resource
+    a = resource.getrusage(resource.RUSAGE_SELF)
+    return a.ru_utime + a.ru_stime
+
+
+def forms_bench(args, api, ctx, e, ev, stream):
+    """Tracking alone (grid to selection) of the batch in each launch form:
+    batched staged (one launch per stage over all instances) and batched
+    persistent (one work-queue launch), both HIP graphs, against the
+    per-sector form (one launch sequence per instance) captured in a graph
+    and eager.  Outputs are checked equal."""
+    import torch
+    ref = None
+    res = {}
+    steps = max(2, args.steps // 4)
+    forms = (("staged", True), ("persistent", True), ("per_sector", True), ("per_sector", False))
+    for mode, graph in forms:
+        name = f"{mode}_{'graph' if graph else 'eager'}"
+        n = steps if mode != "per_sector" or graph else 2
+        with torch.cuda.stream(stream):
+            api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            ru0 = host_cpu_seconds()
+            a.record(stream)
+            for _ in range(n):
+                api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            host = (host_cpu_seconds() - ru0) / n
+        ms = a.elapsed_time(b) / n
+        r = api.results(e, stream)
+        key = (r["trk_off"].tobytes(), r["trk_hits"].tobytes(), r["t_par"].tobytes())
+        ref = key if ref is None else ref
+        res[name] = {"ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3),
+                     "host_cpu_ms": 1e3 * host, "equal_output": bool(key == ref),
+                     "tracks": int(r["status"]["n_tracks"])}
+        log(f"[bench]   {name:18s} {ms:8.3f} ms  {ev.n_clusters / (ms * 1e-3):.3e} clusters/s "
+            f"equal={key == ref}")
+    # per-kernel times of the staged form (eager launches, HIP events)
+    with torch.cuda.stream(stream):
+        api.timing_enable(ctx, True)
+        for _ in range(steps):
+            api.track_batch(ctx, e, mode="staged", use_graph=False, stream=stream)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    res["staged_kernels_us"] = {k: round(ms / steps * 1e3, 1) for k, (n, ms) in
+                                sorted(kt.items(), key=lambda kv: -kv[1][1])}
+    return res
+
+
+def gpu_equivalent_cores(cpu, forms, ms_step, host_cpu_s, steps):
+    """The paper's figure of merit: CPU cores one GPU replaces, counted as
+    (oracle time on one core - host CPU time the GPU run consumed) / GPU
+    wall time, for the whole step and for tracking alone."""
+    t1 = cpu["seconds_one_core"]
+    whole = (t1["tracking"] + t1["refit"] + t1["adjoint"] - host_cpu_s / steps) / (ms_step * 1e-3)
+    tf = forms["staged_graph"]
+    trk = (t1["tracking"] - tf["host_cpu_ms"] * 1e-3) / (tf["ms"] * 1e-3)
+    return {"whole_step": whole, "tracking": trk,
+            "method": "(oracle seconds on one core - host CPU seconds of the GPU run, from "
+                      "getrusage) / GPU seconds, per pass over the batch"}
+
+
+def central_bench(args, api, synth, prm, dev, tuned_batch):
+    """The central Pb-Pb-like event (36 sectors, ~1.3M clusters): the step
+    with events in flight, per-kernel times, cluster attachment and
+    sector-track merging of its tracks."""
+    import torch
+    t0 = time.time()
+    ev = synth.make_config2()
+    log(f"[bench] central event: {ev.n_clusters} clusters, generated in {time.time() - t0:.1f}s")
+    ctx = api.Context(0)
+    stream = torch.cuda.Stream()
+    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
+                       sector_side=ev.sector_side)
+    tuned = pick_layout(args, api, ctx, e, stream)
+    th = torch.as_tensor(synth_theta()).to(dev)
+    gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
     # Events in flight: lane k owns an event's buffers, a context (whose
     # cached graph is that event's) and a stream; step i runs on lane
     # i % depth.  A lane's steps follow each other on its stream, so no
@@ -247,61 +454,22 @@ def main():
     roof = roofline(dom, kernels[dom]["avg_ms"], st, n_cl, n_hits_trk)
     roof["traffic"] = counter_traffic(dom.split("<")[0], "central_event")
     roof["source_sha256"] = source_hash(dom.split("<")[0])
-
-    extra = {}
+    res = {"workload": "central Pb-Pb-like event: 36 sectors, 8000 primaries + 10% secondaries "
+                       "+ 5% noise (seed 2002); step = tracking (graph) + refit + adjoint",
+           "clusters": n_cl, "tracks_found": int(st["n_tracks"]),
+           "ms_per_step": ms_per_step, "clusters_per_s": n_cl / (ms_per_step * 1e-3),
+           "events_in_flight": depth,
+           "events_in_flight_tried_ms": ({str(k): round(v, 4) for k, v in tried.items()}
+                                         if tried else None),
+           "ms_per_step_one_at_a_time": lat_ms, "lanes_equal_output": bool(same),
+           "grid_layout": tuned, "roofline": roof,
+           "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kernels.items()},
+           "eager_kernel_ms_per_step": eager_ms}
     if not args.no_attach_bench:
-        extra["cluster_attachment"] = attach_bench(args, api, ctx, e, ev, stream)
+        res["cluster_attachment"] = attach_bench(args, api, ctx, e, ev, stream)
     if not args.no_merge_bench:
-        extra["sector_merging"] = merge_bench(args, api, ctx, e, ev, stream)
-    if not args.no_batch_bench:
-        extra["batched_vs_per_sector"] = batch_bench(args, api, synth, ctx, stream, prm)
-    if not args.no_slice_bench:
-        extra["continuous_readout"] = slice_bench(args, api, synth, ctx, stream, prm)
-    if not args.no_refit_bench:
-        extra["refit_adjoint"] = refit_bench(args, api, synth, ctx, stream, prm, dev)
-    cpu = None if args.no_cpu else cpu_baseline(ev, prm, args, tuned["occupancy"])
-
-    value = n_cl / (ms_per_step * 1e-3)
-    line = {
-        "metric": ("TPC clusters/s tracked on 1 MI355X (batched vs per-sector); "
-                   "refit+adjoint tracks/s"),
-        "value": value,
-        "unit": "clusters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": "central Pb-Pb-like event: 36 sectors, 8000 primaries + 10% secondaries "
-                        "+ 5% noise, float32 SoA clusters (seed 2002); step = grid, neighbours, "
-                        "cleaning, starts, tracklets, selection (one graph replay) + calibrated "
-                        "refit and adjoint of the found tracks",
-            "clusters": n_cl,
-            "tracks_found": int(st["n_tracks"]),
-            "track_hits": n_hits_trk,
-            "launch_form": "staged stages over all sectors, HIP graph",
-            "events_in_flight": depth,
-            "events_in_flight_tried_ms": ({str(k): round(v, 4) for k, v in tried.items()}
-                                          if tried else None),
-            "ms_per_step_one_at_a_time": lat_ms,
-            "lanes_equal_output": bool(same),
-            "grid_layout": tuned,
-            "parallelism": "single GPU",
-        },
-        "roofline": roof,
-        "kernels": {k: {"avg_us": round(v["avg_ms"] * 1e3, 2),
-                        "launches_per_step": v["launches"] // args.steps}
-                    for k, v in kernels.items()},
-        "eager_kernel_ms_per_step": eager_ms,
-        "cpu_baseline": cpu,
-        **extra,
-    }
-    print(json.dumps(line), flush=True)
+        res["sector_merging"] = merge_bench(args, api, ctx, e, ev, stream)
+    return res
 
 
 def roofline(name, avg_ms, st, n_cl, n_trk_hits):
@@ -334,6 +502,8 @@ def roofline(name, avg_ms, st, n_cl, n_trk_hits):
         tf = fl / sec / 1e12
         return {"kernel": name, "bound": "alu", "achieved": tf, "peak": ALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": tf / ALU_PEAK_TFLOPS, "traffic": None,
+                "issue_ceiling_tops": ALU_ISSUE_PEAK_TOPS,
+                "frac_of_issue_ceiling": tf / ALU_ISSUE_PEAK_TOPS,
                 "flops_per_launch": fl, "propagations": st["n_propagations"],
                 "updates": st["n_updates"], "candidates": st["n_candidates"]}
     if base in ("k_refit_fwd", "k_refit_adj"):
@@ -399,65 +569,6 @@ def counter_traffic(kernel, workload):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
-
-
-def batch_bench(args, api, synth, ctx, stream, prm):
-    """The 512 uneven single-sector instances (~14M clusters) tracked in the
-    three launch forms; the outputs are checked equal."""
-    import numpy as np
-    import torch
-    t0 = time.time()
-    ev = synth.make_config4()
-    log(f"[bench] batched set: {ev.n_sectors} instances, {ev.n_clusters} clusters, generated in "
-        f"{time.time() - t0:.1f}s")
-    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
-                       sector_side=ev.sector_side)
-    res = {"grid_layout": pick_layout(args, api, ctx, e, stream)}
-    ref = None
-    steps = max(2, args.steps // 4)
-    forms = (("staged", True), ("persistent", True)) + (() if args.no_per_sector else
-                                                       (("per_sector", False),))
-    for mode, graph in forms:
-        with torch.cuda.stream(stream):
-            api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(steps):
-                api.track_batch(ctx, e, mode=mode, use_graph=graph, stream=stream)
-            b.record(stream)
-            torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / steps
-        r = api.results(e, stream)
-        key = (r["trk_off"].tobytes(), r["trk_hits"].tobytes(), r["t_par"].tobytes())
-        if ref is None:
-            ref = key
-        same = key == ref
-        res[mode] = {"ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3), "graph": graph,
-                     "equal_output": bool(same), "tracks": int(r["status"]["n_tracks"])}
-        log(f"[bench]   {mode:11s} {ms:8.3f} ms  {ev.n_clusters / (ms * 1e-3):.3e} clusters/s "
-            f"equal={same}")
-    # per-kernel times of the staged form (eager launches, HIP events)
-    with torch.cuda.stream(stream):
-        api.timing_enable(ctx, True)
-        for _ in range(steps):
-            api.track_batch(ctx, e, mode="staged", use_graph=False, stream=stream)
-        torch.cuda.synchronize()
-        kt = api.timing_report(ctx)
-        api.timing_enable(ctx, False)
-    per = {k: ms / steps for k, (n, ms) in kt.items()}
-    res["staged_kernels_us"] = {k: round(v * 1e3, 1) for k, v in
-                                sorted(per.items(), key=lambda kv: -kv[1])}
-    res["roofline_grid_to_starts"] = seeding_roofline(api, ctx, e, stream, steps,
-                                                      ev.n_clusters, "batched_set")
-    log(f"[bench]   grid..starts {res['roofline_grid_to_starts']['ms'] * 1e3:.1f} us, "
-        f"{res['roofline_grid_to_starts']['frac'] * 100:.1f}% of HBM peak at "
-        f"{SEEDING_BYTES_PER_CLUSTER} B/cluster")
-    res["workload"] = ("512 single-sector instances, half pp-like (20-200 tracks), half "
-                       "Pb-Pb-like (50-800), log-uniform, shuffled (seed 40040000)")
-    res["clusters"] = ev.n_clusters
-    return res
 
 
 def attach_bench(args, api, ctx, e, ev, stream):
@@ -810,17 +921,42 @@ def refit_bench(args, api, synth, ctx, stream, prm, dev):
     }
 
 
-def cpu_baseline(ev, prm, args, occupancy=None):
-    """The oracle (plain single-threaded C) on the host: the whole tracking
-    chain over the event, the float refit of the found tracks, and the
-    float64 central-difference gradient on a sample of them, scaled to all
-    tracks."""
+# the batch the forked oracle workers read (set before the pool forks)
+_ORACLE_EVENT = None
+
+
+def _oracle_instance(k):
+    """Worker: the oracle's tracking of instance k of the batch, alone."""
     import numpy as np
 
     import oracle
     from paper_1905_05515_amd.layout import grid_layout
-    occ = occupancy if occupancy is not None else 0.25
-    tab, nb = grid_layout(ev.sector_offsets, ev.sector_range, occupancy=occ,
+    ev, prm, occ = _ORACLE_EVENT
+    b0, b1 = int(ev.sector_offsets[k]), int(ev.sector_offsets[k + 1])
+    off = np.array([0, b1 - b0], np.int64)
+    tab, nb = grid_layout(off, ev.sector_range[k:k + 1], occupancy=occ,
+                          sides=ev.sector_side[k:k + 1])
+    t0 = time.perf_counter()
+    r = oracle.track_event(ev.row[b0:b1], ev.y[b0:b1], ev.z[b0:b1], tab, nb, ev.row_x, prm)
+    return time.perf_counter() - t0, r["tracks"]["trk_off"].shape[0] - 1
+
+
+def cpu_baseline(args, ev, prm, occupancy=0.25):
+    """The oracle (plain single-threaded C) on the host over the same batch:
+    tracking of every instance on one core, the same on all host cores with
+    one instance per task (the paper's sector-parallel CPU tracking), the
+    float refit of the found tracks, and the float64 reverse-mode gradient
+    timed on a sample of them and scaled to all.  Runs before the GPU is
+    used, so the worker processes fork from a process without device
+    state."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    from paper_1905_05515_amd.layout import grid_layout
+    global _ORACLE_EVENT
+    tab, nb = grid_layout(ev.sector_offsets, ev.sector_range, occupancy=occupancy,
                           sides=ev.sector_side)
     t0 = time.perf_counter()
     res = oracle.track_event(ev.row, ev.y, ev.z, tab, nb, ev.row_x, prm)
@@ -834,23 +970,39 @@ def cpu_baseline(ev, prm, args, occupancy=None):
     t0 = time.perf_counter()
     oracle.refit(off, ev.row[ids], ev.y[ids], ev.z[ids], ev.row_x, prm, th, side=side)
     t_refit = time.perf_counter() - t0
-    k = min(200, n_trk)
-    sub = np.arange(k)
+    k = min(4000, n_trk)
     so = off[:k + 1]
     sel = ids[:so[-1]]
     t0 = time.perf_counter()
-    oracle.refit_fd_grad(so, ev.row[sel], ev.y[sel], ev.z[sel], ev.row_x, prm,
-                         th.astype(np.float64), np.ones(k), side=side[sub])
-    t_grad = (time.perf_counter() - t0) * n_trk / max(k, 1)
-    total = t_track + t_refit + t_grad
-    log(f"[bench] oracle: tracking {t_track:.2f}s, refit {t_refit:.2f}s, "
-        f"gradient {t_grad:.1f}s (from {k} tracks)")
-    return {"value": ev.n_clusters / total, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-            "sample": f"whole event tracked ({ev.n_clusters} clusters, {n_trk} tracks) and "
-                      f"refit; float64 central-difference gradient timed on {k} tracks and "
-                      f"scaled to {n_trk}",
-            "tracking_only_clusters_per_s": ev.n_clusters / t_track,
-            "seconds": {"tracking": t_track, "refit": t_refit, "gradient_scaled": t_grad}}
+    oracle.refit_adjoint64(so, ev.row[sel], ev.y[sel], ev.z[sel], ev.row_x, prm,
+                           th.astype(np.float64), np.ones(k), side=side[:k])
+    t_adj = (time.perf_counter() - t0) * n_trk / max(k, 1)
+    # all host cores, one instance per task, largest first
+    cores = min(16, len(os.sched_getaffinity(0)))
+    _ORACLE_EVENT = (ev, prm, occupancy)
+    order = np.argsort(-np.diff(ev.sector_offsets), kind="stable").tolist()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_instance, order[-cores:])          # start-up of the workers
+        t0 = time.perf_counter()
+        per = pool.map(_oracle_instance, order, chunksize=1)
+        t_par = time.perf_counter() - t0
+    _ORACLE_EVENT = None
+    same = sum(n for _, n in per) == n_trk
+    log(f"[bench] oracle: tracking {t_track:.2f}s on one core, {t_par:.2f}s on {cores} "
+        f"(tracks equal {same}), refit {t_refit:.2f}s, reverse-mode gradient {t_adj:.1f}s "
+        f"(from {k} tracks)")
+    total = t_track + t_refit + t_adj
+    return {"value": ev.n_clusters / t_track, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole batch ({ev.n_clusters} clusters, {ev.n_sectors} instances) "
+                      f"tracked on one core; value = tracking (grid to selection) only",
+            "whole_step_clusters_per_s": ev.n_clusters / total,
+            "whole_step_sample": f"tracking + float refit of the {n_trk} found tracks + "
+                                 f"float64 reverse-mode gradient timed on {k} of them and "
+                                 f"scaled to all",
+            "multi_core": {"cores": cores, "clusters_per_s": ev.n_clusters / t_par,
+                           "seconds": t_par, "same_track_count": bool(same),
+                           "form": "one instance per task over a process pool, largest first"},
+            "seconds_one_core": {"tracking": t_track, "refit": t_refit, "adjoint": t_adj}}
 
 
 def synth_theta():

@@ -417,6 +417,24 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                       const float* grad_chi2, float* grad_y, float* grad_z,
                       float* grad_theta, void* d_ws, size_t ws_bytes, void* stream);
 
+/* tpc_refit_adjoint for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the per-block partial sums
+ * of the theta gradient in a static device array of the library (64 KiB x
+ * 16 = 1 MiB per GPU, held until the process ends) instead of a workspace.
+ * The adjoint never uses more than 16384 blocks, so every n_tracks fits;
+ * TPC_ERR_CAPACITY would report one that did not.  The context's device must
+ * be current (else TPC_ERR_INVALID_ARG).  Allocates nothing and calls no
+ * allocating routine.  All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (two streams, two threads) race on it and
+ * must be serialised by the caller.  Otherwise as tpc_refit_adjoint. */
+int tpc_refit_adjoint_noalloc(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                              const float* d_row_x, const tpc_params* h_params,
+                              const tpc_calib_model* h_model, const float* d_theta,
+                              const float* checkpoints, size_t ck_bytes,
+                              const int32_t* status, const float* grad_chi2, float* grad_y,
+                              float* grad_z, float* grad_theta, void* stream);
+
 /* Per-kernel timing.  While enabled, every kernel the context launches
  * (outside graph capture) is bracketed by two HIP events on its stream.
  * tpc_timing_report synchronises on them and returns, per kernel name in

@@ -92,6 +92,9 @@ EXPORTS = {
     "tpc_refit_adjoint": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params),
                                     C.POINTER(CalibModel), P, P, C.c_size_t, P, P, P, P, P, P,
                                     C.c_size_t, P]),
+    "tpc_refit_adjoint_noalloc": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params),
+                                            C.POINTER(CalibModel), P, P, C.c_size_t, P, P, P,
+                                            P, P, P]),
     "tpc_attach_workspace_size": (C.c_int, [C.POINTER(Problem), C.POINTER(C.c_size_t)]),
     "tpc_attach_clusters": (C.c_int, [P, C.POINTER(Problem), Clusters, Grid, Tracklets, Tracks,
                                       P, F32, F32, P, P, P, C.c_size_t, P]),

@@ -13,6 +13,8 @@
 // symmetric covariance carries a symmetric adjoint G with
 // dL = sum_ij G_ij dC_ij.  Hit gradients are written per hit; the theta
 // gradient is reduced per block in a fixed order, then over blocks.
+#include <mutex>
+
 #include "tpc_internal.hpp"
 
 namespace tpc {
@@ -769,9 +771,67 @@ __global__ __launch_bounds__(kBlock) void k_reduce_theta(const float* __restrict
     if (threadIdx.x == 0) out[k] = red[0];
 }
 
+constexpr int64_t kRefitMaxBlocks = 16384;
+
 static unsigned refit_grid(int64_t n_tracks)
 {
-    return grid_for_block(n_tracks, kWave, 16384);
+    return grid_for_block(n_tracks, kWave, kRefitMaxBlocks);
+}
+
+// the adjoint and its theta reduction, partials[16 * refit_grid(n_tracks)]
+static int launch_refit_adjoint(tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
+                                const tpc_params& prm, const tpc_calib_model& m,
+                                const float* d_theta, const float* checkpoints,
+                                const int32_t* status, const float* grad_chi2, float* grad_y,
+                                float* grad_z, float* grad_theta, float* partials,
+                                hipStream_t st)
+{
+    CalibModel cm{m.drift_len, m.vd, m.tan_half, m.u_centre, m.u_scale};
+    const unsigned nb = refit_grid(hits.n_tracks);
+    TPC_LAUNCH(k_refit_adj, dim3(nb), dim3(kWave), 0, st, hits.off, hits.idx, hits.row, hits.y,
+               hits.z, hits.side, hits.d_count, hits.n_tracks, n_rows, d_row_x, prm, cm,
+               d_theta, checkpoints, status, grad_chi2, grad_y, grad_z, partials);
+    TPC_LAUNCH(k_reduce_theta, dim3(16), dim3(kBlock), 0, st, (const float*)partials, (int)nb,
+               grad_theta);
+    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+}  // namespace tpc
+
+// Theta partials of the adjoint's blocks for callers that cannot allocate
+// (tpc_refit_adjoint_noalloc): one copy per GPU, held until the process
+// ends, shared by every call on that GPU (calls that overlap on one GPU
+// race on it).  Every block of the adjoint writes its 16 partials before the
+// reduction reads them, so nothing needs clearing between calls.
+static __device__ __align__(256) float scratch[16 * tpc::kRefitMaxBlocks];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per GPU
+
+}  // namespace
+
+namespace tpc {
+
+// Device address of this GPU's copy of `scratch`, taken once per device at
+// context creation with that device current (the array's name is only a
+// host-side stand-in and cannot be passed to a kernel).
+int refit_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return TPC_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return TPC_OK;
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return TPC_ERR_HIP;
+    if (prev != device && hipSetDevice(device) != hipSuccess) return TPC_ERR_HIP;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !ptr) return TPC_ERR_HIP;
+    g_scratch_ptr[device] = static_cast<float*>(ptr);
+    return TPC_OK;
 }
 
 }  // namespace tpc
@@ -835,18 +895,39 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
         tpc_refit_workspace_size(hits.n_tracks, &need) || need > ws_bytes ||
         tpc_refit_checkpoint_size(hits.n_tracks, n_rows, &need) || need > ck_bytes)
         return TPC_ERR_INVALID_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
-                       h_model->u_scale};
-    const unsigned nb = tpc::refit_grid(hits.n_tracks);
-    float* partials = (float*)d_ws;
-    TPC_LAUNCH(tpc::k_refit_adj, dim3(nb), dim3(tpc::kWave), 0, st, hits.off, hits.idx,
-                       hits.row, hits.y, hits.z, hits.side, hits.d_count, hits.n_tracks, n_rows,
-                       d_row_x, *h_params, cm, d_theta, checkpoints, status, grad_chi2, grad_y,
-                       grad_z, partials);
-    TPC_LAUNCH(tpc::k_reduce_theta, dim3(16), dim3(tpc::kBlock), 0, st, (const float*)partials,
-                       (int)nb, grad_theta);
-    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+    return tpc::launch_refit_adjoint(hits, n_rows, d_row_x, *h_params, *h_model, d_theta,
+                                     checkpoints, status, grad_chi2, grad_y, grad_z,
+                                     grad_theta, (float*)d_ws, (hipStream_t)stream);
+}
+
+int tpc_refit_adjoint_noalloc(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                              const float* d_row_x, const tpc_params* h_params,
+                              const tpc_calib_model* h_model, const float* d_theta,
+                              const float* checkpoints, size_t ck_bytes, const int32_t* status,
+                              const float* grad_chi2, float* grad_y, float* grad_z,
+                              float* grad_theta, void* stream)
+{
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
+    size_t need = 0;
+    if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !checkpoints || !status ||
+        !grad_chi2 || !grad_y || !grad_z || !grad_theta || hits.n_tracks < 0 ||
+        n_rows < 3 || n_rows > 255 ||
+        (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
+        tpc_refit_checkpoint_size(hits.n_tracks, n_rows, &need) || need > ck_bytes)
+        return TPC_ERR_INVALID_ARG;
+    if (tpc::refit_grid(hits.n_tracks) > tpc::kRefitMaxBlocks) return TPC_ERR_CAPACITY;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return TPC_ERR_HIP;
+    if (dev != ctx->device || dev < 0 || dev >= kMaxDevices) return TPC_ERR_INVALID_ARG;
+    float* partials = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        partials = g_scratch_ptr[dev];
+    }
+    if (!partials) return TPC_ERR_HIP;   // set up when the context was created
+    return tpc::launch_refit_adjoint(hits, n_rows, d_row_x, *h_params, *h_model, d_theta,
+                                     checkpoints, status, grad_chi2, grad_y, grad_z,
+                                     grad_theta, partials, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -220,6 +220,9 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
                     int64_t count_cap, tpc_tracklets trl, const Workspace& ws, hipStream_t st);
 int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
                        tpc_tracklets trl, tpc_tracks trk, const Workspace& ws, hipStream_t st);
+// device address of the refit adjoint's static scratch on `device`, taken
+// once per device (context creation)
+int refit_scratch_setup(int device);
 // task table of the persistent form (host work, no launch; call before
 // any capture)
 int prepare_persistent(tpc_context* ctx, const tpc_problem* p);

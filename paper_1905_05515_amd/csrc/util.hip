@@ -268,6 +268,8 @@ int tpc_context_create(tpc_context** out, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TPC_ERR_HIP;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TPC_ERR_UNSUPPORTED;
+    const int se = tpc::refit_scratch_setup(device);
+    if (se) return se;
     tpc_context* c = new (std::nothrow) tpc_context();
     if (!c) return TPC_ERR_HIP;
     c->device = device;

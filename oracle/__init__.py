@@ -315,6 +315,45 @@ def refit_fd_grad(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None,
     return gy, gz, gt
 
 
+def fit_merged(sector_offsets, sectors_per_side, row_x, prm, row, y, z, trk_off, trk_hits, par,
+               rin, link_up, link_dn, group, n_pass=3, cos_w=None, sin_w=None):
+    """Full-track fit of merged sector tracks (float64): per track index,
+    filled for group leaders.  Returns dict(par_in, par_out, cov_out, chi2,
+    n_hits, n_members, status)."""
+    offs = np.ascontiguousarray(sector_offsets, np.int64)
+    n_sec = offs.shape[0] - 1
+    if cos_w is None:
+        cos_w, sin_w = sector_width_cs(360.0 / sectors_per_side)
+    nt = trk_off.shape[0] - 1
+    m = max(nt, 1)
+    out = dict(par_in=np.zeros((m, 5)), par_out=np.zeros((m, 5)), cov_out=np.zeros((m, 15)),
+               chi2=np.zeros(m), n_hits=np.zeros(m, np.int32), n_members=np.zeros(m, np.int32),
+               status=np.zeros(m, np.int32))
+    P = params(prm)
+    i32 = lambda a: _p(np.ascontiguousarray(a, np.int32))
+    lib().orc_fit_merged64(C.c_int(n_sec), _p(offs), C.c_int(sectors_per_side),
+                           _p(np.ascontiguousarray(row_x, np.float32)), C.byref(P),
+                           _p(np.ascontiguousarray(row, np.uint8)),
+                           _p(np.ascontiguousarray(y, np.float32)),
+                           _p(np.ascontiguousarray(z, np.float32)), C.c_int64(nt), i32(trk_off),
+                           i32(trk_hits), _p(np.ascontiguousarray(par, np.float32)), i32(rin),
+                           i32(link_up), i32(link_dn), i32(group), C.c_float(cos_w),
+                           C.c_float(sin_w), C.c_int(n_pass), _p(out["par_in"]),
+                           _p(out["par_out"]), _p(out["cov_out"]), _p(out["chi2"]),
+                           _p(out["n_hits"]), _p(out["n_members"]), _p(out["status"]))
+    return {k: v[:nt] for k, v in out.items()}
+
+
+def rotate(x, p, Cov, c, sd, curv, s_max=0.95):
+    """One frame turn (float64); returns (ok, x', p', C')."""
+    xx = C.c_double(x)
+    p = np.array(p, np.float64)
+    Cv = np.array(Cov, np.float64)
+    ok = lib().orc_rotate64(C.byref(xx), _p(p), _p(Cv), C.c_double(c), C.c_double(sd),
+                            C.c_double(curv), C.c_double(s_max))
+    return bool(ok), xx.value, p, Cv
+
+
 def refit_adjoint64(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None):
     """Gradient of L = sum_t g_t chi2_t of the float64 refit with respect to
     the raw hit y, z and the 16 calibration parameters, by reverse-mode

@@ -19,6 +19,7 @@
 #define CAT(a, b) CAT_(a, b)
 #define FN(name) CAT(name, SUF)
 
+#define R0 ((REAL)0)
 #define R1 ((REAL)1)
 #define R2 ((REAL)2)
 #define RH ((REAL)0.5)
@@ -98,6 +99,58 @@ static int FN(propagate)(REAL* p, REAL* C, REAL dx, REAL curv, REAL s_max)
     }
     p[0] = p[0] + dx * T;
     p[1] = p[1] + t * S;
+    p[2] = s2;
+    return 1;
+}
+
+/* Turn the frame: the state at plane *x of one sector frame is taken into
+ * a frame turned by D (cos D = c, sin D = sd; a point (x, y) becomes
+ * (x c - y sd, x sd + y c), the direction angle grows by D), at the plane
+ * through the same point, which becomes *x.  Returns 0 (nothing changed)
+ * when the direction would not point along +x in the new frame or
+ * |sin(phi)| would reach s_max there.
+ * Covariance: a change dy of y (at fixed plane) moves the point by
+ * dy (-sd, c); sliding it back along the track onto the plane (transverse
+ * arc dl = sd dy / cos') changes y by (c + sd sin'/cos') dy, z by
+ * t sd / cos' dy and sin by k sd dy (k = curv w); a change ds of sin(phi)
+ * turns the direction by ds / cos, so sin' changes by cos'/cos ds.
+ * C' = J C J^T over those entries, the rest the identity. */
+static int FN(rotate)(REAL* x, REAL* p, REAL* C, REAL c, REAL sd, REAL curv, REAL s_max)
+{
+    REAL y = p[0], s = p[2], t = p[3];
+    REAL cs = SQRT((R1 - s) * (R1 + s));
+    REAL s2 = s * c + cs * sd;
+    REAL c2 = cs * c - s * sd;
+    if (!(R0 < c2) || !(FABS(s2) < s_max)) return 0;
+    REAL jyy = c + (sd * s2) / c2;
+    REAL jzy = (t * sd) / c2;
+    REAL jsy = (curv * p[4]) * sd;
+    REAL jss = c2 / cs;
+    /* B = J C (rows y, z, s change), then C' = B J^T */
+    REAL B[5][5];
+    for (int j = 0; j < 5; j++) {
+        REAL cy = C[FN(lt)(0, j)], cz = C[FN(lt)(1, j)], cc = C[FN(lt)(2, j)];
+        B[0][j] = jyy * cy;
+        B[1][j] = cz + jzy * cy;
+        B[2][j] = jsy * cy + jss * cc;
+        B[3][j] = C[FN(lt)(3, j)];
+        B[4][j] = C[FN(lt)(4, j)];
+    }
+    for (int i = 0; i < 5; i++) {
+        for (int j = 0; j <= i; j++) {
+            REAL v;
+            switch (j) {
+            case 0: v = jyy * B[i][0]; break;
+            case 1: v = B[i][1] + jzy * B[i][0]; break;
+            case 2: v = jsy * B[i][0] + jss * B[i][2]; break;
+            default: v = B[i][j]; break;
+            }
+            C[FN(lt)(i, j)] = v;
+        }
+    }
+    REAL x0 = *x;
+    *x = x0 * c - y * sd;
+    p[0] = x0 * sd + y * c;
     p[2] = s2;
     return 1;
 }
@@ -220,6 +273,7 @@ static int FN(refit_track)(int n, const uint8_t* row, const REAL* y, const REAL*
     return 0;
 }
 
+#undef R0
 #undef R1
 #undef R2
 #undef RH

@@ -847,6 +847,149 @@ void orc_merge_sector_tracks(int n_sec, const int64_t* sector_offsets, int sps,
     free(members);
 }
 
+/* ---- full-track fit of merged sector tracks (section 2: the first fit of
+ * the sector tracks finds the whole track, which is then fitted; section 3:
+ * several fit iterations, inwards and outwards, across sector boundaries) --
+ * Readings: the members of a merged track form a chain through the merging
+ * links.  The chain is walked from its down end (link_dn) to its up end
+ * (link_up), or the other way when the up end's first hit lies on a lower
+ * row than the down end's first hit; the merged hit list is the members'
+ * hits in that order, each member's row-ascending.  Between consecutive hits
+ * of neighbouring sectors the state is turned into the next sector's frame
+ * (D = alpha_now - alpha_next: sin D = -sin(width) towards the up
+ * neighbour, +sin(width) towards the down neighbour) and transported to the
+ * next hit's row plane.  The fit starts from the first member's tracklet
+ * state (at the plane of its innermost fitted row) and makes n_pass passes
+ * over all hits, alternately outwards (first to last hit) and inwards; every
+ * pass starts with the initial covariance and the previous pass's
+ * parameters, and updates with every hit (the first at the plane where the
+ * previous pass ended).  Outputs, for the chain's least track index (its
+ * group) only: the state after the last outward pass at the last hit (its
+ * sector's frame) and its covariance, the state after the last inward pass
+ * at the first hit, the chi2 sum of the last pass, the hit count and the
+ * member count.  status: 0 fitted, 1 fewer than 3 hits, 2 a transport or a
+ * frame turn stopped, -1 not a group's leader. */
+static int sector_of_id(int n_sec, const int64_t* sector_offsets, int c)
+{
+    int s = 0;
+    while (s + 1 < n_sec && c >= sector_offsets[s + 1]) s++;
+    return s;
+}
+
+void orc_fit_merged64(int n_sec, const int64_t* sector_offsets, int sps, const float* row_x,
+                      const orc_params* prm, const uint8_t* row, const float* y, const float* z,
+                      int64_t n_tracks, const int* trk_off, const int* trk_hits,
+                      const float* par, const int* rin, const int* link_up, const int* link_dn,
+                      const int* group, float cos_w, float sin_w, int n_pass, double* par_in,
+                      double* par_out, double* cov_out, double* chi2_out, int* n_hits,
+                      int* n_members, int* status)
+{
+    int64_t nh_all = n_tracks > 0 ? trk_off[n_tracks] : 0;
+    int* hits = malloc(sizeof(int) * (size_t)(nh_all > 0 ? nh_all : 1));
+    int* hsec = malloc(sizeof(int) * (size_t)(nh_all > 0 ? nh_all : 1));
+    int* chain = malloc(sizeof(int) * (size_t)(n_sec + 1));
+    for (int64_t g = 0; g < n_tracks; g++) {
+        for (int i = 0; i < 5; i++) par_in[5 * g + i] = par_out[5 * g + i] = 0.0;
+        for (int i = 0; i < 15; i++) cov_out[15 * g + i] = 0.0;
+        chi2_out[g] = 0.0;
+        n_hits[g] = 0;
+        n_members[g] = 0;
+        if (group[g] != (int)g) {
+            status[g] = -1;
+            continue;
+        }
+        /* the chain: down end first, at most one member per sector */
+        int j = (int)g;
+        for (int step = 0; step < n_sec && link_dn[j] >= 0 && link_dn[j] != (int)g; step++)
+            j = link_dn[j];
+        int m = 0;
+        while (j >= 0 && m < n_sec) {
+            chain[m++] = j;
+            j = link_up[j];
+            if (j == chain[0]) break;
+        }
+        int r_dn = trk_off[chain[0] + 1] > trk_off[chain[0]] ? row[trk_hits[trk_off[chain[0]]]] : 0;
+        int r_up = trk_off[chain[m - 1] + 1] > trk_off[chain[m - 1]]
+                       ? row[trk_hits[trk_off[chain[m - 1]]]] : 0;
+        if (r_up < r_dn)
+            for (int a = 0, b = m - 1; a < b; a++, b--) {
+                int t = chain[a];
+                chain[a] = chain[b];
+                chain[b] = t;
+            }
+        int n = 0;
+        for (int a = 0; a < m; a++)
+            for (int q = trk_off[chain[a]]; q < trk_off[chain[a] + 1]; q++) {
+                hits[n] = trk_hits[q];
+                hsec[n] = sector_of_id(n_sec, sector_offsets, trk_hits[q]);
+                n++;
+            }
+        n_hits[g] = n;
+        n_members[g] = m;
+        if (n < 3) {
+            status[g] = 1;
+            continue;
+        }
+        double p[5], C[15], x = (double)row_x[rin[chain[0]]];
+        for (int i = 0; i < 5; i++) p[i] = (double)par[5 * chain[0] + i];
+        int cur = hsec[0], ok = 1;
+        double chi2 = 0.0;
+        for (int pass = 0; pass < n_pass && ok; pass++) {
+            int out = pass % 2 == 0;
+            for (int i = 0; i < 15; i++) C[i] = 0.0;
+            C[0] = prm->sigma_y2;
+            C[2] = prm->sigma_z2;
+            C[5] = prm->c_ss0;
+            C[9] = prm->c_tt0;
+            C[14] = prm->c_ww0;
+            chi2 = 0.0;
+            for (int k = 0; k < n && ok; k++) {
+                int i = out ? k : n - 1 - k;
+                if (hsec[i] != cur) {
+                    /* neighbouring sectors of one side: up or down */
+                    int side = cur / sps, ic = cur % sps;
+                    int up = side * sps + (ic + 1) % sps;
+                    double sd = hsec[i] == up ? -(double)sin_w : (double)sin_w;
+                    if (!rotate_d(&x, p, C, (double)cos_w, sd, prm->curv, prm->s_max)) {
+                        ok = 0;
+                        break;
+                    }
+                    cur = hsec[i];
+                }
+                double xh = (double)row_x[row[hits[i]]];
+                if (!propagate_d(p, C, xh - x, prm->curv, prm->s_max)) {
+                    ok = 0;
+                    break;
+                }
+                x = xh;
+                chi2 = chi2 + update_d(p, C, (double)y[hits[i]], (double)z[hits[i]],
+                                       prm->sigma_y2, prm->sigma_z2);
+            }
+            if (ok && !out)
+                for (int i = 0; i < 5; i++) par_in[5 * g + i] = p[i];
+        }
+        if (!ok) {
+            for (int i = 0; i < 5; i++) par_in[5 * g + i] = 0.0;
+            status[g] = 2;
+            continue;
+        }
+        for (int i = 0; i < 5; i++) par_out[5 * g + i] = p[i];
+        for (int i = 0; i < 15; i++) cov_out[15 * g + i] = C[i];
+        chi2_out[g] = chi2;
+        status[g] = 0;
+    }
+    free(hits);
+    free(hsec);
+    free(chain);
+}
+
+/* One frame turn (float64) for the pins: x, p[5], C[15] in place. */
+int orc_rotate64(double* x, double* p, double* C, double c, double sd, double curv,
+                 double s_max)
+{
+    return rotate_d(x, p, C, c, sd, curv, s_max);
+}
+
 /* ---- per-track interaction time (section 2: continuous read-out; the z of
  * a hit depends on the unknown time of its collision) -----------------------
  * Readings: a primary track comes from the beam axis at z = 0; the tracker

@@ -163,6 +163,18 @@ void orc_attach_clusters(int n_sec, const int64_t* sector_offsets, int n_rows,
  * the linked track in the next sector of the side (index + 1 mod sps),
  * link_dn[k]: in the previous one, -1 none; group[k]: least index on k's
  * chain of links. */
+/* Full-track fit of the merged sector tracks (float64; see oracle.c): per
+ * track index, defined for group leaders (group[k] == k). */
+void orc_fit_merged64(int n_sec, const int64_t* sector_offsets, int sps, const float* row_x,
+                      const orc_params* prm, const uint8_t* row, const float* y, const float* z,
+                      int64_t n_tracks, const int* trk_off, const int* trk_hits,
+                      const float* par, const int* rin, const int* link_up, const int* link_dn,
+                      const int* group, float cos_w, float sin_w, int n_pass, double* par_in,
+                      double* par_out, double* cov_out, double* chi2_out, int* n_hits,
+                      int* n_members, int* status);
+int orc_rotate64(double* x, double* p, double* C, double c, double sd, double curv,
+                 double s_max);
+
 void orc_merge_sector_tracks(int n_sec, const int64_t* sector_offsets, int sps,
                              const float* row_x, const orc_params* prm, int64_t n_tracks,
                              const int* trk_off, const int* trk_hits, const float* par,

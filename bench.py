@@ -71,6 +71,10 @@ def parse():
                     help="only build the grid and find the chain starts of the 512-instance "
                          "set three times (eager launches; the workload of the HBM byte "
                          "counters of those stages) and exit")
+    ap.add_argument("--tracking-probe", choices=("central", "batched", "slice"),
+                    help="only track the central event, the 512-instance set or the "
+                         "continuous read-out slice three times (eager staged launches; the "
+                         "workload of the counter profiles of the tracking kernels) and exit")
     ap.add_argument("--inflight", default="3",
                     help="central event: events in flight in its timed step loop (each on its own stream "
                          "with its own buffers; with four hardware queues per process more "
@@ -112,8 +116,22 @@ def main():
     import synth
     from paper_1905_05515_amd import api
 
-    if args.copy_probe or args.seeding_probe:
+    if args.copy_probe or args.seeding_probe or args.tracking_probe:
         assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.tracking_probe:
+        make = {"central": synth.make_config2, "batched": synth.make_config4,
+                "slice": synth.make_config3}[args.tracking_probe]
+        ev = make()
+        occ = 0.125 if args.occupancy == "auto" else float(args.occupancy)
+        e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x,
+                           synth.default_params(), occupancy=occ, sector_side=ev.sector_side)
+        ctx = api.Context(0)
+        for _ in range(3):
+            api.track_batch(ctx, e, mode="staged", use_graph=False)
+        torch.cuda.synchronize()
+        log(f"[bench] tracked {ev.n_clusters} clusters ({args.tracking_probe}), occupancy "
+            f"{occ}, 3 times")
+        return
     if args.copy_probe:
         n = 1 << 28
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -701,6 +719,36 @@ def merge_bench(args, api, ctx, e, ev, stream):
            "link_purity": float(np.mean(maj[k] == maj[up[k]])) if len(k) else None}
     log(f"[bench] merging {ms:.3f} ms ({nt} tracks, {pairs} pairs): {res['links']} links, "
         f"purity {res['link_purity']}, {res['groups']} groups")
+    res["full_track_fit"] = fullfit_bench(api, ctx, e, stream, steps, nt, (up, dn, grp))
+    return res
+
+
+def fullfit_bench(api, ctx, e, stream, steps, n_tracks, links):
+    """Full-track fit of the merged tracks (three passes, out-in-out):
+    time per call, per-kernel time, merged tracks and their chi2 / ndf."""
+    import torch
+    with torch.cuda.stream(stream):
+        api.fit_merged_tracks(ctx, e, links, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            f = api.fit_merged_tracks(ctx, e, links, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    nt = min(n_tracks, e.track_capacity)
+    st = f["status"][:nt]
+    ok = st == 0
+    nh = f["n_hits"][:nt][ok].double()
+    chi2 = f["chi2"][:nt][ok].double()
+    res = {"ms": ms, "merged_tracks": int((st >= 0).sum()), "fitted": int(ok.sum()),
+           "multi_sector": int((ok & (f["n_members"][:nt] > 1)).sum()),
+           "hits_fitted": int(nh.sum()), "passes": 3,
+           "chi2_per_ndf": float(chi2.sum() / (2 * nh - 5).sum()) if int(ok.sum()) else None}
+    log(f"[bench]   full-track fit {ms:.3f} ms: {res['fitted']} merged tracks "
+        f"({res['multi_sector']} over sectors), chi2/ndf {res['chi2_per_ndf']}")
     return res
 
 
@@ -807,6 +855,7 @@ def slice_merge(api, ctx, e, stream, steps, n_tracks):
     res = {"ms": ms, "tracks": nt, "tracks_per_s": nt / (ms * 1e-3), "links": links,
            "kernels_us": {k: round(ms_ / n * 1e3, 1) for k, (n, ms_) in kt.items()}}
     log(f"[bench]   slice merging {ms:.3f} ms for {nt} tracks, {links} links")
+    res["full_track_fit"] = fullfit_bench(api, ctx, e, stream, steps, nt, (up, dn, grp))
     return res
 
 

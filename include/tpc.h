@@ -330,6 +330,55 @@ int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
                             int32_t* link_dn, int32_t* group, void* d_ws, size_t ws_bytes,
                             void* stream);
 
+/* ---- full-track fit of merged sector tracks ------------------------------ */
+
+/* Per-track outputs of tpc_fit_merged_tracks (device arrays of
+ * tracks.capacity entries each, owned by the caller). */
+typedef struct tpc_fit_out {
+    float* par_in;         /* [5 per track] state at the first hit after the last inward pass */
+    float* par_out;        /* [5 per track] state at the last hit after the last outward pass */
+    float* cov_out;        /* [15 per track] its covariance (lower triangle, row by row) */
+    float* chi2;           /* chi2 sum of the last pass */
+    int32_t* n_hits;       /* hits of the merged track */
+    int32_t* n_members;    /* sector tracks in it */
+    int32_t* status;       /* 0 fitted, 1 fewer than 3 hits, 2 a transport or turn
+                              stopped, -1 not a group leader (no output) */
+} tpc_fit_out;
+
+/* Full-track fit of the merged sector tracks (section 2: the first fit of
+ * the sector tracks serves to find the whole track, which is then fitted;
+ * section 3: several fit iterations, in and out, across sector
+ * boundaries).  Inputs: the clusters, tracklets and tracks of the tracking
+ * calls and link_up, link_dn, group of tpc_merge_sector_tracks (same
+ * problem, sectors_per_side, cos_width, sin_width).  For every track g with
+ * group[g] == g (the chain's least index): the chain is walked from its down
+ * end (following link_dn from g, at most n_sectors steps, stopping before
+ * g) along link_up, or from its up end along link_dn when the up end's first
+ * hit lies on a lower row than the down end's first hit; the merged hit list
+ * is the members' hits in that order, each member's row-ascending.  The fit
+ * starts from the first member's tracklet state (par at the plane of
+ * row_inner) and makes n_pass passes over all hits, alternately outwards
+ * (first to last) and inwards, each from the previous pass's parameters and
+ * a diagonal covariance: the variances of the first member's tracklet (cov)
+ * for the first pass, of the previous pass's end for the others, times
+ * cov_scale (params' initial variances stand in for any that is not
+ * positive and finite); between hits of neighbouring sectors the
+ * state is turned into the next sector's frame (D = alpha_now - alpha_next:
+ * sin D = -sin_width towards the up neighbour, +sin_width towards the down
+ * one; the point (x, y) goes to (x c - y sd, x sd + y c), the covariance by
+ * the first-order map of moving onto the new plane; refused when cos' <= 0
+ * or |sin'| >= s_max) and transported to the hit's row plane, then updated
+ * with the hit.  par_in is zero with one pass.  Tracks from the track count
+ * on are not written.  Float32.  Returns TPC_ERR_INVALID_ARG for a null
+ * pointer, a capacity outside [0, 2^31), n_pass outside [1, 64],
+ * sectors_per_side < 3 or not dividing the sector count, a non-finite width
+ * or cov_scale not finite and > 0; asynchronous on stream. */
+int tpc_fit_merged_tracks(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters clusters,
+                          tpc_tracklets tracklets, tpc_tracks tracks, const int64_t* d_n_tracks,
+                          const int32_t* link_up, const int32_t* link_dn, const int32_t* group,
+                          int32_t sectors_per_side, float cos_width, float sin_width,
+                          int32_t n_pass, float cov_scale, tpc_fit_out out, void* stream);
+
 /* ---- per-track interaction time ----------------------------------------- */
 
 /* Interaction time of every track in continuous read-out (section 2: the z
@@ -338,8 +387,8 @@ int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
  * tracker sees by -side * vd * t (side of the track's sector: that of its
  * first hit; +1 for a track without hits).  The state of the track's
  * tracklet (par at the plane of row_inner, x_in) is transported to the
- * plane x = 0 of its sector frame with the tracklet transport (one step,
- * dx = 0 - x_in).  Per track k (device arrays of tracks.capacity entries,
+ * plane x = 0 of its sector frame with the tracklet transport in
+ * n = ceil(x_in / 20 cm) (at least 1) equal steps of dx = (0 - x_in) / n.  Per track k (device arrays of tracks.capacity entries,
  * owned by the caller; entries from the track count on are not written):
  *   y0[k], z0[k]: the state's y and z at x = 0 (y0 is 0 for a primary);
  *   t0[k]: (side > 0 ? -z0 : z0) / vd, float32 [time unit of vd];
@@ -416,6 +465,50 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
                       const float* checkpoints, size_t ck_bytes, const int32_t* status,
                       const float* grad_chi2, float* grad_y, float* grad_z,
                       float* grad_theta, void* d_ws, size_t ws_bytes, void* stream);
+
+/* tpc_refit_adjoint for an objective that also depends on each track's
+ * final state: L = sum_k grad_chi2[k] chi2[k] + sum_k grad_par[k] . par[k]
+ * + sum_k grad_x[k] x[k], where par[k] is the refit state after the last
+ * update and x[k] the calibrated plane of the track's last hit (the seeds
+ * are the derivatives of the caller's terms, e.g. from
+ * tpc_vertex_residual).  grad_par [5 per track] and grad_x [per track] are
+ * device arrays, each nullable (zero).  Otherwise as tpc_refit_adjoint. */
+int tpc_refit_adjoint_seeded(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                             const float* d_row_x, const tpc_params* h_params,
+                             const tpc_calib_model* h_model, const float* d_theta,
+                             const float* checkpoints, size_t ck_bytes, const int32_t* status,
+                             const float* grad_chi2, const float* grad_par, const float* grad_x,
+                             float* grad_y, float* grad_z, float* grad_theta, void* d_ws,
+                             size_t ws_bytes, void* stream);
+
+/* Beam-axis term of the calibration objective (section 3: online
+ * calibration of drift velocity, t0 and distortions; section 2: primaries
+ * from the origin).  For every track k with status[k] == 0 (of tpc_refit
+ * with the same inputs) and at least 3 hits: x = the calibrated plane of its
+ * last hit; its refit state and covariance (par[k], cov[k] at x) are
+ * transported to the beam-axis plane x = 0 of its sector frame with the
+ * tracklet transport in n = ceil(x / 20 cm) (at least 1) equal steps; with
+ * r = (y0, z0) there and W = (w00, w01, w11) either w_in[k] (held by the
+ * caller) or, when w_in is NULL, the inverse of the transported (y, z)
+ * covariance plus sigma_v^2 on its diagonal (the chi2 increment of a vertex
+ * measurement; written to w_out[k] when w_out is not NULL):
+ *   loss[k] = r^T W r,
+ *   grad_par[5 k .. 5 k + 4] = d loss / d par[k] (W held; product of the
+ *     steps' transport Jacobians),
+ *   grad_x[k] = d loss / d x = -2 ((W r)_0 s0 + (W r)_1 t) / c0 (moving the
+ *     plane with the state held translates the track along x; s0, c0 sin
+ *     and cos of phi at x = 0, t = tan(lambda)),
+ *   ok[k] = 1 (nullable); all zero where the fit or the transport stopped.
+ * Device arrays of hits.n_tracks entries (5 per track for grad_par, 3 for
+ * the weights); the track count is read from hits.d_count when given.
+ * Returns TPC_ERR_INVALID_ARG for a null pointer or sigma_v not finite and
+ * >= 0; asynchronous on stream. */
+int tpc_vertex_residual(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                        const float* d_row_x, const tpc_params* h_params,
+                        const tpc_calib_model* h_model, const float* d_theta, const float* par,
+                        const float* cov, const int32_t* status, float sigma_v,
+                        const float* w_in, float* w_out, float* loss, float* grad_par,
+                        float* grad_x, int8_t* ok, void* stream);
 
 /* tpc_refit_adjoint for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

@@ -316,29 +316,36 @@ def refit_fd_grad(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None,
 
 
 def fit_merged(sector_offsets, sectors_per_side, row_x, prm, row, y, z, trk_off, trk_hits, par,
-               rin, link_up, link_dn, group, n_pass=3, cos_w=None, sin_w=None):
-    """Full-track fit of merged sector tracks (float64): per track index,
-    filled for group leaders.  Returns dict(par_in, par_out, cov_out, chi2,
-    n_hits, n_members, status)."""
+               cov, rin, link_up, link_dn, group, n_pass=3, cov_scale=100.0, cos_w=None,
+               sin_w=None, fp64=True):
+    """Full-track fit of merged sector tracks (float64, or float32 with the
+    same expressions in the same order): per track index, filled for group
+    leaders.  Returns dict(par_in, par_out, cov_out, chi2, n_hits,
+    n_members, status)."""
     offs = np.ascontiguousarray(sector_offsets, np.int64)
     n_sec = offs.shape[0] - 1
     if cos_w is None:
         cos_w, sin_w = sector_width_cs(360.0 / sectors_per_side)
     nt = trk_off.shape[0] - 1
     m = max(nt, 1)
-    out = dict(par_in=np.zeros((m, 5)), par_out=np.zeros((m, 5)), cov_out=np.zeros((m, 15)),
-               chi2=np.zeros(m), n_hits=np.zeros(m, np.int32), n_members=np.zeros(m, np.int32),
+    dt = np.float64 if fp64 else np.float32
+    out = dict(par_in=np.zeros((m, 5), dt), par_out=np.zeros((m, 5), dt),
+               cov_out=np.zeros((m, 15), dt), chi2=np.zeros(m, dt),
+               n_hits=np.zeros(m, np.int32), n_members=np.zeros(m, np.int32),
                status=np.zeros(m, np.int32))
     P = params(prm)
     i32 = lambda a: _p(np.ascontiguousarray(a, np.int32))
-    lib().orc_fit_merged64(C.c_int(n_sec), _p(offs), C.c_int(sectors_per_side),
+    fn = lib().orc_fit_merged64 if fp64 else lib().orc_fit_merged32
+    fn(C.c_int(n_sec), _p(offs), C.c_int(sectors_per_side),
                            _p(np.ascontiguousarray(row_x, np.float32)), C.byref(P),
                            _p(np.ascontiguousarray(row, np.uint8)),
                            _p(np.ascontiguousarray(y, np.float32)),
                            _p(np.ascontiguousarray(z, np.float32)), C.c_int64(nt), i32(trk_off),
-                           i32(trk_hits), _p(np.ascontiguousarray(par, np.float32)), i32(rin),
+                           i32(trk_hits), _p(np.ascontiguousarray(par, np.float32)),
+                           _p(np.ascontiguousarray(cov, np.float32)), i32(rin),
                            i32(link_up), i32(link_dn), i32(group), C.c_float(cos_w),
-                           C.c_float(sin_w), C.c_int(n_pass), _p(out["par_in"]),
+                           C.c_float(sin_w), C.c_int(n_pass), C.c_float(cov_scale),
+                           _p(out["par_in"]),
                            _p(out["par_out"]), _p(out["cov_out"]), _p(out["chi2"]),
                            _p(out["n_hits"]), _p(out["n_members"]), _p(out["status"]))
     return {k: v[:nt] for k, v in out.items()}
@@ -352,6 +359,49 @@ def rotate(x, p, Cov, c, sd, curv, s_max=0.95):
     ok = lib().orc_rotate64(C.byref(xx), _p(p), _p(Cv), C.c_double(c), C.c_double(sd),
                             C.c_double(curv), C.c_double(s_max))
     return bool(ok), xx.value, p, Cv
+
+
+def vertex_weights(trk_off, row, y, z, row_x, prm, theta, sigma_v=0.01, side=None, cm=None):
+    """Per-track weights (w00, w01, w11) of the beam-axis term at theta
+    (float64) and the tracks that have one."""
+    cm = cm or calib_model()
+    n = trk_off.shape[0] - 1
+    w = np.zeros((max(n, 1), 3), np.float64)
+    ok = np.zeros(max(n, 1), np.int32)
+    sd = None if side is None else np.ascontiguousarray(side, np.int8)
+    lib().orc_vertex_weights64(C.c_int64(n), _p(np.ascontiguousarray(trk_off, np.int32)), _p(row),
+                               _p(np.ascontiguousarray(y, np.float64)),
+                               _p(np.ascontiguousarray(z, np.float64)), _p(sd), _p(row_x),
+                               C.byref(params(prm)), C.byref(cm),
+                               _p(np.ascontiguousarray(theta, np.float64)),
+                               C.c_double(sigma_v * sigma_v), _p(w), _p(ok))
+    return w[:n], ok[:n]
+
+
+def calib_objective(trk_off, row, y, z, row_x, prm, theta, w, g=None, side=None, cm=None,
+                    grad=True):
+    """Calibration objective with the beam-axis constraint (float64):
+    L = sum_t g_t (chi2_t + r_t^T W_t r_t) with the per-track weights w
+    (vertex_weights; None: chi2 only).  Returns (L, dL/dtheta or None,
+    per-track terms, vertex-term flags)."""
+    L = lib()
+    L.orc_calib_objective64.restype = C.c_double
+    P = params(prm)
+    cm = cm or calib_model()
+    n = trk_off.shape[0] - 1
+    g = np.ones(n) if g is None else np.ascontiguousarray(g, np.float64)
+    gt = np.zeros(16, np.float64) if grad else None
+    per = np.zeros(max(n, 1), np.float64)
+    vok = np.zeros(max(n, 1), np.int32)
+    sd = None if side is None else np.ascontiguousarray(side, np.int8)
+    wv = None if w is None else np.ascontiguousarray(w, np.float64)
+    val = L.orc_calib_objective64(C.c_int64(n), _p(np.ascontiguousarray(trk_off, np.int32)),
+                                  _p(row), _p(np.ascontiguousarray(y, np.float64)),
+                                  _p(np.ascontiguousarray(z, np.float64)), _p(sd), _p(row_x),
+                                  C.byref(P), C.byref(cm),
+                                  _p(np.ascontiguousarray(theta, np.float64)), _p(g), _p(wv),
+                                  _p(gt), _p(per), _p(vok))
+    return val, gt, per[:n], vok[:n]
 
 
 def refit_adjoint64(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None):

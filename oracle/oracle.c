@@ -861,126 +861,95 @@ void orc_merge_sector_tracks(int n_sec, const int64_t* sector_offsets, int sps,
  * next hit's row plane.  The fit starts from the first member's tracklet
  * state (at the plane of its innermost fitted row) and makes n_pass passes
  * over all hits, alternately outwards (first to last hit) and inwards; every
- * pass starts with the initial covariance and the previous pass's
- * parameters, and updates with every hit (the first at the plane where the
- * previous pass ended).  Outputs, for the chain's least track index (its
- * group) only: the state after the last outward pass at the last hit (its
- * sector's frame) and its covariance, the state after the last inward pass
- * at the first hit, the chi2 sum of the last pass, the hit count and the
- * member count.  status: 0 fitted, 1 fewer than 3 hits, 2 a transport or a
+ * pass starts from the previous pass's parameters and a diagonal covariance,
+ * the variances of the first member's tracklet (first pass) or of the
+ * previous pass's end, times cov_scale (a weak prior that keeps the float32
+ * filter away from the cancellation a restart from the tracklet's initial
+ * variances causes), and updates with every hit (the first at the plane
+ * where the previous pass ended).  Outputs, for the chain's least track index
+ * (its group) only: the state after the last outward pass at the last hit
+ * (its sector's frame) and its covariance, the state after the last inward
+ * pass at the first hit (zero with one pass), the chi2 sum of the last pass,
+ * the hit count and the member count.  status: 0 fitted, 1 fewer than 3 hits, 2 a transport or a
  * frame turn stopped, -1 not a group's leader. */
-static int sector_of_id(int n_sec, const int64_t* sector_offsets, int c)
-{
-    int s = 0;
-    while (s + 1 < n_sec && c >= sector_offsets[s + 1]) s++;
-    return s;
-}
+#define REAL float
+#define SUF _f
+#include "fullfit_impl.h"
+#undef REAL
+#undef SUF
+#define REAL double
+#define SUF _d
+#include "fullfit_impl.h"
+#undef REAL
+#undef SUF
 
 void orc_fit_merged64(int n_sec, const int64_t* sector_offsets, int sps, const float* row_x,
                       const orc_params* prm, const uint8_t* row, const float* y, const float* z,
                       int64_t n_tracks, const int* trk_off, const int* trk_hits,
-                      const float* par, const int* rin, const int* link_up, const int* link_dn,
-                      const int* group, float cos_w, float sin_w, int n_pass, double* par_in,
+                      const float* par, const float* cov, const int* rin,
+                      const int* link_up, const int* link_dn, const int* group, float cos_w,
+                      float sin_w, int n_pass, float cov_scale, double* par_in,
                       double* par_out, double* cov_out, double* chi2_out, int* n_hits,
                       int* n_members, int* status)
 {
-    int64_t nh_all = n_tracks > 0 ? trk_off[n_tracks] : 0;
-    int* hits = malloc(sizeof(int) * (size_t)(nh_all > 0 ? nh_all : 1));
-    int* hsec = malloc(sizeof(int) * (size_t)(nh_all > 0 ? nh_all : 1));
-    int* chain = malloc(sizeof(int) * (size_t)(n_sec + 1));
-    for (int64_t g = 0; g < n_tracks; g++) {
-        for (int i = 0; i < 5; i++) par_in[5 * g + i] = par_out[5 * g + i] = 0.0;
-        for (int i = 0; i < 15; i++) cov_out[15 * g + i] = 0.0;
-        chi2_out[g] = 0.0;
-        n_hits[g] = 0;
-        n_members[g] = 0;
-        if (group[g] != (int)g) {
-            status[g] = -1;
+    fit_merged_d(n_sec, sector_offsets, sps, row_x, prm, row, y, z, n_tracks, trk_off, trk_hits,
+                 par, cov, rin, link_up, link_dn, group, cos_w, sin_w, n_pass, cov_scale,
+                 par_in, par_out,
+                 cov_out, chi2_out, n_hits, n_members, status);
+}
+
+void orc_fit_merged32(int n_sec, const int64_t* sector_offsets, int sps, const float* row_x,
+                      const orc_params* prm, const uint8_t* row, const float* y, const float* z,
+                      int64_t n_tracks, const int* trk_off, const int* trk_hits,
+                      const float* par, const float* cov, const int* rin,
+                      const int* link_up, const int* link_dn, const int* group, float cos_w,
+                      float sin_w, int n_pass, float cov_scale, float* par_in,
+                      float* par_out, float* cov_out, float* chi2_out, int* n_hits,
+                      int* n_members, int* status)
+{
+    fit_merged_f(n_sec, sector_offsets, sps, row_x, prm, row, y, z, n_tracks, trk_off, trk_hits,
+                 par, cov, rin, link_up, link_dn, group, cos_w, sin_w, n_pass, cov_scale,
+                 par_in, par_out,
+                 cov_out, chi2_out, n_hits, n_members, status);
+}
+
+/* ---- weights of the beam-axis term of the calibration objective ---------
+ * Per track (refit at theta, float64): the state and covariance of the last
+ * hit, at its calibrated plane, transported to x = 0 in ceil(x / 20 cm)
+ * equal steps; S = the (y, z) block of the covariance there plus
+ * sigma_v2 on the diagonal; W = S^-1 as (w00, w01, w11); zeros and ok = 0
+ * where the refit or the transport stops. */
+void orc_vertex_weights64(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                          const double* y, const double* z, const signed char* side,
+                          const float* row_x, const orc_params* prm,
+                          const orc_calib_model* cm, const double* theta, double sigma_v2,
+                          double* w, int* ok)
+{
+    for (int64_t t = 0; t < n_tracks; t++) {
+        int a = trk_off[t], n = trk_off[t + 1] - a;
+        double sd = side ? (double)side[t] : 1.0;
+        double p[5], C[15], chi2;
+        w[3 * t] = w[3 * t + 1] = w[3 * t + 2] = 0.0;
+        ok[t] = 0;
+        if (refit_track_d(n, row + a, y + a, z + a, sd, row_x, prm, cm, theta, p, C, &chi2))
             continue;
-        }
-        /* the chain: down end first, at most one member per sector */
-        int j = (int)g;
-        for (int step = 0; step < n_sec && link_dn[j] >= 0 && link_dn[j] != (int)g; step++)
-            j = link_dn[j];
-        int m = 0;
-        while (j >= 0 && m < n_sec) {
-            chain[m++] = j;
-            j = link_up[j];
-            if (j == chain[0]) break;
-        }
-        int r_dn = trk_off[chain[0] + 1] > trk_off[chain[0]] ? row[trk_hits[trk_off[chain[0]]]] : 0;
-        int r_up = trk_off[chain[m - 1] + 1] > trk_off[chain[m - 1]]
-                       ? row[trk_hits[trk_off[chain[m - 1]]]] : 0;
-        if (r_up < r_dn)
-            for (int a = 0, b = m - 1; a < b; a++, b--) {
-                int t = chain[a];
-                chain[a] = chain[b];
-                chain[b] = t;
-            }
-        int n = 0;
-        for (int a = 0; a < m; a++)
-            for (int q = trk_off[chain[a]]; q < trk_off[chain[a] + 1]; q++) {
-                hits[n] = trk_hits[q];
-                hsec[n] = sector_of_id(n_sec, sector_offsets, trk_hits[q]);
-                n++;
-            }
-        n_hits[g] = n;
-        n_members[g] = m;
-        if (n < 3) {
-            status[g] = 1;
-            continue;
-        }
-        double p[5], C[15], x = (double)row_x[rin[chain[0]]];
-        for (int i = 0; i < 5; i++) p[i] = (double)par[5 * chain[0] + i];
-        int cur = hsec[0], ok = 1;
-        double chi2 = 0.0;
-        for (int pass = 0; pass < n_pass && ok; pass++) {
-            int out = pass % 2 == 0;
-            for (int i = 0; i < 15; i++) C[i] = 0.0;
-            C[0] = prm->sigma_y2;
-            C[2] = prm->sigma_z2;
-            C[5] = prm->c_ss0;
-            C[9] = prm->c_tt0;
-            C[14] = prm->c_ww0;
-            chi2 = 0.0;
-            for (int k = 0; k < n && ok; k++) {
-                int i = out ? k : n - 1 - k;
-                if (hsec[i] != cur) {
-                    /* neighbouring sectors of one side: up or down */
-                    int side = cur / sps, ic = cur % sps;
-                    int up = side * sps + (ic + 1) % sps;
-                    double sd = hsec[i] == up ? -(double)sin_w : (double)sin_w;
-                    if (!rotate_d(&x, p, C, (double)cos_w, sd, prm->curv, prm->s_max)) {
-                        ok = 0;
-                        break;
-                    }
-                    cur = hsec[i];
-                }
-                double xh = (double)row_x[row[hits[i]]];
-                if (!propagate_d(p, C, xh - x, prm->curv, prm->s_max)) {
-                    ok = 0;
-                    break;
-                }
-                x = xh;
-                chi2 = chi2 + update_d(p, C, (double)y[hits[i]], (double)z[hits[i]],
-                                       prm->sigma_y2, prm->sigma_z2);
-            }
-            if (ok && !out)
-                for (int i = 0; i < 5; i++) par_in[5 * g + i] = p[i];
-        }
-        if (!ok) {
-            for (int i = 0; i < 5; i++) par_in[5 * g + i] = 0.0;
-            status[g] = 2;
-            continue;
-        }
-        for (int i = 0; i < 5; i++) par_out[5 * g + i] = p[i];
-        for (int i = 0; i < 15; i++) cov_out[15 * g + i] = C[i];
-        chi2_out[g] = chi2;
-        status[g] = 0;
+        double xl, yl, zl;
+        calibrate_d(theta, (double)row_x[row[a + n - 1]], y[a + n - 1], z[a + n - 1], sd,
+                    cm->drift_len, cm->vd, cm->tan_half, cm->u_centre, cm->u_scale, &xl, &yl,
+                    &zl);
+        int ns = (int)ceil(xl / 20.0);
+        if (ns < 1) ns = 1;
+        double dx = (0.0 - xl) / (double)ns;
+        int good = 1;
+        for (int i = 0; i < ns && good; i++) good = propagate_d(p, C, dx, prm->curv, prm->s_max);
+        if (!good) continue;
+        double s00 = C[0] + sigma_v2, s10 = C[1], s11 = C[2] + sigma_v2;
+        double det = s00 * s11 - s10 * s10;
+        w[3 * t] = s11 / det;
+        w[3 * t + 1] = -s10 / det;
+        w[3 * t + 2] = s00 / det;
+        ok[t] = 1;
     }
-    free(hits);
-    free(hsec);
-    free(chain);
 }
 
 /* One frame turn (float64) for the pins: x, p[5], C[15] in place. */

@@ -140,6 +140,24 @@ void orc_refit64_adjoint(int64_t n_tracks, const int* trk_off, const uint8_t* ro
                          const orc_calib_model* cm, const double* theta, const double* g,
                          double* grad_y, double* grad_z, double* grad_theta);
 
+/* Calibration objective (adjoint.cc): L = sum_t g_t (chi2_t + r_t^T W_t r_t),
+ * r_t the refit state of the last hit transported to the beam-axis plane
+ * x = 0 (20 cm steps), W_t given per track (w00, w01, w11; NULL: no vertex
+ * term); returns L, writes dL/dtheta (nullable), the per-track terms and
+ * whether the vertex term was taken (nullable). */
+double orc_calib_objective64(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                             const double* y, const double* z, const signed char* side,
+                             const float* row_x, const orc_params* prm,
+                             const orc_calib_model* cm, const double* theta, const double* g,
+                             const double* w, double* grad_theta, double* per_track,
+                             int* vertex_ok);
+/* Weights of the beam-axis term at theta (oracle.c). */
+void orc_vertex_weights64(int64_t n_tracks, const int* trk_off, const uint8_t* row,
+                          const double* y, const double* z, const signed char* side,
+                          const float* row_x, const orc_params* prm,
+                          const orc_calib_model* cm, const double* theta, double sigma_v2,
+                          double* w, int* ok);
+
 /* Track-based cluster attachment (section 6): tube of `radius` around
  * every track over the rows of its hits, its axis the track state par[5k]
  * (at the plane of row rin[k]) transported outwards row by row; unowned
@@ -168,9 +186,18 @@ void orc_attach_clusters(int n_sec, const int64_t* sector_offsets, int n_rows,
 void orc_fit_merged64(int n_sec, const int64_t* sector_offsets, int sps, const float* row_x,
                       const orc_params* prm, const uint8_t* row, const float* y, const float* z,
                       int64_t n_tracks, const int* trk_off, const int* trk_hits,
-                      const float* par, const int* rin, const int* link_up, const int* link_dn,
-                      const int* group, float cos_w, float sin_w, int n_pass, double* par_in,
+                      const float* par, const float* cov, const int* rin,
+                      const int* link_up, const int* link_dn, const int* group, float cos_w,
+                      float sin_w, int n_pass, float cov_scale, double* par_in,
                       double* par_out, double* cov_out, double* chi2_out, int* n_hits,
+                      int* n_members, int* status);
+void orc_fit_merged32(int n_sec, const int64_t* sector_offsets, int sps, const float* row_x,
+                      const orc_params* prm, const uint8_t* row, const float* y, const float* z,
+                      int64_t n_tracks, const int* trk_off, const int* trk_hits,
+                      const float* par, const float* cov, const int* rin,
+                      const int* link_up, const int* link_dn, const int* group, float cos_w,
+                      float sin_w, int n_pass, float cov_scale, float* par_in,
+                      float* par_out, float* cov_out, float* chi2_out, int* n_hits,
                       int* n_members, int* status);
 int orc_rotate64(double* x, double* p, double* C, double c, double sd, double curv,
                  double s_max);

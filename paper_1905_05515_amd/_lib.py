@@ -66,6 +66,11 @@ class MergeCuts(C.Structure):
                 ("sin_width", C.c_float), ("inv_window", C.c_float * 5)]
 
 
+class FitOut(C.Structure):
+    _fields_ = [("par_in", P), ("par_out", P), ("cov_out", P), ("chi2", P), ("n_hits", P),
+                ("n_members", P), ("status", P)]
+
+
 class TrackHits(C.Structure):
     _fields_ = [("off", P), ("idx", P), ("row", P), ("y", P), ("z", P), ("side", P),
                 ("d_count", P), ("n_tracks", I64), ("n_hits", I64)]
@@ -92,6 +97,12 @@ EXPORTS = {
     "tpc_refit_adjoint": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params),
                                     C.POINTER(CalibModel), P, P, C.c_size_t, P, P, P, P, P, P,
                                     C.c_size_t, P]),
+    "tpc_refit_adjoint_seeded": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params),
+                                           C.POINTER(CalibModel), P, P, C.c_size_t, P, P, P, P,
+                                           P, P, P, P, C.c_size_t, P]),
+    "tpc_vertex_residual": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params),
+                                      C.POINTER(CalibModel), P, P, P, P, F32, P, P, P, P, P, P,
+                                      P]),
     "tpc_refit_adjoint_noalloc": (C.c_int, [P, TrackHits, I32, P, C.POINTER(Params),
                                             C.POINTER(CalibModel), P, P, C.c_size_t, P, P, P,
                                             P, P, P]),
@@ -101,6 +112,8 @@ EXPORTS = {
     "tpc_merge_workspace_size": (C.c_int, [C.POINTER(Problem), I64, C.POINTER(C.c_size_t)]),
     "tpc_merge_sector_tracks": (C.c_int, [P, C.POINTER(Problem), Tracklets, Tracks, P, MergeCuts,
                                           P, P, P, P, C.c_size_t, P]),
+    "tpc_fit_merged_tracks": (C.c_int, [P, C.POINTER(Problem), Clusters, Tracklets, Tracks, P,
+                                        P, P, P, I32, F32, F32, I32, F32, FitOut, P]),
     "tpc_track_t0": (C.c_int, [P, C.POINTER(Problem), Tracklets, Tracks, P, F32, P, P, P, P, P]),
     "tpc_status_string": (C.c_char_p, [C.c_int]),
     "tpc_timing_enable": (C.c_int, [P, C.c_int]),

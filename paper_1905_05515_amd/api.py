@@ -329,6 +329,34 @@ def merge_sector_tracks(ctx: Context, ev: Event, sectors_per_side: int = 18,
     return tuple(out)
 
 
+def fit_merged_tracks(ctx: Context, ev: Event, links, sectors_per_side: int = 18,
+                      n_pass: int = 3, cov_scale: float = 100.0, stream=None):
+    """Full-track fit of the merged sector tracks (after merge_sector_tracks,
+    whose (link_up, link_dn, group) are `links`): dict of device tensors of
+    tracks.capacity entries (par_in, par_out [cap, 5], cov_out [cap, 15],
+    chi2, n_hits, n_members, status); the first n_tracks are written, group
+    leaders carry the fit."""
+    dev = ev.t["row"].device
+    cap = max(ev.track_capacity, 1)
+    f32 = dict(dtype=torch.float32, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(par_in=torch.empty(cap, 5, **f32), par_out=torch.empty(cap, 5, **f32),
+               cov_out=torch.empty(cap, 15, **f32), chi2=torch.empty(cap, **f32),
+               n_hits=torch.empty(cap, **i32), n_members=torch.empty(cap, **i32),
+               status=torch.empty(cap, **i32))
+    fo = L.FitOut(*[_ptr(out[k]) for k in ("par_in", "par_out", "cov_out", "chi2", "n_hits",
+                                             "n_members", "status")])
+    cuts = merge_cuts(sectors_per_side)
+    up, dn, grp = links
+    L.check(L.lib().tpc_fit_merged_tracks(ctx.handle, C.byref(ev.problem), _clusters(ev),
+                                          _tracklets(ev), _tracks(ev), status_count_ptr(ev),
+                                          _ptr(up), _ptr(dn), _ptr(grp), int(sectors_per_side),
+                                          cuts.cos_width, cuts.sin_width, int(n_pass),
+                                          float(cov_scale), fo, _stream(stream)),
+            "tpc_fit_merged_tracks")
+    return out
+
+
 def track_t0(ctx: Context, ev: Event, vd: float = 2.58, stream=None):
     """Interaction time of the event's found tracks in continuous read-out
     (after the tracking calls): device tensors (z0, y0, t0 float32, ok int8)
@@ -510,11 +538,12 @@ def refit(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta: 
 
 def refit_adjoint(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
                   theta: torch.Tensor, fwd: dict, grad_chi2: torch.Tensor, cm=None, stream=None,
-                  y=None, z=None, out=None):
-    """Gradients of sum_k grad_chi2[k] chi2[k]: (grad_y, grad_z, grad_theta),
-    grad_y/grad_z per hit entry of the track list.  `out` (dict with ws, gy,
-    gz, gt of an earlier call, or any of them) is reused; entries of tracks
-    past the device track count are not written."""
+                  y=None, z=None, out=None, grad_par=None, grad_x=None):
+    """Gradients of sum_k grad_chi2[k] chi2[k] (+ sum_k grad_par[k] . par[k]
+    + sum_k grad_x[k] x_last[k] when either seed is given): (grad_y, grad_z,
+    grad_theta), grad_y/grad_z per hit entry of the track list.  `out` (dict
+    with ws, gy, gz, gt of an earlier call, or any of them) is reused;
+    entries of tracks past the device track count are not written."""
     dev = hits.row.device
     nb = C.c_size_t()
     L.check(L.lib().tpc_refit_workspace_size(hits.n_tracks, C.byref(nb)), "workspace")
@@ -531,10 +560,149 @@ def refit_adjoint(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
     CM = calib_struct(cm)
     th = theta.detach().to(device=dev, dtype=torch.float32).contiguous()
     g = grad_chi2.detach().to(device=dev, dtype=torch.float32).contiguous()
-    L.check(L.lib().tpc_refit_adjoint(ctx.handle, hits.struct(y, z), int(row_x.shape[0]),
-                                      _ptr(row_x), C.byref(P), C.byref(CM), _ptr(th),
-                                      _ptr(fwd["checkpoints"]), _nbytes(fwd["checkpoints"]),
-                                      _ptr(fwd["status"]), _ptr(g),
-                                      _ptr(gy), _ptr(gz), _ptr(gt), _ptr(ws), int(nb.value),
-                                      _stream(stream)), "tpc_refit_adjoint")
+    if grad_par is None and grad_x is None:
+        L.check(L.lib().tpc_refit_adjoint(ctx.handle, hits.struct(y, z), int(row_x.shape[0]),
+                                          _ptr(row_x), C.byref(P), C.byref(CM), _ptr(th),
+                                          _ptr(fwd["checkpoints"]), _nbytes(fwd["checkpoints"]),
+                                          _ptr(fwd["status"]), _ptr(g),
+                                          _ptr(gy), _ptr(gz), _ptr(gt), _ptr(ws), int(nb.value),
+                                          _stream(stream)), "tpc_refit_adjoint")
+    else:
+        L.check(L.lib().tpc_refit_adjoint_seeded(
+            ctx.handle, hits.struct(y, z), int(row_x.shape[0]), _ptr(row_x), C.byref(P),
+            C.byref(CM), _ptr(th), _ptr(fwd["checkpoints"]), _nbytes(fwd["checkpoints"]),
+            _ptr(fwd["status"]), _ptr(g), _ptr(grad_par), _ptr(grad_x), _ptr(gy), _ptr(gz),
+            _ptr(gt), _ptr(ws), int(nb.value), _stream(stream)), "tpc_refit_adjoint_seeded")
     return gy[:hits.n_hits], gz[:hits.n_hits], gt
+
+
+def vertex_residual(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
+                    theta: torch.Tensor, fwd: dict, sigma_v: float = 0.01, weights=None, cm=None,
+                    stream=None, out=None):
+    """Beam-axis term of the calibration objective for every track of the
+    refit `fwd` (with its covariance): (loss [n], grad_par [n, 5], grad_x [n],
+    ok [n], weights [n, 3]) device tensors.  weights: held per-track weights
+    (an earlier call's), or None to take them from the refit covariance.
+    `out` (the dict of an earlier call of the same size) is reused."""
+    dev = hits.row.device
+    n = max(hits.n_tracks, 1)
+    out = {} if out is None else out
+    if "loss" not in out:
+        out["loss"] = torch.empty(n, dtype=torch.float32, device=dev)
+        out["gp"] = torch.empty(n, 5, dtype=torch.float32, device=dev)
+        out["gx"] = torch.empty(n, dtype=torch.float32, device=dev)
+        out["ok"] = torch.empty(n, dtype=torch.int8, device=dev)
+        out["w"] = torch.empty(n, 3, dtype=torch.float32, device=dev)
+    P = params_struct(prm)
+    CM = calib_struct(cm)
+    th = theta.detach().to(device=dev, dtype=torch.float32).contiguous()
+    L.check(L.lib().tpc_vertex_residual(ctx.handle, hits.struct(), int(row_x.shape[0]),
+                                        _ptr(row_x), C.byref(P), C.byref(CM), _ptr(th),
+                                        _ptr(fwd["par"]), _ptr(fwd["cov"]), _ptr(fwd["status"]),
+                                        float(sigma_v), _ptr(weights),
+                                        _ptr(out["w"]) if weights is None else None,
+                                        _ptr(out["loss"]), _ptr(out["gp"]), _ptr(out["gx"]),
+                                        _ptr(out["ok"]), _stream(stream)),
+            "tpc_vertex_residual")
+    return out["loss"], out["gp"], out["gx"], out["ok"], (out["w"] if weights is None
+                                                          else weights)
+
+
+# parameters the calibration fits by default: t0 and the azimuthal distortion
+# terms that move clusters without rescaling the measured coordinates
+# (functions of the row and the drift only: 1, u, u^2, w).  The drift velocity
+# scale is not separable from t0 for primaries of a known vertex on one z
+# side; the radial terms move the row planes along the track, which the track
+# curvature nearly absorbs (the chi2 pins them only weakly and with a bias of
+# many statistical errors); the terms in the raw y rescale the cluster
+# errors, which a chi2 objective rewards (it prefers shrunken coordinates):
+# those stay at theta0.
+CALIB_FREE = (1, 9, 10, 12, 15)
+
+
+def calibration_objective(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict,
+                          theta: torch.Tensor, weights=None, sigma_v: float = 0.01, cm=None,
+                          stream=None, state=None, grad=True):
+    """Calibration objective with the beam-axis constraint (section 3,
+    online calibration; section 2, primaries from the origin):
+    L(theta) = sum_k chi2_k(theta) + r_k^T W_k r_k over the tracks of `hits`,
+    r_k the refit state of the last hit at the beam-axis plane, W_k held
+    weights (None: taken from this refit's covariance), computed by the
+    refit, the beam-axis kernel and the seeded adjoint.  Returns (L as a
+    float, dL/dtheta float32 [16] device tensor or None, the weights).
+    `state` (a dict) keeps the buffers between calls."""
+    state = {} if state is None else state
+    state["fwd"] = refit(ctx, hits, row_x, prm, theta, cm=cm, stream=stream,
+                         out=state.get("fwd"))
+    fwd = state["fwd"]
+    state.setdefault("vtx", {})
+    loss, gp, gx, ok, w = vertex_residual(ctx, hits, row_x, prm, theta, fwd, sigma_v, weights,
+                                          cm, stream, out=state["vtx"])
+    n = hits.n_tracks
+    val = float(fwd["chi2"][:n].double().sum() + loss[:n].double().sum())
+    if not grad:
+        return val, None, w
+    if "g1" not in state:
+        state["g1"] = torch.ones(max(n, 1), dtype=torch.float32, device=hits.row.device)
+    state.setdefault("adj", {})
+    _, _, gt = refit_adjoint(ctx, hits, row_x, prm, theta, fwd, state["g1"], cm=cm,
+                             stream=stream, out=state["adj"], grad_par=gp, grad_x=gx)
+    return val, gt, w
+
+
+def calibrate(ctx: Context, hits: TrackHits, row_x: torch.Tensor, prm: dict, theta0,
+              free=CALIB_FREE, sigma_v: float = 0.01, n_iter: int = 12, fd_step: float = 1e-4,
+              cm=None, stream=None):
+    """Global calibration (section 3's online calibration) by damped Newton
+    (Levenberg-Marquardt) steps on the calibration objective: each iteration
+    takes the beam-axis weights at the current theta and holds them, the
+    gradient is the adjoint's, the Hessian over the free parameters is taken
+    by central differences of that gradient (step fd_step), and a step is
+    kept only when the objective decreases (else the damping grows).  free:
+    the indices of theta to fit; the others stay at theta0.  Returns dict
+    theta (float64 numpy [16]), objective, history, hessian (free x free),
+    cov = 2 H^-1 and sigma (the estimator's statistical errors)."""
+    import numpy as np
+    free = np.asarray(free)
+    th = np.asarray(theta0, np.float64).copy()
+    dev = hits.row.device
+    state = {}
+
+    def f(t, w, grad=True):
+        v, g, w2 = calibration_objective(ctx, hits, row_x, prm, torch.as_tensor(t, device=dev),
+                                         w, sigma_v, cm, stream, state, grad)
+        return v, (g.double().cpu().numpy() if g is not None else None), w2
+
+    hist = []
+    lam = 1e-3
+    H = None
+    for it in range(n_iter):
+        val, g, w = f(th, None)
+        w = w.clone()
+        H = np.zeros((free.size, free.size))
+        for j, k in enumerate(free):
+            e = np.zeros(16)
+            e[k] = fd_step
+            H[:, j] = (f(th + e, w)[1][free] - f(th - e, w)[1][free]) / (2.0 * fd_step)
+        H = 0.5 * (H + H.T)
+        D = np.diag(np.diag(H))
+        moved = False
+        while lam < 1e12:
+            step = -np.linalg.solve(H + lam * D, g[free])
+            cand = th.copy()
+            cand[free] += step
+            v_new = f(cand, w, grad=False)[0]
+            if v_new < val:
+                th = cand
+                lam = max(lam / 3.0, 1e-9)
+                moved = True
+                break
+            lam *= 10.0
+        hist.append(dict(objective=val, step=float(np.abs(step).max()) if moved else 0.0,
+                         damping=lam))
+        if not moved:
+            break
+    cov = 2.0 * np.linalg.inv(H)
+    val = f(th, None, grad=False)[0]
+    return dict(theta=th, objective=val, history=hist, free=free, hessian=H, cov=cov,
+                sigma=np.sqrt(np.abs(np.diag(cov))))

@@ -611,6 +611,7 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
     const float* __restrict__ row_x, tpc_params prm, CalibModel cm,
     const float* __restrict__ d_theta, const float* __restrict__ ck,
     const int32_t* __restrict__ status, const float* __restrict__ gchi2,
+    const float* __restrict__ seed_p, const float* __restrict__ seed_x,
     float* __restrict__ gy, float* __restrict__ gz, float* __restrict__ partials)
 {
     __shared__ float th[16];
@@ -650,7 +651,12 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
         const float4* ckt = ck_tile(const_cast<float*>(ck), tb + lane, n_rows);
         const float sd = fit && side ? (float)side[t] : 1.0f;
         const float cb = fit ? gchi2[t] : 0.0f;
+        // adjoint of the final state: the seed of the caller's terms in the
+        // state after the last update (dL/dp), zero without one
         float pb[5] = {0, 0, 0, 0, 0}, G[15];
+        if (fit && seed_p)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) pb[i] = seed_p[t * 5 + i];
 #pragma unroll
         for (int i = 0; i < 15; ++i) G[i] = 0.0f;
         CalHit cur{};
@@ -660,7 +666,8 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
             cur = H.cal(n - 1, th, xs, sd, cm);
             load_ck(ckt, n - 2, ck4);
         }
-        float Xcarry = 0.0f;
+        // dL/dx of the last hit's calibrated plane from the caller's terms
+        float Xcarry = fit && seed_x ? seed_x[t] : 0.0f;
         float X2 = 0.0f, Y2 = 0.0f, Z2 = 0.0f;
         // steps i = top .. lo need hits lo - 1 .. top - 1 (the previous hit)
         for (int top = M - 1; top >= 1;) {
@@ -771,6 +778,104 @@ __global__ __launch_bounds__(kBlock) void k_reduce_theta(const float* __restrict
     if (threadIdx.x == 0) out[k] = red[0];
 }
 
+// Beam-axis term of the calibration objective (section 3's online
+// calibration with section 2's primaries from the origin): the refit state of
+// a track's last hit (par, cov at the calibrated plane of that hit) is
+// transported to the plane x = 0 of its sector frame, which holds the beam
+// axis, in ceil(x / 20 cm) equal steps; r = (y0, z0) there and
+// loss = r^T W r, with W = S^-1, S the transported (y, z) covariance plus
+// sigma_v^2 on the diagonal (the chi2 increment of a vertex measurement) --
+// or W given by the caller (w_in: held fixed while the calibration moves).
+// Derivatives: with respect to the state through the product of the step
+// Jacobians, and to the plane of the last hit (moving the plane with the
+// state held translates the track along x: dr/dx = -(s0, t) / c0 at the axis
+// plane).  Zero (ok = 0) for tracks without a fit or whose transport stops.
+// One thread per track.
+__global__ __launch_bounds__(kBlock) void k_vertex_residual(
+    const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+    const uint8_t* __restrict__ row, const float* __restrict__ y, const float* __restrict__ z,
+    const int8_t* __restrict__ side, const int64_t* __restrict__ d_count, int64_t n_tracks,
+    const float* __restrict__ row_x, tpc_params prm, CalibModel cm,
+    const float* __restrict__ d_theta, const float* __restrict__ par,
+    const float* __restrict__ cov, const int32_t* __restrict__ status, float sv2,
+    const float* __restrict__ w_in, float* __restrict__ w_out, float* __restrict__ loss,
+    float* __restrict__ seed_p, float* __restrict__ seed_x, int8_t* __restrict__ ok)
+{
+    __shared__ float th[16];
+    if (threadIdx.x < 16) th[threadIdx.x] = d_theta[threadIdx.x];
+    __syncthreads();
+    const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int a = off[t], n = off[t + 1] - a;
+        float l = 0.0f, gx = 0.0f, gp[5] = {0, 0, 0, 0, 0}, w[3] = {0, 0, 0};
+        bool good = status[t] == 0 && n >= 3;
+        if (good) {
+            const HitRef H{idx, row, y, z, a};
+            const int c = H.cl(n - 1);
+            const float sd = side ? (float)side[t] : 1.0f;
+            const float xl = calibrate(th, row_x[row[c]], y[c], z[c], sd, cm).x;
+            float p[5], C[15];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) p[i] = par[t * 5 + i];
+#pragma unroll
+            for (int i = 0; i < 15; ++i) C[i] = cov[t * 15 + i];
+            // rows y, z, sin of the accumulated Jacobian d(p at x)/d(p at xl)
+            float J0[5] = {1, 0, 0, 0, 0}, J1[5] = {0, 1, 0, 0, 0}, J2[5] = {0, 0, 1, 0, 0};
+            int n_step = (int)ceilf(xl / 20.0f);
+            if (n_step < 1) n_step = 1;
+            const float dx = (0.0f - xl) / (float)n_step;
+            for (int i = 0; i < n_step && good; ++i) {
+                Prop P;
+                if (!prop_fwd(p, C, dx, prm.curv, prm.s_max, P)) {
+                    good = false;
+                    break;
+                }
+                // rows 3, 4 of every step Jacobian are those of the identity
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const float e3 = k == 3 ? 1.0f : 0.0f, e4 = k == 4 ? 1.0f : 0.0f;
+                    const float n0 = J0[k] + P.ys * J2[k] + P.yw * e4;
+                    const float n1 = J1[k] + P.zs * J2[k] + P.zt * e3 + P.zw * e4;
+                    J2[k] = J2[k] + P.sw * e4;
+                    J0[k] = n0;
+                    J1[k] = n1;
+                }
+            }
+            if (good) {
+                if (w_in) {
+                    w[0] = w_in[t * 3];
+                    w[1] = w_in[t * 3 + 1];
+                    w[2] = w_in[t * 3 + 2];
+                } else {
+                    const float s00 = C[0] + sv2, s10 = C[1], s11 = C[2] + sv2;
+                    const float det = s00 * s11 - s10 * s10;
+                    w[0] = s11 / det;
+                    w[1] = -s10 / det;
+                    w[2] = s00 / det;
+                }
+                const float y0 = p[0], z0 = p[1];
+                const float u0 = w[0] * y0 + w[1] * z0, u1 = w[1] * y0 + w[2] * z0;
+                l = y0 * u0 + z0 * u1;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) gp[k] = 2.0f * (u0 * J0[k] + u1 * J1[k]);
+                const float c0 = sqrtf((1.0f - p[2]) * (1.0f + p[2]));
+                gx = -2.0f * (u0 * p[2] + u1 * p[3]) / c0;
+            }
+        }
+        loss[t] = l;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) seed_p[t * 5 + k] = gp[k];
+        seed_x[t] = gx;
+        if (w_out) {
+            w_out[t * 3] = w[0];
+            w_out[t * 3 + 1] = w[1];
+            w_out[t * 3 + 2] = w[2];
+        }
+        if (ok) ok[t] = good ? 1 : 0;
+    }
+}
+
 constexpr int64_t kRefitMaxBlocks = 16384;
 
 static unsigned refit_grid(int64_t n_tracks)
@@ -782,7 +887,8 @@ static unsigned refit_grid(int64_t n_tracks)
 static int launch_refit_adjoint(tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
                                 const tpc_params& prm, const tpc_calib_model& m,
                                 const float* d_theta, const float* checkpoints,
-                                const int32_t* status, const float* grad_chi2, float* grad_y,
+                                const int32_t* status, const float* grad_chi2,
+                                const float* seed_p, const float* seed_x, float* grad_y,
                                 float* grad_z, float* grad_theta, float* partials,
                                 hipStream_t st)
 {
@@ -790,7 +896,7 @@ static int launch_refit_adjoint(tpc_track_hits hits, int32_t n_rows, const float
     const unsigned nb = refit_grid(hits.n_tracks);
     TPC_LAUNCH(k_refit_adj, dim3(nb), dim3(kWave), 0, st, hits.off, hits.idx, hits.row, hits.y,
                hits.z, hits.side, hits.d_count, hits.n_tracks, n_rows, d_row_x, prm, cm,
-               d_theta, checkpoints, status, grad_chi2, grad_y, grad_z, partials);
+               d_theta, checkpoints, status, grad_chi2, seed_p, seed_x, grad_y, grad_z, partials);
     TPC_LAUNCH(k_reduce_theta, dim3(16), dim3(kBlock), 0, st, (const float*)partials, (int)nb,
                grad_theta);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
@@ -896,8 +1002,53 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
         tpc_refit_checkpoint_size(hits.n_tracks, n_rows, &need) || need > ck_bytes)
         return TPC_ERR_INVALID_ARG;
     return tpc::launch_refit_adjoint(hits, n_rows, d_row_x, *h_params, *h_model, d_theta,
-                                     checkpoints, status, grad_chi2, grad_y, grad_z,
-                                     grad_theta, (float*)d_ws, (hipStream_t)stream);
+                                     checkpoints, status, grad_chi2, nullptr, nullptr, grad_y,
+                                     grad_z, grad_theta, (float*)d_ws, (hipStream_t)stream);
+}
+
+int tpc_refit_adjoint_seeded(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                             const float* d_row_x, const tpc_params* h_params,
+                             const tpc_calib_model* h_model, const float* d_theta,
+                             const float* checkpoints, size_t ck_bytes, const int32_t* status,
+                             const float* grad_chi2, const float* grad_par, const float* grad_x,
+                             float* grad_y, float* grad_z, float* grad_theta, void* d_ws,
+                             size_t ws_bytes, void* stream)
+{
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
+    size_t need = 0;
+    if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !checkpoints || !status ||
+        !grad_chi2 || !grad_y || !grad_z || !grad_theta || !d_ws || hits.n_tracks < 0 ||
+        n_rows < 3 || n_rows > 255 ||
+        (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
+        tpc_refit_workspace_size(hits.n_tracks, &need) || need > ws_bytes ||
+        tpc_refit_checkpoint_size(hits.n_tracks, n_rows, &need) || need > ck_bytes)
+        return TPC_ERR_INVALID_ARG;
+    return tpc::launch_refit_adjoint(hits, n_rows, d_row_x, *h_params, *h_model, d_theta,
+                                     checkpoints, status, grad_chi2, grad_par, grad_x, grad_y,
+                                     grad_z, grad_theta, (float*)d_ws, (hipStream_t)stream);
+}
+
+int tpc_vertex_residual(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
+                        const float* d_row_x, const tpc_params* h_params,
+                        const tpc_calib_model* h_model, const float* d_theta, const float* par,
+                        const float* cov, const int32_t* status, float sigma_v,
+                        const float* w_in, float* w_out, float* loss, float* grad_par,
+                        float* grad_x, int8_t* ok, void* stream)
+{
+    tpc::TimerScope timing(ctx ? ctx->timer : nullptr);
+    if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !par || !cov || !status ||
+        !loss || !grad_par || !grad_x || hits.n_tracks < 0 || n_rows < 3 || n_rows > 255 ||
+        (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
+        !(sigma_v >= 0.0f) || !std::isfinite(sigma_v))
+        return TPC_ERR_INVALID_ARG;
+    if (hits.n_tracks == 0) return TPC_OK;
+    tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
+                       h_model->u_scale};
+    TPC_LAUNCH(tpc::k_vertex_residual, dim3(tpc::grid_for(hits.n_tracks)), dim3(tpc::kBlock), 0,
+               (hipStream_t)stream, hits.off, hits.idx, hits.row, hits.y, hits.z, hits.side,
+               hits.d_count, hits.n_tracks, d_row_x, *h_params, cm, d_theta, par, cov, status,
+               sigma_v * sigma_v, w_in, w_out, loss, grad_par, grad_x, ok);
+    return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
 int tpc_refit_adjoint_noalloc(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
@@ -926,8 +1077,8 @@ int tpc_refit_adjoint_noalloc(tpc_context* ctx, tpc_track_hits hits, int32_t n_r
     }
     if (!partials) return TPC_ERR_HIP;   // set up when the context was created
     return tpc::launch_refit_adjoint(hits, n_rows, d_row_x, *h_params, *h_model, d_theta,
-                                     checkpoints, status, grad_chi2, grad_y, grad_z,
-                                     grad_theta, partials, (hipStream_t)stream);
+                                     checkpoints, status, grad_chi2, nullptr, nullptr, grad_y,
+                                     grad_z, grad_theta, partials, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -527,7 +527,8 @@ def make_config5(seed=CONFIG_SEEDS[5], n_tracks=1_000_000, n_min=40, n_max=152,
                  chunk=200_000):
     """Refit workload: n_tracks truth segments of n_min..n_max consecutive
     rows, helices from the origin in a single-sector frame with pT >= 0.2,
-    distorted by theta_true, smeared; the refit is evaluated at theta_eval.
+    smeared (Gaussian in calibrated coordinates) and distorted by theta_true;
+    the refit is evaluated at theta_eval.
     Segments whose outgoing crossings leave |sin(phi)| <= 0.9 or the drift
     volume are redrawn (same length and first row)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -571,17 +572,22 @@ def make_config5(seed=CONFIG_SEEDS[5], n_tracks=1_000_000, n_min=40, n_max=152,
         ti = np.repeat(np.arange(a, b), cnt)
         ri = (np.arange(ti.shape[0]) - np.repeat(off[a:b] - off[a], cnt)) + np.repeat(r0[a:b], cnt)
         xr = ROW_X64[ri]
+        # the cluster error is Gaussian in the calibrated coordinates: the
+        # raw point is the one the calibration at theta maps onto the true
+        # crossing of the calibrated plane plus the error
+        ey = rng.normal(0.0, SIGMA, ti.shape[0])
+        ez = rng.normal(0.0, SIGMA, ti.shape[0])
         _, y_raw, z_raw, _ = _segment_points(trk, ti, xr)
-        for _ in range(3):     # fixed point: raw -> distortion -> true point
+        for _ in range(4):     # fixed point: raw -> distortion -> true point
             dr, drphi, _ = _distortion(theta, xr, y_raw, z_raw)
             _, yt, zt, _ = _segment_points(trk, ti, xr + dr)
-            y_raw = yt - drphi
-            d_raw = (DRIFT_LEN - zt) / (1.0 + theta[0]) + VD_CM_PER_US * theta[1]
+            y_raw = yt + ey - drphi
+            d_raw = (DRIFT_LEN - (zt + ez)) / (1.0 + theta[0]) + VD_CM_PER_US * theta[1]
             z_raw = DRIFT_LEN - d_raw
         sl = slice(int(off[a]), int(off[b]))
         row[sl] = ri.astype(np.uint8)
-        y[sl] = _smear32(rng, y_raw)
-        z[sl] = _smear32(rng, z_raw)
+        y[sl] = y_raw.astype(np.float32)
+        z[sl] = z_raw.astype(np.float32)
     return RefitSet(off.astype(np.int32), row, y, z, ROW_X.copy(), theta, theta_eval,
                     dict(trk, n_hits=nh, first_row=r0),
                     dict(config=5, seed=seed, n_tracks=n_tracks))

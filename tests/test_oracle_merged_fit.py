@@ -200,10 +200,17 @@ def _close(a, b, tol=TOL):
     assert np.all(d <= tol), (a, b, d)
 
 
-def _fit(ev, n_pass=3):
+# tracklet covariance of every member: a diagonal of the size a fitted
+# tracklet has (the fit restarts from these variances times cov_scale)
+COV0 = np.array([0.01 if i in (0, 2) else 1e-4 if i in (5, 9) else 1e-2 if i == 14 else 0.0
+                 for i in range(15)], np.float32)
+
+
+def _fit(ev, n_pass=3, fp64=True):
+    cov = np.tile(COV0, (len(ev["par"]), 1))
     return oracle.fit_merged(ev["offs"], 18, synth.ROW_X, PRM, ev["row"], ev["y"], ev["z"],
-                             ev["off"], ev["hits"], ev["par"], ev["rin"], ev["up"], ev["dn"],
-                             ev["grp"], n_pass=n_pass)
+                             ev["off"], ev["hits"], ev["par"], cov, ev["rin"], ev["up"],
+                             ev["dn"], ev["grp"], n_pass=n_pass, fp64=fp64)
 
 
 def test_noiseless_helices_across_boundaries():

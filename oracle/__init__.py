@@ -404,6 +404,74 @@ def calib_objective(trk_off, row, y, z, row_x, prm, theta, w, g=None, side=None,
     return val, gt, per[:n], vok[:n]
 
 
+class CmpParams(C.Structure):
+    _fields_ = [("qbits", C.c_int32), ("cbits", C.c_int32), ("chunk", C.c_int32)]
+
+
+def compress(layout, n_rows, row_x, prm, row, y, z, charge, grid, trk_off, trk_hits, tpar,
+             trin, qbits=5, cbits=5, chunk=16384):
+    """Cluster compression (section 6): the blob (uint8 array).  grid: the
+    grid of the same clusters (bin_start, idg); tpar, trin: each track's
+    tracklet state and innermost row."""
+    L = lib()
+    L.orc_compress.restype = C.c_int64
+    tab = _sectors(layout)
+    cp = CmpParams(qbits, cbits, chunk)
+    n = row.shape[0]
+    nt = trk_off.shape[0] - 1
+    i32 = lambda a: _p(np.ascontiguousarray(a, np.int32))
+    args = (C.c_int(tab.shape[0]), _p(tab), C.c_int(n_rows),
+            _p(np.ascontiguousarray(row_x, np.float32)), C.byref(params(prm)),
+            _p(np.ascontiguousarray(row, np.uint8)), _p(np.ascontiguousarray(y, np.float32)),
+            _p(np.ascontiguousarray(z, np.float32)), _p(np.ascontiguousarray(charge, np.float32)),
+            C.c_int64(n), i32(grid["bin_start"]), i32(grid["idg"]), C.c_int64(nt), i32(trk_off),
+            i32(trk_hits), _p(np.ascontiguousarray(tpar, np.float32)), i32(trin), C.byref(cp))
+    cap = 64 * n + 4096 + 32 * nt
+    out = np.zeros(cap, np.uint8)
+    size = L.orc_compress(*args, _p(out), C.c_int64(cap))
+    if size < 0:
+        out = np.zeros(-size, np.uint8)
+        size = L.orc_compress(*args, _p(out), C.c_int64(-size))
+    return out[:size]
+
+
+def decompress(blob, n_clusters, row_x, prm):
+    """Clusters of a blob in its order: dict(row, yq, zq, qcode, track,
+    sector) (track -1 for clusters on no track; sector -1 for clusters on
+    tracks)."""
+    L = lib()
+    L.orc_decompress.restype = C.c_int64
+    m = max(n_clusters, 1)
+    o = dict(row=np.zeros(m, np.uint8), yq=np.zeros(m, np.int32), zq=np.zeros(m, np.int32),
+             qcode=np.zeros(m, np.int32), track=np.zeros(m, np.int32),
+             sector=np.zeros(m, np.int32))
+    blob = np.ascontiguousarray(blob, np.uint8)
+    n = L.orc_decompress(_p(blob), C.c_int64(blob.shape[0]),
+                         _p(np.ascontiguousarray(row_x, np.float32)), C.byref(params(prm)),
+                         _p(o["row"]), _p(o["yq"]), _p(o["zq"]), _p(o["qcode"]),
+                         _p(o["track"]), _p(o["sector"]), C.c_int64(m))
+    if n < 0:
+        raise ValueError("malformed blob")
+    return {k: v[:n] for k, v in o.items()}
+
+
+def charge_decode(code, cbits=5):
+    return lib().orc_charge_decode(C.c_int(int(code)), C.c_int(cbits))
+
+
+def rans_roundtrip(sym):
+    """rANS code of a byte stream with its own table: (bytes, decoded)."""
+    L = lib()
+    L.orc_rans_roundtrip.restype = C.c_int64
+    sym = np.ascontiguousarray(sym, np.uint8)
+    out = np.zeros(2 * sym.shape[0] + 8, np.uint8)
+    back = np.zeros(max(sym.shape[0], 1), np.uint8)
+    nb = L.orc_rans_roundtrip(_p(sym), C.c_int64(sym.shape[0]), _p(out), _p(back))
+    if nb < 0:
+        raise ValueError("rANS decode failed")
+    return out[:nb], back[:sym.shape[0]]
+
+
 def refit_adjoint64(trk_off, row, y, z, row_x, prm, theta, g, side=None, cm=None):
     """Gradient of L = sum_t g_t chi2_t of the float64 refit with respect to
     the raw hit y, z and the 16 calibration parameters, by reverse-mode

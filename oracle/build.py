@@ -1,6 +1,6 @@
 """Build the oracle shared library with gcc/g++ (test infrastructure only):
-oracle.c (the plain C oracle) and adjoint.cc (the double-precision refit
-differentiated by a recorded tape)."""
+oracle.c (the plain C oracle), compress.c (cluster compression) and
+adjoint.cc (the double-precision refit differentiated by a recorded tape)."""
 import os
 import subprocess
 import sys
@@ -14,12 +14,15 @@ def build(verbose=False):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     c_obj = os.path.join(objdir, "oracle.o")
+    z_obj = os.path.join(objdir, "compress.o")
     cc_obj = os.path.join(objdir, "adjoint.o")
     cmds = [
         ["gcc", "-std=c11", *FPFLAGS, "-fexcess-precision=standard", "-c", os.path.join(HERE, "oracle.c"), "-o", c_obj],
+        ["gcc", "-std=c11", *FPFLAGS, "-fexcess-precision=standard", "-Wno-unused-function",
+         "-c", os.path.join(HERE, "compress.c"), "-o", z_obj],
         ["g++", "-std=c++17", *FPFLAGS, "-Wno-unused-function", "-c",
          os.path.join(HERE, "adjoint.cc"), "-o", cc_obj],
-        ["g++", "-shared", "-fPIC", "-o", SO + ".tmp", c_obj, cc_obj, "-lm"],
+        ["g++", "-shared", "-fPIC", "-o", SO + ".tmp", c_obj, z_obj, cc_obj, "-lm"],
     ]
     for cmd in cmds:
         if verbose:

@@ -158,6 +158,37 @@ void orc_vertex_weights64(int64_t n_tracks, const int* trk_off, const uint8_t* r
                           const orc_calib_model* cm, const double* theta, double sigma_v2,
                           double* w, int* ok);
 
+/* ---- cluster compression (section 6, steps 2-4; compress.c) ------------
+ * Integer format: y, z rounded to 2^-qbits cm; charge rounded to a count in
+ * [0, 65535] keeping its leading cbits significant bits.  Clusters on tracks
+ * (track by track, row-ascending): the number of hits, the row step, the
+ * residuals of y and z to the track's prediction (its tracklet state rounded
+ * into a 16-byte header and carried row by row with the tracker's float32
+ * transport, updated with each decoded cluster), the charge.  The other
+ * clusters sector by sector and row by row in grid order: their count per
+ * row, the z step to the previous one of the row, y (offset 2048) as two
+ * bytes, the charge.  Byte symbols, 255 escapes a 32-bit value; each stream
+ * is rANS coded in chunks of `chunk` symbols with its own 12-bit table.
+ * orc_compress returns the blob size (negative: the size needed when it
+ * exceeds out_cap); orc_decompress the clusters in blob order. */
+typedef struct {
+    int32_t qbits;         /* position quantum 2^-qbits cm */
+    int32_t cbits;         /* significant bits kept of the charge */
+    int32_t chunk;         /* symbols per rANS chunk */
+} orc_cmp_params;
+
+int64_t orc_compress(int n_sec, const orc_sector* sec, int n_rows, const float* row_x,
+                     const orc_params* prm, const uint8_t* row, const float* y, const float* z,
+                     const float* charge, int64_t n_clusters, const int* bin_start,
+                     const int* idg, int64_t n_tracks, const int* trk_off, const int* trk_hits,
+                     const float* tpar, const int* trin, const orc_cmp_params* cp,
+                     uint8_t* out, int64_t out_cap);
+int64_t orc_decompress(const uint8_t* blob, int64_t size, const float* row_x,
+                       const orc_params* prm, uint8_t* o_row, int32_t* o_yq, int32_t* o_zq,
+                       int32_t* o_qcode, int32_t* o_track, int32_t* o_sector, int64_t cap);
+int orc_charge_decode(int code, int cbits);
+int64_t orc_rans_roundtrip(const uint8_t* sym, int64_t n, uint8_t* bytes, uint8_t* back);
+
 /* Track-based cluster attachment (section 6): tube of `radius` around
  * every track over the rows of its hits, its axis the track state par[5k]
  * (at the plane of row rin[k]) transported outwards row by row; unowned

@@ -487,6 +487,45 @@ def central_bench(args, api, synth, prm, dev, tuned_batch):
         res["cluster_attachment"] = attach_bench(args, api, ctx, e, ev, stream)
     if not args.no_merge_bench:
         res["sector_merging"] = merge_bench(args, api, ctx, e, ev, stream)
+    res["compression"] = compress_bench(args, api, ctx, e, ev, stream)
+    return res
+
+
+def compress_bench(args, api, ctx, e, ev, stream):
+    """Cluster compression of the tracked central event (integer format,
+    residuals to tracks, rANS): time per event, per-kernel times, blob size
+    against the float32 SoA input (row, y, z, charge: 13 bytes per
+    cluster)."""
+    import torch
+    steps = max(args.steps // 2, 2)
+    charge = torch.as_tensor(ev.charge).cuda()
+    state = {}
+    with torch.cuda.stream(stream):
+        api.track_batch(ctx, e, mode="staged", use_graph=False, stream=stream)
+        api.compress_clusters(ctx, e, charge, stream=stream, state=state)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            blob, size = api.compress_clusters(ctx, e, charge, stream=stream, state=state)
+        b.record(stream)
+        torch.cuda.synchronize()
+        api.timing_enable(ctx, True)
+        api.compress_clusters(ctx, e, charge, stream=stream, state=state)
+        torch.cuda.synchronize()
+        kt = api.timing_report(ctx)
+        api.timing_enable(ctx, False)
+    ms = a.elapsed_time(b) / steps
+    n = int(size.item())
+    res = {"workload": "clusters of the tracked central event: y, z at 2^-5 cm, charge with 5 "
+                       "significant bits, residuals to tracks, rANS in 16384-symbol chunks",
+           "ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3), "bytes": n,
+           "bytes_per_cluster": n / ev.n_clusters,
+           "factor_vs_float_soa": 13.0 * ev.n_clusters / n,
+           "kernels_us": {k: round(ms_ / c * 1e3, 1) for k, (c, ms_) in kt.items()}}
+    log(f"[bench] compression {ms:.3f} ms: {n} bytes, {n / ev.n_clusters:.3f} B/cluster, "
+        f"factor {res['factor_vs_float_soa']:.2f} against 13 B/cluster")
     return res
 
 
@@ -952,7 +991,9 @@ def refit_bench(args, api, synth, ctx, stream, prm, dev):
     fwd_b = nh * (9 + 80)
     adj_b = nh * (9 + 80 + 8)
     log(f"[bench] refit+adjoint {ms:.3f} ms per pass, {rs.n_tracks / (ms * 1e-3):.3e} tracks/s")
+    calib = calibration_bench(api, ctx, stream, prm, rs, h, rx, th, steps)
     return {
+        "calibration": calib,
         "workload": "1M truth track segments of 40-152 consecutive-row hits (seed 5005), "
                     "calibrated refit (16 parameters) + adjoint, float32",
         "tracks": rs.n_tracks, "hits": nh,
@@ -967,6 +1008,42 @@ def refit_bench(args, api, synth, ctx, stream, prm, dev):
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": adj_b / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "algorithmic_bytes_per_hit": 97},
+    }
+
+
+def calibration_bench(api, ctx, stream, prm, rs, h, rx, th, steps):
+    """Global calibration on the refit set: one evaluation of the objective
+    and its gradient (refit, beam-axis term, seeded adjoint, the value read
+    back to the host), then a whole damped-Newton calibration from the
+    evaluation point to convergence."""
+    import numpy as np
+    import torch
+    st = {}
+    with torch.cuda.stream(stream):
+        api.calibration_objective(ctx, h, rx, prm, th, None, stream=stream, state=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            api.calibration_objective(ctx, h, rx, prm, th, None, stream=stream, state=st)
+        torch.cuda.synchronize()
+        ms_eval = (time.perf_counter() - t0) / steps * 1e3
+        free = np.array(api.CALIB_FREE)
+        th_true = rs.theta_true.astype(np.float64)
+        th0 = th_true.copy()
+        th0[free] = rs.theta_eval.astype(np.float64)[free]
+        t0 = time.perf_counter()
+        res = api.calibrate(ctx, h, rx, prm, th0, stream=stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    left = np.abs(res["theta"][free] - th_true[free]) / np.abs(th0[free] - th_true[free])
+    log(f"[bench] calibration: objective+gradient {ms_eval:.3f} ms, fit {wall:.2f} s in "
+        f"{len(res['history'])} iterations, offset left {np.round(left, 3).tolist()}")
+    return {
+        "free_parameters": [int(k) for k in free],
+        "ms_per_objective_and_gradient": ms_eval,
+        "fit_seconds": wall,
+        "iterations": len(res["history"]),
+        "offset_left_fraction": [float(x) for x in left],
     }
 
 

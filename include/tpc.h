@@ -379,6 +379,59 @@ int tpc_fit_merged_tracks(tpc_context* ctx, const tpc_problem* h_prob, tpc_clust
                           int32_t sectors_per_side, float cos_width, float sin_width,
                           int32_t n_pass, float cov_scale, tpc_fit_out out, void* stream);
 
+/* ---- cluster compression ------------------------------------------------ */
+
+typedef struct tpc_compress_params {
+    int32_t qbits;         /* y, z quantum 2^-qbits cm (0..12) */
+    int32_t cbits;         /* leading significant bits kept of the charge (2..8) */
+    int32_t chunk;         /* symbols per rANS chunk (64..2^20) */
+} tpc_compress_params;
+
+/* Bytes of device workspace of tpc_compress_clusters. */
+int tpc_compress_workspace_size(const tpc_problem* h_prob, int64_t track_capacity,
+                                int64_t hit_capacity, int32_t chunk, size_t* h_bytes);
+
+/* Compression of the clusters of a tracked problem (section 6, TPC data
+ * compression, steps 2-4: integer format with the resolution's precision
+ * and a charge precision relative to its value; residuals to tracks for the
+ * clusters on tracks, position differences otherwise; an entropy coder,
+ * rANS).  Integer format: y, z -> rint(v 2^qbits); charge -> its count
+ * rint(charge) in [0, 65535] keeping cbits leading significant bits
+ * (code = v below 2^cbits, else 2^cbits + (e - 1) 2^(cbits-1) + (v >> e) -
+ * 2^(cbits-1), e = bitlength(v) - cbits).  Nine byte streams, 255 escaping a
+ * 32-bit value on the stream's escape list:
+ *   tracks in track order: hit count; per hit the row step (from the
+ *   header's row), the zigzag y and z residuals to the prediction, the
+ *   charge code.  The prediction: the tracklet state (par at row_inner)
+ *   rounded into a 16-byte header (row_inner, 0, sin, tan at 2^-14 and q/pT
+ *   at 2^-10 as int16, y and z as int32 at 2^-qbits), the initial covariance
+ *   of params, the tracklet transport to each hit's row and the tracklet
+ *   update with the hit as decoded;
+ *   the other clusters, sector by sector and row by row in grid order: the
+ *   count per row, the zigzag z step to the previous one of the row (from 0),
+ *   y + 2048 as a high byte (escaped outside [0, 4096)) and a low byte, the
+ *   charge code after the tracks' codes.
+ * Each stream: 12-bit frequencies normalised from its counts (floor of the
+ * share, at least 1, then +-1 steps on the largest frequency above 1 or the
+ * largest count, ties to the lower symbol), rANS (state in [2^23, 2^31),
+ * byte output) in chunks of `chunk` symbols.  Blob (little-endian): magic
+ * "TPCZ", version 1, cbits, qbits, chunk, n_sectors, n_rows (u32); n_clusters,
+ * n_tracks, clusters on tracks, others (u64); per stream n_symbols,
+ * n_escapes (u64), n_chunks (u32), 256 u16 frequencies (0xffff for 4096),
+ * the chunks' byte counts (u32); then every stream's chunk bytes, every
+ * stream's escapes (i32), the track headers.  Inputs: the clusters (with
+ * charge), grid, tracklets and tracks of the tracking calls; d_n_tracks
+ * (device) the track count.  *d_size (device) receives the blob size; when
+ * it exceeds out_cap nothing is written to out (the caller re-sizes).
+ * d_ws: tpc_compress_workspace_size bytes.  Returns TPC_ERR_INVALID_ARG for a
+ * null pointer, parameters out of range or a short workspace; asynchronous
+ * on stream. */
+int tpc_compress_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters clusters,
+                          const float* charge, tpc_grid grid, tpc_tracklets tracklets,
+                          tpc_tracks tracks, const int64_t* d_n_tracks, tpc_compress_params cp,
+                          uint8_t* out, int64_t out_cap, int64_t* d_size, void* d_ws,
+                          size_t ws_bytes, void* stream);
+
 /* ---- per-track interaction time ----------------------------------------- */
 
 /* Interaction time of every track in continuous read-out (section 2: the z

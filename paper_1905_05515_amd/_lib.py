@@ -66,6 +66,10 @@ class MergeCuts(C.Structure):
                 ("sin_width", C.c_float), ("inv_window", C.c_float * 5)]
 
 
+class CompressParams(C.Structure):
+    _fields_ = [("qbits", C.c_int32), ("cbits", C.c_int32), ("chunk", C.c_int32)]
+
+
 class FitOut(C.Structure):
     _fields_ = [("par_in", P), ("par_out", P), ("cov_out", P), ("chi2", P), ("n_hits", P),
                 ("n_members", P), ("status", P)]
@@ -112,6 +116,10 @@ EXPORTS = {
     "tpc_merge_workspace_size": (C.c_int, [C.POINTER(Problem), I64, C.POINTER(C.c_size_t)]),
     "tpc_merge_sector_tracks": (C.c_int, [P, C.POINTER(Problem), Tracklets, Tracks, P, MergeCuts,
                                           P, P, P, P, C.c_size_t, P]),
+    "tpc_compress_workspace_size": (C.c_int, [C.POINTER(Problem), I64, I64, I32,
+                                              C.POINTER(C.c_size_t)]),
+    "tpc_compress_clusters": (C.c_int, [P, C.POINTER(Problem), Clusters, P, Grid, Tracklets,
+                                        Tracks, P, CompressParams, P, I64, P, P, C.c_size_t, P]),
     "tpc_fit_merged_tracks": (C.c_int, [P, C.POINTER(Problem), Clusters, Tracklets, Tracks, P,
                                         P, P, P, I32, F32, F32, I32, F32, FitOut, P]),
     "tpc_track_t0": (C.c_int, [P, C.POINTER(Problem), Tracklets, Tracks, P, F32, P, P, P, P, P]),

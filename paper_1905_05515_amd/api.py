@@ -357,6 +357,37 @@ def fit_merged_tracks(ctx: Context, ev: Event, links, sectors_per_side: int = 18
     return out
 
 
+def compress_clusters(ctx: Context, ev: Event, charge: torch.Tensor, qbits: int = 5,
+                      cbits: int = 5, chunk: int = 16384, stream=None, state=None):
+    """Cluster compression of a tracked event (section 6): returns (blob
+    uint8 device tensor, its size as a device int64 tensor).  The blob buffer
+    holds 16 bytes per cluster plus the tables; a larger blob (never seen on
+    tracked events) raises.  `state` (a dict) keeps the buffers between
+    calls."""
+    dev = ev.t["row"].device
+    state = {} if state is None else state
+    need = C.c_size_t(0)
+    L.check(L.lib().tpc_compress_workspace_size(C.byref(ev.problem), ev.track_capacity,
+                                                ev.track_hit_capacity, int(chunk),
+                                                C.byref(need)), "tpc_compress_workspace_size")
+    if "ws" not in state or state["ws"].numel() < need.value:
+        state["ws"] = torch.empty(max(need.value, 1), dtype=torch.uint8, device=dev)
+    cap = 16 * int(ev.problem.n_clusters) + 16 * ev.track_capacity + (1 << 20)
+    if "out" not in state or state["out"].numel() < cap:
+        state["out"] = torch.empty(cap, dtype=torch.uint8, device=dev)
+        state["size"] = torch.zeros(1, dtype=torch.int64, device=dev)
+    cp = L.CompressParams(int(qbits), int(cbits), int(chunk))
+    ch = charge.detach().to(device=dev, dtype=torch.float32).contiguous()
+    state["charge"] = ch
+    L.check(L.lib().tpc_compress_clusters(ctx.handle, C.byref(ev.problem), _clusters(ev),
+                                          _ptr(ch), _grid(ev), _tracklets(ev), _tracks(ev),
+                                          status_count_ptr(ev), cp, _ptr(state["out"]),
+                                          state["out"].numel(), _ptr(state["size"]),
+                                          _ptr(state["ws"]), state["ws"].numel(),
+                                          _stream(stream)), "tpc_compress_clusters")
+    return state["out"], state["size"]
+
+
 def track_t0(ctx: Context, ev: Event, vd: float = 2.58, stream=None):
     """Interaction time of the event's found tracks in continuous read-out
     (after the tracking calls): device tensors (z0, y0, t0 float32, ok int8)

@@ -49,3 +49,13 @@ def test_binding_has_no_fallback():
             _lib.lib()
     finally:
         _lib._lib, _lib.SO = saved, saved_so
+
+
+def test_binding_modules_import_and_declare_every_export():
+    """The Python binding imports on a machine without a GPU, and every
+    symbol the header declares has a ctypes signature."""
+    import re as _re
+    from paper_1905_05515_amd import _lib, api, autograd  # noqa: F401
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "tpc.h")).read()
+    declared = set(_re.findall(r"^(?:int|const char\*)\s+(tpc_\w+)\(", hdr, _re.M))
+    assert declared and declared <= set(_lib.EXPORTS), declared - set(_lib.EXPORTS)

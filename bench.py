@@ -99,6 +99,23 @@ def pick_layout(args, api, ctx, e, stream, mode="staged"):
     return {"occupancy": float(args.occupancy)}
 
 
+def pick_shapes(args, api, ctx, e, stream, modes):
+    """Tune the launch shapes of the context for each tracking form (the
+    tracks are checked equal for every shape tried); returns the record for
+    the JSON line.  The staged form's shapes last: they are the ones in
+    force for the timed step."""
+    rec = {}
+    if args.occupancy != "auto":
+        return rec
+    for mode in modes:
+        shapes, times = api.autotune_shapes(ctx, e, mode=mode, stream=stream)
+        tried = ", ".join(f"{f}={v}: {ms:.3f} ms" for (f, v), ms in times.items())
+        log(f"[bench] launch shapes ({mode}): {tried}")
+        rec[mode] = {"tried_ms": {f"{f}={v}": round(ms, 4) for (f, v), ms in times.items()}}
+    rec["chosen"] = api.get_tuning(ctx)
+    return rec
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -167,6 +184,7 @@ def main():
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
                        sector_side=ev.sector_side)
     tuned = pick_layout(args, api, ctx, e, stream)
+    tuned["launch_shapes"] = pick_shapes(args, api, ctx, e, stream, ("persistent", "staged"))
     th = torch.as_tensor(synth_theta()).to(dev)
     gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
     hits = api.found_track_hits(e)
@@ -365,6 +383,7 @@ def central_bench(args, api, synth, prm, dev, tuned_batch):
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
                        sector_side=ev.sector_side)
     tuned = pick_layout(args, api, ctx, e, stream)
+    tuned["launch_shapes"] = pick_shapes(args, api, ctx, e, stream, ("persistent", "staged"))
     th = torch.as_tensor(synth_theta()).to(dev)
     gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
     # Events in flight: lane k owns an event's buffers, a context (whose
@@ -519,7 +538,7 @@ def compress_bench(args, api, ctx, e, ev, stream):
     ms = a.elapsed_time(b) / steps
     n = int(size.item())
     res = {"workload": "clusters of the tracked central event: y, z at 2^-5 cm, charge with 5 "
-                       "significant bits, residuals to tracks, rANS in 16384-symbol chunks",
+                       "significant bits, residuals to tracks, rANS in 4096-symbol chunks",
            "ms": ms, "clusters_per_s": ev.n_clusters / (ms * 1e-3), "bytes": n,
            "bytes_per_cluster": n / ev.n_clusters,
            "factor_vs_float_soa": 13.0 * ev.n_clusters / n,
@@ -722,6 +741,7 @@ def merge_bench(args, api, ctx, e, ev, stream):
     r = api.results(e, stream)
     off, hits = r["trk_off"], r["trk_hits"]
     nt = len(off) - 1
+    links = (up, dn, grp)             # device tensors for the full-track fit
     up = up[:nt].cpu().numpy()
     grp = grp[:nt].cpu().numpy()
     sec = np.searchsorted(ev.sector_offsets, hits[off[:-1]], side="right") - 1
@@ -758,7 +778,7 @@ def merge_bench(args, api, ctx, e, ev, stream):
            "link_purity": float(np.mean(maj[k] == maj[up[k]])) if len(k) else None}
     log(f"[bench] merging {ms:.3f} ms ({nt} tracks, {pairs} pairs): {res['links']} links, "
         f"purity {res['link_purity']}, {res['groups']} groups")
-    res["full_track_fit"] = fullfit_bench(api, ctx, e, stream, steps, nt, (up, dn, grp))
+    res["full_track_fit"] = fullfit_bench(api, ctx, e, stream, steps, nt, links)
     return res
 
 

@@ -196,6 +196,33 @@ typedef struct tpc_context tpc_context;
 int tpc_context_create(tpc_context** out, int device);
 int tpc_context_destroy(tpc_context* ctx);
 
+/* Launch shapes of a context (none changes any output; every field 0 is
+ * the library's own choice).  tracklet_form: how tpc_construct_tracklets
+ * holds the hit lists while it builds them and deals the starts to
+ * waves: TPC_TRACKLETS_LDS (one LDS column per lane, written out at the
+ * end), TPC_TRACKLETS_DIRECT (written into the output as found) or
+ * TPC_TRACKLETS_QUEUE (written directly; resident waves whose lanes take a
+ * new start from a device queue whenever theirs is done); automatic takes
+ * the LDS form while all its waves are resident at once, else the direct
+ * form.  neighbour_block: threads per block
+ * of the neighbour kernel (64, 128 or 256).  persistent_scale: tile size
+ * multiplier of the persistent form (1, 2, 4 or 8; automatic grows it with
+ * the clusters per resident block).  persistent_blocks_per_cu: blocks of
+ * the persistent launch per compute unit (at most the resident count;
+ * automatic: all resident).  tpc_context_set_tuning returns
+ * TPC_ERR_INVALID_ARG for any other value and drops the context's cached
+ * graph. */
+enum { TPC_TRACKLETS_AUTO = 0, TPC_TRACKLETS_LDS = 1, TPC_TRACKLETS_DIRECT = 2,
+       TPC_TRACKLETS_QUEUE = 3 };
+typedef struct tpc_tuning {
+    int32_t tracklet_form;
+    int32_t neighbour_block;
+    int32_t persistent_scale;
+    int32_t persistent_blocks_per_cu;
+} tpc_tuning;
+int tpc_context_set_tuning(tpc_context* ctx, const tpc_tuning* h_tuning);
+int tpc_context_get_tuning(const tpc_context* ctx, tpc_tuning* h_tuning);
+
 /* Bytes of device workspace needed by the tracking calls for this problem
  * and start capacity.  The same workspace must be passed, unchanged, to the
  * calls of one event in order; it holds the status block at offset 0. */

@@ -409,7 +409,7 @@ class CmpParams(C.Structure):
 
 
 def compress(layout, n_rows, row_x, prm, row, y, z, charge, grid, trk_off, trk_hits, tpar,
-             trin, qbits=5, cbits=5, chunk=16384):
+             trin, qbits=5, cbits=5, chunk=4096):
     """Cluster compression (section 6): the blob (uint8 array).  grid: the
     grid of the same clusters (bin_start, idg); tpar, trin: each track's
     tracklet state and innermost row."""

@@ -75,6 +75,11 @@ class FitOut(C.Structure):
                 ("n_members", P), ("status", P)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("tracklet_form", C.c_int32), ("neighbour_block", C.c_int32),
+                ("persistent_scale", C.c_int32), ("persistent_blocks_per_cu", C.c_int32)]
+
+
 class TrackHits(C.Structure):
     _fields_ = [("off", P), ("idx", P), ("row", P), ("y", P), ("z", P), ("side", P),
                 ("d_count", P), ("n_tracks", I64), ("n_hits", I64)]
@@ -83,6 +88,8 @@ class TrackHits(C.Structure):
 EXPORTS = {
     "tpc_context_create": (C.c_int, [C.POINTER(P), C.c_int]),
     "tpc_context_destroy": (C.c_int, [P]),
+    "tpc_context_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
+    "tpc_context_get_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
     "tpc_workspace_size": (C.c_int, [C.POINTER(Problem), I64, C.POINTER(C.c_size_t)]),
     "tpc_build_grid": (C.c_int, [P, C.POINTER(Problem), Clusters, Grid, P, C.c_size_t, P]),
     "tpc_find_neighbours": (C.c_int, [P, C.POINTER(Problem), Grid, Links, Starts, P,

@@ -173,6 +173,88 @@ def relayout(ev: Event, occupancy: float = None, layout=None):
     ev.occupancy = occupancy
 
 
+TUNING_FIELDS = ("tracklet_form", "neighbour_block", "persistent_scale",
+                 "persistent_blocks_per_cu")
+
+
+def get_tuning(ctx: "Context") -> dict:
+    """The context's launch shapes (0: the library's automatic choice)."""
+    t = L.Tuning()
+    L.check(L.lib().tpc_context_get_tuning(ctx.handle, C.byref(t)), "tpc_context_get_tuning")
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
+
+
+def set_tuning(ctx: "Context", **kw):
+    """Set launch shapes of the context (fields of TUNING_FIELDS; the others
+    keep their values).  No output depends on them."""
+    cur = get_tuning(ctx)
+    for k, v in kw.items():
+        if k not in cur:
+            raise KeyError(k)
+        cur[k] = int(v)
+    L.check(L.lib().tpc_context_set_tuning(ctx.handle, C.byref(L.Tuning(**cur))),
+            "tpc_context_set_tuning")
+
+
+# launch shapes the shape tuner tries, per tracking form, one field at a time
+TUNE_SHAPES = {
+    "staged": (("tracklet_form", (0, 1, 2, 3)), ("neighbour_block", (256, 128, 64))),
+    "per_sector": (("tracklet_form", (0, 1, 2, 3)), ("neighbour_block", (256, 128, 64))),
+    "persistent": (("persistent_scale", (0, 1, 2, 4, 8)), ("persistent_blocks_per_cu", (0, 2, 1)),
+                   ("tracklet_form", (0,))),
+}
+
+
+def _time_batch(ctx, ev, mode, reps, s):
+    with torch.cuda.stream(s):
+        track_batch(ctx, ev, mode=mode, stream=s)          # warm
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            track_batch(ctx, ev, mode=mode, stream=s)
+            b.record(s)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+    return sorted(ms)[len(ms) // 2]
+
+
+def _track_digest(ev, s):
+    """The track list on the host (offsets, hits) for the invariance check."""
+    s.synchronize()
+    st = get_status(ev, s)
+    nt, nh = int(st["n_tracks"]), int(st["n_track_hits"])
+    return (ev.t["trk_off"][:nt + 1].cpu().numpy().tobytes(),
+            ev.t["trk_hits"][:nh].cpu().numpy().tobytes())
+
+
+def autotune_shapes(ctx: "Context", ev: Event, mode: str = "staged", reps: int = 3,
+                    stream=None):
+    """Time the tracking chain for the launch shapes of TUNE_SHAPES[mode],
+    one field at a time (each field keeps its fastest value before the next
+    is tried), check that every shape gives the same tracks (raises
+    otherwise) and leave the fastest shapes set.  Returns (shapes, {(field,
+    value): ms})."""
+    s = stream if stream is not None else torch.cuda.current_stream()
+    times = {}
+    ref = None
+    for field_, values in TUNE_SHAPES[mode]:
+        best_v, best_ms = None, None
+        for v in values:
+            set_tuning(ctx, **{field_: v})
+            ms = _time_batch(ctx, ev, mode, reps, s)
+            dig = _track_digest(ev, s)
+            if ref is None:
+                ref = dig
+            elif dig != ref:
+                raise RuntimeError(f"tracks differ with {field_}={v}")
+            times[(field_, v)] = ms
+            if best_ms is None or ms < best_ms:
+                best_v, best_ms = v, ms
+        set_tuning(ctx, **{field_: best_v})
+    return get_tuning(ctx), times
+
+
 def autotune(ctx: "Context", ev: Event, mode: str = "staged", candidates=TUNE_OCCUPANCIES,
              reps: int = 3, stream=None):
     """Time the tracking chain of this event for each bin occupancy and keep
@@ -358,7 +440,7 @@ def fit_merged_tracks(ctx: Context, ev: Event, links, sectors_per_side: int = 18
 
 
 def compress_clusters(ctx: Context, ev: Event, charge: torch.Tensor, qbits: int = 5,
-                      cbits: int = 5, chunk: int = 16384, stream=None, state=None):
+                      cbits: int = 5, chunk: int = 4096, stream=None, state=None):
     """Cluster compression of a tracked event (section 6): returns (blob
     uint8 device tensor, its size as a device int64 tensor).  The blob buffer
     holds 16 bytes per cluster plus the tables; a larger blob (never seen on

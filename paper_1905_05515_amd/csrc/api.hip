@@ -66,7 +66,7 @@ int tpc_find_neighbours(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid gr
     if (e) return e;
     if (!grid_ok(grid) || !links_ok(links) || !starts_ok(starts)) return TPC_ERR_INVALID_ARG;
     return tpc::run_find_neighbours(h_prob, 0, h_prob->n_sectors, grid, links, starts, ws,
-                                    (hipStream_t)stream);
+                                    (hipStream_t)stream, ctx ? &ctx->tune : nullptr);
 }
 
 int tpc_construct_tracklets(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid grid,
@@ -80,7 +80,8 @@ int tpc_construct_tracklets(tpc_context* ctx, const tpc_problem* h_prob, tpc_gri
     if (!grid_ok(grid) || !links_ok(links) || !starts_ok(starts) || !trl_ok(tracklets, starts))
         return TPC_ERR_INVALID_ARG;
     return tpc::run_construct_tracklets(h_prob, 0, h_prob->n_sectors, grid, links, starts,
-                                        tracklets, ws, (hipStream_t)stream);
+                                        tracklets, ws, (hipStream_t)stream,
+                                        ctx ? &ctx->tune : nullptr);
 }
 
 int tpc_select_tracks(tpc_context* ctx, const tpc_problem* h_prob, tpc_grid grid,
@@ -120,14 +121,16 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
     // never more tracklets than starts: the selection runs over the start
     // capacity the workspace was sized for
     const int64_t count_cap = starts.capacity;
+    const tpc_tuning* tune = ctx ? &ctx->tune : nullptr;
     auto body = [&]() -> int {
         int r = TPC_OK;
         if (mode == TPC_MODE_STAGED) {
             r = tpc::run_build_grid(h_prob, 0, ns, in, grid, ws, st);
-            if (!r) r = tpc::run_find_neighbours(h_prob, 0, ns, grid, links, starts, ws, st);
+            if (!r)
+                r = tpc::run_find_neighbours(h_prob, 0, ns, grid, links, starts, ws, st, tune);
             if (!r)
                 r = tpc::run_construct_tracklets(h_prob, 0, ns, grid, links, starts, tracklets,
-                                                 ws, st);
+                                                 ws, st, tune);
             if (!r) r = tpc::run_select_tracks(h_prob, grid, count_cap, tracklets, tracks, ws, st);
         } else if (mode == TPC_MODE_PER_SECTOR) {
             // every stage sector by sector, then one dense compaction of the
@@ -135,10 +138,12 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
             tpc::launch_fill<uint64_t>(ws.tlen, 0ull, count_cap + 1, st);
             for (int s = 0; s < ns && !r; ++s) {
                 r = tpc::run_build_grid(h_prob, s, s + 1, in, grid, ws, st);
-                if (!r) r = tpc::run_find_neighbours(h_prob, s, s + 1, grid, links, starts, ws, st);
+                if (!r)
+                    r = tpc::run_find_neighbours(h_prob, s, s + 1, grid, links, starts, ws, st,
+                                                 tune);
                 if (!r)
                     r = tpc::run_construct_tracklets(h_prob, s, s + 1, grid, links, starts,
-                                                     tracklets, ws, st);
+                                                     tracklets, ws, st, tune);
                 if (!r) r = tpc::run_select_keys(h_prob, s, s + 1, grid, count_cap, tracklets, ws, st);
             }
             if (!r) r = tpc::run_select_compact(h_prob, grid, count_cap, tracklets, tracks, ws, st);
@@ -158,6 +163,11 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
                           tracks.tracklet, d_ws, h_prob->d_sectors, h_prob->d_row_x, stream};
     for (const void* q : ptrs) key = mix(key, (uint64_t)(uintptr_t)q);
     key = mix(key, (uint64_t)starts.capacity);
+    if (tune)
+        key = mix(key, (uint64_t)(uint32_t)tune->tracklet_form |
+                           (uint64_t)(uint32_t)tune->neighbour_block << 8 |
+                           (uint64_t)(uint32_t)tune->persistent_scale << 24 |
+                           (uint64_t)(uint32_t)tune->persistent_blocks_per_cu << 32);
     key = mix(key, (uint64_t)tracklets.capacity);
     key = mix(key, (uint64_t)tracks.capacity);
     key = mix(key, (uint64_t)tracks.hit_capacity);

@@ -21,9 +21,10 @@
 // Kernels: mark the clusters on tracks; one thread per track writes its
 // header and symbols; one thread per (sector, row) counts, then (after a
 // scan) writes the other clusters' symbols; per-stream histograms in LDS;
-// one thread per stream normalises its table; one thread per chunk encodes
+// one block per stream normalises its table; one thread per chunk encodes
 // backwards into the end of its chunk slot; scans order the escapes; one
 // thread lays out the blob; copies place chunks, escapes and headers.
+#include "block_dev.hpp"
 #include "tracklet_dev.hpp"
 
 namespace tpc {
@@ -269,71 +270,125 @@ __global__ __launch_bounds__(kBlock) void k_cz_hist(CmpWs w)
 // share, at least 1, then the sum is brought to 2^12 one unit at a time, down
 // on the largest frequency above 1, up on the largest count, ties to the
 // lower symbol); one thread per stream
-__global__ void k_cz_norm(CmpWs w)
+__global__ __launch_bounds__(kBlock) void k_cz_norm(CmpWs w)
 {
-    const int k = blockIdx.x;
-    if (threadIdx.x != 0) return;
-    const uint32_t* cnt = w.hist + k * 256;
-    uint32_t* f = w.freq + k * 256;
-    uint64_t total = 0;
-    for (int i = 0; i < 256; ++i) total += cnt[i];
-    uint32_t sum = 0;
-    for (int i = 0; i < 256; ++i) {
-        f[i] = 0;
-        if (cnt[i]) {
-            const uint64_t v = (uint64_t)cnt[i] * kProbScale / total;
-            f[i] = v ? (uint32_t)v : 1u;
-            sum += f[i];
-        }
+    // one thread per symbol.  The rule, decrementing the largest frequency
+    // above 1 (lowest symbol on ties) one step at a time, is applied in
+    // closed form: with E the excess and D(L) = sum_i max(0, f_i - L), the
+    // steps bring every f_i above L + 1 down to L + 1, L the largest level
+    // with D(L) >= E, and the remaining E - D(L + 1) steps take the lowest
+    // symbols at L + 1 to L (the maximum is then L + 1 and ties go to the
+    // lowest symbol first).  Incrementing the largest count (lowest symbol
+    // on ties) always picks the same symbol: it takes the whole deficit.
+    __shared__ uint64_t red[kBlock / kWave];
+    const int k = blockIdx.x, i = threadIdx.x;
+    const uint32_t ci = w.hist[k * 256 + i];
+    const uint64_t total = block_sum<uint64_t>(ci, red);
+    uint32_t fi = 0;
+    if (ci) {
+        const uint64_t v = (uint64_t)ci * kProbScale / total;
+        fi = v ? (uint32_t)v : 1u;
     }
-    if (total) {
-        while (sum > kProbScale) {
-            int b = -1;
-            for (int i = 0; i < 256; ++i)
-                if (f[i] > 1 && (b < 0 || f[i] > f[b])) b = i;
-            --f[b];
-            --sum;
+    const uint64_t sum = block_sum<uint64_t>(fi, red);
+    if (total && sum > kProbScale) {
+        const uint64_t E = sum - kProbScale;
+        uint32_t lo = 1, hi = kProbScale;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            const uint64_t d = block_sum<uint64_t>(fi > mid ? fi - mid : 0u, red);
+            if (d >= E) lo = mid;
+            else hi = mid - 1;
         }
-        while (sum < kProbScale) {
-            int b = -1;
-            for (int i = 0; i < 256; ++i)
-                if (cnt[i] && (b < 0 || cnt[i] > cnt[b])) b = i;
-            ++f[b];
-            ++sum;
+        const uint32_t L = lo;
+        const uint64_t d1 = block_sum<uint64_t>(fi > L + 1 ? fi - (L + 1) : 0u, red);
+        const uint64_t r = E - d1;
+        const bool at = fi >= L + 1;
+        uint64_t n_at;
+        const uint64_t rank = block_excl_scan<uint64_t>(at ? 1u : 0u, red, &n_at);
+        if (fi > L + 1) fi = L + 1;
+        if (at && rank < r) fi = L;
+    } else if (total && sum < kProbScale) {
+        // largest count, lowest symbol on ties: max of count << 8 | (255 - symbol)
+        const uint64_t key = ((uint64_t)ci << 8) | (uint64_t)(255 - i);
+        uint64_t m = key;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const uint64_t v = __shfl_xor(m, o, kWave);
+            m = v > m ? v : m;
         }
+        __shared__ uint64_t mx[kBlock / kWave];
+        if ((i & (kWave - 1)) == 0) mx[i / kWave] = m;
+        __syncthreads();
+        uint64_t best = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; ++q) best = mx[q] > best ? mx[q] : best;
+        if (key == best) fi += (uint32_t)(kProbScale - sum);
     }
-    uint32_t* c = w.cum + k * 256;
-    c[0] = 0;
-    for (int i = 1; i < 256; ++i) c[i] = c[i - 1] + f[i - 1];
+    w.freq[k * 256 + i] = fi;
+    uint64_t tot;
+    const uint64_t c = block_excl_scan<uint64_t>(fi, red, &tot);
+    w.cum[k * 256 + i] = (uint32_t)c;
+}
+
+// Symbols of chunk j, read backwards 16 at a time when the chunk starts on
+// a multiple of 16, the next block loaded while the current one is coded;
+// the tables in LDS.  Encoding is a serial chain per chunk: the chunk size
+// sets the parallelism.
+__device__ __forceinline__ uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
+
+__device__ __forceinline__ uint32_t byte_of(const uint4& v, int b)
+{
+    const uint32_t word = b < 4 ? v.x : b < 8 ? v.y : b < 12 ? v.z : v.w;
+    return (word >> (8 * (b & 3))) & 255u;
 }
 
 // one thread per (chunk, stream): rANS encode backwards; the bytes end at the
 // end of the chunk's slot
 __global__ __launch_bounds__(kBlock) void k_cz_encode(CmpWs w, int chunk)
 {
+    __shared__ uint32_t fl[256], cl[256];
     const int k = blockIdx.y;
+    fl[threadIdx.x] = w.freq[k * 256 + threadIdx.x];
+    cl[threadIdx.x] = w.cum[k * 256 + threadIdx.x];
+    __syncthreads();
     const int64_t n = w.counts[3 + k];
     const int64_t nch = (n + chunk - 1) / chunk;
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= nch) return;
-    const uint32_t* f = w.freq + k * 256;
-    const uint32_t* c = w.cum + k * 256;
     const uint8_t* s = w.sym[k];
     const int64_t a = j * chunk, e = a + chunk < n ? a + chunk : n;
     uint8_t* end = w.cbuf + ((int64_t)k * w.chunk_cap + j) * w.slot + w.slot;
     int64_t m = 0;
     uint32_t x = kRansL;
-    for (int64_t i = e - 1; i >= a; --i) {
-        const uint8_t sy = s[i];
-        const uint32_t fs = f[sy];
+    auto code = [&](uint32_t sy) {
+        const uint32_t fs = fl[sy];
         const uint32_t x_max = ((kRansL >> kProbBits) << 8) * fs;
         while (x >= x_max) {
             *(end - 1 - m) = (uint8_t)(x & 255u);
             ++m;
             x >>= 8;
         }
-        x = ((x / fs) << kProbBits) + (x % fs) + c[sy];
+        x = ((x / fs) << kProbBits) + (x % fs) + cl[sy];
+    };
+    int64_t i = e;
+    if ((a & 15) == 0) {          // 16-byte blocks (chunk sizes that are multiples of 16)
+        // the ragged tail first (symbols past the last multiple of 16)
+        const int64_t e16 = a + (e - a) / 16 * 16;
+        while (i > e16) code(s[--i]);
+        if (i > a) {
+            uint4 cur = load16(s + i - 16);
+            while (i > a) {
+                const int64_t nx = i - 16;
+                uint4 nxt = cur;
+                if (nx > a) nxt = load16(s + nx - 16);
+#pragma unroll
+                for (int b = 15; b >= 0; --b) code(byte_of(cur, b));
+                cur = nxt;
+                i = nx;
+            }
+        }
     }
+    while (i > a) code(s[--i]);
     for (int b = 0; b < 4; ++b) {
         *(end - 1 - m) = (uint8_t)(x & 255u);
         ++m;
@@ -578,7 +633,7 @@ int tpc_compress_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_clust
                (const int32_t*)grid.id, clusters.y, clusters.z, charge,
                (const int32_t*)tracks.off, d_n_tracks, tcap, inv_q, cp.cbits, w);
     TPC_LAUNCH(tpc::k_cz_hist, dim3(256, tpc::kStreams), dim3(tpc::kBlock), 0, st, w);
-    TPC_LAUNCH(tpc::k_cz_norm, dim3(tpc::kStreams), dim3(64), 0, st, w);
+    TPC_LAUNCH(tpc::k_cz_norm, dim3(tpc::kStreams), dim3(tpc::kBlock), 0, st, w);
     TPC_LAUNCH(tpc::k_cz_encode,
                dim3((unsigned)tpc::ceil_div(w.chunk_cap, tpc::kBlock), tpc::kStreams),
                dim3(tpc::kBlock), 0, st, w, (int)cp.chunk);

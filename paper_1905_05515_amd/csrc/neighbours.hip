@@ -137,12 +137,14 @@ __global__ void k_sector_starts(const tpc_sector* __restrict__ sec, int sec_lo, 
 // are the same range.  Starts are appended in id order after those of the
 // earlier sectors.
 int run_find_neighbours(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
-                        tpc_links links, tpc_starts starts, const Workspace& ws, hipStream_t st)
+                        tpc_links links, tpc_starts starts, const Workspace& ws, hipStream_t st,
+                        const tpc_tuning* tune)
 {
     const int64_t c0 = p->h_sectors[sec_lo].begin, c1 = p->h_sectors[sec_hi - 1].end;
     const int64_t n = c1 - c0;
     const unsigned gn = grid_for(n);
-    TPC_LAUNCH(k_neighbours, dim3(grid_for(n, 65536)), dim3(kBlock), 0, st, p->d_sectors,
+    const int nbk = tune && tune->neighbour_block ? tune->neighbour_block : kBlock;
+    TPC_LAUNCH(k_neighbours, dim3(grid_for_block(n, nbk, 65536)), dim3(nbk), 0, st, p->d_sectors,
                p->n_rows, p->d_row_x, p->params, (const int32_t*)grid.bin_start,
                (const float*)grid.y, (const float*)grid.z, (const int32_t*)grid.id,
                (const int32_t*)ws.gsr, c0, c1, links.up0, links.down0);

@@ -523,12 +523,15 @@ int64_t persistent_blocks(const tpc_context* ctx)
             per_cu = 1;
         if (cached) cache[ctx->device] = per_cu;
     }
-    return (int64_t)per_cu * ctx->n_cu;
+    const int want = ctx->tune.persistent_blocks_per_cu;
+    return (int64_t)(want > 0 && want < per_cu ? want : per_cu) * ctx->n_cu;
 }
 
-// tile scale: 1, 2 or 4, growing with the clusters per resident block
-int tile_scale(const tpc_problem* p, int64_t blocks)
+// tile scale: 1, 2 or 4, growing with the clusters per resident block,
+// unless the context fixes it
+int tile_scale(const tpc_context* ctx, const tpc_problem* p, int64_t blocks)
 {
+    if (ctx->tune.persistent_scale > 0) return ctx->tune.persistent_scale;
     const int64_t per_block = p->n_clusters / (blocks > 0 ? blocks : 1);
     return per_block >= 8192 ? 4 : per_block >= 4096 ? 2 : 1;
 }
@@ -561,7 +564,7 @@ const tpc_context::TaskTable* find_table(const tpc_context* ctx, uint64_t key)
 
 int prepare_persistent(tpc_context* ctx, const tpc_problem* p)
 {
-    const int scale = tile_scale(p, persistent_blocks(ctx));
+    const int scale = tile_scale(ctx, p, persistent_blocks(ctx));
     const uint64_t key = sectors_key(p, scale);
     if (find_table(ctx, key)) return TPC_OK;
     // the table depends on the sector table only: built once per problem
@@ -596,7 +599,7 @@ int run_persistent(tpc_context* ctx, const tpc_problem* p, tpc_clusters in, tpc_
                    const Workspace& ws, hipStream_t st)
 {
     const int64_t resident = persistent_blocks(ctx);
-    const int scale = tile_scale(p, resident);
+    const int scale = tile_scale(ctx, p, resident);
     const tpc_context::TaskTable* tab = find_table(ctx, sectors_key(p, scale));
     if (!tab) return TPC_ERR_INVALID_ARG;
     PArgs a;

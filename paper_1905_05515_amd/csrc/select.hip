@@ -8,9 +8,8 @@
 namespace tpc {
 
 // Sectors whose row chunks hold on average several times more positions
-// than the LDS table take the tracklet-parallel form with device-wide
-// atomics instead (same keys and counts): one block per chunk would loop
-// over too many tracklets.  A chunk just over the table still uses its
+// than the LDS table take the row form below instead (same keys and
+// counts).  A chunk just over the table still uses its
 // block (with device-wide keys).  Host and device decide alike from the
 // sector's size.
 __host__ __device__ inline bool sel_big(const tpc_sector& s, int n_rows)
@@ -32,91 +31,183 @@ __global__ __launch_bounds__(kBlock) void k_sel_chunk(
     const int si = sec_lo + (int)(blockIdx.x / nq);
     const int q = (int)(blockIdx.x % nq);
     const tpc_sector s = sec[si];
-    if (sel_big(s, n_rows)) {   // the tracklet-parallel kernels take this sector
-        const int ra = q * kSelRows, rb = ra + kSelRows < n_rows ? ra + kSelRows : n_rows;
-        const int per_row = s.nbz * s.nby;
-        const int p0 = bin_start[s.bin_base + ra * per_row];
-        const int np = bin_start[s.bin_base + rb * per_row] - p0;
-        for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[p0 + k] = 0ull;
-        return;
-    }
+    if (sel_big(s, n_rows)) return;   // the row kernels take this sector
     int64_t lo = sec_start[si], hi = sec_start[si + 1];
     if (lo < 0) lo = 0;
     sel_chunk_block(s, q, n_rows, prm, bin_start, idg, t_start, t_hits, t_nhits, lo, hi,
                     count_cap, cap, hitkey, ccnt, kl, kSelLds);
 }
 
-// Tracklet-parallel form for big sectors.  Keys: one thread per tracklet
-// claims its hits with device-wide 64-bit atomics, reading its rows upwards
-// from its innermost hit until all its hits are seen (every hit row lies in
-// [t_rin, last hit row]), and records that row span.  Tracklets of other
-// sectors are left to k_sel_chunk.
-constexpr uint16_t kSpanOther = 0xFFFE;   // tracklet of a sector that is not big
-constexpr uint16_t kSpanNone = 0xFFFF;    // takes no part in the selection
+// Row form for big sectors.  One block per (sector, pad row) keeps the
+// ownership keys of the row's grid positions in LDS (in slices of 64 KB of
+// keys when the row has more), reads the row's entry of
+// every tracklet of the sector, claims with a 64-bit LDS atomic max, writes
+// the keys out and records which tracklets keep their hit on the row as one
+// bit per tracklet (kbits[row][t / 64], bit t % 64).  A second kernel sums
+// the bits of every row chunk into the kept counts.  No device-wide atomic
+// per hit: on a continuous read-out slice (1.9M tracklets over 36 sectors
+// of 1.9M clusters) the tracklet-parallel form with one 64-bit device atomic
+// per hit took 11 + 3.5 ms, this form with 64-bit keys in slices of 8192
+// positions (two per row there) 5.1 + 0.7 ms.
+constexpr int kSelRowBytes = 65536;      // LDS key table of one block
+constexpr int kSelRowBlock = 1024;
+constexpr int kSelRowUnroll = 4;          // tracklet entries loaded together
+constexpr unsigned long long kKeyNotBig = ~0ull;   // tracklet of a sector that is not big
 
-__global__ __launch_bounds__(kBlock) void k_sel_keys_big(
+// tkey[t]: the tracklet's key (0: takes no part), kKeyNotBig outside big
+// sectors; kbits cleared over the words of tracklets [lo, m).
+__global__ __launch_bounds__(kBlock) void k_sel_prep_big(
     const tpc_sector* __restrict__ sec, int n_rows, tpc_params prm,
     const int32_t* __restrict__ idg, const int32_t* __restrict__ gsr,
-    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const int32_t* __restrict__ t_rin,
+    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_nhits,
     const int64_t* __restrict__ t_lo, const int64_t* __restrict__ t_hi, int64_t count_cap,
-    int64_t cap, unsigned long long* __restrict__ hitkey, uint16_t* __restrict__ tspan)
+    int64_t n_words, unsigned long long* __restrict__ tkey,
+    unsigned long long* __restrict__ kbits)
 {
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
-    for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        if (!sel_big(sec[gsr[t_start[t]] >> 8], n_rows)) {
-            tspan[t] = kSpanOther;
-            continue;
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = lo + g; t < m; t += stride)
+        tkey[t] = sel_big(sec[gsr[t_start[t]] >> 8], n_rows) ? key_of(t, prm, idg, t_start, t_nhits)
+                                                            : kKeyNotBig;
+    if (m <= lo) return;
+    const int64_t w0 = lo >> 6, nw = ((m - 1) >> 6) - w0 + 1;
+    for (int64_t i = g; i < nw * n_rows; i += stride)
+        kbits[(i / nw) * n_words + w0 + i % nw] = 0ull;
+}
+
+// Keys in LDS: 32 bits when the sector has at most 2^24 clusters
+// (hits << 24 | (2^24 - 1 - start id + first id of the sector), the same
+// order as the 64-bit key), else the 64-bit key.
+struct Key32 {
+    using T = unsigned int;
+    int64_t begin;
+    __device__ T pack(unsigned long long k) const
+    {
+        if (!k) return 0u;
+        const unsigned nh = (unsigned)(k >> 32);
+        const int64_t id = (int64_t)(0xFFFFFFFFull - (k & 0xFFFFFFFFull));
+        return (nh << 24) | (0xFFFFFFu - (unsigned)(id - begin));
+    }
+    __device__ unsigned long long unpack(T k) const
+    {
+        if (!k) return 0ull;
+        const int64_t id = begin + (int64_t)(0xFFFFFFu - (k & 0xFFFFFFu));
+        return ((unsigned long long)(k >> 24) << 32) | (0xFFFFFFFFull - (unsigned long long)id);
+    }
+};
+struct Key64 {
+    using T = unsigned long long;
+    int64_t begin;
+    __device__ T pack(unsigned long long k) const { return k; }
+    __device__ unsigned long long unpack(T k) const { return k; }
+};
+
+template <typename KF>
+__global__ __launch_bounds__(kSelRowBlock) void k_sel_rows_big(
+    const tpc_sector* __restrict__ sec, int sec_lo, int n_rows,
+    const int32_t* __restrict__ bin_start, const int32_t* __restrict__ t_hits,
+    const int64_t* __restrict__ sec_start, int64_t count_cap, int64_t cap, int64_t n_words,
+    const unsigned long long* __restrict__ tkey, unsigned long long* __restrict__ hitkey,
+    unsigned long long* __restrict__ kbits)
+{
+    using T = typename KF::T;
+    constexpr int kLds = kSelRowBytes / (int)sizeof(T);
+    __shared__ T kl[kLds];
+    const int si = sec_lo + (int)(blockIdx.x / n_rows);
+    const int r = (int)(blockIdx.x % n_rows);
+    const tpc_sector s = sec[si];
+    if (!sel_big(s, n_rows)) return;
+    const KF kf{s.begin};
+    const int per_row = s.nbz * s.nby;
+    const int p0 = bin_start[s.bin_base + r * per_row];
+    const int p1 = bin_start[s.bin_base + (r + 1) * per_row];
+    int64_t lo = sec_start[si], hi = sec_start[si + 1];
+    if (hi > count_cap) hi = count_cap;
+    if (lo < 0) lo = 0;
+    if (lo > hi) lo = hi;
+    // whole waves over 64-aligned tracklet ranges: lane 0 of a wave owns one
+    // word of kbits; words shared with a neighbouring sector (the first and
+    // the last) are merged with an atomic or, the others written by their
+    // owner alone
+    const int64_t a0 = lo & ~(int64_t)63, a1 = (hi + 63) & ~(int64_t)63;
+    const int64_t w_first = lo >> 6, w_last = (hi - 1) >> 6;
+    const int32_t* __restrict__ row = t_hits + (int64_t)r * cap;
+    unsigned long long* __restrict__ kb = kbits + (int64_t)r * n_words;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t bd = blockDim.x;
+    for (int ps = p0, slice = 0; ps < p1; ps += kLds, ++slice) {
+        const int np = p1 - ps < kLds ? p1 - ps : kLds;
+        for (int k = threadIdx.x; k < np; k += blockDim.x) kl[k] = 0;
+        __syncthreads();
+        // claims: kSelRowUnroll entries per thread in flight
+        for (int64_t t0 = a0 + threadIdx.x; t0 < hi; t0 += bd * kSelRowUnroll) {
+            int h[kSelRowUnroll];
+#pragma unroll
+            for (int u = 0; u < kSelRowUnroll; ++u) {
+                const int64_t t = t0 + u * bd;
+                h[u] = t >= lo && t < hi ? row[t] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kSelRowUnroll; ++u) {
+                const unsigned o = (unsigned)(h[u] - ps);
+                if (h[u] < 0 || o >= (unsigned)np) continue;
+                const T key = kf.pack(tkey[t0 + u * bd]);
+                if (key) atomicMax(&kl[o], key);
+            }
         }
-        const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        const int nh = t_nhits[t];
-        int r = t_rin[t];
-        if (!key || r < 0 || r >= n_rows) {
-            tspan[t] = kSpanNone;
-            continue;
+        __syncthreads();
+        for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[ps + k] = kf.unpack(kl[k]);
+        // kept bits, kSelRowUnroll waves' worth of entries per thread in flight
+        for (int64_t t0 = a0 + threadIdx.x; t0 < a1; t0 += bd * kSelRowUnroll) {
+            int h[kSelRowUnroll];
+#pragma unroll
+            for (int u = 0; u < kSelRowUnroll; ++u) {
+                const int64_t t = t0 + u * bd;
+                h[u] = t >= lo && t < hi ? row[t] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kSelRowUnroll; ++u) {
+                const int64_t t = t0 + u * bd;
+                if (t >= a1) break;   // whole waves: t's wave is a 64-aligned block
+                bool kept = false;
+                const unsigned o = (unsigned)(h[u] - ps);
+                if (h[u] >= 0 && o < (unsigned)np) {
+                    const T key = kf.pack(tkey[t]);
+                    kept = key && kl[o] == key;
+                }
+                const unsigned long long mask = __ballot(kept);
+                if (lane == 0 && mask) {
+                    const int64_t w = t >> 6;
+                    if (slice == 0 && w != w_first && w != w_last) kb[w] = mask;
+                    else atomicOr(&kb[w], mask);
+                }
+            }
         }
-        const int first = r;
-        int last = r, seen = 0;
-        for (; r < n_rows && seen < nh; ++r) {
-            const int h = t_hits[(int64_t)r * cap + t];
-            if (h < 0) continue;
-            // keys only grow: a value seen here is a lower bound of the
-            // current one, so a hit that already holds a key >= ours needs
-            // no atomic (most hits are claimed by several tracklets)
-            const unsigned long long seen_key =
-                __hip_atomic_load(&hitkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (seen_key < key) atomicMax(&hitkey[h], (unsigned long long)key);
-            ++seen;
-            last = r;
-        }
-        tspan[t] = (uint16_t)(first | (last << 8));
+        __syncthreads();
     }
 }
 
-// Counts: item (t, blockIdx.y) handles rows [8 y, 8 y + 8) of tracklet t;
-// a chunk outside the tracklet's row span is zero without a load.
-__global__ __launch_bounds__(kBlock) void k_sel_count_big(
-    int n_rows, tpc_params prm, const int32_t* __restrict__ idg,
-    const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
-    const int32_t* __restrict__ t_nhits, const int64_t* __restrict__ t_lo,
-    const int64_t* __restrict__ t_hi, int64_t count_cap, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, const uint16_t* __restrict__ tspan,
-    uint8_t* __restrict__ ccnt)
+// Kept counts per row chunk of the tracklets of big sectors from the bits.
+__global__ __launch_bounds__(kBlock) void k_sel_count_bits(
+    int n_rows, const int64_t* __restrict__ t_lo, const int64_t* __restrict__ t_hi,
+    int64_t count_cap, int64_t n_words, const unsigned long long* __restrict__ tkey,
+    const unsigned long long* __restrict__ kbits, uint8_t* __restrict__ ccnt)
 {
     const int64_t lo = *t_lo < count_cap ? *t_lo : count_cap;
     const int64_t m = *t_hi < count_cap ? *t_hi : count_cap;
-    const int ra = blockIdx.y * kSelRows;
     for (int64_t t = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int sp = tspan[t];
-        if (sp == kSpanOther) continue;
-        int kept = 0;
-        if (sp != kSpanNone && ra + kSelRows > (sp & 255) && ra <= (sp >> 8))
-            kept = sel_count_chunk(t, ra, n_rows, key_of(t, prm, idg, t_start, t_nhits), t_hits,
-                                   cap, hitkey);
-        ccnt[blockIdx.y * count_cap + t] = (uint8_t)kept;
+        if (tkey[t] == kKeyNotBig) continue;     // k_sel_chunk counts it
+        const int64_t w = t >> 6;
+        const int b = (int)(t & 63);
+        for (int ra = 0, q = 0; ra < n_rows; ra += kSelRows, ++q) {
+            const int rb = ra + kSelRows < n_rows ? ra + kSelRows : n_rows;
+            int kept = 0;
+            for (int rr = ra; rr < rb; ++rr) kept += (int)((kbits[(int64_t)rr * n_words + w] >> b) & 1ull);
+            ccnt[q * count_cap + t] = (uint8_t)kept;
+        }
     }
 }
 
@@ -200,16 +291,33 @@ int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
     bool any_big = false;
     for (int s = sec_lo; s < sec_hi && !any_big; ++s) any_big = sel_big(p->h_sectors[s], p->n_rows);
     if (any_big) {
-        TPC_LAUNCH(k_sel_keys_big, dim3(gx), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
+        const int64_t n_words = sel_words(count_cap);
+        TPC_LAUNCH(k_sel_prep_big, dim3(gx), dim3(kBlock), 0, st, p->d_sectors, p->n_rows,
                    p->params, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
-                   (const int32_t*)trl.start, (const int32_t*)trl.hits,
-                   (const int32_t*)trl.nhits, (const int32_t*)trl.row_inner, lo, hi, count_cap,
-                   trl.capacity, (unsigned long long*)ws.hitkey, ws.tspan);
-        TPC_LAUNCH(k_sel_count_big, dim3(gx, nq), dim3(kBlock), 0, st, p->n_rows, p->params,
-                   (const int32_t*)grid.id, (const int32_t*)trl.start,
-                   (const int32_t*)trl.hits, (const int32_t*)trl.nhits, lo, hi, count_cap,
-                   trl.capacity, (const unsigned long long*)ws.hitkey,
-                   (const uint16_t*)ws.tspan, ws.ccnt);
+                   (const int32_t*)trl.start, (const int32_t*)trl.nhits, lo, hi, count_cap,
+                   n_words, (unsigned long long*)ws.tkey, (unsigned long long*)ws.kbits);
+        // 32-bit keys in LDS when every big sector has at most 2^24 clusters
+        bool k32 = true;
+        for (int s = sec_lo; s < sec_hi; ++s)
+            if (sel_big(p->h_sectors[s], p->n_rows) &&
+                p->h_sectors[s].end - p->h_sectors[s].begin > (int64_t(1) << 24))
+                k32 = false;
+        const dim3 gr((unsigned)((sec_hi - sec_lo) * p->n_rows));
+        if (k32)
+            TPC_LAUNCH(k_sel_rows_big<Key32>, gr, dim3(kSelRowBlock), 0, st, p->d_sectors, sec_lo,
+                       p->n_rows, (const int32_t*)grid.bin_start, (const int32_t*)trl.hits,
+                       (const int64_t*)ws.sec_start, count_cap, trl.capacity, n_words,
+                       (const unsigned long long*)ws.tkey, (unsigned long long*)ws.hitkey,
+                       (unsigned long long*)ws.kbits);
+        else
+            TPC_LAUNCH(k_sel_rows_big<Key64>, gr, dim3(kSelRowBlock), 0, st, p->d_sectors, sec_lo,
+                       p->n_rows, (const int32_t*)grid.bin_start, (const int32_t*)trl.hits,
+                       (const int64_t*)ws.sec_start, count_cap, trl.capacity, n_words,
+                       (const unsigned long long*)ws.tkey, (unsigned long long*)ws.hitkey,
+                       (unsigned long long*)ws.kbits);
+        TPC_LAUNCH(k_sel_count_bits, dim3(gx), dim3(kBlock), 0, st, p->n_rows, lo, hi, count_cap,
+                   n_words, (const unsigned long long*)ws.tkey,
+                   (const unsigned long long*)ws.kbits, ws.ccnt);
     }
     TPC_LAUNCH(k_sel_len, dim3(gx), dim3(kBlock), 0, st, nq, p->params, lo, hi, count_cap,
                (const uint8_t*)ws.ccnt, ws.tlen);

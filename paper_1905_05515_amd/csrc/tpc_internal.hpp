@@ -30,7 +30,8 @@ struct Workspace {
     uint64_t* tlen;        // [start_cap + 1] per tracklet: accepted << 32 | kept
     uint64_t* toff;        // [start_cap + 1] exclusive scan of tlen
     uint8_t* ccnt;         // [row chunks * start_cap] kept hits per tracklet and row chunk
-    uint16_t* tspan;       // [start_cap] selection, big sectors: hit rows first | last << 8
+    uint64_t* tkey;        // [start_cap] selection, big sectors: key per tracklet
+    uint64_t* kbits;       // [n_rows * sel_words(start_cap)] selection, big sectors: kept bits
     // grid build: clusters per (sector, row bucket), their running fill and
     // starts; the row-partitioned copy of the clusters; the binned order
     int32_t* rcnt;         // [n_sectors * (n_rows + 1) * S]
@@ -49,6 +50,7 @@ struct Workspace {
     uint64_t* tsum;        // persistent form: [n_sectors] tracks << 32 | hits per sector
     int64_t* ptile;        // persistent form: starts per counting tile
     int32_t* pchunk;       // persistent form: [n_sectors] next tracklet chunk of each sector
+    uint64_t* tq;          // [8] queue form of the tracklets: starts taken per XCD share
     size_t bytes;
 };
 
@@ -74,6 +76,8 @@ int grid_slabs(const tpc_problem* p);
 // Rows of a tracklet handled by one selection work item.
 constexpr int kSelRows = 8;
 inline int sel_chunks(int n_rows) { return (n_rows + kSelRows - 1) / kSelRows; }
+// 64-bit words of one row of the big-sector kept bits
+inline int64_t sel_words(int64_t start_cap) { return (start_cap + 63) / 64 + 1; }
 
 // Offsets of the workspace members for a problem; returns false on overflow.
 bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Workspace* ws);
@@ -203,6 +207,7 @@ struct tpc_context {
     static constexpr int kTaskTables = 8;
     TaskTable tables[kTaskTables];
     int n_tables;
+    tpc_tuning tune;           // launch shapes (0: automatic)
 };
 
 // stage launchers (stream-ordered, no host synchronisation); the sector
@@ -210,12 +215,14 @@ struct tpc_context {
 namespace tpc {
 int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in,
                    tpc_grid out, const Workspace& ws, hipStream_t st);
+// `tune` (may be null: automatic) picks launch shapes only
 int run_find_neighbours(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
                         tpc_links links, tpc_starts starts, const Workspace& ws,
-                        hipStream_t st);
+                        hipStream_t st, const tpc_tuning* tune = nullptr);
 int run_construct_tracklets(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
                             tpc_links links, tpc_starts starts, tpc_tracklets trl,
-                            const Workspace& ws, hipStream_t st);
+                            const Workspace& ws, hipStream_t st,
+                            const tpc_tuning* tune = nullptr);
 int run_select_keys(const tpc_problem* p, int sec_lo, int sec_hi, tpc_grid grid,
                     int64_t count_cap, tpc_tracklets trl, const Workspace& ws, hipStream_t st);
 int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,

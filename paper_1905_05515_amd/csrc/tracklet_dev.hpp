@@ -352,6 +352,195 @@ __device__ __forceinline__ void build_tracklet(
     t_chi2[t] = csum;
 }
 
+// ---- queue form ------------------------------------------------------------
+// One thread per tracklet at a time, every lane at its own row and pass:
+// a loop step advances each lane by one row of its current pass (the same
+// transport, search and update code for both passes), and a lane that
+// finishes takes the next start from a device queue.  Lanes wait idle
+// until kRefill of them are free (or no lane of the wave works), so that
+// the refill (the tracklet's column of -1 entries and its first state) is
+// issued for several lanes at once.  Per tracklet the arithmetic is the
+// same sequence of operations as build_tracklet's.
+constexpr int kRefill = 8;
+
+enum : int { kLaneIdle = 0, kLaneUp = 1, kLaneDown = 2, kLaneDone = 3, kLaneOut = 4 };
+
+struct LaneTracklet {
+    int64_t t;
+    int32_t* th;          // the tracklet's column: th[r * cap]
+    tpc_sector s;
+    int ph, r, r0, last, miss, nh, rin, h0, hl;
+    int cc, cn, an;       // chain hit of this row, of the next (up); assigned hit below (down)
+    float cy, cz, ay, az, csum;
+    KState st, in;
+    float plast[5];
+};
+
+// start of the down pass from the outermost hit (state at the up pass's
+// last update, position of that hit, initial covariance)
+__device__ __forceinline__ void lane_begin_down(LaneTracklet& L, const tpc_params& prm,
+                                                const float* __restrict__ yg,
+                                                const float* __restrict__ zg, int64_t cap)
+{
+#pragma unroll
+    for (int i = 0; i < 5; ++i) L.st.p[i] = L.plast[i];
+    L.st.p[0] = yg[L.hl];
+    L.st.p[1] = zg[L.hl];
+    reset_cov(L.st, prm);
+    L.in = L.st;
+    L.csum = 0.0f;
+    L.rin = L.last;
+    L.miss = 0;
+    L.an = -1;
+    if (L.last - 1 >= L.r0) {
+        L.an = L.th[(int64_t)(L.last - 1) * cap];
+        if (L.an >= 0) {
+            L.ay = yg[L.an];
+            L.az = zg[L.an];
+        }
+    }
+    L.r = L.last - 1;
+    L.ph = L.r >= 0 ? kLaneDown : kLaneDone;
+}
+
+// first state of tracklet t (its column already holds -1 everywhere)
+__device__ __forceinline__ void lane_init(LaneTracklet& L, int64_t t,
+                                          const tpc_sector* __restrict__ sec, int n_rows,
+                                          const float* xs, const tpc_params& prm,
+                                          const float* __restrict__ yg,
+                                          const float* __restrict__ zg,
+                                          const int32_t* __restrict__ gsr,
+                                          const int32_t* __restrict__ up,
+                                          const int32_t* __restrict__ starts, int64_t cap)
+{
+    const int h0 = starts[t];
+    const int v0 = gsr[h0];
+    L.s = sec[v0 >> 8];
+    L.r0 = v0 & 255;
+    const int h1 = up[h0], h2 = up[h1];
+    const int r2 = gsr[h2] & 255;
+    const float dX = xs[r2] - xs[L.r0];
+    const float T0 = (yg[h2] - yg[h0]) / dX;
+    const float q0 = sqrtf(1.0f + T0 * T0);
+    L.st.p[0] = yg[h0];
+    L.st.p[1] = zg[h0];
+    L.st.p[2] = T0 / q0;
+    L.st.p[3] = (zg[h2] - zg[h0]) / (dX * q0);
+    L.st.p[4] = 0.0f;
+    reset_cov(L.st, prm);
+    L.th[(int64_t)L.r0 * cap] = h0;
+    L.h0 = h0;
+    L.hl = h0;
+    L.last = L.r0;
+    L.nh = 1;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) L.plast[i] = L.st.p[i];
+    L.cc = h1;
+    L.cn = h2;
+    L.cy = yg[h1];
+    L.cz = zg[h1];
+    L.miss = 0;
+    L.r = L.r0 + 1;
+    L.ph = kLaneUp;
+    if (L.r >= n_rows) lane_begin_down(L, prm, yg, zg, cap);
+}
+
+// one row of the lane's current pass
+__device__ __forceinline__ void lane_step(LaneTracklet& L, int n_rows, const float* xs,
+                                          const tpc_params& prm,
+                                          const int32_t* __restrict__ bin_start,
+                                          const float* __restrict__ yg,
+                                          const float* __restrict__ zg,
+                                          const int32_t* __restrict__ idg,
+                                          const int32_t* __restrict__ up, int64_t cap,
+                                          int& n_prop, int& n_upd, int& n_cand)
+{
+    const bool upp = L.ph == kLaneUp;
+    const int r = L.r;
+    int c;
+    float my, mz, ny = 0.0f, nz = 0.0f;
+    int cnn = -1;
+    if (upp) {
+        if (L.cn >= 0) {
+            ny = yg[L.cn];
+            nz = zg[L.cn];
+            cnn = up[L.cn];
+        }
+        c = L.cc;
+        my = L.cy;
+        mz = L.cz;
+    } else {
+        c = L.an;
+        my = L.ay;
+        mz = L.az;
+        L.an = -1;
+        if (r - 1 >= L.r0) {
+            L.an = L.th[(int64_t)(r - 1) * cap];
+            if (L.an >= 0) {
+                L.ay = yg[L.an];
+                L.az = zg[L.an];
+            }
+        }
+    }
+    ++n_prop;
+    const float dx = upp ? xs[r] - xs[r - 1] : xs[r] - xs[r + 1];
+    if (!propagate(L.st, dx, prm.curv, prm.s_max)) {
+        if (upp) {
+            lane_begin_down(L, prm, yg, zg, cap);
+        } else {
+            for (int q = r; q >= 0; --q) {
+                L.nh -= L.th[(int64_t)q * cap] >= 0;
+                L.th[(int64_t)q * cap] = -1;
+            }
+            L.ph = kLaneDone;
+        }
+        return;
+    }
+    const bool search = upp ? c < 0 : r < L.r0;
+    if (search) {
+        c = search_row(L.st, L.s, r, prm, n_cand, bin_start, yg, zg, idg, my, mz);
+        if (c < 0) {
+            if (++L.miss >= prm.max_miss) {
+                if (upp) lane_begin_down(L, prm, yg, zg, cap);
+                else L.ph = kLaneDone;
+                return;
+            }
+        } else {
+            L.miss = 0;
+        }
+    }
+    if (c >= 0) {
+        ++n_upd;
+        const float chi = kupdate(L.st, my, mz, prm.sigma_y2, prm.sigma_z2);
+        L.th[(int64_t)r * cap] = c;
+        if (upp) {
+            L.last = r;
+            L.hl = c;
+            ++L.nh;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) L.plast[i] = L.st.p[i];
+        } else {
+            L.csum = L.csum + chi;
+            L.rin = r;
+            L.in = L.st;
+            L.nh += r < L.r0;
+        }
+    }
+    if (upp) {
+        if (!search) {
+            L.cc = L.cn;
+            L.cy = ny;
+            L.cz = nz;
+            L.cn = cnn;
+        }
+        L.r = r + 1;
+        if (L.r >= n_rows) lane_begin_down(L, prm, yg, zg, cap);
+    } else {
+        L.r = r - 1;
+        if (L.r < 0) L.ph = kLaneDone;
+    }
+}
+
 // per-wave sum of the work counters into the status block
 __device__ __forceinline__ void add_work(tpc_status* status, int n_prop, int n_upd, int n_cand)
 {

@@ -165,6 +165,7 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->tsum = (uint64_t*)take(sizeof(uint64_t) * (size_t)p->n_sectors);
     ws->ptile = (int64_t*)take(sizeof(int64_t) * (size_t)(n / 1024 + p->n_sectors + 2));
     ws->pchunk = (int32_t*)take(sizeof(int32_t) * (size_t)p->n_sectors);
+    ws->tq = (uint64_t*)take(sizeof(uint64_t) * 8);
     const size_t nrb = (size_t)p->n_sectors * (size_t)(p->n_rows + 1) * (size_t)grid_slabs(p);
     const size_t nn = (size_t)(n > 0 ? n : 1);
     ws->rcnt = (int32_t*)take(sizeof(int32_t) * nrb);
@@ -181,7 +182,9 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->tlen = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 1));
     ws->toff = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap + 2));
     ws->ccnt = (uint8_t*)take((size_t)sel_chunks(p->n_rows) * (size_t)(start_cap > 0 ? start_cap : 1));
-    ws->tspan = (uint16_t*)take(sizeof(uint16_t) * (size_t)(start_cap > 0 ? start_cap : 1));
+    ws->tkey = (uint64_t*)take(sizeof(uint64_t) * (size_t)(start_cap > 0 ? start_cap : 1));
+    ws->kbits = (uint64_t*)take(sizeof(uint64_t) * (size_t)p->n_rows *
+                                (size_t)sel_words(start_cap));
     ws->bytes = o;
     return true;
 }
@@ -279,7 +282,32 @@ int tpc_context_create(tpc_context** out, int device)
     c->graph_valid = false;
     c->timer = nullptr;
     c->n_tables = 0;
+    c->tune = tpc_tuning{0, 0, 0, 0};
     *out = c;
+    return TPC_OK;
+}
+
+int tpc_context_set_tuning(tpc_context* ctx, const tpc_tuning* t)
+{
+    if (!ctx || !t) return TPC_ERR_INVALID_ARG;
+    const bool ok = t->tracklet_form >= TPC_TRACKLETS_AUTO &&
+                    t->tracklet_form <= TPC_TRACKLETS_QUEUE &&
+                    (t->neighbour_block == 0 || t->neighbour_block == 64 ||
+                     t->neighbour_block == 128 || t->neighbour_block == 256) &&
+                    (t->persistent_scale == 0 || t->persistent_scale == 1 ||
+                     t->persistent_scale == 2 || t->persistent_scale == 4 ||
+                     t->persistent_scale == 8) &&
+                    t->persistent_blocks_per_cu >= 0 && t->persistent_blocks_per_cu <= 64;
+    if (!ok) return TPC_ERR_INVALID_ARG;
+    ctx->tune = *t;
+    ctx->graph_valid = false;
+    return TPC_OK;
+}
+
+int tpc_context_get_tuning(const tpc_context* ctx, tpc_tuning* t)
+{
+    if (!ctx || !t) return TPC_ERR_INVALID_ARG;
+    *t = ctx->tune;
     return TPC_OK;
 }
 

@@ -114,3 +114,45 @@ def test_persistent_tile_scales():
     assert r[("persistent", False)]["status"]["overflow"] == 0
     _same(r[("staged", False)], r[("persistent", False)])
     _same(r[("staged", False)], r[("persistent", True)])
+
+
+@pytest.mark.timeout(600)
+def test_launch_shapes_change_no_output():
+    """Every launch shape the context accepts (tracklet hit lists in LDS or
+    written directly, starts dealt by a device queue, neighbour blocks of 64-256 threads, persistent tile
+    scales 1-8 and 1-2 blocks per compute unit) gives the outputs of the
+    automatic shapes bit for bit; the shape tuner keeps the tracks and
+    leaves valid shapes set; invalid shapes are refused."""
+    ev = synth.make_config2()
+    print(f"case c2 launch shapes n={ev.n_clusters}", flush=True)
+    c = api.Context(0)
+    e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x,
+                       synth.default_params(), sector_side=ev.sector_side)
+    side = torch.cuda.Stream()             # graphs are captured on a stream of their own
+    torch.cuda.synchronize()
+    api.track_batch(c, e, mode="staged", stream=side)
+    ref = api.results(e, side)
+    cases = [("staged", dict(tracklet_form=1)), ("staged", dict(tracklet_form=2)),
+             ("staged", dict(tracklet_form=3)), ("per_sector", dict(tracklet_form=3)),
+             ("staged", dict(neighbour_block=64)), ("staged", dict(neighbour_block=128)),
+             ("per_sector", dict(tracklet_form=2, neighbour_block=128)),
+             ("persistent", dict(persistent_scale=1)), ("persistent", dict(persistent_scale=8)),
+             ("persistent", dict(persistent_scale=2, persistent_blocks_per_cu=1))]
+    for mode, kw in cases:
+        api.set_tuning(c, **{k: 0 for k in api.TUNING_FIELDS})
+        api.set_tuning(c, **kw)
+        for graph in (False, True, True):
+            with torch.cuda.stream(side):
+                api.track_batch(c, e, mode=mode, use_graph=graph, stream=side)
+            print(f"  {mode} {kw} graph={graph}", flush=True)
+            _same(ref, api.results(e, side))
+    api.set_tuning(c, **{k: 0 for k in api.TUNING_FIELDS})
+    for mode in ("staged", "persistent"):
+        shapes, times = api.autotune_shapes(c, e, mode=mode, reps=1, stream=side)
+        print(f"  tuned {mode}: {shapes} {times}", flush=True)
+        _same(ref, api.results(e, side))
+    for bad in (dict(tracklet_form=4), dict(neighbour_block=96), dict(persistent_scale=3),
+                dict(persistent_blocks_per_cu=-1)):
+        with pytest.raises(api.L.TPCError):
+            api.set_tuning(c, **bad)
+    c.close()

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 PRM = synth.default_params()
 
 
-def _check(ev, qbits=5, cbits=5, chunk=16384):
+def _check(ev, qbits=5, cbits=5, chunk=4096):
     e, g = run_gpu(ev)
     blob, size = api.compress_clusters(ctx(), e, torch.as_tensor(ev.charge), qbits, cbits, chunk)
     torch.cuda.synchronize()
@@ -41,8 +41,10 @@ def test_compression_matches_the_oracle_byte_for_byte():
     print(f"case compress c1 n={ev.n_clusters}", flush=True)
     _check(ev)
     _check(ev, qbits=3, cbits=4, chunk=64)
+    _check(ev, chunk=1000)             # chunks that do not start on 16-byte boundaries
     ev = synth.make_config2()
     print(f"case compress c2 n={ev.n_clusters}", flush=True)
+    _check(ev, chunk=16384)
     blob = _check(ev)
     d = oracle.decompress(blob, ev.n_clusters, ev.row_x, PRM)
     assert d["row"].size == ev.n_clusters

@@ -126,9 +126,9 @@ def test_sampled_sectors_match_the_oracle(slice_run, s):
 @pytest.mark.timeout(600)
 def test_big_sector_between_small_ones(slice_run):
     """A sector of the slice (millions of clusters: the selection takes its
-    tracklet-parallel form there) between two central-event sectors (row
-    chunks in LDS) in one problem: staged and per-sector launches equal the
-    oracle."""
+    row form there, one block per pad row) between two central-event sectors
+    (row chunks in LDS) in one problem: staged and per-sector launches equal
+    the oracle."""
     ev3 = slice_run[0]
     ev2 = synth.make_config2()
     parts = [ev2.sector(0), ev3.sector(SAMPLED_SECTORS[0]), ev2.sector(1)]

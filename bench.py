@@ -75,6 +75,11 @@ def parse():
                     help="only track the central event, the 512-instance set or the "
                          "continuous read-out slice three times (eager staged launches; the "
                          "workload of the counter profiles of the tracking kernels) and exit")
+    ap.add_argument("--step-probe", action="store_true",
+                    help="only run the batched-set step (tracking with eager staged launches, "
+                         "refit and adjoint of the found tracks) --steps times after one "
+                         "warm-up, with the automatic launch shapes, and exit (the workload of "
+                         "the profiles of the step's kernels)")
     ap.add_argument("--inflight", default="3",
                     help="central event: events in flight in its timed step loop (each on its own stream "
                          "with its own buffers; with four hardware queues per process more "
@@ -133,8 +138,27 @@ def main():
     import synth
     from paper_1905_05515_amd import api
 
-    if args.copy_probe or args.seeding_probe or args.tracking_probe:
+    if args.copy_probe or args.seeding_probe or args.tracking_probe or args.step_probe:
         assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.step_probe:
+        ev = synth.make_config4()
+        prm = synth.default_params()
+        occ = 0.125 if args.occupancy == "auto" else float(args.occupancy)
+        e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x,
+                           prm, occupancy=occ, sector_side=ev.sector_side)
+        ctx = api.Context(0)
+        th = torch.as_tensor(synth_theta()).cuda()
+        g = torch.ones(e.track_capacity, dtype=torch.float32, device="cuda")
+        hits = api.found_track_hits(e, copies=True)
+        fwd, adj = None, {}
+        for _ in range(args.steps + 1):
+            api.track_batch(ctx, e, mode="staged", use_graph=False)
+            fwd = api.refit(ctx, hits, e.t["row_x"], prm, th, out=fwd)
+            api.refit_adjoint(ctx, hits, e.t["row_x"], prm, th, fwd, g, out=adj)
+        torch.cuda.synchronize()
+        log(f"[bench] batched-set step of {ev.n_clusters} clusters, occupancy {occ}, "
+            f"{args.steps + 1} times")
+        return
     if args.tracking_probe:
         make = {"central": synth.make_config2, "batched": synth.make_config4,
                 "slice": synth.make_config3}[args.tracking_probe]
@@ -187,7 +211,7 @@ def main():
     tuned["launch_shapes"] = pick_shapes(args, api, ctx, e, stream, ("persistent", "staged"))
     th = torch.as_tensor(synth_theta()).to(dev)
     gchi2 = torch.ones(e.track_capacity, dtype=torch.float32, device=dev)
-    hits = api.found_track_hits(e)
+    hits = api.found_track_hits(e, copies=True)
     S = dict(fwd=None, adj={})
 
     def step(mode="staged", graph=True):
@@ -391,7 +415,7 @@ def central_bench(args, api, synth, prm, dev, tuned_batch):
     # i % depth.  A lane's steps follow each other on its stream, so no
     # buffer is shared between steps in flight; lanes overlap on the GPU (one
     # central event keeps only a fraction of the chip busy).
-    lanes = [dict(ctx=ctx, e=e, stream=stream, hits=api.found_track_hits(e),
+    lanes = [dict(ctx=ctx, e=e, stream=stream, hits=api.found_track_hits(e, copies=True),
                   fwd=None, adj={})]
 
     def lane(k):
@@ -400,7 +424,7 @@ def central_bench(args, api, synth, prm, dev, tuned_batch):
                                  ev.row_x, prm, sector_side=ev.sector_side)
             api.relayout(e_k, tuned["occupancy"])
             lanes.append(dict(ctx=api.Context(0), e=e_k, stream=torch.cuda.Stream(),
-                              hits=api.found_track_hits(e_k), fwd=None, adj={}))
+                              hits=api.found_track_hits(e_k, copies=True), fwd=None, adj={}))
         return lanes[k]
 
     def step(L, graph=True):

@@ -163,7 +163,10 @@ typedef struct tpc_tracklets {
 
 /* Tracks (CSR): off[n_tracks + 1], hits[off[k]..off[k+1]) cluster ids in
  * ascending row, tracklet[k] the tracklet it came from (ascending), side[k]
- * (nullable) the z side of its sector. */
+ * (nullable) the z side of its sector.  hit_row, hit_y, hit_z (nullable,
+ * all three or none, hit_capacity entries): the pad row and coordinates of
+ * every hit in the order of hits, so that a refit reads the track hits as
+ * contiguous runs instead of gathering them by cluster id. */
 typedef struct tpc_tracks {
     int32_t* off;
     int32_t* hits;
@@ -171,6 +174,9 @@ typedef struct tpc_tracks {
     int8_t* side;
     int64_t capacity;      /* tracks; off needs capacity + 1 entries */
     int64_t hit_capacity;
+    uint8_t* hit_row;
+    float* hit_y;
+    float* hit_z;
 } tpc_tracks;
 
 /* Device status block at the start of the workspace. */

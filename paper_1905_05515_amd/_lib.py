@@ -48,7 +48,7 @@ class Tracklets(C.Structure):
 
 class Tracks(C.Structure):
     _fields_ = [("off", P), ("hits", P), ("tracklet", P), ("side", P), ("capacity", I64),
-                ("hit_capacity", I64)]
+                ("hit_capacity", I64), ("hit_row", P), ("hit_y", P), ("hit_z", P)]
 
 
 class Status(C.Structure):

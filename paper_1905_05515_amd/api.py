@@ -123,6 +123,10 @@ def make_event(row, y, z, sector_offsets, sector_range, row_x, prm: dict, device
     t["t_chi2"] = torch.empty(cap, **f32)
     t["trk_off"] = torch.empty(tcap + 1, **i32)
     t["trk_hits"] = torch.empty(hcap, **i32)
+    # the hits' rows and coordinates in track order (written by the selection)
+    t["trk_row"] = torch.empty(hcap, dtype=torch.uint8, device=dev)
+    t["trk_y"] = torch.empty(hcap, dtype=torch.float32, device=dev)
+    t["trk_z"] = torch.empty(hcap, dtype=torch.float32, device=dev)
     t["trk_tracklet"] = torch.empty(max(tcap, 1), **i32)
     t["trk_side"] = torch.empty(max(tcap, 1), dtype=torch.int8, device=dev)
     prob = L.Problem()
@@ -310,7 +314,8 @@ def _tracklets(ev):
 def _tracks(ev):
     t = ev.t
     return L.Tracks(_ptr(t["trk_off"]), _ptr(t["trk_hits"]), _ptr(t["trk_tracklet"]),
-                    _ptr(t["trk_side"]), ev.track_capacity, ev.track_hit_capacity)
+                    _ptr(t["trk_side"]), ev.track_capacity, ev.track_hit_capacity,
+                    _ptr(t["trk_row"]), _ptr(t["trk_y"]), _ptr(t["trk_z"]))
 
 
 def build_grid(ctx: Context, ev: Event, stream=None):
@@ -539,11 +544,19 @@ def status_count_ptr(ev: Event, field_name: str = "n_tracks") -> C.c_void_p:
     return C.c_void_p(ev.t["ws"].data_ptr() + off)
 
 
-def found_track_hits(ev: Event) -> "TrackHits":
+def found_track_hits(ev: Event, copies: bool = False) -> "TrackHits":
     """The tracks of an event as refit input, without a host round trip:
-    the CSR and hit ids the selection wrote, the event's clusters, the
-    tracks' sides, and the device track count of the status block."""
+    the CSR the selection wrote, the tracks' sides and the device track
+    count of the status block.  copies=False: the hits are the event's
+    clusters gathered through the track's cluster ids (hit gradients then
+    belong to clusters); copies=True: the selection's track-ordered copies
+    of the hits' rows and coordinates, read as contiguous runs (the same
+    values; hit gradients per track entry)."""
     t = ev.t
+    if copies:
+        return TrackHits(off=t["trk_off"], row=t["trk_row"], y=t["trk_y"], z=t["trk_z"],
+                         side=t["trk_side"], idx=None, d_count=status_count_ptr(ev),
+                         n_tracks_cap=ev.track_capacity, n_hits_cap=ev.track_hit_capacity)
     return TrackHits(off=t["trk_off"], row=t["row"], y=t["y"], z=t["z"], side=t["trk_side"],
                      idx=t["trk_hits"], d_count=status_count_ptr(ev),
                      n_tracks_cap=ev.track_capacity, n_hits_cap=ev.track_hit_capacity)

@@ -32,7 +32,9 @@ bool trl_ok(const tpc_tracklets& t, const tpc_starts& s)
 }
 bool trk_ok(const tpc_tracks& t)
 {
-    return t.off && t.hits && t.tracklet && t.capacity >= 0 && t.hit_capacity >= 0;
+    const bool copies = t.hit_row || t.hit_y || t.hit_z;
+    return t.off && t.hits && t.tracklet && t.capacity >= 0 && t.hit_capacity >= 0 &&
+           (!copies || (t.hit_row && t.hit_y && t.hit_z));
 }
 
 uint64_t mix(uint64_t h, uint64_t v)
@@ -160,7 +162,8 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
                           links.up0, links.down0, links.up, links.down, starts.pos,
                           tracklets.start, tracklets.hits, tracklets.nhits, tracklets.row_inner,
                           tracklets.par, tracklets.cov, tracklets.chi2, tracks.off, tracks.hits,
-                          tracks.tracklet, d_ws, h_prob->d_sectors, h_prob->d_row_x, stream};
+                          tracks.tracklet, tracks.side, tracks.hit_row, tracks.hit_y,
+                          tracks.hit_z, d_ws, h_prob->d_sectors, h_prob->d_row_x, stream};
     for (const void* q : ptrs) key = mix(key, (uint64_t)(uintptr_t)q);
     key = mix(key, (uint64_t)starts.capacity);
     if (tune)

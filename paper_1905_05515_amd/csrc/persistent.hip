@@ -158,10 +158,10 @@ __device__ __noinline__ void write_track_hits(
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, int64_t cap,
     const unsigned long long* __restrict__ hitkey, const uint8_t* __restrict__ ccnt,
-    int64_t count_cap, int32_t* __restrict__ trk_hits, int64_t hit_cap)
+    int64_t count_cap, const TrkHitOut& out, int64_t hit_cap)
 {
     sel_write_hits(t, o, n_rows, prm, idg, t_start, t_hits, t_nhits, cap, hitkey, ccnt,
-                   count_cap, trk_hits, hit_cap);
+                   count_cap, out, hit_cap);
 }
 
 __global__ __launch_bounds__(kBlock)
@@ -439,14 +439,15 @@ void k_persistent(PArgs a)
             break;
         }
         case P_TWRITE: {
+            const TrkHitOut out{nullptr, a.trk.hits, a.trk.hit_row, a.trk.hit_y, a.trk.hit_z,
+                                (const float*)a.grid.y, (const float*)a.grid.z};
             for (int64_t t = t_lo + i0 + threadIdx.x; t < t_hi && t < t_lo + i0 + items;
                  t += kBlock)
                 if (a.ws.tlen[t])
                     write_track_hits(t, (int64_t)(a.ws.toff[t] & 0xFFFFFFFFull), n_rows, a.prm,
-                                   a.grid.id, a.trl.start, a.trl.hits, a.trl.nhits,
-                                   a.trl.capacity, (const unsigned long long*)a.ws.hitkey,
-                                     a.ws.ccnt, count_cap,
-                                   a.trk.hits, a.trk.hit_capacity);
+                                     a.grid.id, a.trl.start, a.trl.hits, a.trl.nhits,
+                                     a.trl.capacity, (const unsigned long long*)a.ws.hitkey,
+                                     a.ws.ccnt, count_cap, out, a.trk.hit_capacity);
             break;
         }
         default:

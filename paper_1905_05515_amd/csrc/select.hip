@@ -234,9 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(
     int64_t cap, const unsigned long long* __restrict__ hitkey, const uint64_t* __restrict__ tlen,
     const uint64_t* __restrict__ toff, const uint8_t* __restrict__ ccnt,
     const tpc_sector* __restrict__ sec, const int32_t* __restrict__ gsr,
-    int32_t* __restrict__ trk_off, int32_t* __restrict__ trk_hits,
-    int32_t* __restrict__ trk_tracklet, int8_t* __restrict__ trk_side, int64_t trk_cap,
-    int64_t hit_cap)
+    int32_t* __restrict__ trk_off, TrkHitOut out, int32_t* __restrict__ trk_tracklet,
+    int8_t* __restrict__ trk_side, int64_t trk_cap, int64_t hit_cap)
 {
     int64_t m = status->n_starts;
     if (m > count_cap) m = count_cap;
@@ -252,8 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(
         if (!ccnt[q * count_cap + t]) continue;     // the chunk keeps nothing
         for (int j = 0; j < q; ++j) o += ccnt[j * count_cap + t];
         const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
-        sel_write_chunk(t, q * kSelRows, n_rows, key, o, idg, t_hits, cap, hitkey, trk_hits,
-                        hit_cap);
+        sel_write_chunk(t, q * kSelRows, n_rows, key, o, idg, t_hits, cap, hitkey, out, hit_cap);
     }
 }
 
@@ -268,6 +266,33 @@ __global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status
     if (nt <= trk_cap) trk_off[nt] = (int32_t)nh;
     if (nt > trk_cap) status->overflow |= 2;
     if (nh > hit_cap) status->overflow |= 4;
+}
+
+// Track hits from their grid positions (written by k_sel_write in track
+// order): cluster ids and, when asked for, rows and coordinates, one thread
+// per hit, coalesced writes (the positions of one track lie in one sector's
+// part of the grid).  Writing all of them from k_sel_write, whose threads
+// hold a tracklet's row chunk each and write short runs at scattered
+// offsets, took 923 us on the 512-instance set against 175 us for the ids
+// alone.
+__global__ __launch_bounds__(kBlock) void k_trk_copy(
+    const tpc_status* __restrict__ status, int64_t cap, const int32_t* __restrict__ tpos,
+    const int32_t* __restrict__ idg, const int32_t* __restrict__ gsr,
+    const float* __restrict__ yg, const float* __restrict__ zg, int32_t* __restrict__ trk_hits,
+    uint8_t* __restrict__ trk_row, float* __restrict__ trk_y, float* __restrict__ trk_z)
+{
+    int64_t n = status->n_track_hits;
+    if (n > cap) n = cap;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int p = tpos[j];
+        trk_hits[j] = idg[p];
+        if (trk_y) {
+            trk_row[j] = (uint8_t)(gsr[p] & 255);
+            trk_y[j] = yg[p];
+            trk_z[j] = zg[p];
+        }
+    }
 }
 
 static unsigned sel_grid_x(int64_t n) { return grid_for_block(n, kBlock, 1024); }
@@ -336,10 +361,17 @@ int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
                (const int32_t*)trl.hits, (const int32_t*)trl.nhits, (const tpc_status*)ws.status,
                count_cap, trl.capacity, (const unsigned long long*)ws.hitkey,
                (const uint64_t*)ws.tlen, (const uint64_t*)ws.toff, (const uint8_t*)ws.ccnt,
-               p->d_sectors, (const int32_t*)ws.gsr, trk.off, trk.hits, trk.tracklet, trk.side,
+               p->d_sectors, (const int32_t*)ws.gsr, trk.off,
+               TrkHitOut{ws.tpos, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
+               trk.tracklet, trk.side,
                trk.capacity, trk.hit_capacity);
     TPC_LAUNCH(k_sel_finish, dim3(1), dim3(1), 0, st, (const uint64_t*)(ws.toff + count_cap),
                ws.status, trk.off, trk.capacity, trk.hit_capacity);
+    const int64_t hb = trk.hit_capacity < p->n_clusters ? trk.hit_capacity : p->n_clusters;
+    TPC_LAUNCH(k_trk_copy, dim3(grid_for(hb)), dim3(kBlock), 0, st, (const tpc_status*)ws.status,
+               hb, (const int32_t*)ws.tpos, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
+               (const float*)grid.y, (const float*)grid.z, trk.hits, trk.hit_row, trk.hit_y,
+               trk.hit_z);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

@@ -54,13 +54,26 @@ __device__ __forceinline__ int sel_count_chunk(int64_t t, int ra, int n_rows, ui
     return kept;
 }
 
-// write the kept hits (cluster ids) of one row chunk from hit offset o on;
-// returns the offset after them
+// where the kept hits go: with pos set, only their grid positions (a
+// coalesced pass writes the rest, see k_trk_copy); else the cluster ids and
+// (when y is set) the hits' rows and coordinates in the same order, read
+// from the grid
+struct TrkHitOut {
+    int32_t* pos;
+    int32_t* id;
+    uint8_t* row;
+    float* y;
+    float* z;
+    const float* yg;
+    const float* zg;
+};
+
+// write the kept hits of one row chunk from hit offset o on; returns the
+// offset after them
 __device__ __forceinline__ int64_t sel_write_chunk(
     int64_t t, int ra, int n_rows, uint64_t key, int64_t o, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ t_hits, int64_t cap,
-    const unsigned long long* __restrict__ hitkey, int32_t* __restrict__ trk_hits,
-    int64_t hit_cap)
+    const unsigned long long* __restrict__ hitkey, const TrkHitOut& out, int64_t hit_cap)
 {
     int c[kSelRows];
     load_chunk(t, ra, n_rows, t_hits, cap, c);
@@ -70,7 +83,16 @@ __device__ __forceinline__ int64_t sel_write_chunk(
 #pragma unroll
     for (int k = 0; k < kSelRows; ++k)
         if (keep[k]) {
-            if (o < hit_cap) trk_hits[o] = idg[c[k]];
+            if (o < hit_cap && out.pos) {
+                out.pos[o] = c[k];
+            } else if (o < hit_cap) {
+                out.id[o] = idg[c[k]];
+                if (out.y) {
+                    out.row[o] = (uint8_t)(ra + k);
+                    out.y[o] = out.yg[c[k]];
+                    out.z[o] = out.zg[c[k]];
+                }
+            }
             ++o;
         }
     return o;
@@ -164,13 +186,12 @@ __device__ __forceinline__ void sel_write_hits(
     const int32_t* __restrict__ t_start, const int32_t* __restrict__ t_hits,
     const int32_t* __restrict__ t_nhits, int64_t cap,
     const unsigned long long* __restrict__ hitkey, const uint8_t* __restrict__ ccnt,
-    int64_t count_cap, int32_t* __restrict__ trk_hits, int64_t hit_cap)
+    int64_t count_cap, const TrkHitOut& out, int64_t hit_cap)
 {
     const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
     for (int ra = 0, q = 0; ra < n_rows; ra += kSelRows, ++q) {
         const int kept = ccnt[q * count_cap + t];
-        if (kept)
-            sel_write_chunk(t, ra, n_rows, key, o, idg, t_hits, cap, hitkey, trk_hits, hit_cap);
+        if (kept) sel_write_chunk(t, ra, n_rows, key, o, idg, t_hits, cap, hitkey, out, hit_cap);
         o += kept;
     }
 }

@@ -51,6 +51,7 @@ struct Workspace {
     int64_t* ptile;        // persistent form: starts per counting tile
     int32_t* pchunk;       // persistent form: [n_sectors] next tracklet chunk of each sector
     uint64_t* tq;          // [8] queue form of the tracklets: starts taken per XCD share
+    int32_t* tpos;         // [n] selection: grid position of every track hit, in track order
     size_t bytes;
 };
 

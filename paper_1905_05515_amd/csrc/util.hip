@@ -166,6 +166,7 @@ bool layout_workspace(const tpc_problem* p, int64_t start_cap, void* base, Works
     ws->ptile = (int64_t*)take(sizeof(int64_t) * (size_t)(n / 1024 + p->n_sectors + 2));
     ws->pchunk = (int32_t*)take(sizeof(int32_t) * (size_t)p->n_sectors);
     ws->tq = (uint64_t*)take(sizeof(uint64_t) * 8);
+    ws->tpos = (int32_t*)take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     const size_t nrb = (size_t)p->n_sectors * (size_t)(p->n_rows + 1) * (size_t)grid_slabs(p);
     const size_t nn = (size_t)(n > 0 ? n : 1);
     ws->rcnt = (int32_t*)take(sizeof(int32_t) * nrb);

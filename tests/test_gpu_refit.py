@@ -160,6 +160,47 @@ def test_autograd_through_the_trackers_own_tracks():
     assert not bool((y.grad[~on] != 0).any())
 
 
+def test_track_ordered_hit_copies_give_the_same_refit():
+    """The selection's track-ordered copies of the hits' rows and
+    coordinates equal the clusters gathered through the track's ids, and
+    the refit and its adjoint on the copies (contiguous reads) equal those
+    through the ids bit for bit, in the staged and the persistent form."""
+    from gpu_common import run_gpu
+    ev = synth.make_config2()
+    print(f"case track hit copies n={ev.n_clusters}", flush=True)
+    prm = synth.default_params()
+    th = torch.as_tensor(rs_theta()).cuda()
+    for mode in ("staged", "persistent"):
+        e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
+                           sector_side=ev.sector_side)
+        api.track_batch(ctx(), e, mode=mode)
+        torch.cuda.synchronize()
+        st = api.get_status(e)
+        m = int(st["n_track_hits"])
+        ids = e.t["trk_hits"][:m].long()
+        assert torch.equal(e.t["trk_row"][:m], e.t["row"][ids]), mode
+        assert torch.equal(e.t["trk_y"][:m].view(torch.int32), e.t["y"][ids].view(torch.int32))
+        assert torch.equal(e.t["trk_z"][:m].view(torch.int32), e.t["z"][ids].view(torch.int32))
+        rx = e.t["row_x"]
+        w = torch.linspace(0.5, 1.5, e.track_capacity, device="cuda")
+        res = []
+        for copies in (False, True):
+            hits = api.found_track_hits(e, copies=copies)
+            out = api.refit(ctx(), hits, rx, prm, th)
+            gy, gz, gt = api.refit_adjoint(ctx(), hits, rx, prm, th, out, w)
+            res.append((out, gy, gz, gt))
+        nt = int(st["n_tracks"])
+        (o0, y0, z0, t0), (o1, y1, z1, t1) = res
+        for k in ("par", "cov", "chi2", "status"):
+            a, b = o0[k][:nt], o1[k][:nt]
+            if a.dtype == torch.float32:
+                a, b = a.view(torch.int32), b.view(torch.int32)
+            assert torch.equal(a, b), (mode, k)
+        assert torch.equal(y0[:m].view(torch.int32), y1[:m].view(torch.int32))
+        assert torch.equal(z0[:m].view(torch.int32), z1[:m].view(torch.int32))
+        assert torch.equal(t0.view(torch.int32), t1.view(torch.int32))
+
+
 def rs_theta():
     return synth.make_config5(n_tracks=1).theta_eval
 

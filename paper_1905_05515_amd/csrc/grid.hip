@@ -105,7 +105,14 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows_scatter(
     __shared__ int sf_sh;
     const int Rb = (n_rows + 1) * S;
     const int64_t n_tiles = (c1 - c0 + kRowTile - 1) / kRowTile;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // each pass over gridDim.x tiles deals them to the XCDs in contiguous
+    // ranges (block b runs on XCD b mod 8), so that the short runs that
+    // neighbouring tiles write into one bucket meet in one L2 and leave it
+    // as whole lines
+    for (int64_t b0 = 0; b0 < n_tiles; b0 += gridDim.x) {
+        const int64_t chunk = n_tiles - b0 < (int64_t)gridDim.x ? n_tiles - b0 : (int64_t)gridDim.x;
+        if ((int64_t)blockIdx.x >= chunk) break;
+        const int64_t tile = b0 + xcd_remap(blockIdx.x, (int)chunk);
         const int64_t i0 = c0 + tile * kRowTile;
         const int64_t i1 = i0 + kRowTile < c1 ? i0 + kRowTile : c1;
         const int ns = tile_setup(sec, n_sec, Rb, ts, i0, hist, ends, &sf_sh);

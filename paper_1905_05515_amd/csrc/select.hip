@@ -283,8 +283,14 @@ __global__ __launch_bounds__(kBlock) void k_trk_copy(
 {
     int64_t n = status->n_track_hits;
     if (n > cap) n = cap;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    // blocks of hits dealt to the XCDs in contiguous ranges: the tracks of
+    // one sector, and the grid rows their hits lie in, stay in one L2
+    const int64_t nb = (n + blockDim.x - 1) / blockDim.x;
+    for (int64_t b0 = 0; b0 < nb; b0 += gridDim.x) {
+        const int64_t chunk = nb - b0 < (int64_t)gridDim.x ? nb - b0 : (int64_t)gridDim.x;
+        if ((int64_t)blockIdx.x >= chunk) break;
+        const int64_t j = (b0 + xcd_remap(blockIdx.x, (int)chunk)) * blockDim.x + threadIdx.x;
+        if (j >= n) continue;
         const int p = tpos[j];
         trk_hits[j] = idg[p];
         if (trk_y) {

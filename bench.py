@@ -75,11 +75,20 @@ def parse():
                     help="only track the central event, the 512-instance set or the "
                          "continuous read-out slice three times (eager staged launches; the "
                          "workload of the counter profiles of the tracking kernels) and exit")
-    ap.add_argument("--step-probe", action="store_true",
-                    help="only run the batched-set step (tracking with eager staged launches, "
-                         "refit and adjoint of the found tracks) --steps times after one "
-                         "warm-up, with the automatic launch shapes, and exit (the workload of "
-                         "the profiles of the step's kernels)")
+    ap.add_argument("--step-probe", nargs="?", const="batched", choices=("batched", "central"),
+                    help="only run the step on the batched set (default) or the central event "
+                         "(tracking with eager staged launches, refit and adjoint of the found "
+                         "tracks) --steps times after one warm-up, with the automatic launch "
+                         "shapes, and exit (the workload of the profiles of the step's kernels)")
+    ap.add_argument("--refit-probe", action="store_true",
+                    help="only run the refit and adjoint of the 1M-track refit set three times "
+                         "and exit")
+    ap.add_argument("--probe-mode", default="staged", choices=("staged", "persistent"),
+                    help="launch form of --tracking-probe")
+    ap.add_argument("--batches-in-flight", type=int, default=3,
+                    help="batched set: independent batches (same recipe, seeds 40040000 + k) "
+                         "whose steps overlap in the timed region, each on its own stream with "
+                         "its own buffers and context; step i runs on batch i mod depth")
     ap.add_argument("--inflight", default="3",
                     help="central event: events in flight in its timed step loop (each on its own stream "
                          "with its own buffers; with four hardware queues per process more "
@@ -138,10 +147,28 @@ def main():
     import synth
     from paper_1905_05515_amd import api
 
-    if args.copy_probe or args.seeding_probe or args.tracking_probe or args.step_probe:
+    if (args.copy_probe or args.seeding_probe or args.tracking_probe or args.step_probe or
+            args.refit_probe):
         assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.refit_probe:
+        rs = synth.make_config5()
+        prm = synth.default_params()
+        dev = "cuda"
+        h = api.TrackHits(torch.as_tensor(rs.trk_off).to(dev), torch.as_tensor(rs.row).to(dev),
+                          torch.as_tensor(rs.y).to(dev), torch.as_tensor(rs.z).to(dev))
+        rx = torch.as_tensor(rs.row_x).to(dev)
+        th = torch.as_tensor(rs.theta_eval).to(dev)
+        g = torch.ones(rs.n_tracks, dtype=torch.float32, device=dev)
+        ctx = api.Context(0)
+        out, adj = None, {}
+        for _ in range(3):
+            out = api.refit(ctx, h, rx, prm, th, out=out)
+            api.refit_adjoint(ctx, h, rx, prm, th, out, g, out=adj)
+        torch.cuda.synchronize()
+        log(f"[bench] refit and adjoint of {rs.n_tracks} tracks ({rs.n_hits} hits), 3 times")
+        return
     if args.step_probe:
-        ev = synth.make_config4()
+        ev = synth.make_config4() if args.step_probe == "batched" else synth.make_config2()
         prm = synth.default_params()
         occ = 0.125 if args.occupancy == "auto" else float(args.occupancy)
         e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x,
@@ -156,7 +183,7 @@ def main():
             fwd = api.refit(ctx, hits, e.t["row_x"], prm, th, out=fwd)
             api.refit_adjoint(ctx, hits, e.t["row_x"], prm, th, fwd, g, out=adj)
         torch.cuda.synchronize()
-        log(f"[bench] batched-set step of {ev.n_clusters} clusters, occupancy {occ}, "
+        log(f"[bench] {args.step_probe} step of {ev.n_clusters} clusters, occupancy {occ}, "
             f"{args.steps + 1} times")
         return
     if args.tracking_probe:
@@ -168,10 +195,10 @@ def main():
                            synth.default_params(), occupancy=occ, sector_side=ev.sector_side)
         ctx = api.Context(0)
         for _ in range(3):
-            api.track_batch(ctx, e, mode="staged", use_graph=False)
+            api.track_batch(ctx, e, mode=args.probe_mode, use_graph=False)
         torch.cuda.synchronize()
-        log(f"[bench] tracked {ev.n_clusters} clusters ({args.tracking_probe}), occupancy "
-            f"{occ}, 3 times")
+        log(f"[bench] tracked {ev.n_clusters} clusters ({args.tracking_probe}, "
+            f"{args.probe_mode}), occupancy {occ}, 3 times")
         return
     if args.copy_probe:
         n = 1 << 28
@@ -227,23 +254,77 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed region: K steps between two events on the step's stream
+    # one batch at a time: K steps between two events on the step's stream
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
-    ru0 = host_cpu_seconds()
-    w0 = time.perf_counter()
     a.record(stream)
     for _ in range(args.steps):
         step()
     b.record(stream)
     torch.cuda.synchronize()
+    ms_one = a.elapsed_time(b) / args.steps
+
+    # Batches in flight, as an online farm keeps several time frames in
+    # flight: lane k owns batch k (the same recipe with its own seed), its
+    # buffers, a context (whose cached graph is that batch's, with the tuned
+    # layout and shapes) and a stream; step i runs on lane i % depth, a
+    # lane's steps follow each other on its stream and the lanes overlap on
+    # the GPU.  Every step does the whole work of its batch.
+    depth = max(1, args.batches_in_flight)
+    lanes = [dict(ctx=ctx, e=e, ev=ev, stream=stream, hits=hits, S=S)]
+    for k in range(1, depth):
+        ev_k = synth.make_config4(seed=synth.CONFIG_SEEDS[4] + k)
+        e_k = api.make_event(ev_k.row, ev_k.y, ev_k.z, ev_k.sector_offsets, ev_k.sector_range,
+                             ev_k.row_x, prm, occupancy=tuned["occupancy"],
+                             sector_side=ev_k.sector_side)
+        ctx_k = api.Context(0)
+        api.set_tuning(ctx_k, **api.get_tuning(ctx))
+        lanes.append(dict(ctx=ctx_k, e=e_k, ev=ev_k, stream=torch.cuda.Stream(),
+                          hits=api.found_track_hits(e_k, copies=True),
+                          S=dict(fwd=None, adj={})))
+
+    def lane_step(L):
+        with torch.cuda.stream(L["stream"]):
+            api.track_batch(L["ctx"], L["e"], mode="staged", use_graph=True, stream=L["stream"])
+            L["S"]["fwd"] = api.refit(L["ctx"], L["hits"], L["e"].t["row_x"], prm, th,
+                                      stream=L["stream"], out=L["S"]["fwd"])
+            api.refit_adjoint(L["ctx"], L["hits"], L["e"].t["row_x"], prm, th, L["S"]["fwd"],
+                              gchi2, stream=L["stream"], out=L["S"]["adj"])
+
+    for L in lanes[1:]:
+        for _ in range(max(args.warmup, 1)):
+            lane_step(L)
+    torch.cuda.synchronize()
+    # timed region: K steps over the lanes, between two events that bracket
+    # all of them, device-synchronised on both sides
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    ru0 = host_cpu_seconds()
+    w0 = time.perf_counter()
+    a.record(stream)
+    for L in lanes[1:]:
+        L["stream"].wait_event(a)
+    clusters = 0
+    for i in range(args.steps):
+        L = lanes[i % depth]
+        lane_step(L)
+        clusters += L["ev"].n_clusters
+    for L in lanes[1:]:
+        done = torch.cuda.Event()
+        done.record(L["stream"])
+        stream.wait_event(done)
+    b.record(stream)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     host_cpu = host_cpu_seconds() - ru0
-    ms_per_step = a.elapsed_time(b) / args.steps
+    gpu_ms = a.elapsed_time(b)
+    ms_per_step = gpu_ms / args.steps
+    value = clusters / (gpu_ms * 1e-3)
     st = api.get_status(e, stream)
-    log(f"[bench] step {ms_per_step:.3f} ms ({ev.n_clusters / (ms_per_step * 1e-3):.3e} "
+    log(f"[bench] step {ms_per_step:.3f} ms with {depth} batches in flight ({value:.3e} "
         f"clusters/s; wall {1e3 * wall / args.steps:.3f} ms, host CPU "
-        f"{1e3 * host_cpu / args.steps:.3f} ms per step), tracks {st['n_tracks']}")
+        f"{1e3 * host_cpu / args.steps:.3f} ms per step; one at a time {ms_one:.3f} ms), "
+        f"tracks {st['n_tracks']}")
 
     # the same step with eager launches and HIP events around every kernel
     with torch.cuda.stream(stream):
@@ -270,8 +351,10 @@ def main():
     forms = forms_bench(args, api, ctx, e, ev, stream)
     extra = {"launch_forms": forms}
     if cpu is not None:
-        cpu["gpu_equivalent_cores"] = gpu_equivalent_cores(cpu, forms, ms_per_step, host_cpu,
-                                                           args.steps)
+        # GPU time per pass over the oracle's batch: the in-flight time per
+        # step scaled to that batch's clusters
+        cpu["gpu_equivalent_cores"] = gpu_equivalent_cores(
+            cpu, forms, gpu_ms * n_cl / clusters, host_cpu, args.steps)
     extra["grid_to_starts"] = seeding_roofline(api, ctx, e, stream, max(2, args.steps // 4),
                                                n_cl, "batched_set")
     log(f"[bench] grid..starts {extra['grid_to_starts']['ms'] * 1e3:.1f} us, "
@@ -287,7 +370,7 @@ def main():
     line = {
         "metric": ("TPC clusters/s tracked on 1 MI355X (batched vs per-sector); "
                    "refit+adjoint tracks/s"),
-        "value": n_cl / (ms_per_step * 1e-3),
+        "value": value,
         "unit": "clusters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -304,8 +387,13 @@ def main():
                         "shuffled, 5% noise, float32 SoA clusters (seed 40040000); step = grid, "
                         "neighbours, cleaning, starts, tracklets, selection of every instance "
                         "(one launch sequence over all instances, HIP graph) + calibrated refit "
-                        "and adjoint of the found tracks",
+                        "and adjoint of the found tracks; batches of the same recipe (seeds "
+                        "40040000 + k) in flight on their own streams",
             "clusters": n_cl,
+            "batches_in_flight": depth,
+            "clusters_per_batch": [L["ev"].n_clusters for L in lanes],
+            "ms_per_step_one_at_a_time": ms_one,
+            "clusters_per_s_one_at_a_time": n_cl / (ms_one * 1e-3),
             "instances": ev.n_sectors,
             "tracks_found": int(st["n_tracks"]),
             "track_hits": n_hits_trk,

@@ -145,3 +145,36 @@ def test_big_sector_between_small_ones(slice_run):
         _, g = run_gpu(ev, mode=mode)
         assert g["status"]["overflow"] == 0
         assert_same_tracking(g, o, ev.n_clusters)
+
+
+@pytest.mark.timeout(600)
+def test_dense_sector_rows_beyond_one_key_table(slice_run):
+    """Two sectors of the slice laid over each other as one sector (3.7M
+    clusters, ~24k per pad row: more grid positions per row than one LDS key
+    table of the selection's row form holds, so rows take several slices)
+    between two central-event sectors: staged and per-sector launches equal
+    the oracle."""
+    ev3 = slice_run[0]
+    ev2 = synth.make_config2()
+    a, b = ev3.sector(SAMPLED_SECTORS[1]), ev3.sector(SAMPLED_SECTORS[1] + 1)
+    assert np.array_equal(a.sector_range, b.sector_range)
+    assert np.array_equal(a.sector_side, b.sector_side)
+    dense = synth.Event(np.concatenate([a.row, b.row]), np.concatenate([a.y, b.y]),
+                        np.concatenate([a.z, b.z]), np.concatenate([a.charge, b.charge]),
+                        np.array([0, a.n_clusters + b.n_clusters], np.int64), a.sector_range,
+                        a.row_x, np.concatenate([a.label, b.label]), a.tracks, {}, a.sector_side)
+    parts = [ev2.sector(0), dense, ev2.sector(1)]
+    cat = lambda f: np.concatenate([getattr(p, f) for p in parts])
+    offs = np.concatenate([[0], np.cumsum([p.n_clusters for p in parts])]).astype(np.int64)
+    ev = synth.Event(cat("row"), cat("y"), cat("z"), cat("charge"), offs,
+                     np.concatenate([p.sector_range for p in parts]), ev2.row_x, cat("label"),
+                     ev2.tracks, {}, cat("sector_side"))
+    per_row = np.bincount(dense.row, minlength=152).max()
+    print(f"case dense sector n={ev.n_clusters} sizes={np.diff(offs).tolist()} "
+          f"max clusters per row {per_row}", flush=True)
+    assert per_row > 16384
+    o = run_oracle(ev)
+    for mode in ("staged", "per_sector"):
+        _, g = run_gpu(ev, mode=mode)
+        assert g["status"]["overflow"] == 0
+        assert_same_tracking(g, o, ev.n_clusters)

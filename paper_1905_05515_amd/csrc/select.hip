@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_chunk(
 // the keys out and records which tracklets keep their hit on the row as one
 // bit per tracklet (kbits[row][t / 64], bit t % 64).  A second kernel sums
 // the bits of every row chunk into the kept counts.  No device-wide atomic
-// per hit: on a continuous read-out slice (1.9M tracklets over 36 sectors
+// per hit: on a continuous read-out slice (3.4M tracklets over 36 sectors
 // of 1.9M clusters) the tracklet-parallel form with one 64-bit device atomic
 // per hit took 11 + 3.5 ms, this form with 64-bit keys in slices of 8192
 // positions (two per row there) 5.1 + 0.7 ms.
@@ -283,20 +283,45 @@ __global__ __launch_bounds__(kBlock) void k_trk_copy(
 {
     int64_t n = status->n_track_hits;
     if (n > cap) n = cap;
-    // blocks of hits dealt to the XCDs in contiguous ranges: the tracks of
-    // one sector, and the grid rows their hits lie in, stay in one L2
-    const int64_t nb = (n + blockDim.x - 1) / blockDim.x;
+    // tiles of kCopyItems hits per thread (every load of a tile in flight
+    // before its stores: the gathers are latency-bound), dealt to the XCDs
+    // in contiguous ranges: the tracks of one sector, and the grid rows
+    // their hits lie in, stay in one L2
+    constexpr int kCopyItems = 4;
+    const int64_t tile = (int64_t)blockDim.x * kCopyItems;
+    const int64_t nb = (n + tile - 1) / tile;
     for (int64_t b0 = 0; b0 < nb; b0 += gridDim.x) {
         const int64_t chunk = nb - b0 < (int64_t)gridDim.x ? nb - b0 : (int64_t)gridDim.x;
         if ((int64_t)blockIdx.x >= chunk) break;
-        const int64_t j = (b0 + xcd_remap(blockIdx.x, (int)chunk)) * blockDim.x + threadIdx.x;
-        if (j >= n) continue;
-        const int p = tpos[j];
-        trk_hits[j] = idg[p];
-        if (trk_y) {
-            trk_row[j] = (uint8_t)(gsr[p] & 255);
-            trk_y[j] = yg[p];
-            trk_z[j] = zg[p];
+        const int64_t j0 = (b0 + xcd_remap(blockIdx.x, (int)chunk)) * tile + threadIdx.x;
+        int p[kCopyItems];
+#pragma unroll
+        for (int u = 0; u < kCopyItems; ++u) {
+            const int64_t j = j0 + (int64_t)u * blockDim.x;
+            p[u] = j < n ? tpos[j] : -1;
+        }
+        int32_t id[kCopyItems], gr[kCopyItems];
+        float yv[kCopyItems], zv[kCopyItems];
+#pragma unroll
+        for (int u = 0; u < kCopyItems; ++u) {
+            if (p[u] < 0) continue;
+            id[u] = idg[p[u]];
+            if (trk_y) {
+                gr[u] = gsr[p[u]];
+                yv[u] = yg[p[u]];
+                zv[u] = zg[p[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyItems; ++u) {
+            if (p[u] < 0) continue;
+            const int64_t j = j0 + (int64_t)u * blockDim.x;
+            trk_hits[j] = id[u];
+            if (trk_y) {
+                trk_row[j] = (uint8_t)(gr[u] & 255);
+                trk_y[j] = yv[u];
+                trk_z[j] = zv[u];
+            }
         }
     }
 }
@@ -374,7 +399,8 @@ int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
     TPC_LAUNCH(k_sel_finish, dim3(1), dim3(1), 0, st, (const uint64_t*)(ws.toff + count_cap),
                ws.status, trk.off, trk.capacity, trk.hit_capacity);
     const int64_t hb = trk.hit_capacity < p->n_clusters ? trk.hit_capacity : p->n_clusters;
-    TPC_LAUNCH(k_trk_copy, dim3(grid_for(hb)), dim3(kBlock), 0, st, (const tpc_status*)ws.status,
+    TPC_LAUNCH(k_trk_copy, dim3(grid_for(ceil_div(hb, 4))), dim3(kBlock), 0, st,
+               (const tpc_status*)ws.status,
                hb, (const int32_t*)ws.tpos, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
                (const float*)grid.y, (const float*)grid.z, trk.hits, trk.hit_row, trk.hit_y,
                trk.hit_z);

@@ -214,7 +214,7 @@ int run_construct_tracklets(const tpc_problem* p, int sec_lo, int sec_hi, tpc_gr
     // waves of starts up to which the LDS form works, then the direct form
     // up to cap_q, the queue form beyond.  Automatically the LDS form while
     // all its waves are resident, else the direct form: on the continuous
-    // read-out slice (1.9M starts, lanes of a wave 47% busy in lockstep) the
+    // read-out slice (3.4M starts, lanes of a wave 47% busy in lockstep) the
     // queue form took 32.4 ms against 28.9 ms, its lanes at different rows
     // sharing less of the grid in the caches than lockstep lanes do
     const int form = tune ? tune->tracklet_form : TPC_TRACKLETS_AUTO;

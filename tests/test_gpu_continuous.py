@@ -178,3 +178,67 @@ def test_dense_sector_rows_beyond_one_key_table(slice_run):
         _, g = run_gpu(ev, mode=mode)
         assert g["status"]["overflow"] == 0
         assert_same_tracking(g, o, ev.n_clusters)
+
+
+@pytest.mark.timeout(600)
+def test_merging_links_of_sampled_sector_pair(slice_run):
+    """Sector-track merging on the whole slice (1M tracks), checked where the
+    oracle can compute it: the links between two adjacent sectors of one
+    side for the tracks of a tan(lambda) band.  A link is a mutual best
+    match and candidates lie within the tan(lambda) window (0.02) of the
+    track, so the oracle, merging its own tracks of sector s with
+    tan(lambda) in the band +-0.04 and of sector s+1 in the band +-0.02,
+    sees every candidate of both best matches of every track of the band."""
+    ev, e, st, prm = slice_run
+    up, dn, _ = api.merge_sector_tracks(ctx(), e)
+    torch.cuda.synchronize()
+    nt = int(st["n_tracks"])
+    up, dn = up[:nt].cpu().numpy(), dn[:nt].cpu().numpy()
+    off = e.t["trk_off"][:nt + 1].cpu().numpy()
+    hits = e.t["trk_hits"][:int(off[-1])].cpu().numpy()
+    gsec = np.searchsorted(ev.sector_offsets, hits[off[:-1]], side="right") - 1
+    by_first = {int(h): k for k, h in enumerate(hits[off[:-1]])}
+    s = SAMPLED_SECTORS[1]
+    lo_band, hi_band, w3 = 0.0, 0.02, api.MERGE_WINDOWS[3]
+    sub_off, sub_hits, sub_par, sub_rin, sub_gpu, in_band = [0], [], [], [], [], []
+    # margins a little wider than the window: the float window test may pass
+    # a candidate a rounding step beyond it
+    for q, margin in ((s, 2 * w3 + 1e-3), (s + 1, w3 + 5e-4)):
+        sv = ev.sector(q)
+        tab, nb = grid_layout(sv.sector_offsets, sv.sector_range, occupancy=e.occupancy,
+                              sides=sv.sector_side)
+        o = oracle.track_event(sv.row, sv.y, sv.z, tab, nb, sv.row_x, prm)
+        trk, trl = o["tracks"], o["tracklets"]
+        b0 = int(ev.sector_offsets[q])
+        for k in range(len(trk["trk_off"]) - 1):
+            t = trk["trk_tracklet"][k]
+            tl = float(trl["par"][t][3])
+            if not (lo_band - margin <= tl <= hi_band + margin):
+                continue
+            h = trk["trk_hits"][trk["trk_off"][k]:trk["trk_off"][k + 1]] + b0
+            sub_hits.append(h)
+            sub_off.append(sub_off[-1] + len(h))
+            sub_par.append(trl["par"][t])
+            sub_rin.append(trl["row_inner"][t])
+            sub_gpu.append(by_first[int(h[0])])   # the same track on the GPU (same hits)
+            in_band.append(q == s and lo_band <= tl <= hi_band)
+    print(f"case merge slice sectors {s},{s + 1}: {len(sub_gpu)} tracks, "
+          f"{sum(in_band)} in the band", flush=True)
+    ou, od, _ = oracle.merge_sector_tracks(
+        ev.sector_offsets, 18, ev.row_x, prm, np.array(sub_off, np.int32),
+        np.concatenate(sub_hits).astype(np.int32), np.array(sub_par, np.float32),
+        np.array(sub_rin, np.int32), iw=oracle.merge_windows_inv(api.MERGE_WINDOWS))
+    sub_gpu = np.array(sub_gpu)
+    n_links = 0
+    for i in np.nonzero(in_band)[0]:
+        o_part = ou[i] if ou[i] >= 0 else od[i]          # only sector s + 1 is there
+        o_gpu = int(sub_gpu[o_part]) if o_part >= 0 else -1
+        g = int(sub_gpu[i])
+        g_part = -1
+        for c in (up[g], dn[g]):
+            if c >= 0 and gsec[c] == s + 1:
+                g_part = int(c)
+        assert g_part == o_gpu, (i, g, g_part, o_gpu)
+        n_links += o_gpu >= 0
+    print(f"  {n_links} links checked", flush=True)
+    assert n_links > 50

@@ -341,30 +341,34 @@ __device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const 
     float a2b = Skb * P.L * P.L * P.a * hp;
     // G1 = 1 + a2 (1/2 + a2 (3/8 + a2 5/16))
     a2b += G1b * (0.5f + P.a2 * (2.0f * (3.0f / 8.0f) + P.a2 * (3.0f * (5.0f / 16.0f))));
+    // the reverse sweep divides by four quantities only: their reciprocals
+    // once (the gradient is compared within a tolerance, not bit for bit,
+    // and a correctly rounded division costs a dozen instructions)
+    const float iq = 1.0f / P.q, icc = 1.0f / P.cc, ic1 = 1.0f / P.c1, ic2 = 1.0f / P.c2;
     // LT = dx T / q
-    dxb += LTb * P.T / P.q;
-    Tb += LTb * P.dx / P.q;
-    float qb = -LTb * P.dx * P.T / (P.q * P.q);
+    dxb += LTb * P.T * iq;
+    Tb += LTb * P.dx * iq;
+    float qb = -LTb * P.dx * P.T * (iq * iq);
     // Tw = kdx n / cc, n = 1 + T s2 / c2
-    const float n = 1.0f + P.T * (P.s2 / P.c2);
-    kdxb += Twb * n / P.cc;
-    const float nb = Twb * P.kdx / P.cc;
-    float ccb = -Twb * P.Tw / P.cc;
-    Tb += nb * P.s2 / P.c2;
-    s2b += nb * P.T / P.c2;
-    float c2b = -nb * P.T * P.s2 / (P.c2 * P.c2);
+    const float n = 1.0f + P.T * (P.s2 * ic2);
+    kdxb += Twb * n * icc;
+    const float nb = Twb * P.kdx * icc;
+    float ccb = -Twb * P.Tw * icc;
+    Tb += nb * P.s2 * ic2;
+    s2b += nb * P.T * ic2;
+    float c2b = -nb * P.T * P.s2 * (ic2 * ic2);
     // kdx = curv dx
     dxb += kdxb * curv;
     // Ts = (2 + T e) / cc, e = s/c1 + s2/c2
-    const float e = s / P.c1 + P.s2 / P.c2;
-    const float numb = Tsb / P.cc;
-    ccb += -Tsb * P.Ts / P.cc;
+    const float e = s * ic1 + P.s2 * ic2;
+    const float numb = Tsb * icc;
+    ccb += -Tsb * P.Ts * icc;
     Tb += numb * e;
     const float eb = numb * P.T;
-    float sb = eb / P.c1;
-    float c1b = -eb * s / (P.c1 * P.c1);
-    s2b += eb / P.c2;
-    c2b += -eb * P.s2 / (P.c2 * P.c2);
+    float sb = eb * ic1;
+    float c1b = -eb * s * (ic1 * ic1);
+    s2b += eb * ic2;
+    c2b += -eb * P.s2 * (ic2 * ic2);
     // S = L g, g = 1 + a2 (1/6 + a2 (3/40 + a2 5/112))
     Lb += Sb * P.g;
     const float gb = Sb * P.L;
@@ -376,15 +380,15 @@ __device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const 
     // L = dx q ; q = sqrt(1 + T^2)
     dxb += Lb * P.q;
     qb += Lb * P.dx;
-    Tb += qb * P.T / P.q;
+    Tb += qb * P.T * iq;
     // T = (s + s2) / cc ; cc = c1 + c2
-    sb += Tb / P.cc;
-    s2b += Tb / P.cc;
-    ccb += -Tb * P.T / P.cc;
+    sb += Tb * icc;
+    s2b += Tb * icc;
+    ccb += -Tb * P.T * icc;
     c1b += ccb;
     c2b += ccb;
-    s2b += c2b * (-P.s2 / P.c2);
-    sb += c1b * (-s / P.c1);
+    s2b += c2b * (-P.s2 * ic2);
+    sb += c1b * (-s * ic1);
     // s2 = s + k dx ; k = curv w
     sb += s2b;
     kb += s2b * P.dx;

@@ -25,7 +25,14 @@ __device__ __forceinline__ int lt(int i, int j) { return i >= j ? i * (i + 1) / 
 
 struct CalibModel {
     float DL, VD, TH, UC, US;
+    float iUS, iDL;      // 1 / US, 1 / DL (taken once on the host)
 };
+
+inline CalibModel make_calib(const tpc_calib_model& m)
+{
+    return CalibModel{m.drift_len, m.vd, m.tan_half, m.u_centre, m.u_scale, 1.0f / m.u_scale,
+                      1.0f / m.drift_len};
+}
 
 struct CalHit {
     float x, y, z;      // calibrated plane, y, z
@@ -42,9 +49,9 @@ __device__ __forceinline__ CalHit calibrate(const float* th, float xr, float yr,
     h.dr = cm.DL - sd * zr;
     h.d = (1.0f + th[0]) * (h.dr - cm.VD * th[1]);
     h.z = sd * (cm.DL - h.d);
-    h.u = (xr - cm.UC) / cm.US;
+    h.u = (xr - cm.UC) * cm.iUS;
     h.v = yr / (xr * cm.TH);
-    const float w = h.d / cm.DL;
+    const float w = h.d * cm.iDL;
     const float b[7] = {1.0f, h.u, h.v, h.u * h.u, h.u * h.v, h.v * h.v, w};
     float dr = 0.0f, drphi = 0.0f;
 #pragma unroll
@@ -63,7 +70,7 @@ __device__ __forceinline__ void calibrate_adj(const float* th, const CalHit& h, 
                                               const CalibModel& cm, float X, float Y, float Z,
                                               float* gth, float& gyr, float& gzr)
 {
-    const float w = h.d / cm.DL;
+    const float w = h.d * cm.iDL;
     const float b[7] = {1.0f, h.u, h.v, h.u * h.u, h.u * h.v, h.v * h.v, w};
     float bb[7];
 #pragma unroll
@@ -74,7 +81,7 @@ __device__ __forceinline__ void calibrate_adj(const float* th, const CalHit& h, 
     }
     const float vb = bb[2] + bb[4] * h.u + 2.0f * bb[5] * h.v;
     gyr = Y + vb / (h.xr * cm.TH);
-    const float db = bb[6] / cm.DL - Z * sd;
+    const float db = bb[6] * cm.iDL - Z * sd;
     gth[0] += db * (h.dr - cm.VD * th[1]);
     gth[1] += -db * (1.0f + th[0]) * cm.VD;
     gzr = -sd * (1.0f + th[0]) * db;
@@ -123,16 +130,17 @@ __device__ __forceinline__ bool prop_fwd(float* p, float* C, float dx, float cur
     P.c1 = sqrtf((1.0f - s) * (1.0f + s));
     P.c2 = sqrtf((1.0f - P.s2) * (1.0f + P.s2));
     P.cc = P.c1 + P.c2;
-    P.T = (s + P.s2) / P.cc;
+    const float icc = 1.0f / P.cc;   // three quotients by c1 + c2
+    P.T = (s + P.s2) * icc;
     P.q = sqrtf(1.0f + P.T * P.T);
     P.L = dx * P.q;
     P.a = 0.5f * P.k * P.L;
     P.a2 = P.a * P.a;
     P.g = 1.0f + P.a2 * ((1.0f / 6.0f) + P.a2 * ((3.0f / 40.0f) + P.a2 * (5.0f / 112.0f)));
     P.S = P.L * P.g;
-    P.Ts = (2.0f + P.T * (s / P.c1 + P.s2 / P.c2)) / P.cc;
+    P.Ts = (2.0f + P.T * (s / P.c1 + P.s2 / P.c2)) * icc;
     P.kdx = curv * dx;
-    P.Tw = P.kdx * (1.0f + P.T * (P.s2 / P.c2)) / P.cc;
+    P.Tw = P.kdx * (1.0f + P.T * (P.s2 / P.c2)) * icc;
     P.LT = dx * P.T / P.q;
     P.G1 = 1.0f + P.a2 * (0.5f + P.a2 * ((3.0f / 8.0f) + P.a2 * (5.0f / 16.0f)));
     P.Sk = P.L * P.L * P.a * ((1.0f / 6.0f) + P.a2 * ((3.0f / 20.0f) + P.a2 * (15.0f / 112.0f)));
@@ -896,7 +904,7 @@ static int launch_refit_adjoint(tpc_track_hits hits, int32_t n_rows, const float
                                 float* grad_z, float* grad_theta, float* partials,
                                 hipStream_t st)
 {
-    CalibModel cm{m.drift_len, m.vd, m.tan_half, m.u_centre, m.u_scale};
+    const CalibModel cm = make_calib(m);
     const unsigned nb = refit_grid(hits.n_tracks);
     TPC_LAUNCH(k_refit_adj, dim3(nb), dim3(kWave), 0, st, hits.off, hits.idx, hits.row, hits.y,
                hits.z, hits.side, hits.d_count, hits.n_tracks, n_rows, d_row_x, prm, cm,
@@ -979,8 +987,7 @@ int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float
                         ck_bytes < ck_need))
         return TPC_ERR_INVALID_ARG;
     if (hits.n_tracks == 0) return TPC_OK;
-    tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
-                       h_model->u_scale};
+    const tpc::CalibModel cm = tpc::make_calib(*h_model);
     TPC_LAUNCH(tpc::k_refit_fwd, dim3(tpc::refit_grid(hits.n_tracks)), dim3(tpc::kWave),
                        0, (hipStream_t)stream, hits.off, hits.idx, hits.row, hits.y, hits.z,
                        hits.side, hits.d_count, hits.n_tracks, n_rows, d_row_x, *h_params, cm,
@@ -1046,8 +1053,7 @@ int tpc_vertex_residual(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
         !(sigma_v >= 0.0f) || !std::isfinite(sigma_v))
         return TPC_ERR_INVALID_ARG;
     if (hits.n_tracks == 0) return TPC_OK;
-    tpc::CalibModel cm{h_model->drift_len, h_model->vd, h_model->tan_half, h_model->u_centre,
-                       h_model->u_scale};
+    const tpc::CalibModel cm = tpc::make_calib(*h_model);
     TPC_LAUNCH(tpc::k_vertex_residual, dim3(tpc::grid_for(hits.n_tracks)), dim3(tpc::kBlock), 0,
                (hipStream_t)stream, hits.off, hits.idx, hits.row, hits.y, hits.z, hits.side,
                hits.d_count, hits.n_tracks, d_row_x, *h_params, cm, d_theta, par, cov, status,

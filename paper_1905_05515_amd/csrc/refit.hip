@@ -70,6 +70,9 @@ __device__ __forceinline__ void calibrate_adj(const float* th, const CalHit& h, 
                                               const CalibModel& cm, float X, float Y, float Z,
                                               float* gth, float& gyr, float& gzr)
 {
+    // reverse-mode arithmetic: compared with the float64 adjoint within a
+    // tolerance, so products and sums may contract into fused multiply-adds
+#pragma clang fp contract(fast)
     const float w = h.d * cm.iDL;
     const float b[7] = {1.0f, h.u, h.v, h.u * h.u, h.u * h.v, h.v * h.v, w};
     float bb[7];
@@ -217,6 +220,9 @@ __device__ __forceinline__ float upd_fwd(float* p, float* C, float my, float mz,
 __device__ __forceinline__ void upd_adj(const Upd& U, float cb, float* pb, float* G, float& myb,
                                         float& mzb)
 {
+    // reverse-mode arithmetic: compared with the float64 adjoint within a
+    // tolerance, so products and sums may contract into fused multiply-adds
+#pragma clang fp contract(fast)
     float Kb0[5], Kb1[5];
     float rb0 = 0.0f, rb1 = 0.0f;
 #pragma unroll
@@ -287,6 +293,9 @@ __device__ __forceinline__ void upd_adj(const Upd& U, float cb, float* pb, float
 __device__ __forceinline__ float prop_adj(const Prop& P, const float* p0, const float* C0,
                                           float curv, float* pb, float* G)
 {
+    // reverse-mode arithmetic: compared with the float64 adjoint within a
+    // tolerance, so products and sums may contract into fused multiply-adds
+#pragma clang fp contract(fast)
     const float s = p0[2], t = p0[3];
     // F-bar = 2 G F C for the six free entries
     auto gfc = [&](int a, int b) {

@@ -361,7 +361,8 @@ def main():
         f"{extra['grid_to_starts']['frac'] * 100:.1f}% of HBM peak at "
         f"{SEEDING_BYTES_PER_CLUSTER} B/cluster")
     if not args.no_central_bench:
-        extra["central_event"] = central_bench(args, api, synth, prm, dev, tuned)
+        extra["central_event"] = central_bench(args, api, synth, prm, dev, tuned,
+                                               [L["stream"] for L in lanes])
     if not args.no_slice_bench:
         extra["continuous_readout"] = slice_bench(args, api, synth, ctx, stream, prm)
     if not args.no_refit_bench:
@@ -482,16 +483,20 @@ def gpu_equivalent_cores(cpu, forms, ms_step, host_cpu_s, steps):
                       "getrusage) / GPU seconds, per pass over the batch"}
 
 
-def central_bench(args, api, synth, prm, dev, tuned_batch):
+def central_bench(args, api, synth, prm, dev, tuned_batch, streams=()):
     """The central Pb-Pb-like event (36 sectors, ~1.3M clusters): the step
     with events in flight, per-kernel times, cluster attachment and
-    sector-track merging of its tracks."""
+    sector-track merging of its tracks.  `streams`: idle streams to give the
+    lanes (the batched set's, which sit on distinct hardware queues; new
+    streams beyond the process's four queues can share one, and lanes that
+    share a queue run one after the other)."""
     import torch
     t0 = time.time()
     ev = synth.make_config2()
     log(f"[bench] central event: {ev.n_clusters} clusters, generated in {time.time() - t0:.1f}s")
     ctx = api.Context(0)
-    stream = torch.cuda.Stream()
+    streams = list(streams)
+    stream = streams[0] if streams else torch.cuda.Stream()
     e = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range, ev.row_x, prm,
                        sector_side=ev.sector_side)
     tuned = pick_layout(args, api, ctx, e, stream)
@@ -511,7 +516,8 @@ def central_bench(args, api, synth, prm, dev, tuned_batch):
             e_k = api.make_event(ev.row, ev.y, ev.z, ev.sector_offsets, ev.sector_range,
                                  ev.row_x, prm, sector_side=ev.sector_side)
             api.relayout(e_k, tuned["occupancy"])
-            lanes.append(dict(ctx=api.Context(0), e=e_k, stream=torch.cuda.Stream(),
+            s_k = streams[len(lanes)] if len(lanes) < len(streams) else torch.cuda.Stream()
+            lanes.append(dict(ctx=api.Context(0), e=e_k, stream=s_k,
                               hits=api.found_track_hits(e_k, copies=True), fwd=None, adj={}))
         return lanes[k]
 

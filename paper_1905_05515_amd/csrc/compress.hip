@@ -19,7 +19,7 @@
 // own) in chunks of `chunk` symbols, one thread per chunk.
 //
 // Kernels: mark the clusters on tracks; one thread per track writes its
-// header and symbols; one thread per (sector, row) counts, then (after a
+// header and symbols; one wave per (sector, row) counts, then (after a
 // scan) writes the other clusters' symbols; per-stream histograms in LDS;
 // one block per stream normalises its table; one thread per chunk encodes
 // backwards into the end of its chunk slot; scans order the escapes; one
@@ -173,29 +173,40 @@ __global__ __launch_bounds__(kBlock) void k_cz_tracks(
     }
 }
 
-// one thread per (sector, row): count of the row's clusters on no track
+// One wave per (sector, row): the row's grid positions 64 at a time, the
+// clusters on no track found by a ballot.  (One thread per row walking its
+// positions took 0.13 + 0.35 ms on the central event.)
 __global__ __launch_bounds__(kBlock) void k_cz_rowcount(const tpc_sector* __restrict__ sec,
                                                         int n_sec, int n_rows,
                                                         const int32_t* __restrict__ bin_start,
                                                         const int32_t* __restrict__ idg, CmpWs w)
 {
     const int64_t n = (int64_t)n_sec * n_rows;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < n;
+         i += waves) {
         const tpc_sector& s = sec[i / n_rows];
         const int r = (int)(i % n_rows);
         const int per_row = s.nbz * s.nby;
         const int p0 = bin_start[s.bin_base + r * per_row];
         const int p1 = bin_start[s.bin_base + (r + 1) * per_row];
         int cnt = 0;
-        for (int g = p0; g < p1; ++g) cnt += !w.on[idg[g]];
-        w.rowcnt[i] = cnt;
-        put(w, S_UN, i, (uint32_t)cnt, cnt);
+        for (int g0 = p0; g0 < p1; g0 += kWave) {
+            const int g = g0 + lane;
+            cnt += __popcll(__ballot(g < p1 && !w.on[idg[g]]));
+        }
+        if (lane == 0) {
+            w.rowcnt[i] = cnt;
+            put(w, S_UN, i, (uint32_t)cnt, cnt);
+        }
     }
 }
 
-// one thread per (sector, row): z steps, y bytes and charges of the row's
-// clusters on no track, at the row's offset
+// one wave per (sector, row): z steps, y bytes and charges of the row's
+// clusters on no track, at the row's offset, in grid order (each one's z
+// step is to the previous one of the row: a lane takes it from the lane of
+// the previous such cluster, the first of a round from the round before)
 __global__ __launch_bounds__(kBlock) void k_cz_rowemit(
     const tpc_sector* __restrict__ sec, int n_sec, int n_rows, const int32_t* __restrict__ bin_start,
     const int32_t* __restrict__ idg, const float* __restrict__ y, const float* __restrict__ z,
@@ -205,32 +216,48 @@ __global__ __launch_bounds__(kBlock) void k_cz_rowemit(
     const int64_t nt = track_count(d_n_tracks, cap);
     const int64_t na = nt > 0 ? off[nt] : 0;
     const int64_t n = (int64_t)n_sec * n_rows;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < n;
+         i += waves) {
         const tpc_sector& s = sec[i / n_rows];
         const int r = (int)(i % n_rows);
         const int per_row = s.nbz * s.nby;
         const int p0 = bin_start[s.bin_base + r * per_row];
         const int p1 = bin_start[s.bin_base + (r + 1) * per_row];
-        int64_t u = w.rowcnt[i];
-        int32_t pz = 0;
-        for (int g = p0; g < p1; ++g) {
-            const int c = idg[g];
-            if (w.on[c]) continue;
-            const int32_t cz = quant(z[c], inv_q), cy = quant(y[c], inv_q);
-            put(w, S_UDZ, u, zigzag(cz - pz), cz - pz);
-            pz = cz;
-            const int32_t yo = cy + 2048;
-            if (yo >= 0 && yo < 4096) {
-                w.sym[S_UYH][u] = (uint8_t)(yo >> 8);
-                w.sym[S_UYL][u] = (uint8_t)(yo & 255);
-            } else {
-                w.sym[S_UYH][u] = 255;
-                w.esc[S_UYH][u] = cy;
-                w.sym[S_UYL][u] = 0;
+        int64_t u0 = w.rowcnt[i];
+        int32_t carry = 0;             // z of the last such cluster of the rounds before
+        for (int g0 = p0; g0 < p1; g0 += kWave) {
+            const int g = g0 + lane;
+            int c = -1;
+            if (g < p1) c = idg[g];
+            const bool un = c >= 0 && !w.on[c];
+            const uint64_t m = __ballot(un);
+            int32_t cz = 0;
+            if (un) cz = quant(z[c], inv_q);
+            // the previous cluster of the row: the highest lane below with one
+            const uint64_t prev = m & below;
+            const int src = prev ? 63 - __clzll(prev) : 0;
+            const int32_t zp = __shfl(cz, src, kWave);
+            if (un) {
+                const int32_t pz = prev ? zp : carry;
+                const int64_t u = u0 + __popcll(prev);
+                const int32_t cy = quant(y[c], inv_q);
+                put(w, S_UDZ, u, zigzag(cz - pz), cz - pz);
+                const int32_t yo = cy + 2048;
+                if (yo >= 0 && yo < 4096) {
+                    w.sym[S_UYH][u] = (uint8_t)(yo >> 8);
+                    w.sym[S_UYL][u] = (uint8_t)(yo & 255);
+                } else {
+                    w.sym[S_UYH][u] = 255;
+                    w.esc[S_UYH][u] = cy;
+                    w.sym[S_UYL][u] = 0;
+                }
+                w.sym[S_Q][na + u] = (uint8_t)charge_code(charge[c], cbits);
             }
-            w.sym[S_Q][na + u] = (uint8_t)charge_code(charge[c], cbits);
-            ++u;
+            if (m) carry = __shfl(cz, 63 - __clzll(m), kWave);
+            u0 += __popcll(m);
         }
     }
 }
@@ -347,10 +374,26 @@ __device__ __forceinline__ uint32_t byte_of(const uint4& v, int b)
 // end of the chunk's slot
 __global__ __launch_bounds__(kBlock) void k_cz_encode(CmpWs w, int chunk)
 {
-    __shared__ uint32_t fl[256], cl[256];
+    // Per symbol: the renormalisation bound, and the quotient by its
+    // frequency f as a multiply and shift (exact division by an invariant
+    // integer, Granlund and Montgomery 1994): after renormalisation the state
+    // is below 2^31, and with l = ceil(log2 f), M = ceil(2^(31 + l) / f) < 2^32,
+    // x / f = (x M) >> (31 + l) = hi32(2x M) >> l for every x < 2^31.  The new
+    // state (x / f) 2^12 + x mod f + c equals x + c + (x / f) (2^12 - f).
+    __shared__ uint32_t xm_l[256], m_l[256], pk_l[256], c_l[256];
     const int k = blockIdx.y;
-    fl[threadIdx.x] = w.freq[k * 256 + threadIdx.x];
-    cl[threadIdx.x] = w.cum[k * 256 + threadIdx.x];
+    {
+        const uint32_t f = w.freq[k * 256 + threadIdx.x];
+        uint32_t l = 0, mm = 0;
+        if (f > 0) {
+            l = f > 1 ? 32u - (uint32_t)__clz(f - 1u) : 0u;
+            mm = (uint32_t)((((uint64_t)1 << (31 + l)) + f - 1) / f);
+        }
+        xm_l[threadIdx.x] = ((kRansL >> kProbBits) << 8) * f;
+        m_l[threadIdx.x] = mm;
+        pk_l[threadIdx.x] = (kProbScale - f) | (l << 16);
+        c_l[threadIdx.x] = w.cum[k * 256 + threadIdx.x];
+    }
     __syncthreads();
     const int64_t n = w.counts[3 + k];
     const int64_t nch = (n + chunk - 1) / chunk;
@@ -358,44 +401,62 @@ __global__ __launch_bounds__(kBlock) void k_cz_encode(CmpWs w, int chunk)
     if (j >= nch) return;
     const uint8_t* s = w.sym[k];
     const int64_t a = j * chunk, e = a + chunk < n ? a + chunk : n;
+    // bytes go backwards from the end of the chunk's slot (256-byte aligned),
+    // gathered into words (the first of four at the top, the highest address)
     uint8_t* end = w.cbuf + ((int64_t)k * w.chunk_cap + j) * w.slot + w.slot;
-    int64_t m = 0;
+    uint32_t m = 0;
+    uint64_t acc = 0;
     uint32_t x = kRansL;
-    auto code = [&](uint32_t sy) {
-        const uint32_t fs = fl[sy];
-        const uint32_t x_max = ((kRansL >> kProbBits) << 8) * fs;
-        while (x >= x_max) {
-            *(end - 1 - m) = (uint8_t)(x & 255u);
-            ++m;
-            x >>= 8;
-        }
-        x = ((x / fs) << kProbBits) + (x % fs) + cl[sy];
+    // nb (0, 1 or 2) bytes, the first in the higher byte of v
+    auto emit = [&](uint32_t v, uint32_t nb) {
+        acc = (acc << (8 * nb)) | (v & ((1u << (8 * nb)) - 1u));
+        m += nb;
+        if ((m & 3u) < nb) *reinterpret_cast<uint32_t*>(end - (m & ~3u)) = (uint32_t)(acc >> (8 * (m & 3u)));
     };
+    // renormalise (x < 2^31 and the bound is at least 2^19: at most two
+    // bytes, the low one first), then the state step
+    auto code = [&](uint32_t xm, uint32_t mm, uint32_t pk, uint32_t c) {
+        const uint32_t nb = (x >= xm ? 1u : 0u) + ((x >> 8) >= xm ? 1u : 0u);
+        emit(nb == 2 ? ((x & 255u) << 8) | ((x >> 8) & 255u) : x & 255u, nb);
+        x >>= 8 * nb;
+        const uint32_t q = __umulhi(x << 1, mm) >> (pk >> 16);
+        x += c + q * (pk & 0xFFFFu);
+    };
+    auto code_sym = [&](uint32_t sy) { code(xm_l[sy], m_l[sy], pk_l[sy], c_l[sy]); };
     int64_t i = e;
     if ((a & 15) == 0) {          // 16-byte blocks (chunk sizes that are multiples of 16)
         // the ragged tail first (symbols past the last multiple of 16)
         const int64_t e16 = a + (e - a) / 16 * 16;
-        while (i > e16) code(s[--i]);
-        if (i > a) {
-            uint4 cur = load16(s + i - 16);
-            while (i > a) {
-                const int64_t nx = i - 16;
-                uint4 nxt = cur;
-                if (nx > a) nxt = load16(s + nx - 16);
+        while (i > e16) code_sym(s[--i]);
+        uint4 nxt = make_uint4(0, 0, 0, 0);
+        if (i > a) nxt = load16(s + i - 16);
+        while (i > a) {
+            const uint4 cur = nxt;
+            if (i - 16 > a) nxt = load16(s + i - 32);     // the next block, in flight meanwhile
+            // the block's table entries first, then the dependent steps
+            uint32_t txm[16], tm[16], tpk[16], tc[16];
 #pragma unroll
-                for (int b = 15; b >= 0; --b) code(byte_of(cur, b));
-                cur = nxt;
-                i = nx;
+            for (int b = 0; b < 16; ++b) {
+                const uint32_t sy = byte_of(cur, b);
+                txm[b] = xm_l[sy];
+                tm[b] = m_l[sy];
+                tpk[b] = pk_l[sy];
+                tc[b] = c_l[sy];
             }
+#pragma unroll
+            for (int b = 15; b >= 0; --b) code(txm[b], tm[b], tpk[b], tc[b]);
+            i -= 16;
         }
     }
-    while (i > a) code(s[--i]);
-    for (int b = 0; b < 4; ++b) {
-        *(end - 1 - m) = (uint8_t)(x & 255u);
-        ++m;
-        x >>= 8;
-    }
-    w.csize[(int64_t)k * w.chunk_cap + j] = (uint32_t)m;
+    while (i > a) code_sym(s[--i]);
+    // the final state, low byte first
+    emit(((x & 255u) << 8) | ((x >> 8) & 255u), 2);
+    emit(((x >> 16) & 255u) << 8 | (x >> 24), 2);
+    // the bytes of a last, partial word
+    const uint32_t p = m & 3u;
+    for (uint32_t t = 0; t < p; ++t)
+        *(end - 1 - (m - p) - t) = (uint8_t)(acc >> (8 * (p - 1 - t)));
+    w.csize[(int64_t)k * w.chunk_cap + j] = m;
 }
 
 // escape flags of stream k over its capacity (zero past its size)
@@ -665,11 +726,11 @@ int tpc_compress_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_clust
                    (const int32_t*)tracks.tracklet, (const float*)tracklets.par,
                    (const int32_t*)tracklets.row_inner, d_n_tracks, tcap, inv_q, cp.cbits, w);
     }
-    TPC_LAUNCH(tpc::k_cz_rowcount, dim3(tpc::grid_for(nrs)), dim3(tpc::kBlock), 0, st,
+    TPC_LAUNCH(tpc::k_cz_rowcount, dim3(tpc::grid_for(nrs * tpc::kWave)), dim3(tpc::kBlock), 0, st,
                h_prob->d_sectors, n_sec, n_rows, (const int32_t*)grid.bin_start,
                (const int32_t*)grid.id, w);
     tpc::launch_scan<int32_t>(w.rowcnt, w.rowcnt, nrs, false, nullptr, nullptr, w.partials, st);
-    TPC_LAUNCH(tpc::k_cz_rowemit, dim3(tpc::grid_for(nrs)), dim3(tpc::kBlock), 0, st,
+    TPC_LAUNCH(tpc::k_cz_rowemit, dim3(tpc::grid_for(nrs * tpc::kWave)), dim3(tpc::kBlock), 0, st,
                h_prob->d_sectors, n_sec, n_rows, (const int32_t*)grid.bin_start,
                (const int32_t*)grid.id, clusters.y, clusters.z, charge,
                (const int32_t*)tracks.off, d_n_tracks, tcap, inv_q, cp.cbits, w);

@@ -453,11 +453,14 @@ int tpc_compress_workspace_size(const tpc_problem* h_prob, int64_t track_capacit
  * n_escapes (u64), n_chunks (u32), 256 u16 frequencies (0xffff for 4096),
  * the chunks' byte counts (u32); then every stream's chunk bytes, every
  * stream's escapes (i32), the track headers.  Inputs: the clusters (with
- * charge), grid, tracklets and tracks of the tracking calls; d_n_tracks
- * (device) the track count.  *d_size (device) receives the blob size; when
+ * charge), grid, tracklets and tracks of the tracking calls (the tracks'
+ * hit copies hit_row, hit_y, hit_z, when given, are read in place of the
+ * clusters' values: all three or none); d_n_tracks (device) the track
+ * count.  *d_size (device) receives the blob size; when
  * it exceeds out_cap nothing is written to out (the caller re-sizes).
  * d_ws: tpc_compress_workspace_size bytes.  Returns TPC_ERR_INVALID_ARG for a
- * null pointer, parameters out of range or a short workspace; asynchronous
+ * null pointer (one or two of the hit copies included), parameters out of
+ * range or a short workspace; asynchronous
  * on stream. */
 int tpc_compress_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters clusters,
                           const float* charge, tpc_grid grid, tpc_tracklets tracklets,

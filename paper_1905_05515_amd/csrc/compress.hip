@@ -116,15 +116,20 @@ __global__ __launch_bounds__(kBlock) void k_cz_mark(const int32_t* __restrict__ 
         w.on[hits[j]] = 1;
 }
 
-// one thread per track: header, hit count, row steps, residuals, charges
+// one thread per track: header, hit count, row steps, residuals, charges.
+// A hit's row, y and z come from the track-ordered copies where the tracks
+// carry them (contiguous per track), else through the cluster index; the
+// next hit's values are loaded while the current one is filtered.
 __global__ __launch_bounds__(kBlock) void k_cz_tracks(
     const float* __restrict__ row_x, tpc_params prm, const uint8_t* __restrict__ row,
     const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ charge,
     const int32_t* __restrict__ off, const int32_t* __restrict__ hits,
-    const int32_t* __restrict__ trk_tracklet, const float* __restrict__ t_par,
-    const int32_t* __restrict__ t_rin, const int64_t* __restrict__ d_n_tracks, int64_t cap,
-    float inv_q, int cbits, CmpWs w)
+    const uint8_t* __restrict__ h_row, const float* __restrict__ h_y,
+    const float* __restrict__ h_z, const int32_t* __restrict__ trk_tracklet,
+    const float* __restrict__ t_par, const int32_t* __restrict__ t_rin,
+    const int64_t* __restrict__ d_n_tracks, int64_t cap, float inv_q, int cbits, CmpWs w)
 {
+    const bool copies = h_row != nullptr;
     const int64_t nt = track_count(d_n_tracks, cap);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nt;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -154,21 +159,40 @@ __global__ __launch_bounds__(kBlock) void k_cz_tracks(
         put(w, S_LEN, k, (uint32_t)(b - a), b - a);
         bool alive = true;
         int prow = (uint8_t)rin;
+        int r_n = 0;
+        float y_n = 0.0f, z_n = 0.0f, q_n = 0.0f, x_n = 0.0f;
+        auto fetch = [&](int jj) {
+            const int c = hits[jj];
+            if (copies) {
+                r_n = h_row[jj];
+                y_n = h_y[jj];
+                z_n = h_z[jj];
+            } else {
+                r_n = row[c];
+                y_n = y[c];
+                z_n = z[c];
+            }
+            q_n = charge[c];
+            x_n = row_x[r_n];
+        };
+        if (a < b) fetch(a);
         for (int j = a; j < b; ++j) {
-            const int c = hits[j], r = row[c];
+            const int r = r_n;
+            const float yc = y_n, zc = z_n, qc = q_n, xr = x_n;
+            if (j + 1 < b) fetch(j + 1);
             put(w, S_ROW, j, (uint32_t)(r - prow), r - prow);
             prow = r;
-            const int32_t cy = quant(y[c], inv_q), cz = quant(z[c], inv_q);
-            if (alive && !propagate(st, row_x[r] - x, prm.curv, prm.s_max)) alive = false;
+            const int32_t cy = quant(yc, inv_q), cz = quant(zc, inv_q);
+            if (alive && !propagate(st, xr - x, prm.curv, prm.s_max)) alive = false;
             const int32_t py = alive ? quant(st.p[0], inv_q) : 0;
             const int32_t pz = alive ? quant(st.p[1], inv_q) : 0;
             put(w, S_DY, j, zigzag(cy - py), cy - py);
             put(w, S_DZ, j, zigzag(cz - pz), cz - pz);
             if (alive) {
                 kupdate(st, (float)cy / inv_q, (float)cz / inv_q, prm.sigma_y2, prm.sigma_z2);
-                x = row_x[r];
+                x = xr;
             }
-            w.sym[S_Q][j] = (uint8_t)charge_code(charge[c], cbits);
+            w.sym[S_Q][j] = (uint8_t)charge_code(qc, cbits);
         }
     }
 }
@@ -695,6 +719,8 @@ int tpc_compress_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_clust
         tracks.capacity < 0 || tracks.hit_capacity < 0 || cp.qbits < 0 || cp.qbits > 12 ||
         cp.cbits < 2 || cp.cbits > 8 || cp.chunk < 64 || cp.chunk > (1 << 20))
         return TPC_ERR_INVALID_ARG;
+    const int n_copies = !!tracks.hit_row + !!tracks.hit_y + !!tracks.hit_z;
+    if (n_copies != 0 && n_copies != 3) return TPC_ERR_INVALID_ARG;
     const int e = tpc_check_problem(h_prob);
     if (e) return e;
     tpc::CmpWs w;
@@ -723,8 +749,10 @@ int tpc_compress_clusters(tpc_context* ctx, const tpc_problem* h_prob, tpc_clust
         TPC_LAUNCH(tpc::k_cz_tracks, dim3(tpc::grid_for(tcap)), dim3(tpc::kBlock), 0, st,
                    h_prob->d_row_x, h_prob->params, clusters.row, clusters.y, clusters.z, charge,
                    (const int32_t*)tracks.off, (const int32_t*)tracks.hits,
-                   (const int32_t*)tracks.tracklet, (const float*)tracklets.par,
-                   (const int32_t*)tracklets.row_inner, d_n_tracks, tcap, inv_q, cp.cbits, w);
+                   (const uint8_t*)tracks.hit_row, (const float*)tracks.hit_y,
+                   (const float*)tracks.hit_z, (const int32_t*)tracks.tracklet,
+                   (const float*)tracklets.par, (const int32_t*)tracklets.row_inner, d_n_tracks,
+                   tcap, inv_q, cp.cbits, w);
     }
     TPC_LAUNCH(tpc::k_cz_rowcount, dim3(tpc::grid_for(nrs * tpc::kWave)), dim3(tpc::kBlock), 0, st,
                h_prob->d_sectors, n_sec, n_rows, (const int32_t*)grid.bin_start,

@@ -84,3 +84,41 @@ def test_compression_small_output_and_bad_arguments():
     torch.cuda.synchronize()
     assert int(state["size"].item()) > 64
     assert int(state["out"].sum().item()) == 0
+
+
+def test_compression_with_and_without_the_hit_copies():
+    """The tracks' hit copies are read in place of the gathered cluster
+    values: without them the blob is the same; one or two of them null is an
+    argument error."""
+    import ctypes as C
+    ev = synth.make_config1()
+    print("case compress hit copies c1", flush=True)
+    e, g = run_gpu(ev)
+    ch = torch.as_tensor(ev.charge)
+    blob, size = api.compress_clusters(ctx(), e, ch)
+    torch.cuda.synchronize()
+    ref = blob[:int(size.item())].cpu().numpy().copy()
+    need = C.c_size_t(0)
+    L.lib().tpc_compress_workspace_size(C.byref(e.problem), e.track_capacity,
+                                        e.track_hit_capacity, 4096, C.byref(need))
+    ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(ref.size + 4096, dtype=torch.uint8, device="cuda")
+    sz = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chd = ch.cuda()
+
+    def call(trk):
+        return L.lib().tpc_compress_clusters(ctx().handle, C.byref(e.problem), api._clusters(e),
+                                             api._ptr(chd), api._grid(e), api._tracklets(e), trk,
+                                             api.status_count_ptr(e), L.CompressParams(5, 5, 4096),
+                                             api._ptr(out), out.numel(), api._ptr(sz),
+                                             api._ptr(ws), ws.numel(), None)
+
+    trk = api._tracks(e)
+    trk.hit_row = trk.hit_y = trk.hit_z = None
+    assert call(trk) == 0
+    torch.cuda.synchronize()
+    assert int(sz.item()) == ref.size
+    assert np.array_equal(out[:ref.size].cpu().numpy(), ref)
+    trk = api._tracks(e)
+    trk.hit_z = None
+    assert call(trk) == 1            # TPC_ERR_INVALID_ARG

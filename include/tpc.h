@@ -529,8 +529,11 @@ typedef struct tpc_track_hits {
  * checkpoints (nullable, ck_bytes long, at least tpc_refit_checkpoint_size
  * of the n_tracks member): the state and covariance after every update but
  * the last, for tpc_refit_adjoint, in a layout private to the library (tiles
- * of 64 tracks, 20 floats per hit slot).  A shorter buffer is an argument
- * error. */
+ * of 64 tracks, 20 floats per hit slot; with a checkpoint buffer the tracks
+ * are taken in order of decreasing hit count, equal counts in track order,
+ * and that order is kept in the buffer too).  A shorter buffer is an
+ * argument error, as are n_hits or n_tracks of 2^31 or more.  Outputs do not
+ * depend on the order; the adjoint's theta reduction follows it. */
 int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
               const tpc_params* h_params, const tpc_calib_model* h_model,
               const float* d_theta, float* par, float* cov, float* chi2, int32_t* status,
@@ -602,8 +605,9 @@ int tpc_vertex_residual(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
 /* tpc_refit_adjoint for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same kernels and results, with the per-block partial sums
- * of the theta gradient in a static device array of the library (64 KiB x
- * 16 = 1 MiB per GPU, held until the process ends) instead of a workspace.
+ * of the theta gradient in a static device array of the library (16384
+ * blocks x 16 float64 = 2 MiB per GPU, held until the process ends) instead
+ * of a workspace.
  * The adjoint never uses more than 16384 blocks, so every n_tracks fits;
  * TPC_ERR_CAPACITY would report one that did not.  The context's device must
  * be current (else TPC_ERR_INVALID_ARG).  Allocates nothing and calls no

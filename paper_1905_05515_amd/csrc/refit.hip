@@ -68,25 +68,29 @@ __device__ __forceinline__ CalHit calibrate(const float* th, float xr, float yr,
 // raw (y, z) adjoints, accumulated theta adjoint
 __device__ __forceinline__ void calibrate_adj(const float* th, const CalHit& h, float sd,
                                               const CalibModel& cm, float X, float Y, float Z,
-                                              float* gth, float& gyr, float& gzr)
+                                              double* gth, float& gyr, float& gzr)
 {
     // reverse-mode arithmetic: compared with the float64 adjoint within a
-    // tolerance, so products and sums may contract into fused multiply-adds
+    // tolerance, so products and sums may contract into fused multiply-adds.
+    // The theta adjoint is summed in float64 (per lane over its hits, then
+    // over lanes and blocks): it is a sum of ~1e8 terms that cancel at the
+    // calibration's minimum, where float32 sums would leave a noise floor
+    // that stops the fit short of it.
 #pragma clang fp contract(fast)
     const float w = h.d * cm.iDL;
     const float b[7] = {1.0f, h.u, h.v, h.u * h.u, h.u * h.v, h.v * h.v, w};
     float bb[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-        gth[2 + j] += X * b[j];
-        gth[9 + j] += Y * b[j];
+        gth[2 + j] += (double)(X * b[j]);
+        gth[9 + j] += (double)(Y * b[j]);
         bb[j] = X * th[2 + j] + Y * th[9 + j];
     }
     const float vb = bb[2] + bb[4] * h.u + 2.0f * bb[5] * h.v;
     gyr = Y + vb / (h.xr * cm.TH);
     const float db = bb[6] * cm.iDL - Z * sd;
-    gth[0] += db * (h.dr - cm.VD * th[1]);
-    gth[1] += -db * (1.0f + th[0]) * cm.VD;
+    gth[0] += (double)(db * (h.dr - cm.VD * th[1]));
+    gth[1] += (double)(-db * (1.0f + th[0]) * cm.VD);
     gzr = -sd * (1.0f + th[0]) * db;
 }
 
@@ -515,6 +519,95 @@ __device__ __forceinline__ void stage_hits(Stage& S, int* bad, int i0, int a, in
 
 }  // namespace
 
+// ---- tile order ---------------------------------------------------------------
+// With a checkpoint buffer the tracks are taken in order of decreasing hit
+// count (stable: equal counts in track order), so that the 64 tracks of a
+// tile have similar lengths: a tile steps to its longest track, storing and
+// loading whole checkpoint lines, and tiles of uniformly drawn lengths would
+// otherwise move about 1.5 times the checkpoint bytes their tracks need.
+// A counting sort by key (n_rows + 1) - min(n, n_rows + 1): per block of
+// 256 tracks the key counts (one wave's equal keys found by nine ballots),
+// an exclusive scan over (key, block), then every track's position.
+constexpr int kOrdBlock = 256;
+
+__device__ __forceinline__ int order_key(const int32_t* __restrict__ off, int64_t t, int n_rows)
+{
+    const int n = off[t + 1] - off[t];
+    const int c = n < 0 ? 0 : n > n_rows + 1 ? n_rows + 1 : n;
+    return n_rows + 1 - c;
+}
+
+// lanes of the wave holding the same key as this lane (keys below 512)
+__device__ __forceinline__ uint64_t same_key(int key)
+{
+    uint64_t m = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        const uint64_t v = __ballot((key >> b) & 1);
+        m &= ((key >> b) & 1) ? v : ~v;
+    }
+    return m;
+}
+
+// wc[w][key]: count of the key among wave w's tracks of the block
+__device__ __forceinline__ void order_counts(const int32_t* __restrict__ off, int64_t nt,
+                                             int n_rows, int nkeys, int (*wc)[256 + 2], int& key,
+                                             int& rank)
+{
+    for (int i = threadIdx.x; i < (kOrdBlock / kWave) * nkeys; i += kOrdBlock)
+        wc[i / nkeys][i % nkeys] = 0;
+    __syncthreads();
+    const int64_t t = blockIdx.x * (int64_t)kOrdBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    key = t < nt ? order_key(off, t, n_rows) : 511;   // 511: no track, no key
+    const uint64_t m = same_key(key);
+    rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (key != 511 && rank == 0) wc[threadIdx.x / kWave][key] = __popcll(m);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kOrdBlock) void k_order_count(const int32_t* __restrict__ off,
+                                                           const int64_t* __restrict__ d_count,
+                                                           int64_t n_tracks, int n_rows,
+                                                           int32_t* __restrict__ cnt)
+{
+    __shared__ int wc[kOrdBlock / kWave][256 + 2];
+    const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
+    const int nkeys = n_rows + 2;
+    int key, rank;
+    order_counts(off, nt, n_rows, nkeys, wc, key, rank);
+    for (int k = threadIdx.x; k < nkeys; k += kOrdBlock) {
+        int c = 0;
+#pragma unroll
+        for (int w = 0; w < kOrdBlock / kWave; ++w) c += wc[w][k];
+        cnt[(int64_t)k * gridDim.x + blockIdx.x] = c;
+    }
+}
+
+// after the scan of cnt: position of every track t < nt, order[pos] = t
+__global__ __launch_bounds__(kOrdBlock) void k_order_place(const int32_t* __restrict__ off,
+                                                           const int64_t* __restrict__ d_count,
+                                                           int64_t n_tracks, int n_rows,
+                                                           const int32_t* __restrict__ base,
+                                                           int32_t* __restrict__ order)
+{
+    __shared__ int wc[kOrdBlock / kWave][256 + 2];
+    const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
+    int key, rank;
+    order_counts(off, nt, n_rows, n_rows + 2, wc, key, rank);
+    if (key == 511) return;
+    int pos = base[(int64_t)key * gridDim.x + blockIdx.x] + rank;
+    for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) pos += wc[w][key];
+    order[pos] = (int32_t)(blockIdx.x * (int64_t)kOrdBlock + threadIdx.x);
+}
+
+// track of tile position q (q itself past the count, or without an order)
+__device__ __forceinline__ int64_t track_at(const int32_t* __restrict__ order, int64_t q,
+                                            int64_t nt)
+{
+    return order && q < nt ? (int64_t)order[q] : q;
+}
+
 __global__ __launch_bounds__(kWave) void k_refit_fwd(
     const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
     const uint8_t* __restrict__ row, const float* __restrict__ y, const float* __restrict__ z,
@@ -522,7 +615,8 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
     int n_rows,
     const float* __restrict__ row_x, tpc_params prm, CalibModel cm,
     const float* __restrict__ d_theta, float* __restrict__ par, float* __restrict__ cov,
-    float* __restrict__ chi2_out, int32_t* __restrict__ status, float* __restrict__ ck)
+    float* __restrict__ chi2_out, int32_t* __restrict__ status, float* __restrict__ ck,
+    const int32_t* __restrict__ order)
 {
     __shared__ float th[16];
     __shared__ float xs[256];
@@ -533,9 +627,9 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
-    // one wave per tile of 64 consecutive tracks
+    // one wave per tile of 64 tracks (consecutive in the tile order)
     for (int64_t tb = blockIdx.x * (int64_t)kWave; tb < nt; tb += (int64_t)gridDim.x * kWave) {
-        const int64_t t = tb + lane;
+        const int64_t t = track_at(order, tb + lane, nt);
         int a = 0, n = 0;
         if (t < nt) {
             a = off[t];
@@ -557,7 +651,7 @@ __global__ __launch_bounds__(kWave) void k_refit_fwd(
         // track (a lane past its own track stores its unchanged state, which
         // nothing reads), so that each store writes whole lines; the tile of
         // the last, partial wave is allocated in full
-        float4* ckt = ck ? ck_tile(ck, t, n_rows) : nullptr;
+        float4* ckt = ck ? ck_tile(ck, tb + lane, n_rows) : nullptr;
         const int M_ck = M < n_rows ? M : n_rows;
         for (int i0 = 0; i0 < M; i0 += kChunk) {
             __syncthreads();      // the previous chunk is consumed
@@ -633,7 +727,8 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
     const float* __restrict__ d_theta, const float* __restrict__ ck,
     const int32_t* __restrict__ status, const float* __restrict__ gchi2,
     const float* __restrict__ seed_p, const float* __restrict__ seed_x,
-    float* __restrict__ gy, float* __restrict__ gz, float* __restrict__ partials)
+    float* __restrict__ gy, float* __restrict__ gz, double* __restrict__ partials,
+    const int32_t* __restrict__ order)
 {
     __shared__ float th[16];
     __shared__ float xs[256];
@@ -643,9 +738,9 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
     load_theta(d_theta, th);
     for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
     __syncthreads();
-    float gth[16];
+    double gth[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) gth[k] = 0.0f;
+    for (int k = 0; k < 16; ++k) gth[k] = 0.0;
     const int64_t nt = d_count && *d_count < n_tracks ? *d_count : n_tracks;
     const int lane = threadIdx.x & (kWave - 1);
     // one wave per tile of 64 tracks; the reverse sweep runs over the slots
@@ -653,7 +748,7 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
     // more than i hits), so that checkpoint loads are whole lines; hits come
     // through LDS in chunks, from the top down
     for (int64_t tb = blockIdx.x * (int64_t)kWave; tb < nt; tb += (int64_t)gridDim.x * kWave) {
-        const int64_t t = tb + lane;
+        const int64_t t = track_at(order, tb + lane, nt);
         int a = 0, n = 0;
         if (t < nt) {
             a = off[t];
@@ -774,7 +869,7 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
     // deterministic wave reduction of the theta adjoint (one wave per block)
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        float v = gth[k];
+        double v = gth[k];
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
         if (lane == k) partials[blockIdx.x * 16 + k] = v;
@@ -783,12 +878,12 @@ __global__ __launch_bounds__(kWave) void k_refit_adj(
 
 // sum of the per-block partials in a fixed order: block k sums parameter k;
 // thread j adds partials j, j + 256, ... of it, then a fixed tree
-__global__ __launch_bounds__(kBlock) void k_reduce_theta(const float* __restrict__ partials,
+__global__ __launch_bounds__(kBlock) void k_reduce_theta(const double* __restrict__ partials,
                                                          int nb, float* __restrict__ out)
 {
-    __shared__ float red[kBlock];
+    __shared__ double red[kBlock];
     const int k = blockIdx.x;
-    float v = 0.0f;
+    double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += kBlock) v += partials[b * 16 + k];
     red[threadIdx.x] = v;
     __syncthreads();
@@ -796,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_theta(const float* __restrict
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = red[0];
+    if (threadIdx.x == 0) out[k] = (float)red[0];
 }
 
 // Beam-axis term of the calibration objective (section 3's online
@@ -904,21 +999,67 @@ static unsigned refit_grid(int64_t n_tracks)
     return grid_for_block(n_tracks, kWave, kRefitMaxBlocks);
 }
 
+// The checkpoint buffer: the tiles, then the tile order (int32 per track),
+// the per-(key, block) counts of the ordering and its scan partials.
+struct CkLayout {
+    size_t order_off, cnt_off, part_off, total;
+    int64_t nblk;
+    int nkeys;
+};
+
+static size_t ck_align(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static CkLayout ck_layout(int64_t n_tracks, int n_rows)
+{
+    CkLayout L;
+    const int64_t tiles = (n_tracks + kWave - 1) / kWave;
+    L.nblk = ceil_div(n_tracks > 0 ? n_tracks : 1, kOrdBlock);
+    L.nkeys = n_rows + 2;
+    const int64_t ncnt = L.nblk * L.nkeys;
+    L.order_off = ck_align(sizeof(float) * (size_t)tiles * kWave * (size_t)n_rows * 20);
+    L.cnt_off = L.order_off + ck_align(sizeof(int32_t) * (size_t)(n_tracks > 0 ? n_tracks : 1));
+    L.part_off = L.cnt_off + ck_align(sizeof(int32_t) * (size_t)ncnt);
+    L.total = L.part_off + sizeof(int64_t) * (size_t)(ceil_div(ncnt, kScanTile) + 1);
+    return L;
+}
+
+static const int32_t* ck_order(const float* ck, int64_t n_tracks, int n_rows)
+{
+    return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(ck) +
+                                            ck_layout(n_tracks, n_rows).order_off);
+}
+
+// the tile order of the forward pass, into the checkpoint buffer
+static void launch_order(const tpc_track_hits& hits, int n_rows, float* ck, hipStream_t st)
+{
+    const CkLayout L = ck_layout(hits.n_tracks, n_rows);
+    char* b = reinterpret_cast<char*>(ck);
+    int32_t* order = reinterpret_cast<int32_t*>(b + L.order_off);
+    int32_t* cnt = reinterpret_cast<int32_t*>(b + L.cnt_off);
+    int64_t* part = reinterpret_cast<int64_t*>(b + L.part_off);
+    TPC_LAUNCH(k_order_count, dim3((unsigned)L.nblk), dim3(kOrdBlock), 0, st, hits.off,
+               hits.d_count, hits.n_tracks, n_rows, cnt);
+    launch_scan<int32_t>(cnt, cnt, L.nblk * L.nkeys, false, nullptr, nullptr, part, st);
+    TPC_LAUNCH(k_order_place, dim3((unsigned)L.nblk), dim3(kOrdBlock), 0, st, hits.off,
+               hits.d_count, hits.n_tracks, n_rows, (const int32_t*)cnt, order);
+}
+
 // the adjoint and its theta reduction, partials[16 * refit_grid(n_tracks)]
 static int launch_refit_adjoint(tpc_track_hits hits, int32_t n_rows, const float* d_row_x,
                                 const tpc_params& prm, const tpc_calib_model& m,
                                 const float* d_theta, const float* checkpoints,
                                 const int32_t* status, const float* grad_chi2,
                                 const float* seed_p, const float* seed_x, float* grad_y,
-                                float* grad_z, float* grad_theta, float* partials,
+                                float* grad_z, float* grad_theta, double* partials,
                                 hipStream_t st)
 {
     const CalibModel cm = make_calib(m);
     const unsigned nb = refit_grid(hits.n_tracks);
     TPC_LAUNCH(k_refit_adj, dim3(nb), dim3(kWave), 0, st, hits.off, hits.idx, hits.row, hits.y,
                hits.z, hits.side, hits.d_count, hits.n_tracks, n_rows, d_row_x, prm, cm,
-               d_theta, checkpoints, status, grad_chi2, seed_p, seed_x, grad_y, grad_z, partials);
-    TPC_LAUNCH(k_reduce_theta, dim3(16), dim3(kBlock), 0, st, (const float*)partials, (int)nb,
+               d_theta, checkpoints, status, grad_chi2, seed_p, seed_x, grad_y, grad_z, partials,
+               ck_order(checkpoints, hits.n_tracks, n_rows));
+    TPC_LAUNCH(k_reduce_theta, dim3(16), dim3(kBlock), 0, st, (const double*)partials, (int)nb,
                grad_theta);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
@@ -930,13 +1071,13 @@ static int launch_refit_adjoint(tpc_track_hits hits, int32_t n_rows, const float
 // ends, shared by every call on that GPU (calls that overlap on one GPU
 // race on it).  Every block of the adjoint writes its 16 partials before the
 // reduction reads them, so nothing needs clearing between calls.
-static __device__ __align__(256) float scratch[16 * tpc::kRefitMaxBlocks];
+static __device__ __align__(256) double scratch[16 * tpc::kRefitMaxBlocks];
 
 namespace {
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
-float* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per GPU
+double* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per GPU
 
 }  // namespace
 
@@ -957,7 +1098,7 @@ int refit_scratch_setup(int device)
     const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
     if (prev != device) (void)hipSetDevice(prev);
     if (e != hipSuccess || !ptr) return TPC_ERR_HIP;
-    g_scratch_ptr[device] = static_cast<float*>(ptr);
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
     return TPC_OK;
 }
 
@@ -968,15 +1109,14 @@ extern "C" {
 int tpc_refit_workspace_size(int64_t n_tracks, size_t* h_bytes)
 {
     if (!h_bytes || n_tracks < 0) return TPC_ERR_INVALID_ARG;
-    *h_bytes = sizeof(float) * 16 * (size_t)tpc::refit_grid(n_tracks);
+    *h_bytes = sizeof(double) * 16 * (size_t)tpc::refit_grid(n_tracks);
     return TPC_OK;
 }
 
 int tpc_refit_checkpoint_size(int64_t n_tracks, int32_t n_rows, size_t* h_bytes)
 {
     if (!h_bytes || n_tracks < 0 || n_rows < 3 || n_rows > 255) return TPC_ERR_INVALID_ARG;
-    const int64_t tiles = (n_tracks + tpc::kWave - 1) / tpc::kWave;
-    *h_bytes = sizeof(float) * (size_t)tiles * tpc::kWave * (size_t)n_rows * 20;
+    *h_bytes = tpc::ck_layout(n_tracks, n_rows).total;
     return TPC_OK;
 }
 
@@ -989,7 +1129,7 @@ int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float
     if (!ctx || !h_params || !h_model || !d_theta || !d_row_x || !par || !cov || !chi2 ||
         !status || hits.n_tracks < 0 || hits.n_hits < 0 || n_rows < 3 || n_rows > 255 ||
         (hits.n_tracks > 0 && (!hits.off || !hits.row || !hits.y || !hits.z)) ||
-        hits.n_hits >= (int64_t(1) << 31))
+        hits.n_hits >= (int64_t(1) << 31) || hits.n_tracks >= (int64_t(1) << 31))
         return TPC_ERR_INVALID_ARG;
     size_t ck_need = 0;
     if (checkpoints && (tpc_refit_checkpoint_size(hits.n_tracks, n_rows, &ck_need) ||
@@ -997,10 +1137,13 @@ int tpc_refit(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows, const float
         return TPC_ERR_INVALID_ARG;
     if (hits.n_tracks == 0) return TPC_OK;
     const tpc::CalibModel cm = tpc::make_calib(*h_model);
+    hipStream_t st = (hipStream_t)stream;
+    if (checkpoints) tpc::launch_order(hits, n_rows, checkpoints, st);
     TPC_LAUNCH(tpc::k_refit_fwd, dim3(tpc::refit_grid(hits.n_tracks)), dim3(tpc::kWave),
-                       0, (hipStream_t)stream, hits.off, hits.idx, hits.row, hits.y, hits.z,
+                       0, st, hits.off, hits.idx, hits.row, hits.y, hits.z,
                        hits.side, hits.d_count, hits.n_tracks, n_rows, d_row_x, *h_params, cm,
-                       d_theta, par, cov, chi2, status, checkpoints);
+                       d_theta, par, cov, chi2, status, checkpoints,
+                       checkpoints ? tpc::ck_order(checkpoints, hits.n_tracks, n_rows) : nullptr);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
@@ -1023,7 +1166,7 @@ int tpc_refit_adjoint(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
         return TPC_ERR_INVALID_ARG;
     return tpc::launch_refit_adjoint(hits, n_rows, d_row_x, *h_params, *h_model, d_theta,
                                      checkpoints, status, grad_chi2, nullptr, nullptr, grad_y,
-                                     grad_z, grad_theta, (float*)d_ws, (hipStream_t)stream);
+                                     grad_z, grad_theta, (double*)d_ws, (hipStream_t)stream);
 }
 
 int tpc_refit_adjoint_seeded(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
@@ -1045,7 +1188,7 @@ int tpc_refit_adjoint_seeded(tpc_context* ctx, tpc_track_hits hits, int32_t n_ro
         return TPC_ERR_INVALID_ARG;
     return tpc::launch_refit_adjoint(hits, n_rows, d_row_x, *h_params, *h_model, d_theta,
                                      checkpoints, status, grad_chi2, grad_par, grad_x, grad_y,
-                                     grad_z, grad_theta, (float*)d_ws, (hipStream_t)stream);
+                                     grad_z, grad_theta, (double*)d_ws, (hipStream_t)stream);
 }
 
 int tpc_vertex_residual(tpc_context* ctx, tpc_track_hits hits, int32_t n_rows,
@@ -1089,7 +1232,7 @@ int tpc_refit_adjoint_noalloc(tpc_context* ctx, tpc_track_hits hits, int32_t n_r
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return TPC_ERR_HIP;
     if (dev != ctx->device || dev < 0 || dev >= kMaxDevices) return TPC_ERR_INVALID_ARG;
-    float* partials = nullptr;
+    double* partials = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_scratch_mu);
         partials = g_scratch_ptr[dev];

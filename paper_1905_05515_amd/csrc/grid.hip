@@ -165,20 +165,20 @@ __global__ __launch_bounds__(kBlock) void k_grid_bins(
     const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start,
     int32_t* __restrict__ cnt, int32_t* __restrict__ gslot, int32_t* __restrict__ gbin,
     int32_t* __restrict__ gtag, float* __restrict__ yg, float* __restrict__ zg,
-    int32_t* __restrict__ idg, int32_t* __restrict__ gsr, int32_t* __restrict__ bigq)
+    int32_t* __restrict__ idg, int32_t* __restrict__ gsr, int32_t* __restrict__ bigq,
+    int fuse_bins, int lds_ints)
 {
-    constexpr int kLds = kFuseLds > kRowBinsLds ? kFuseLds : kRowBinsLds;
-    __shared__ int lds[kLds];
+    extern __shared__ int lds[];           // lds_ints, sized on the host for the problem
     __shared__ int red[kBlock / kWave];
     const int Rb = (n_rows + 1) * S;
     const int si = sec_lo + (int)(blockIdx.x / Rb);
     const int bk = (int)(blockIdx.x % Rb);
     const tpc_sector s = sec[si];
     if (grid_bins_place_fused(s, si, bk, n_rows, S, rstart, gy, gz, gid, row, bin_start, yg, zg,
-                              idg, gsr, lds, red))
+                              idg, gsr, lds, red, fuse_bins))
         return;
     grid_bins_bucket(s, si, bk, n_rows, S, rstart, gy, gz, gid, row, bin_start, cnt, gslot, gbin,
-                     gtag, lds, red);
+                     gtag, lds, red, lds_ints);
     if (threadIdx.x == 0) bigq[1 + atomicAdd(&bigq[0], 1)] = si * Rb + bk;
 }
 
@@ -231,10 +231,24 @@ int run_build_grid(const tpc_problem* p, int sec_lo, int sec_hi, tpc_clusters in
     TPC_LAUNCH(k_grid_rows_scatter, dim3(gt), dim3(kBlock), 0, st, p->d_sectors, p->n_sectors,
                p->n_rows, S, ts, in.row, in.y, in.z, c0, c1, (const int32_t*)ws.rstart,
                ws.rfill, ws.tmp, ws.gy, ws.gz);
-    TPC_LAUNCH(k_grid_bins, dim3((unsigned)nbk), dim3(kBlock), 0, st, p->d_sectors, sec_lo,
+    // LDS of the bin-sort blocks: the largest slab of these sectors decides
+    // (bin counters of the fused form, or of a larger bucket; fewer bytes,
+    // more resident blocks)
+    int max_nbr = 1;
+    for (int i = sec_lo; i < sec_hi; ++i) {
+        const tpc_sector& s = p->h_sectors[i];
+        const int zs = slab_zbins(s);
+        const int nbr = (zs < s.nbz ? zs : s.nbz) * s.nby;
+        if (nbr > max_nbr) max_nbr = nbr;
+    }
+    const int fuse_bins = max_nbr < kFuseBins ? max_nbr : kFuseBins;
+    const int unfused = max_nbr < kRowBinsLds ? max_nbr : kRowBinsLds;
+    const int lds_ints = fused_lds_ints(fuse_bins) > unfused ? fused_lds_ints(fuse_bins) : unfused;
+    TPC_LAUNCH(k_grid_bins, dim3((unsigned)nbk), dim3(kBlock), sizeof(int) * lds_ints, st,
+               p->d_sectors, sec_lo,
                p->n_rows, S, (const int32_t*)ws.rstart, (const float*)ws.gy, (const float*)ws.gz,
                (const int32_t*)ws.tmp, in.row, out.bin_start, ws.cnt, ws.gslot, ws.gbin,
-               ws.gtag, out.y, out.z, out.id, ws.gsr, ws.bigq);
+               ws.gtag, out.y, out.z, out.id, ws.gsr, ws.bigq, fuse_bins, lds_ints);
     TPC_LAUNCH(k_grid_place, dim3(grid_for_block(nbk, 1, 2048)), dim3(kBlock), 0, st,
                (const int32_t*)ws.bigq, (const int32_t*)ws.rstart,
                (const int32_t*)out.bin_start, (const int32_t*)ws.tmp, (const float*)ws.gy,

@@ -29,7 +29,7 @@ __device__ __forceinline__ void grid_bins_bucket(
     const float* __restrict__ gy, const float* __restrict__ gz, const int32_t* __restrict__ gid,
     const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start, int32_t* __restrict__ cnt,
     int32_t* __restrict__ gslot, int32_t* __restrict__ gbin, int32_t* __restrict__ gtag,
-    int* lds, int* red)
+    int* lds, int* red, int lds_bins = kRowBinsLds)
 {
     const int Rb = (n_rows + 1) * S;
     const int r = bk / S, slab = bk % S;
@@ -41,7 +41,7 @@ __device__ __forceinline__ void grid_bins_bucket(
     const int z_hi = z_lo + zs < s.nbz ? z_lo + zs : s.nbz;
     const int nbr = r < n_rows ? (z_hi - z_lo) * s.nby : 1;
     const int g0 = s.bin_base + r * per_row + (r < n_rows ? z_lo * s.nby : 0);
-    const bool local = nbr <= kRowBinsLds;
+    const bool local = nbr <= lds_bins;
     int* ctr = local ? lds : cnt + g0;
     for (int b = threadIdx.x; b < nbr; b += blockDim.x) ctr[b] = 0;
     if (!local) __threadfence();
@@ -92,21 +92,29 @@ __device__ __forceinline__ void grid_bins_bucket(
 }
 
 // Bucket sort and placement in one block, for buckets of at most
-// kFuseMax clusters over at most kFuseBins bins: the clusters, their bins,
-// the bin counters and the binned order stay in LDS (smem[kFuseLds] ints);
-// every cluster's place is its bin start plus the number of clusters of its
-// bin with a smaller id (the stable order), as in the two-pass form.
+// kFuseMax clusters over at most fuse_bins bins: the cluster ids, their
+// bins, the bin counters and the binned order stay in LDS; every cluster's
+// place is its bin start plus the number of clusters of its bin with a
+// smaller id (the stable order), as in the two-pass form.  The counters are
+// 16-bit offsets from the bucket start (a bucket holds at most kFuseMax
+// clusters), two to a 32-bit word, incremented by 32-bit LDS atomics on the
+// word: a small LDS footprint lets more blocks share a compute unit, which
+// is what this latency-bound step needs.  LDS use (ints): fused_lds_ints.
 // Returns false, touching nothing, when the bucket is larger.
 constexpr int kFuseBins = 4096;
 constexpr int kFuseMax = 1024;
-constexpr int kFuseLds = kFuseBins + 5 * kFuseMax;
+
+__host__ __device__ inline int fused_lds_ints(int fuse_bins)
+{
+    return (fuse_bins + 1) / 2 + 3 * kFuseMax;
+}
 
 __device__ __forceinline__ bool grid_bins_place_fused(
     const tpc_sector& s, int si, int bk, int n_rows, int S, const int32_t* __restrict__ rstart,
     const float* __restrict__ gy, const float* __restrict__ gz, const int32_t* __restrict__ gid,
     const uint8_t* __restrict__ row, int32_t* __restrict__ bin_start, float* __restrict__ yg,
     float* __restrict__ zg, int32_t* __restrict__ idg, int32_t* __restrict__ gsr, int* smem,
-    int* red)
+    int* red, int fuse_bins)
 {
     const int Rb = (n_rows + 1) * S;
     const int r = bk / S, slab = bk % S;
@@ -117,15 +125,14 @@ __device__ __forceinline__ bool grid_bins_place_fused(
     const int z_lo = slab * zs;
     const int z_hi = z_lo + zs < s.nbz ? z_lo + zs : s.nbz;
     const int nbr = r < n_rows ? (z_hi - z_lo) * s.nby : 1;
-    if (n > kFuseMax || nbr > kFuseBins) return false;
+    if (n > kFuseMax || nbr > fuse_bins) return false;
     const int g0 = s.bin_base + r * per_row + (r < n_rows ? z_lo * s.nby : 0);
-    int* ctr = smem;                                   // [kFuseBins]
-    int* lid = smem + kFuseBins;                       // [kFuseMax] cluster ids
-    float* ly = reinterpret_cast<float*>(lid + kFuseMax);
-    float* lz = ly + kFuseMax;
-    int* lb = reinterpret_cast<int*>(lz + kFuseMax);   // bins
-    int* mem = lb + kFuseMax;                          // binned order
-    for (int b = threadIdx.x; b < nbr; b += blockDim.x) ctr[b] = 0;
+    uint32_t* cw = reinterpret_cast<uint32_t*>(smem);   // [(fuse_bins + 1) / 2] counter pairs
+    uint16_t* c16 = reinterpret_cast<uint16_t*>(smem);  // the same as 16-bit counters
+    int* lid = smem + (fuse_bins + 1) / 2;              // [kFuseMax] cluster ids
+    int* lb = lid + kFuseMax;                           // [kFuseMax] bins
+    int* mem = lb + kFuseMax;                           // [kFuseMax] binned order
+    for (int k = threadIdx.x; k < (nbr + 1) / 2; k += blockDim.x) cw[k] = 0u;
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const float y = gy[a + i], z = gz[a + i];
@@ -133,21 +140,20 @@ __device__ __forceinline__ bool grid_bins_place_fused(
                                        bin_of(y, s.y0, s.inv_by, s.nby)
                                  : 0;
         lid[i] = gid[a + i];
-        ly[i] = y;
-        lz[i] = z;
         lb[i] = b;
-        atomicAdd(&ctr[b], 1);
+        atomicAdd(&cw[b >> 1], 1u << ((b & 1) << 4));
     }
     __syncthreads();
-    // bin starts: exclusive scan of the counts from the bucket start
-    int carry = a;
+    // bin starts: exclusive scan of the counts (16-bit offsets in LDS, the
+    // absolute positions a + offset in the grid)
+    int carry = 0;
     for (int b0 = 0; b0 < nbr; b0 += kScanTile) {
         const int base = b0 + (int)threadIdx.x * kScanItems;
         int v[kScanItems];
         int sum = 0;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            v[k] = base + k < nbr ? ctr[base + k] : 0;
+            v[k] = base + k < nbr ? (int)c16[base + k] : 0;
             sum += v[k];
         }
         int tot;
@@ -155,27 +161,31 @@ __device__ __forceinline__ bool grid_bins_place_fused(
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k)
             if (base + k < nbr) {
-                bin_start[g0 + base + k] = ex;
-                ctr[base + k] = ex;
+                bin_start[g0 + base + k] = a + ex;
+                c16[base + k] = (uint16_t)ex;
                 ex += v[k];
             }
         carry += tot;
     }
     if (r == n_rows && threadIdx.x == 0) bin_start[g0 + 1] = a + n;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) mem[atomicAdd(&ctr[lb[i]], 1) - a] = i;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int b = lb[i];
+        const int sh = (b & 1) << 4;
+        mem[(atomicAdd(&cw[b >> 1], 1u << sh) >> sh) & 0xFFFFu] = i;
+    }
     __syncthreads();
-    // ctr[b] is now the end of bin b, i.e. the start of bin b + 1
+    // c16[b] is now the end of bin b, i.e. the start of bin b + 1
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
         const int i = mem[q];
         const int b = lb[i];
-        const int bs = (b > 0 ? ctr[b - 1] : a) - a, be = ctr[b] - a;
+        const int bs = b > 0 ? (int)c16[b - 1] : 0, be = (int)c16[b];
         const int id = lid[i];
         int rank = 0;
         for (int u = bs; u < be; ++u) rank += lid[mem[u]] < id;
         const int o = a + bs + rank;
-        yg[o] = ly[i];
-        zg[o] = lz[i];
+        yg[o] = gy[a + i];
+        zg[o] = gz[a + i];
         idg[o] = id;
         // invalid rows keep their raw row value
         gsr[o] = (si << 8) | (r < n_rows ? r : (int)row[id]);

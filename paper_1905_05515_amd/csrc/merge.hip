@@ -24,8 +24,6 @@
 // (bits(d2) << 32 | index): d2 >= +0 orders like its bit pattern, so the
 // least key is the least d2 and, among equal ones, the lower index, and the
 // result does not depend on the bucket order or the order of the atomics.
-#include <hipcub/hipcub.hpp>
-
 #include "tracklet_dev.hpp"
 
 namespace tpc {
@@ -48,8 +46,6 @@ struct MergeWs {
     uint32_t* key_out;
     int32_t* val_in;           // [cap] fill slot
     int32_t* val_out;
-    void* sort_tmp;            // segmented radix sort scratch
-    size_t sort_bytes;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -69,12 +65,6 @@ bool layout_merge(const tpc_problem* p, int64_t cap, void* base, MergeWs* w, siz
     const size_t o_ko = o;   o += align256(sizeof(uint32_t) * c);
     const size_t o_vi = o;   o += align256(sizeof(int32_t) * c);
     const size_t o_vo = o;   o += align256(sizeof(int32_t) * c);
-    size_t sort_bytes = 0;
-    const hipError_t q = hipcub::DeviceSegmentedRadixSort::SortPairs(
-        nullptr, sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-        (const int32_t*)nullptr, (int32_t*)nullptr, (int)c, p->n_sectors, (const int32_t*)nullptr,
-        (const int32_t*)nullptr, 0, 32, (hipStream_t)0);
-    const size_t o_st = o;   o += align256(sort_bytes > 0 ? sort_bytes : 1);
     *bytes = o;
     if (w) {
         char* b = (char*)base;
@@ -90,10 +80,8 @@ bool layout_merge(const tpc_problem* p, int64_t cap, void* base, MergeWs* w, siz
         w->key_out = (uint32_t*)(b + o_ko);
         w->val_in = (int32_t*)(b + o_vi);
         w->val_out = (int32_t*)(b + o_vo);
-        w->sort_tmp = (void*)(b + o_st);
-        w->sort_bytes = sort_bytes;
     }
-    return q == hipSuccess;
+    return true;
 }
 
 __device__ __forceinline__ int64_t n_tracks_of(const int64_t* d_n, int64_t cap)
@@ -207,6 +195,99 @@ __global__ __launch_bounds__(kBlock) void k_merge_fill(
         w.key_in[slot] = tl != tl ? 0xFFFFFFFFu : (u & 0x80000000u) ? ~u : (u | 0x80000000u);
         w.val_in[slot] = (int32_t)slot;
     }
+}
+
+// Sort of every sector bucket by its tan(lambda) key bits: one 1024-thread
+// block per bucket runs a least-significant-digit radix sort, 8-bit digits,
+// through key_in/val_in and key_out/val_out in turn, leaving the bucket's
+// slots in key order in val_out.  A digit pass is a histogram of the
+// bucket's digits (LDS atomics), its exclusive scan, and a stable scatter of
+// 1024-key tiles: within a wave the keys of one digit are found with one
+// ballot per digit bit, a key's rank is the number of such keys on lower
+// lanes, and the per-wave digit counts are scanned across the waves in LDS,
+// so equal digits keep their order.  A pass whose digit is the same for the
+// whole bucket moves nothing.
+constexpr int kSortBlock = 1024;
+constexpr int kSortWaves = kSortBlock / kWave;
+
+__global__ __launch_bounds__(kSortBlock) void k_merge_sort(int n_sec, MergeWs w)
+{
+    __shared__ int hist[256];
+    __shared__ int off[256];
+    __shared__ int wcnt[kSortWaves * 256];
+    __shared__ int same;
+    const int s = blockIdx.x;
+    if (s >= n_sec) return;
+    const int b0 = w.first[s], n = w.first[s + 1] - b0;
+    const int lane = (int)threadIdx.x & (kWave - 1), wv = (int)threadIdx.x / kWave;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t* ks = w.key_in + b0;
+    int32_t* vs = w.val_in + b0;
+    uint32_t* kd = w.key_out + b0;
+    int32_t* vd = w.val_out + b0;
+    for (int shift = 0; shift < 32; shift += 8) {
+        for (int d = threadIdx.x; d < 256; d += kSortBlock) hist[d] = 0;
+        if (threadIdx.x == 0) same = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kSortBlock) atomicAdd(&hist[(ks[i] >> shift) & 255u], 1);
+        __syncthreads();
+        if (threadIdx.x < 256 && hist[threadIdx.x] == n) same = 1;
+        if (threadIdx.x == 0) {
+            int a = 0;
+            for (int d = 0; d < 256; ++d) {
+                off[d] = a;
+                a += hist[d];
+            }
+        }
+        __syncthreads();
+        const bool skip = same != 0;        // every key has this digit
+        __syncthreads();
+        if (skip) continue;
+        for (int t0 = 0; t0 < n; t0 += kSortBlock) {
+            for (int e = threadIdx.x; e < kSortWaves * 256; e += kSortBlock) wcnt[e] = 0;
+            const int i = t0 + (int)threadIdx.x;
+            const bool valid = i < n;
+            uint32_t key = 0;
+            int32_t val = 0;
+            if (valid) {
+                key = ks[i];
+                val = vs[i];
+            }
+            const int d = (int)((key >> shift) & 255u);
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const uint64_t b = __ballot((d >> bit) & 1);
+                m &= ((d >> bit) & 1) ? b : ~b;
+            }
+            __syncthreads();
+            if (valid && (m & below) == 0) wcnt[wv * 256 + d] = __popcll(m);
+            __syncthreads();
+            if (threadIdx.x < 256) {
+                int a = 0;
+                for (int q = 0; q < kSortWaves; ++q) {
+                    const int c = wcnt[q * 256 + threadIdx.x];
+                    wcnt[q * 256 + threadIdx.x] = a;
+                    a += c;
+                }
+                hist[threadIdx.x] = a;       // the tile's count of this digit
+            }
+            __syncthreads();
+            if (valid) {
+                const int pos = off[d] + wcnt[wv * 256 + d] + __popcll(m & below);
+                kd[pos] = key;
+                vd[pos] = val;
+            }
+            __syncthreads();
+            if (threadIdx.x < 256) off[threadIdx.x] += hist[threadIdx.x];
+            __syncthreads();
+        }
+        uint32_t* tk = ks; ks = kd; kd = tk;
+        int32_t* tv = vs; vs = vd; vd = tv;
+    }
+    // the sorted slots are in vs: leave them in val_out
+    if (vs != w.val_out + b0)
+        for (int i = threadIdx.x; i < n; i += kSortBlock) w.val_out[b0 + i] = vs[i];
 }
 
 // bucket records into tan(lambda) order (both directions)
@@ -408,11 +489,8 @@ int tpc_merge_sector_tracks(tpc_context* ctx, const tpc_problem* h_prob,
                    h_prob->d_row_x, prm.s_max, (const int32_t*)tracks.tracklet,
                    (const float*)tracklets.par, (const int32_t*)tracklets.row_inner, d_n_tracks,
                    cap, cuts.cos_width, cuts.sin_width, w);
-        if (hipcub::DeviceSegmentedRadixSort::SortPairs(
-                w.sort_tmp, w.sort_bytes, (const uint32_t*)w.key_in, w.key_out,
-                (const int32_t*)w.val_in, w.val_out, (int)cap, n_sec, (const int32_t*)w.first,
-                (const int32_t*)(w.first + 1), 0, 32, st) != hipSuccess)
-            return TPC_ERR_HIP;
+        TPC_LAUNCH(tpc::k_merge_sort, dim3((unsigned)n_sec), dim3(tpc::kSortBlock), 0, st,
+                   n_sec, w);
         TPC_LAUNCH(tpc::k_merge_gather, dim3(tpc::grid_for(cap)), dim3(tpc::kBlock), 0, st, n_sec,
                    cap, w);
         TPC_LAUNCH(tpc::k_merge_best,

@@ -111,6 +111,138 @@ __device__ __forceinline__ void nb_pairs(const NbSrc& U, const NbSrc& D, float y
     }
 }
 
+// The same pair for windows that span at most kNbRows z rows of bins (the
+// usual case), with fewer dependent memory round trips: the bin bounds of
+// both neighbouring rows load together, then the first kNbBatch candidates
+// of both rows, and only then are they compared.  A window with more rows,
+// or more than kNbList down candidates, takes nb_pairs; the result is the
+// same lexicographic minimum either way.
+constexpr int kNbRows = 4;
+constexpr int kNbBatch = 4;
+
+// candidate e of a window whose z rows hold [lo[k], lo[k] + n[k])
+__device__ __forceinline__ int nb_cand(int e, const int* lo, const int* n)
+{
+    int p = lo[0] + e;
+#pragma unroll
+    for (int k = 1; k < kNbRows; ++k) {
+        e -= n[k - 1];
+        if (e >= 0) p = lo[k] + e;
+    }
+    return p;
+}
+
+__device__ __forceinline__ void nb_pairs_near(const NbSrc& U, const NbSrc& D, float y, float z,
+                                              float yu_c, float yd_c, int iyu0, int iyu1,
+                                              int iyd0, int iyd1, int iz0, int iz1,
+                                              const tpc_params& prm, const NbList& L, int& bu,
+                                              int& bd)
+{
+    if (iz1 - iz0 >= kNbRows) {
+        nb_pairs(U, D, y, z, yu_c, yd_c, iyu0, iyu1, iyd0, iyd1, iz0, iz1, prm, L, bu, bd);
+        return;
+    }
+    const float Wy = prm.nb_win_y, Wz = prm.nb_win_z, D2max = prm.nb_d2max;
+    int dlo[kNbRows], dn[kNbRows], ulo[kNbRows], un[kNbRows];
+#pragma unroll
+    for (int k = 0; k < kNbRows; ++k) {
+        dlo[k] = ulo[k] = 0;
+        dn[k] = un[k] = 0;
+        if (iz0 + k <= iz1) {
+            dlo[k] = D.first(iz0 + k, iyd0);
+            dn[k] = D.first(iz0 + k, iyd1 + 1);
+            ulo[k] = U.first(iz0 + k, iyu0);
+            un[k] = U.first(iz0 + k, iyu1 + 1);
+        }
+    }
+    int ndc = 0, nuc = 0;
+#pragma unroll
+    for (int k = 0; k < kNbRows; ++k) {
+        dn[k] = dn[k] > dlo[k] ? dn[k] - dlo[k] : 0;
+        un[k] = un[k] > ulo[k] ? un[k] - ulo[k] : 0;
+        ndc += dn[k];
+        nuc += un[k];
+    }
+    if (ndc == 0 || nuc == 0) return;
+    float yb[kNbBatch], zb[kNbBatch], yu[kNbBatch], zu[kNbBatch];
+    int pdb[kNbBatch], pub[kNbBatch];
+#pragma unroll
+    for (int j = 0; j < kNbBatch; ++j) {
+        pdb[j] = nb_cand(j, dlo, dn);
+        pub[j] = nb_cand(j, ulo, un);
+        if (j < ndc) {
+            yb[j] = D.yg[pdb[j]];
+            zb[j] = D.zg[pdb[j]];
+        }
+        if (j < nuc) {
+            yu[j] = U.yg[pub[j]];
+            zu[j] = U.zg[pub[j]];
+        }
+    }
+    // down candidates inside the window -> the lane's list
+    int nd = 0;
+    for (int b = 0; b < ndc; b += kNbBatch) {
+        if (b > 0) {
+#pragma unroll
+            for (int j = 0; j < kNbBatch; ++j) {
+                pdb[j] = nb_cand(b + j, dlo, dn);
+                if (b + j < ndc) {
+                    yb[j] = D.yg[pdb[j]];
+                    zb[j] = D.zg[pdb[j]];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kNbBatch; ++j) {
+            if (b + j >= ndc) break;
+            if (!(fabsf(yb[j] - yd_c) <= Wy && fabsf(zb[j] - z) <= Wz)) continue;
+            if (nd < kNbList) {
+                const int e = L.at(nd);
+                L.y[e] = yb[j];
+                L.z[e] = zb[j];
+                L.pos[e] = pdb[j];
+            }
+            ++nd;
+        }
+    }
+    if (nd == 0) return;
+    if (nd > kNbList) {
+        nb_pairs(U, D, y, z, yu_c, yd_c, iyu0, iyu1, iyd0, iyd1, iz0, iz1, prm, L, bu, bd);
+        return;
+    }
+    float best = 0.0f;
+    for (int b = 0; b < nuc; b += kNbBatch) {
+        if (b > 0) {
+#pragma unroll
+            for (int j = 0; j < kNbBatch; ++j) {
+                pub[j] = nb_cand(b + j, ulo, un);
+                if (b + j < nuc) {
+                    yu[j] = U.yg[pub[j]];
+                    zu[j] = U.zg[pub[j]];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kNbBatch; ++j) {
+            if (b + j >= nuc) break;
+            if (!(fabsf(yu[j] - yu_c) <= Wy && fabsf(zu[j] - z) <= Wz)) continue;
+            for (int k = 0; k < nd; ++k) {
+                const int e = L.at(k);
+                const float dy = (yu[j] + L.y[e]) - (y + y);
+                const float dz = (zu[j] + L.z[e]) - (z + z);
+                const float d2 = dy * dy + dz * dz;
+                if (!(d2 <= D2max)) continue;
+                const int pd = L.pos[e];
+                if (nb_better(d2, pub[j], pd, best, bu, bd, U, D)) {
+                    best = d2;
+                    bu = pub[j];
+                    bd = pd;
+                }
+            }
+        }
+    }
+}
+
 // Best up/down pair of the hit at grid position p, candidates read from
 // global memory.  Candidates on rows r+1 and r-1 come from the bins
 // covering the windows around the straight line from the origin through the
@@ -142,7 +274,8 @@ __device__ __forceinline__ void neighbours_one(
         const int per_row = s.nbz * s.nby;
         const NbSrc U{s.bin_base + (r + 1) * per_row, s.nby, bin_start, yg, zg, idg};
         const NbSrc D{s.bin_base + (r - 1) * per_row, s.nby, bin_start, yg, zg, idg};
-        nb_pairs(U, D, y, z, yu_c, yd_c, iyu0, iyu1, iyd0, iyd1, iz0, iz1, prm, L, bu, bd);
+        nb_pairs_near(U, D, y, z, yu_c, yd_c, iyu0, iyu1, iyd0, iyd1, iz0, iz1, prm, L, bu,
+                      bd);
     }
     up0[p] = bu;
     down0[p] = bd;

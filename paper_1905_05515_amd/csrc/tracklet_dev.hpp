@@ -146,9 +146,12 @@ __device__ __forceinline__ int search_row(const KState& st, const tpc_sector& s,
                                           const float* __restrict__ zg,
                                           const int32_t* __restrict__ idg, float& my, float& mz)
 {
+    // The window only has to contain every hit the gate can accept: the
+    // hardware square root (within 1 ulp) is far inside the 1/64 widening,
+    // so it needs none of the correctly rounded sequence the decisions use.
     const float S00 = st.C[0] + prm.sigma_y2, S11 = st.C[2] + prm.sigma_z2;
-    const float hy = prm.search_nsigma * sqrtf(S00) * TPC_WIDEN + 0.01f;
-    const float hz = prm.search_nsigma * sqrtf(S11) * TPC_WIDEN + 0.01f;
+    const float hy = prm.search_nsigma * __builtin_amdgcn_sqrtf(S00) * TPC_WIDEN + 0.01f;
+    const float hz = prm.search_nsigma * __builtin_amdgcn_sqrtf(S11) * TPC_WIDEN + 0.01f;
     const int iy0 = bin_of(st.p[0] - hy, s.y0, s.inv_by, s.nby);
     const int iy1 = bin_of(st.p[0] + hy, s.y0, s.inv_by, s.nby);
     const int iz0 = bin_of(st.p[1] - hz, s.z0, s.inv_bz, s.nbz);

@@ -286,7 +286,7 @@ int tpc_track_batch(tpc_context* ctx, const tpc_problem* h_prob, tpc_clusters in
 
 /* ---- track-based cluster attachment -------------------------------------- */
 
-/* Cluster attachment and rejection marks (section 5).  Every track of the
+/* Cluster attachment and rejection marks (section 6, data compression).  Every track of the
  * selection gets a tube of `radius` cm over the pad rows from its first to
  * its last hit; its axis is the state of the track's tracklet (par, at the
  * plane of row row_inner) transported outwards row by row as in tracklet

@@ -83,6 +83,7 @@ static AD ad_fabs(const AD& x) { return rec(std::fabs(x.v), x.i, x.v < 0.0 ? -1.
 #define SUF _ad
 #define SQRT ad_sqrt
 #define FABS ad_fabs
+#define FMA(a, b, c) ((a) * (b) + (c))
 #define C_1_6 (AD(1.0 / 6.0))
 #define C_3_40 (AD(3.0 / 40.0))
 #define C_5_112 (AD(5.0 / 112.0))

@@ -20,6 +20,7 @@
 #define SUF _f
 #define SQRT sqrtf
 #define FABS fabsf
+#define FMA fmaf
 #define C_1_6 (1.0f / 6.0f)
 #define C_3_40 (3.0f / 40.0f)
 #define C_5_112 (5.0f / 112.0f)

@@ -14,6 +14,9 @@
  * and the transverse arc length over the step is chord * asin(a)/a with
  * a = k * chord / 2, expanded to a^6 (the remainder is below 1e-10 for
  * single-row steps).
+ *
+ * FMA(a, b, c) is a * b + c with one rounding (fmaf / fma): the transport
+ * and the update add their products that way, in the order written.
  */
 #define CAT_(a, b) a##b
 #define CAT(a, b) CAT_(a, b)
@@ -45,43 +48,44 @@ static int FN(propagate)(REAL* p, REAL* C, REAL dx, REAL curv, REAL s_max)
 {
     REAL s = p[2], t = p[3], w = p[4];
     REAL k = curv * w;
-    REAL s2 = s + k * dx;
+    REAL s2 = FMA(k, dx, s);
     if (!(FABS(s) < s_max) || !(FABS(s2) < s_max)) return 0;
     REAL c1 = SQRT((R1 - s) * (R1 + s));
     REAL c2 = SQRT((R1 - s2) * (R1 + s2));
     REAL cc = c1 + c2;
     REAL T = (s + s2) / cc;               /* dy/dx averaged over the step */
-    REAL q = SQRT(R1 + T * T);
+    REAL q = SQRT(FMA(T, T, R1));
     REAL L = dx * q;                      /* signed transverse chord */
     REAL a = RH * (k * L);
     REAL a2 = a * a;
-    REAL g = R1 + a2 * (C_1_6 + a2 * (C_3_40 + a2 * C_5_112));   /* asin(a)/a */
+    REAL g = FMA(a2, FMA(a2, FMA(a2, C_5_112, C_3_40), C_1_6), R1);   /* asin(a)/a */
     REAL S = L * g;                       /* transverse arc length */
 
     /* exact derivatives of (y2, z2, s2) */
-    REAL Ts = (R2 + T * (s / c1 + s2 / c2)) / cc;
+    REAL Ts = FMA(T, s / c1 + s2 / c2, R2) / cc;
     REAL kdx = curv * dx;
-    REAL Tw = (kdx * (R1 + T * (s2 / c2))) / cc;
+    REAL Tw = (kdx * FMA(T, s2 / c2, R1)) / cc;
     REAL LT = dx * (T / q);               /* dL/dT */
-    REAL G1 = R1 + a2 * (RH + a2 * (C_3_8 + a2 * C_5_16));      /* dS/dL */
-    REAL Sk = (L * (L * a)) * (C_1_6 + a2 * (C_3_20 + a2 * C_15_112));  /* dS/dk */
+    REAL G1 = FMA(a2, FMA(a2, FMA(a2, C_5_16, C_3_8), RH), R1);      /* dS/dL */
+    REAL Sk = (L * (L * a)) * FMA(a2, FMA(a2, C_15_112, C_3_20), C_1_6);  /* dS/dk */
     FN(jac_t) F;
     F.ys = dx * Ts;
     F.yw = dx * Tw;
     F.zs = t * ((G1 * LT) * Ts);
     F.zt = S;
-    F.zw = t * ((G1 * LT) * Tw + Sk * curv);
+    F.zw = t * FMA(Sk, curv, (G1 * LT) * Tw);
     F.sw = kdx;
 
     /* B = F C (full 5x5), then C' = B F^T (lower triangle).  Each sum runs
-     * over the non-zero F entries in increasing column order. */
+     * over the non-zero F entries in increasing column order, every product
+     * added by one fused multiply-add. */
     REAL B[5][5];
     for (int j = 0; j < 5; j++) {
         REAL cy = C[FN(lt)(0, j)], cz = C[FN(lt)(1, j)], cs = C[FN(lt)(2, j)];
         REAL ct = C[FN(lt)(3, j)], cw = C[FN(lt)(4, j)];
-        B[0][j] = (cy + F.ys * cs) + F.yw * cw;
-        B[1][j] = ((cz + F.zs * cs) + F.zt * ct) + F.zw * cw;
-        B[2][j] = cs + F.sw * cw;
+        B[0][j] = FMA(F.yw, cw, FMA(F.ys, cs, cy));
+        B[1][j] = FMA(F.zw, cw, FMA(F.zt, ct, FMA(F.zs, cs, cz)));
+        B[2][j] = FMA(F.sw, cw, cs);
         B[3][j] = ct;
         B[4][j] = cw;
     }
@@ -89,16 +93,16 @@ static int FN(propagate)(REAL* p, REAL* C, REAL dx, REAL curv, REAL s_max)
         for (int j = 0; j <= i; j++) {
             REAL v;
             switch (j) {
-            case 0: v = (B[i][0] + F.ys * B[i][2]) + F.yw * B[i][4]; break;
-            case 1: v = ((B[i][1] + F.zs * B[i][2]) + F.zt * B[i][3]) + F.zw * B[i][4]; break;
-            case 2: v = B[i][2] + F.sw * B[i][4]; break;
+            case 0: v = FMA(F.yw, B[i][4], FMA(F.ys, B[i][2], B[i][0])); break;
+            case 1: v = FMA(F.zw, B[i][4], FMA(F.zt, B[i][3], FMA(F.zs, B[i][2], B[i][1]))); break;
+            case 2: v = FMA(F.sw, B[i][4], B[i][2]); break;
             default: v = B[i][j]; break;
             }
             C[FN(lt)(i, j)] = v;
         }
     }
-    p[0] = p[0] + dx * T;
-    p[1] = p[1] + t * S;
+    p[0] = FMA(dx, T, p[0]);
+    p[1] = FMA(t, S, p[1]);
     p[2] = s2;
     return 1;
 }
@@ -161,34 +165,35 @@ static inline REAL FN(chi2_pred)(const REAL* p, const REAL* C, REAL my, REAL mz,
 {
     REAL r0 = my - p[0], r1 = mz - p[1];
     REAL S00 = C[0] + sy2, S10 = C[1], S11 = C[2] + sz2;
-    REAL det = S00 * S11 - S10 * S10;
+    REAL det = FMA(S00, S11, -(S10 * S10));
     REAL idet = R1 / det;
     REAL B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
-    return r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
+    return FMA(r1, FMA(B11, r1, B10 * r0), r0 * FMA(B10, r1, B00 * r0));
 }
 
-/* Kalman update with the measurement (my, mz); returns its chi2. */
+/* Kalman update with the measurement (my, mz); returns its chi2.  Every
+ * sum of two products is one product and one fused multiply-add. */
 static REAL FN(update)(REAL* p, REAL* C, REAL my, REAL mz, REAL sy2, REAL sz2)
 {
     REAL r0 = my - p[0], r1 = mz - p[1];
     REAL S00 = C[0] + sy2, S10 = C[1], S11 = C[2] + sz2;
-    REAL det = S00 * S11 - S10 * S10;
+    REAL det = FMA(S00, S11, -(S10 * S10));
     REAL idet = R1 / det;
     REAL B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
-    REAL chi2 = r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
+    REAL chi2 = FMA(r1, FMA(B11, r1, B10 * r0), r0 * FMA(B10, r1, B00 * r0));
     REAL A0[5], A1[5], K0[5], K1[5];
     for (int i = 0; i < 5; i++) {
         A0[i] = C[FN(lt)(i, 0)];
         A1[i] = C[FN(lt)(i, 1)];
     }
     for (int i = 0; i < 5; i++) {
-        K0[i] = A0[i] * B00 + A1[i] * B10;
-        K1[i] = A0[i] * B10 + A1[i] * B11;
+        K0[i] = FMA(A1[i], B10, A0[i] * B00);
+        K1[i] = FMA(A1[i], B11, A0[i] * B10);
     }
     for (int i = 0; i < 5; i++) {
-        p[i] = p[i] + (K0[i] * r0 + K1[i] * r1);
+        p[i] = p[i] + FMA(K1[i], r1, K0[i] * r0);
         for (int j = 0; j <= i; j++)
-            C[FN(lt)(i, j)] = C[FN(lt)(i, j)] - (K0[i] * A0[j] + K1[i] * A1[j]);
+            C[FN(lt)(i, j)] = C[FN(lt)(i, j)] - FMA(K1[i], A1[j], K0[i] * A0[j]);
     }
     return chi2;
 }

@@ -14,6 +14,7 @@
 #define SUF _f
 #define SQRT sqrtf
 #define FABS fabsf
+#define FMA fmaf
 #define C_1_6 (1.0f / 6.0f)
 #define C_3_40 (3.0f / 40.0f)
 #define C_5_112 (5.0f / 112.0f)
@@ -26,6 +27,7 @@
 #undef SUF
 #undef SQRT
 #undef FABS
+#undef FMA
 #undef C_1_6
 #undef C_3_40
 #undef C_5_112
@@ -38,6 +40,7 @@
 #define SUF _d
 #define SQRT sqrt
 #define FABS fabs
+#define FMA fma
 #define C_1_6 (1.0 / 6.0)
 #define C_3_40 (3.0 / 40.0)
 #define C_5_112 (5.0 / 112.0)
@@ -50,6 +53,7 @@
 #undef SUF
 #undef SQRT
 #undef FABS
+#undef FMA
 
 /* ---- grid ----------------------------------------------------------------
  * Bin of a coordinate: f = (v - v0) * inv, clamped to [0, nb - 1] in float,

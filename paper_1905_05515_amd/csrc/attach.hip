@@ -1,4 +1,4 @@
-// Track-based cluster attachment (section 5, cluster rejection): a tube of
+// Track-based cluster attachment (section 6, cluster rejection): a tube of
 // fixed radius around every found track; clusters no track owns that lie in
 // tubes are adjacent to the track of highest transverse momentum among
 // them; clusters in the tubes of good tracks are protected; attached or

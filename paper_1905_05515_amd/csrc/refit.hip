@@ -43,6 +43,7 @@ struct CalHit {
 __device__ __forceinline__ CalHit calibrate(const float* th, float xr, float yr, float zr, float sd,
                                             const CalibModel& cm)
 {
+#pragma clang fp contract(fast)
     CalHit h;
     h.xr = xr;
     h.yr = yr;
@@ -129,6 +130,10 @@ struct Prop {
 __device__ __forceinline__ bool prop_fwd(float* p, float* C, float dx, float curv, float s_max,
                                          Prop& P)
 {
+    // the refit is compared with the float64 refit within a tolerance (it
+    // takes no decision but the transport stop), so products and sums may
+    // contract into fused multiply-adds, as in the reverse sweep
+#pragma clang fp contract(fast)
     const float s = p[2], t = p[3], w = p[4];
     P.dx = dx;
     P.k = curv * w;
@@ -191,6 +196,7 @@ struct Upd {
 __device__ __forceinline__ float upd_fwd(float* p, float* C, float my, float mz, float sy2,
                                          float sz2, Upd& U)
 {
+#pragma clang fp contract(fast)
     U.r0 = my - p[0];
     U.r1 = mz - p[1];
     const float S00 = C[0] + sy2, S10 = C[1], S11 = C[2] + sz2;

@@ -7,9 +7,10 @@
 // constant: s grows linearly with x, the y step is dx (s1 + s2)/(c1 + c2)
 // with c = sqrt(1 - s^2), and the arc length over the step is
 // chord * asin(a)/a, a = k chord / 2, expanded to a^6.  Every expression
-// below keeps the association order of its comment's formula; with
-// contraction off and IEEE division and square root the results are the
-// same bits on any conforming implementation.
+// below keeps the association order of its comment's formula, and sums of
+// products are written as explicit fused multiply-adds (fmaf, one
+// rounding); with contraction off otherwise and IEEE division and square
+// root the results are the same bits on any conforming implementation.
 #pragma once
 #include "tpc_internal.hpp"
 
@@ -30,54 +31,54 @@ __device__ __forceinline__ bool propagate(KState& st, float dx, float curv, floa
 {
     const float s = st.p[2], t = st.p[3], w = st.p[4];
     const float k = curv * w;
-    const float s2 = s + k * dx;
+    const float s2 = fmaf(k, dx, s);
     if (!(fabsf(s) < s_max) || !(fabsf(s2) < s_max)) return false;
     const float c1 = sqrtf((1.0f - s) * (1.0f + s));
     const float c2 = sqrtf((1.0f - s2) * (1.0f + s2));
     const float cc = c1 + c2;
     const float T = (s + s2) / cc;
-    const float q = sqrtf(1.0f + T * T);
+    const float q = sqrtf(fmaf(T, T, 1.0f));
     const float L = dx * q;
     const float a = 0.5f * (k * L);
     const float a2 = a * a;
-    const float g = 1.0f + a2 * ((1.0f / 6.0f) + a2 * ((3.0f / 40.0f) + a2 * (5.0f / 112.0f)));
+    const float g = fmaf(a2, fmaf(a2, fmaf(a2, 5.0f / 112.0f, 3.0f / 40.0f), 1.0f / 6.0f), 1.0f);
     const float S = L * g;
-    const float Ts = (2.0f + T * (s / c1 + s2 / c2)) / cc;
+    const float Ts = fmaf(T, s / c1 + s2 / c2, 2.0f) / cc;
     const float kdx = curv * dx;
-    const float Tw = (kdx * (1.0f + T * (s2 / c2))) / cc;
+    const float Tw = (kdx * fmaf(T, s2 / c2, 1.0f)) / cc;
     const float LT = dx * (T / q);
-    const float G1 = 1.0f + a2 * (0.5f + a2 * ((3.0f / 8.0f) + a2 * (5.0f / 16.0f)));
-    const float Sk = (L * (L * a)) * ((1.0f / 6.0f) + a2 * ((3.0f / 20.0f) + a2 * (15.0f / 112.0f)));
+    const float G1 = fmaf(a2, fmaf(a2, fmaf(a2, 5.0f / 16.0f, 3.0f / 8.0f), 0.5f), 1.0f);
+    const float Sk = (L * (L * a)) * fmaf(a2, fmaf(a2, 15.0f / 112.0f, 3.0f / 20.0f), 1.0f / 6.0f);
     const float Fys = dx * Ts;
     const float Fyw = dx * Tw;
     const float Fzs = t * ((G1 * LT) * Ts);
     const float Fzt = S;
-    const float Fzw = t * ((G1 * LT) * Tw + Sk * curv);
+    const float Fzw = t * fmaf(Sk, curv, (G1 * LT) * Tw);
     const float Fsw = kdx;
 
     // B = F C, then C' = B F^T, sums over the non-zero entries of F in
-    // increasing column order
+    // increasing column order, each product added by a fused multiply-add
     float B[5][5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         const float cy = st.C[lt(0, j)], cz = st.C[lt(1, j)], cs = st.C[lt(2, j)];
         const float ct = st.C[lt(3, j)], cw = st.C[lt(4, j)];
-        B[0][j] = (cy + Fys * cs) + Fyw * cw;
-        B[1][j] = ((cz + Fzs * cs) + Fzt * ct) + Fzw * cw;
-        B[2][j] = cs + Fsw * cw;
+        B[0][j] = fmaf(Fyw, cw, fmaf(Fys, cs, cy));
+        B[1][j] = fmaf(Fzw, cw, fmaf(Fzt, ct, fmaf(Fzs, cs, cz)));
+        B[2][j] = fmaf(Fsw, cw, cs);
         B[3][j] = ct;
         B[4][j] = cw;
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        st.C[lt(i, 0)] = (B[i][0] + Fys * B[i][2]) + Fyw * B[i][4];
-        if (i >= 1) st.C[lt(i, 1)] = ((B[i][1] + Fzs * B[i][2]) + Fzt * B[i][3]) + Fzw * B[i][4];
-        if (i >= 2) st.C[lt(i, 2)] = B[i][2] + Fsw * B[i][4];
+        st.C[lt(i, 0)] = fmaf(Fyw, B[i][4], fmaf(Fys, B[i][2], B[i][0]));
+        if (i >= 1) st.C[lt(i, 1)] = fmaf(Fzw, B[i][4], fmaf(Fzt, B[i][3], fmaf(Fzs, B[i][2], B[i][1])));
+        if (i >= 2) st.C[lt(i, 2)] = fmaf(Fsw, B[i][4], B[i][2]);
         if (i >= 3) st.C[lt(i, 3)] = B[i][3];
         if (i >= 4) st.C[lt(i, 4)] = B[i][4];
     }
-    st.p[0] = st.p[0] + dx * T;
-    st.p[1] = st.p[1] + t * S;
+    st.p[0] = fmaf(dx, T, st.p[0]);
+    st.p[1] = fmaf(t, S, st.p[1]);
     st.p[2] = s2;
     return true;
 }
@@ -86,20 +87,20 @@ __device__ __forceinline__ float chi2_pred(const KState& st, float my, float mz,
 {
     const float r0 = my - st.p[0], r1 = mz - st.p[1];
     const float S00 = st.C[0] + sy2, S10 = st.C[1], S11 = st.C[2] + sz2;
-    const float det = S00 * S11 - S10 * S10;
+    const float det = fmaf(S00, S11, -(S10 * S10));
     const float idet = 1.0f / det;
     const float B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
-    return r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
+    return fmaf(r1, fmaf(B11, r1, B10 * r0), r0 * fmaf(B10, r1, B00 * r0));
 }
 
 __device__ __forceinline__ float kupdate(KState& st, float my, float mz, float sy2, float sz2)
 {
     const float r0 = my - st.p[0], r1 = mz - st.p[1];
     const float S00 = st.C[0] + sy2, S10 = st.C[1], S11 = st.C[2] + sz2;
-    const float det = S00 * S11 - S10 * S10;
+    const float det = fmaf(S00, S11, -(S10 * S10));
     const float idet = 1.0f / det;
     const float B00 = S11 * idet, B10 = -(S10 * idet), B11 = S00 * idet;
-    const float chi2 = r0 * (B00 * r0 + B10 * r1) + r1 * (B10 * r0 + B11 * r1);
+    const float chi2 = fmaf(r1, fmaf(B11, r1, B10 * r0), r0 * fmaf(B10, r1, B00 * r0));
     float A0[5], A1[5], K0[5], K1[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -108,15 +109,15 @@ __device__ __forceinline__ float kupdate(KState& st, float my, float mz, float s
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        K0[i] = A0[i] * B00 + A1[i] * B10;
-        K1[i] = A0[i] * B10 + A1[i] * B11;
+        K0[i] = fmaf(A1[i], B10, A0[i] * B00);
+        K1[i] = fmaf(A1[i], B11, A0[i] * B10);
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        st.p[i] = st.p[i] + (K0[i] * r0 + K1[i] * r1);
+        st.p[i] = st.p[i] + fmaf(K1[i], r1, K0[i] * r0);
 #pragma unroll
         for (int j = 0; j <= i; ++j)
-            st.C[lt(i, j)] = st.C[lt(i, j)] - (K0[i] * A0[j] + K1[i] * A1[j]);
+            st.C[lt(i, j)] = st.C[lt(i, j)] - fmaf(K1[i], A1[j], K0[i] * A0[j]);
     }
     return chi2;
 }

@@ -101,7 +101,7 @@ __device__ __forceinline__ void grid_bins_bucket(
 // word: a small LDS footprint lets more blocks share a compute unit, which
 // is what this latency-bound step needs.  LDS use (ints): fused_lds_ints.
 // Returns false, touching nothing, when the bucket is larger.
-constexpr int kFuseBins = 4096;
+constexpr int kFuseBins = kRowBinsLds;   // every slab (16-bit counters, two a word)
 constexpr int kFuseMax = 1024;
 
 __host__ __device__ inline int fused_lds_ints(int fuse_bins)

@@ -164,7 +164,8 @@ __device__ __noinline__ void write_track_hits(
                    count_cap, out, hit_cap);
 }
 
-__global__ __launch_bounds__(kBlock)
+// three waves per SIMD: the register budget of the fused code (168 VGPRs)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 void k_persistent(PArgs a)
 {
     __shared__ float xs[256];

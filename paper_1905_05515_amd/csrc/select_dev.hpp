@@ -119,6 +119,7 @@ __device__ __forceinline__ void sel_write_track(
 // the sector the hits of the chunk it keeps (ccnt[q * count_cap + t]).  A
 // range larger than the LDS table uses the device-wide keys instead.
 constexpr int kSelLds = 6144;   // LDS table of the staged kernel
+constexpr int kSelKeep = 2;     // tracklets per thread kept in registers between passes
 
 // tracklets [lo, hi) of the sector
 __device__ __forceinline__ void sel_chunk_block(
@@ -143,7 +144,31 @@ __device__ __forceinline__ void sel_chunk_block(
     }
     if (!local) __threadfence();
     __syncthreads();
-    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    // the first kSelKeep tracklets of every thread keep their keys and
+    // chunk hits in registers for the counting pass (one read of the
+    // tracklet arrays instead of two for sectors of up to kSelKeep
+    // tracklets per thread)
+    uint64_t kkey[kSelKeep];
+    int kc[kSelKeep][kSelRows];
+#pragma unroll
+    for (int u = 0; u < kSelKeep; ++u) {
+        const int64_t t = lo + threadIdx.x + (int64_t)u * blockDim.x;
+        kkey[u] = t < hi ? key_of(t, prm, idg, t_start, t_nhits) : 0ull;
+        if (kkey[u]) load_chunk(t, ra, n_rows, t_hits, cap, kc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kSelKeep; ++u) {
+        if (!kkey[u]) continue;
+#pragma unroll
+        for (int k = 0; k < kSelRows; ++k) {
+            const unsigned o = (unsigned)(kc[u][k] - p0);
+            if (kc[u][k] < 0 || o >= (unsigned)np) continue;
+            if (local) atomicMax(&kl[o], (unsigned long long)kkey[u]);
+            else atomicMax(&hitkey[kc[u][k]], (unsigned long long)kkey[u]);
+        }
+    }
+    for (int64_t t = lo + threadIdx.x + (int64_t)kSelKeep * blockDim.x; t < hi;
+         t += blockDim.x) {
         const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
         if (!key) continue;
         int c[kSelRows];
@@ -160,7 +185,24 @@ __device__ __forceinline__ void sel_chunk_block(
     __syncthreads();
     if (local)
         for (int k = threadIdx.x; k < np; k += blockDim.x) hitkey[p0 + k] = kl[k];
-    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < kSelKeep; ++u) {
+        const int64_t t = lo + threadIdx.x + (int64_t)u * blockDim.x;
+        if (t >= hi) continue;
+        int kept = 0;
+        if (kkey[u]) {
+#pragma unroll
+            for (int k = 0; k < kSelRows; ++k) {
+                const unsigned o = (unsigned)(kc[u][k] - p0);
+                if (kc[u][k] < 0 || o >= (unsigned)np) continue;
+                const unsigned long long h = local ? kl[o] : hitkey[kc[u][k]];
+                kept += h == kkey[u];
+            }
+        }
+        ccnt[q * count_cap + t] = (uint8_t)kept;
+    }
+    for (int64_t t = lo + threadIdx.x + (int64_t)kSelKeep * blockDim.x; t < hi;
+         t += blockDim.x) {
         const uint64_t key = key_of(t, prm, idg, t_start, t_nhits);
         int kept = 0;
         if (key) {

@@ -303,7 +303,11 @@ __device__ __forceinline__ void build_tracklet(
     float csum = 0.0f;
     int rin = last;
     miss = 0;
-    int an = -1;                          // assigned hit of the next row down
+    // assigned hits of the next two rows down: the hit list entry of row
+    // r - 2 loads during step r, the coordinates of the hit of row r - 1
+    // during step r (its entry loaded a step before), so that no step waits
+    // on a load it issued itself
+    int an = -1, an2 = -1;
     float ay = 0.0f, az = 0.0f;
     if (last - 1 >= r0) {
         an = th[(last - 1) * ths];
@@ -312,17 +316,17 @@ __device__ __forceinline__ void build_tracklet(
             az = zg[an];
         }
     }
+    if (last - 2 >= r0) an2 = th[(last - 2) * ths];
     for (int r = last - 1; r >= 0; --r) {
         int c = an;
         float my = ay, mz = az;
-        an = -1;
-        if (r - 1 >= r0) {
-            an = th[(r - 1) * ths];
-            if (an >= 0) {
-                ay = yg[an];
-                az = zg[an];
-            }
+        an = an2;                         // the hit of row r - 1, or -1
+        an2 = -1;
+        if (an >= 0) {
+            ay = yg[an];
+            az = zg[an];
         }
+        if (r - 2 >= r0) an2 = th[(r - 2) * ths];
         ++n_prop;
         if (!propagate(st, xs[r] - xs[r + 1], prm.curv, prm.s_max)) {
             for (int q = r; q >= 0; --q) th[q * ths] = -1;

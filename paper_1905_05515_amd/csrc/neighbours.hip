@@ -12,8 +12,11 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
     int32_t* __restrict__ up0, int32_t* __restrict__ down0)
 {
     __shared__ float nb_l[3 * kNbList * kBlock];
+    __shared__ float xs[256];
     const NbList L{nb_l, nb_l + kNbList * kBlock,
                    reinterpret_cast<int*>(nb_l + 2 * kNbList * kBlock)};
+    for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
+    __syncthreads();
     // work blocks dealt to the XCDs in contiguous ranges (one sector's rows
     // share an L2)
     const int64_t nblk = (end - begin + blockDim.x - 1) / blockDim.x;
@@ -23,8 +26,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(
         const int64_t p = begin + (b0 + xcd_remap(blockIdx.x, (int)chunk)) * blockDim.x +
                           threadIdx.x;
         if (p < end)
-            neighbours_one(p, sec, n_rows, row_x, prm, bin_start, yg, zg, idg, gsr, up0, down0,
-                           L);
+            neighbours_one(p, sec, n_rows, xs, prm, bin_start, yg, zg, idg, gsr, up0, down0, L);
     }
 }
 

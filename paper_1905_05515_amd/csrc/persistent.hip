@@ -332,7 +332,7 @@ void k_persistent(PArgs a)
             const NbList nbl{nbf, nbf + kNbList * kBlock,
                              reinterpret_cast<int*>(nbf + 2 * kNbList * kBlock)};
             for (int64_t k = c0 + i0 + threadIdx.x; k < c1 && k < c0 + i0 + items; k += kBlock) {
-                neighbours_one(k, a.sec, n_rows, a.row_x, a.prm, a.grid.bin_start, a.grid.y,
+                neighbours_one(k, a.sec, n_rows, xs, a.prm, a.grid.bin_start, a.grid.y,
                                a.grid.z, a.grid.id, a.ws.gsr, a.links.up0, a.links.down0,
                                nbl);
                 a.ws.tmp[k] = -1;   // start flags (the staging array is free again)

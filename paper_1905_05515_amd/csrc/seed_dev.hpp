@@ -244,12 +244,12 @@ __device__ __forceinline__ void nb_pairs_near(const NbSrc& U, const NbSrc& D, fl
 }
 
 // Best up/down pair of the hit at grid position p, candidates read from
-// global memory.  Candidates on rows r+1 and r-1 come from the bins
+// global memory (xs: the row positions, in LDS).  Candidates on rows r+1 and r-1 come from the bins
 // covering the windows around the straight line from the origin through the
 // hit; the exact window test and the pair deviation decide, ties go to the
 // lower (up id, down id).
 __device__ __forceinline__ void neighbours_one(
-    int64_t p, const tpc_sector* __restrict__ sec, int n_rows, const float* __restrict__ row_x,
+    int64_t p, const tpc_sector* __restrict__ sec, int n_rows, const float* xs,
     const tpc_params& prm, const int32_t* __restrict__ bin_start, const float* __restrict__ yg,
     const float* __restrict__ zg, const int32_t* __restrict__ idg,
     const int32_t* __restrict__ gsr, int32_t* __restrict__ up0, int32_t* __restrict__ down0,
@@ -257,14 +257,25 @@ __device__ __forceinline__ void neighbours_one(
 {
     const float Wy = prm.nb_win_y, Wz = prm.nb_win_z;
     const int v = gsr[p];
+    const float y = yg[p], z = zg[p];
+    // the hit's coordinates load with its row tag (one round trip): held
+    // here, the compiler would otherwise sink their loads below the branch
+    asm volatile("" ::"v"(y), "v"(z));
     const int r = v & 255;
+    // The lanes of a wave hold consecutive grid positions, nearly always of
+    // one sector: its record is then loaded at the wave-uniform address
+    // (the scalar cache, a much shorter round trip than a vector load), and
+    // per lane only when the wave spans two sectors.
+    const int vf = __builtin_amdgcn_readfirstlane(v);
+    const tpc_sector su = sec[vf >> 8];
+    const bool mixed = __ballot((v >> 8) != (vf >> 8)) != 0ull;
     int bu = -1, bd = -1;
     if (r > 0 && r + 1 < n_rows) {
-        const tpc_sector s = sec[v >> 8];
-        const float y = yg[p], z = zg[p];
-        const float slope = y / row_x[r];
-        const float yu_c = slope * row_x[r + 1];
-        const float yd_c = slope * row_x[r - 1];
+        tpc_sector s = su;
+        if (mixed) s = sec[v >> 8];
+        const float slope = y / xs[r];
+        const float yu_c = slope * xs[r + 1];
+        const float yd_c = slope * xs[r - 1];
         const int iyu0 = bin_of(yu_c - Wy * TPC_WIDEN, s.y0, s.inv_by, s.nby);
         const int iyu1 = bin_of(yu_c + Wy * TPC_WIDEN, s.y0, s.inv_by, s.nby);
         const int iyd0 = bin_of(yd_c - Wy * TPC_WIDEN, s.y0, s.inv_by, s.nby);

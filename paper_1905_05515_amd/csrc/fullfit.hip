@@ -3,8 +3,8 @@
 // section 3: several fit iterations, inwards and outwards, across sector
 // boundaries).
 //
-// One thread per track; the thread of a chain's least track index (its
-// group) fits the chain, the others mark themselves.  The chain is walked
+// One thread per chain: blocks list the chains' least track indices (their
+// groups) and fit those, the other tracks are marked.  The chain is walked
 // from its down end along the up links, or from its up end along the down
 // links when the up end's first hit lies on a lower row than the down end's;
 // the hits are the members' hits in that order, each member's row-ascending.
@@ -75,21 +75,19 @@ __device__ __forceinline__ int first_row(const uint8_t* __restrict__ row,
     return off[j + 1] > off[j] ? row[hits[off[j]]] : 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fit_merged(
-    const tpc_sector* __restrict__ sec, int n_sec, int sps, const float* __restrict__ row_x,
-    tpc_params prm, const uint8_t* __restrict__ row, const float* __restrict__ cy,
+// Fit of track g (a chain's least index) or, for any other track, its
+// marks (status -1).  xs: the row positions (LDS).
+__device__ __forceinline__ void fit_track(
+    int64_t g, const tpc_sector* __restrict__ sec, int n_sec, int sps, const float* xs,
+    const tpc_params& prm, const uint8_t* __restrict__ row, const float* __restrict__ cy,
     const float* __restrict__ cz, const int32_t* __restrict__ off,
     const int32_t* __restrict__ hits, const int32_t* __restrict__ trk_tracklet,
     const float* __restrict__ t_par, const float* __restrict__ t_cov,
-    const int32_t* __restrict__ t_rin,
-    const int64_t* __restrict__ d_n_tracks, int64_t cap, const int32_t* __restrict__ link_up,
+    const int32_t* __restrict__ t_rin, const int32_t* __restrict__ link_up,
     const int32_t* __restrict__ link_dn, const int32_t* __restrict__ group, float cos_w,
-    float sin_w, int n_pass, float cov_scale, tpc_fit_out out)
+    float sin_w, int n_pass, float cov_scale, const tpc_fit_out& out)
 {
-    const int64_t n = *d_n_tracks;
-    const int64_t nt = n < cap ? n : cap;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nt;
-         g += (int64_t)gridDim.x * blockDim.x) {
+    {
         float pin[5] = {0, 0, 0, 0, 0}, pout[5] = {0, 0, 0, 0, 0}, Cout[15];
 #pragma unroll
         for (int i = 0; i < 15; ++i) Cout[i] = 0.0f;
@@ -131,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_merged(
                     const float v = t_cov[(int64_t)tf * 15 + kDiag[j]];
                     dg[j] = v > 0.0f && v < 1e30f ? v : v0[j];
                 }
-                float x = row_x[t_rin[tf]];
+                float x = xs[t_rin[tf]];
                 int cur = -1;     // frame of the state: the sector of the first hit
                 bool ok = true;
                 for (int pass = 0; pass < n_pass && ok; ++pass) {
@@ -159,16 +157,32 @@ __global__ __launch_bounds__(kBlock) void k_fit_merged(
                                 }
                                 cur = ms;
                             }
-                            for (int q = 0; q < h1 - h0; ++q) {
-                                const int c = hits[outw ? h0 + q : h1 - 1 - q];
-                                const float xh = row_x[row[c]];
+                            // the member's hits in order; the row and
+                            // coordinates of hit q + 1 load during step q,
+                            // the index of hit q + 2 a step earlier still
+                            const int nh = h1 - h0;
+                            const int32_t* hp = hits + (outw ? h0 : h1 - 1);
+                            const int dq = outw ? 1 : -1;
+                            int ca = nh > 1 ? hp[dq] : -1;
+                            const int c0 = hp[0];
+                            int rb = row[c0];
+                            float yb = cy[c0], zb = cz[c0];
+                            for (int q = 0; q < nh; ++q) {
+                                const int rr = rb;
+                                const float my = yb, mz = zb;
+                                if (ca >= 0) {
+                                    rb = row[ca];
+                                    yb = cy[ca];
+                                    zb = cz[ca];
+                                }
+                                ca = q + 2 < nh ? hp[(q + 2) * dq] : -1;
+                                const float xh = xs[rr];
                                 if (!propagate(st, xh - x, prm.curv, prm.s_max)) {
                                     ok = false;
                                     break;
                                 }
                                 x = xh;
-                                chi2 = chi2 + kupdate(st, cy[c], cz[c], prm.sigma_y2,
-                                                      prm.sigma_z2);
+                                chi2 = chi2 + kupdate(st, my, mz, prm.sigma_y2, prm.sigma_z2);
                             }
                         }
                         m = outw ? fwd[m] : bwd[m];
@@ -213,6 +227,57 @@ __global__ __launch_bounds__(kBlock) void k_fit_merged(
     }
 }
 
+// A block takes kFitIds consecutive track ids at a time, marks the tracks
+// that lead no chain and lists the chain leaders in LDS, then its first
+// threads fit the listed chains: about 60% of the tracks lead a chain, and
+// without the list the lanes of the others would idle through every fit;
+// with it, waves left without a chain end at once.  (Blocks of four times
+// as many ids, fitted in rounds, took twice as long on the central event:
+// a quarter of the waves, and every round waits for its longest chain.)
+constexpr int kFitIds = kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_fit_merged(
+    const tpc_sector* __restrict__ sec, int n_sec, int sps, int n_rows,
+    const float* __restrict__ row_x, tpc_params prm, const uint8_t* __restrict__ row,
+    const float* __restrict__ cy, const float* __restrict__ cz, const int32_t* __restrict__ off,
+    const int32_t* __restrict__ hits, const int32_t* __restrict__ trk_tracklet,
+    const float* __restrict__ t_par, const float* __restrict__ t_cov,
+    const int32_t* __restrict__ t_rin,
+    const int64_t* __restrict__ d_n_tracks, int64_t cap, const int32_t* __restrict__ link_up,
+    const int32_t* __restrict__ link_dn, const int32_t* __restrict__ group, float cos_w,
+    float sin_w, int n_pass, float cov_scale, tpc_fit_out out)
+{
+    __shared__ float xs[256];
+    __shared__ int lead[kFitIds];
+    __shared__ int n_lead;
+    for (int i = threadIdx.x; i < n_rows; i += blockDim.x) xs[i] = row_x[i];
+    const int64_t n = *d_n_tracks;
+    const int64_t nt = n < cap ? n : cap;
+    for (int64_t b0 = blockIdx.x * (int64_t)kFitIds; b0 < nt; b0 += (int64_t)gridDim.x * kFitIds) {
+        if (threadIdx.x == 0) n_lead = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < kFitIds && b0 + k < nt; k += blockDim.x) {
+            const int64_t g = b0 + k;
+            if (group[g] == (int32_t)g) {
+                lead[atomicAdd(&n_lead, 1)] = k;
+            } else {
+                fit_track(g, sec, n_sec, sps, xs, prm, row, cy, cz, off, hits, trk_tracklet,
+                          t_par, t_cov, t_rin, link_up, link_dn, group, cos_w, sin_w, n_pass,
+                          cov_scale, out);
+            }
+        }
+        __syncthreads();
+        const int m = n_lead;
+        for (int i = threadIdx.x; i < m; i += blockDim.x)
+            fit_track(b0 + lead[i], sec, n_sec, sps, xs, prm, row, cy, cz, off, hits,
+                      trk_tracklet, t_par, t_cov, t_rin, link_up, link_dn, group, cos_w, sin_w,
+                      n_pass, cov_scale, out);
+        // the list is reused only by a next round (none when the grid covers
+        // every track: waves without a chain then end at once)
+        if (b0 + (int64_t)gridDim.x * kFitIds < nt) __syncthreads();
+    }
+}
+
 }  // namespace
 
 }  // namespace tpc
@@ -244,9 +309,10 @@ int tpc_fit_merged_tracks(tpc_context* ctx, const tpc_problem* h_prob, tpc_clust
     if (hipGetDevice(&dev) != hipSuccess) return TPC_ERR_HIP;
     if (dev != ctx->device && hipSetDevice(ctx->device) != hipSuccess) return TPC_ERR_HIP;
     if (tracks.capacity > 0)
-        TPC_LAUNCH(tpc::k_fit_merged, dim3(tpc::grid_for(tracks.capacity)), dim3(tpc::kBlock), 0,
-                   (hipStream_t)stream, h_prob->d_sectors, h_prob->n_sectors, sps,
-                   h_prob->d_row_x, h_prob->params, clusters.row, clusters.y, clusters.z,
+        TPC_LAUNCH(tpc::k_fit_merged,
+                   dim3(tpc::grid_for_block(tracks.capacity, tpc::kFitIds, 65536)),
+                   dim3(tpc::kBlock), 0, (hipStream_t)stream, h_prob->d_sectors,
+                   h_prob->n_sectors, sps, h_prob->n_rows, h_prob->d_row_x, h_prob->params, clusters.row, clusters.y, clusters.z,
                    (const int32_t*)tracks.off, (const int32_t*)tracks.hits,
                    (const int32_t*)tracks.tracklet, (const float*)tracklets.par,
                    (const float*)tracklets.cov, (const int32_t*)tracklets.row_inner, d_n_tracks,

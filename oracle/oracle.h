@@ -14,8 +14,9 @@
  * this project's reading of that statement, written out step by step.
  *
  * Floating point: built with -ffp-contract=off; every decision is taken in
- * IEEE binary32 with the association order written in the source, so that
- * an implementation evaluating the same expressions in the same order
+ * IEEE binary32 with the association order written in the source and fused
+ * multiply-adds only where the source calls them (fmaf), so that an
+ * implementation evaluating the same expressions in the same order
  * reproduces them bit for bit.
  *
  * Index spaces: cluster ids are indices into the caller's input arrays.

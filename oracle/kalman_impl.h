@@ -53,7 +53,8 @@ static int FN(propagate)(REAL* p, REAL* C, REAL dx, REAL curv, REAL s_max)
     REAL c1 = SQRT((R1 - s) * (R1 + s));
     REAL c2 = SQRT((R1 - s2) * (R1 + s2));
     REAL cc = c1 + c2;
-    REAL T = (s + s2) / cc;               /* dy/dx averaged over the step */
+    REAL icc = R1 / cc;                   /* one reciprocal for the three quotients by cc */
+    REAL T = (s + s2) * icc;              /* dy/dx averaged over the step */
     REAL q = SQRT(FMA(T, T, R1));
     REAL L = dx * q;                      /* signed transverse chord */
     REAL a = RH * (k * L);
@@ -62,9 +63,9 @@ static int FN(propagate)(REAL* p, REAL* C, REAL dx, REAL curv, REAL s_max)
     REAL S = L * g;                       /* transverse arc length */
 
     /* exact derivatives of (y2, z2, s2) */
-    REAL Ts = FMA(T, s / c1 + s2 / c2, R2) / cc;
+    REAL Ts = FMA(T, s / c1 + s2 / c2, R2) * icc;
     REAL kdx = curv * dx;
-    REAL Tw = (kdx * FMA(T, s2 / c2, R1)) / cc;
+    REAL Tw = (kdx * FMA(T, s2 / c2, R1)) * icc;
     REAL LT = dx * (T / q);               /* dL/dT */
     REAL G1 = FMA(a2, FMA(a2, FMA(a2, C_5_16, C_3_8), RH), R1);      /* dS/dL */
     REAL Sk = (L * (L * a)) * FMA(a2, FMA(a2, C_15_112, C_3_20), C_1_6);  /* dS/dk */

@@ -36,16 +36,17 @@ __device__ __forceinline__ bool propagate(KState& st, float dx, float curv, floa
     const float c1 = sqrtf((1.0f - s) * (1.0f + s));
     const float c2 = sqrtf((1.0f - s2) * (1.0f + s2));
     const float cc = c1 + c2;
-    const float T = (s + s2) / cc;
+    const float icc = 1.0f / cc;   // one reciprocal for the three quotients by cc
+    const float T = (s + s2) * icc;
     const float q = sqrtf(fmaf(T, T, 1.0f));
     const float L = dx * q;
     const float a = 0.5f * (k * L);
     const float a2 = a * a;
     const float g = fmaf(a2, fmaf(a2, fmaf(a2, 5.0f / 112.0f, 3.0f / 40.0f), 1.0f / 6.0f), 1.0f);
     const float S = L * g;
-    const float Ts = fmaf(T, s / c1 + s2 / c2, 2.0f) / cc;
+    const float Ts = fmaf(T, s / c1 + s2 / c2, 2.0f) * icc;
     const float kdx = curv * dx;
-    const float Tw = (kdx * fmaf(T, s2 / c2, 1.0f)) / cc;
+    const float Tw = (kdx * fmaf(T, s2 / c2, 1.0f)) * icc;
     const float LT = dx * (T / q);
     const float G1 = fmaf(a2, fmaf(a2, fmaf(a2, 5.0f / 16.0f, 3.0f / 8.0f), 0.5f), 1.0f);
     const float Sk = (L * (L * a)) * fmaf(a2, fmaf(a2, 15.0f / 112.0f, 3.0f / 20.0f), 1.0f / 6.0f);

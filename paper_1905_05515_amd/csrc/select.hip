@@ -269,7 +269,7 @@ __global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status
 }
 
 // Track hits from their grid positions (written by k_sel_write in track
-// order): cluster ids and, when asked for, rows and coordinates, one thread
+// order, with the rows): cluster ids and, when asked for, coordinates, one thread
 // per hit, coalesced writes (the positions of one track lie in one sector's
 // part of the grid).  Writing all of them from k_sel_write, whose threads
 // hold a tracklet's row chunk each and write short runs at scattered
@@ -277,9 +277,9 @@ __global__ void k_sel_finish(const uint64_t* __restrict__ toff_total, tpc_status
 // alone.
 __global__ __launch_bounds__(kBlock) void k_trk_copy(
     const tpc_status* __restrict__ status, int64_t cap, const int32_t* __restrict__ tpos,
-    const int32_t* __restrict__ idg, const int32_t* __restrict__ gsr,
-    const float* __restrict__ yg, const float* __restrict__ zg, int32_t* __restrict__ trk_hits,
-    uint8_t* __restrict__ trk_row, float* __restrict__ trk_y, float* __restrict__ trk_z)
+    const int32_t* __restrict__ idg, const float* __restrict__ yg,
+    const float* __restrict__ zg, int32_t* __restrict__ trk_hits, float* __restrict__ trk_y,
+    float* __restrict__ trk_z)
 {
     int64_t n = status->n_track_hits;
     if (n > cap) n = cap;
@@ -300,14 +300,13 @@ __global__ __launch_bounds__(kBlock) void k_trk_copy(
             const int64_t j = j0 + (int64_t)u * blockDim.x;
             p[u] = j < n ? tpos[j] : -1;
         }
-        int32_t id[kCopyItems], gr[kCopyItems];
+        int32_t id[kCopyItems];
         float yv[kCopyItems], zv[kCopyItems];
 #pragma unroll
         for (int u = 0; u < kCopyItems; ++u) {
             if (p[u] < 0) continue;
             id[u] = idg[p[u]];
             if (trk_y) {
-                gr[u] = gsr[p[u]];
                 yv[u] = yg[p[u]];
                 zv[u] = zg[p[u]];
             }
@@ -318,7 +317,6 @@ __global__ __launch_bounds__(kBlock) void k_trk_copy(
             const int64_t j = j0 + (int64_t)u * blockDim.x;
             trk_hits[j] = id[u];
             if (trk_y) {
-                trk_row[j] = (uint8_t)(gr[u] & 255);
                 trk_y[j] = yv[u];
                 trk_z[j] = zv[u];
             }
@@ -393,17 +391,17 @@ int run_select_compact(const tpc_problem* p, tpc_grid grid, int64_t count_cap,
                count_cap, trl.capacity, (const unsigned long long*)ws.hitkey,
                (const uint64_t*)ws.tlen, (const uint64_t*)ws.toff, (const uint8_t*)ws.ccnt,
                p->d_sectors, (const int32_t*)ws.gsr, trk.off,
-               TrkHitOut{ws.tpos, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
+               TrkHitOut{ws.tpos, nullptr, trk.hit_y ? trk.hit_row : nullptr, nullptr, nullptr,
+                         nullptr, nullptr},
                trk.tracklet, trk.side,
                trk.capacity, trk.hit_capacity);
     TPC_LAUNCH(k_sel_finish, dim3(1), dim3(1), 0, st, (const uint64_t*)(ws.toff + count_cap),
                ws.status, trk.off, trk.capacity, trk.hit_capacity);
     const int64_t hb = trk.hit_capacity < p->n_clusters ? trk.hit_capacity : p->n_clusters;
     TPC_LAUNCH(k_trk_copy, dim3(grid_for(ceil_div(hb, 4))), dim3(kBlock), 0, st,
-               (const tpc_status*)ws.status,
-               hb, (const int32_t*)ws.tpos, (const int32_t*)grid.id, (const int32_t*)ws.gsr,
-               (const float*)grid.y, (const float*)grid.z, trk.hits, trk.hit_row, trk.hit_y,
-               trk.hit_z);
+               (const tpc_status*)ws.status, hb, (const int32_t*)ws.tpos,
+               (const int32_t*)grid.id, (const float*)grid.y, (const float*)grid.z, trk.hits,
+               trk.hit_y, trk.hit_z);
     return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

@@ -54,8 +54,9 @@ __device__ __forceinline__ int sel_count_chunk(int64_t t, int ra, int n_rows, ui
     return kept;
 }
 
-// where the kept hits go: with pos set, only their grid positions (a
-// coalesced pass writes the rest, see k_trk_copy); else the cluster ids and
+// where the kept hits go: with pos set, their grid positions and (row set)
+// their rows (a coalesced pass writes the rest, see k_trk_copy); else the
+// cluster ids and
 // (when y is set) the hits' rows and coordinates in the same order, read
 // from the grid
 struct TrkHitOut {
@@ -85,6 +86,7 @@ __device__ __forceinline__ int64_t sel_write_chunk(
         if (keep[k]) {
             if (o < hit_cap && out.pos) {
                 out.pos[o] = c[k];
+                if (out.row) out.row[o] = (uint8_t)(ra + k);
             } else if (o < hit_cap) {
                 out.id[o] = idg[c[k]];
                 if (out.y) {
